@@ -1,0 +1,424 @@
+/*
+ * msc_oracle.c -- plain, serial CPU oracle for path-compression Morse-Smale
+ * segmentation and connected components.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library calls, links or
+ * loads this file; only the test suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or helper with
+ * the HIP path.  Speed is not a goal: every function is the plain definition
+ * written out so that it can be checked against the paper by eye.
+ *
+ * Paper: Will, Lukasczyk, Tierny, Garth, "Distributed Path Compression for
+ * Piecewise Linear Morse-Smale Segmentations and Connected Components"
+ * (arXiv 2409.03771).
+ *
+ * Conventions (the readings taken where the paper is silent):
+ *  - Grid vertex (x,y,z) of an X*Y*Z grid has id x + X*y + X*Y*z; the field is
+ *    stored in that order (x fastest).
+ *  - The triangulation is the Freudenthal (Kuhn) subdivision of every cube
+ *    into six tetrahedra {0, e_a, e_a+e_b, e_a+e_b+e_c}, (a,b,c) a permutation
+ *    of the three axes.  The edge set is derived from those tetrahedra at run
+ *    time (orc_stencil), not written down by hand.
+ *  - Vertices are totally ordered by (f(v), id(v)): larger value first, ties
+ *    broken by the larger id -- the simulation-of-simplicity order of the
+ *    paper's preprocessing section.  Comparisons use IEEE float semantics.
+ *  - Steepest ascent picks the (f,id)-largest vertex of the closed
+ *    neighbourhood {v} u N(v), steepest descent the (f,id)-smallest (Sec.
+ *    "Ascending and Descending Manifolds" of the background; Alg. 1 init).
+ *    Including v itself makes extrema point to themselves.
+ *  - asc[v] is the maximum reached by steepest ascent from v (the paper's
+ *    descending manifold), desc[v] the minimum reached by steepest descent
+ *    (the paper's ascending manifold).
+ *  - ms[v] is the smallest vertex id u with asc[u]==asc[v] and
+ *    desc[u]==desc[v] (the Morse-Smale cell of the pair, Sec. "Ascending and
+ *    Descending Segmentation").
+ *  - Connected components: label[v] = smallest id of v's component in the
+ *    graph induced by masked vertices; unmasked vertices get -1 (Alg. 3 init).
+ *
+ * Parity pins for every function live in tests/test_oracle_*.py.
+ */
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+/* ------------------------------------------------------------------------ */
+/* Triangulation                                                            */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Edge vectors of the Freudenthal triangulation, derived from its six Kuhn
+ * tetrahedra: every pair of corners of every tetrahedron spans an edge.
+ * Writes the distinct non-zero vectors (both signs) to out[k*3 + {0,1,2}]
+ * (dx,dy,dz) and returns their number (14).
+ */
+int orc_stencil(int32_t *out)
+{
+    static const int perms[6][3] = {
+        {0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+    int count = 0;
+    for (int p = 0; p < 6; ++p) {
+        int corner[4][3];
+        memset(corner, 0, sizeof corner);
+        for (int k = 1; k < 4; ++k) {
+            memcpy(corner[k], corner[k - 1], sizeof corner[k]);
+            corner[k][perms[p][k - 1]] += 1;
+        }
+        for (int i = 0; i < 4; ++i) {
+            for (int j = 0; j < 4; ++j) {
+                if (i == j) continue;
+                int d[3] = {corner[j][0] - corner[i][0],
+                            corner[j][1] - corner[i][1],
+                            corner[j][2] - corner[i][2]};
+                int seen = 0;
+                for (int q = 0; q < count; ++q)
+                    if (out[3 * q] == d[0] && out[3 * q + 1] == d[1] &&
+                        out[3 * q + 2] == d[2])
+                        seen = 1;
+                if (!seen) {
+                    out[3 * count] = d[0];
+                    out[3 * count + 1] = d[1];
+                    out[3 * count + 2] = d[2];
+                    ++count;
+                }
+            }
+        }
+    }
+    return count;
+}
+
+/* Neighbour list of grid vertex v: ids written to nb[], count returned. */
+static int grid_neighbours(int64_t X, int64_t Y, int64_t Z, int64_t v,
+                           const int32_t *st, int nst, int64_t *nb)
+{
+    int64_t x = v % X, y = (v / X) % Y, z = v / (X * Y);
+    int n = 0;
+    for (int k = 0; k < nst; ++k) {
+        int64_t a = x + st[3 * k], b = y + st[3 * k + 1], c = z + st[3 * k + 2];
+        if (a < 0 || a >= X || b < 0 || b >= Y || c < 0 || c >= Z) continue;
+        nb[n++] = a + X * b + X * Y * c;
+    }
+    return n;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Total order and steepest neighbours                                      */
+/* ------------------------------------------------------------------------ */
+
+/* (f(a),a) > (f(b),b) in the simulation-of-simplicity order. */
+static int above(const float *f, int64_t a, int64_t b)
+{
+    if (f[a] > f[b]) return 1;
+    if (f[a] < f[b]) return 0;
+    return a > b;
+}
+
+static int64_t steepest(const float *f, int64_t X, int64_t Y, int64_t Z,
+                        int64_t v, int dir, const int32_t *st, int nst)
+{
+    int64_t nb[32];
+    int n = grid_neighbours(X, Y, Z, v, st, nst, nb);
+    int64_t best = v;
+    for (int k = 0; k < n; ++k) {
+        if (dir > 0 ? above(f, nb[k], best) : above(f, best, nb[k]))
+            best = nb[k];
+    }
+    return best;
+}
+
+/*
+ * One-step successors: sp[v] = steepest ascent neighbour S+(v), sm[v] =
+ * steepest descent neighbour S-(v), each over the closed neighbourhood
+ * (Alg. 1 initialisation, and its mirror for the ascending manifold).
+ */
+void orc_successors(const float *f, int64_t X, int64_t Y, int64_t Z,
+                    int32_t *sp, int32_t *sm)
+{
+    int32_t st[14 * 3];
+    int nst = orc_stencil(st);
+    int64_t n = X * Y * Z;
+    for (int64_t v = 0; v < n; ++v) {
+        sp[v] = (int32_t)steepest(f, X, Y, Z, v, +1, st, nst);
+        sm[v] = (int32_t)steepest(f, X, Y, Z, v, -1, st, nst);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Integral lines                                                           */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Plain walk: root[v] = last vertex of v, S(v), S(S(v)), ... (the path of the
+ * manifold definition, ending at the first fixed point).  O(N * path length).
+ */
+void orc_walk_plain(const int32_t *succ, int64_t n, int32_t *root)
+{
+    for (int64_t v = 0; v < n; ++v) {
+        int64_t u = v;
+        while (succ[u] != u) u = succ[u];
+        root[v] = (int32_t)u;
+    }
+}
+
+/*
+ * Same result in O(N): follow the path until a vertex whose root is already
+ * known (or a fixed point), then write that root back along the path.
+ * `stack` must hold n entries.
+ */
+void orc_walk_memo(const int32_t *succ, int64_t n, int32_t *root,
+                   int32_t *stack)
+{
+    for (int64_t v = 0; v < n; ++v) root[v] = -1;
+    for (int64_t v = 0; v < n; ++v) {
+        if (root[v] >= 0) continue;
+        int64_t top = 0, u = v;
+        while (root[u] < 0 && succ[u] != u) {
+            stack[top++] = (int32_t)u;
+            u = succ[u];
+        }
+        int32_t r = root[u] >= 0 ? root[u] : (int32_t)u;
+        root[u] = r;
+        while (top > 0) root[stack[--top]] = r;
+    }
+}
+
+/* Root of one vertex, walking on the field directly (no successor array). */
+int64_t orc_walk_from(const float *f, int64_t X, int64_t Y, int64_t Z,
+                      int64_t v, int dir)
+{
+    int32_t st[14 * 3];
+    int nst = orc_stencil(st);
+    for (;;) {
+        int64_t u = steepest(f, X, Y, Z, v, dir, st, nst);
+        if (u == v) return v;
+        v = u;
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Morse-Smale cells                                                        */
+/* ------------------------------------------------------------------------ */
+
+static const int32_t *g_asc, *g_desc;
+
+static int pair_then_id(const void *pa, const void *pb)
+{
+    int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
+    if (g_asc[a] != g_asc[b]) return g_asc[a] < g_asc[b] ? -1 : 1;
+    if (g_desc[a] != g_desc[b]) return g_desc[a] < g_desc[b] ? -1 : 1;
+    return a < b ? -1 : (a > b);
+}
+
+/*
+ * ms[v] = min{u : asc[u]==asc[v] && desc[u]==desc[v]}.  Sorts the vertex ids
+ * by (asc, desc, id); the first id of each run is the class minimum.
+ * `order` must hold n int64 entries.  Returns the number of classes.
+ * Not thread-safe (qsort comparator state).
+ */
+int64_t orc_ms_cells(const int32_t *asc, const int32_t *desc, int64_t n,
+                     int32_t *ms, int64_t *order)
+{
+    for (int64_t v = 0; v < n; ++v) order[v] = v;
+    g_asc = asc;
+    g_desc = desc;
+    qsort(order, (size_t)n, sizeof(int64_t), pair_then_id);
+    int64_t classes = 0, first = -1;
+    for (int64_t i = 0; i < n; ++i) {
+        int64_t v = order[i];
+        if (i == 0 || asc[v] != asc[order[i - 1]] ||
+            desc[v] != desc[order[i - 1]]) {
+            first = v;
+            ++classes;
+        }
+        ms[v] = (int32_t)first;
+    }
+    return classes;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Pointer doubling, synchronous (worked example of Fig. 2)                 */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * `rounds` synchronous doubling steps d'[v] = d[d[v]] over a pointer array of
+ * n entries (each round reads the previous round's array only).  `tmp` holds
+ * n entries.
+ */
+void orc_sync_doubling(int64_t *d, int64_t n, int rounds, int64_t *tmp)
+{
+    for (int r = 0; r < rounds; ++r) {
+        for (int64_t v = 0; v < n; ++v) tmp[v] = d[d[v]];
+        memcpy(d, tmp, (size_t)n * sizeof(int64_t));
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Connected components                                                     */
+/* ------------------------------------------------------------------------ */
+
+static int64_t uf_find(int64_t *parent, int64_t v)
+{
+    while (parent[v] != v) {
+        parent[v] = parent[parent[v]]; /* path halving */
+        v = parent[v];
+    }
+    return v;
+}
+
+/* Union by smaller root id: the root of every set is its minimum id. */
+static void uf_union(int64_t *parent, int64_t a, int64_t b)
+{
+    int64_t ra = uf_find(parent, a), rb = uf_find(parent, b);
+    if (ra == rb) return;
+    if (ra < rb) parent[rb] = ra;
+    else parent[ra] = rb;
+}
+
+static int64_t uf_labels(int64_t *parent, const uint8_t *mask, int64_t n,
+                         int64_t *label)
+{
+    int64_t comps = 0;
+    for (int64_t v = 0; v < n; ++v) {
+        if (mask && !mask[v]) {
+            label[v] = -1;
+            continue;
+        }
+        label[v] = uf_find(parent, v);
+        if (label[v] == v) ++comps;
+    }
+    return comps;
+}
+
+/*
+ * Components of the grid graph induced by masked vertices (mask[v] != 0),
+ * by union-find.  label[v] = smallest id in v's component, -1 if unmasked.
+ * label doubles as the union-find forest.  Returns the number of components.
+ */
+int64_t orc_cc_grid_uf(const uint8_t *mask, int64_t X, int64_t Y, int64_t Z,
+                       int64_t *label)
+{
+    int32_t st[14 * 3];
+    int nst = orc_stencil(st);
+    int64_t n = X * Y * Z, nb[32];
+    for (int64_t v = 0; v < n; ++v) label[v] = v;
+    for (int64_t v = 0; v < n; ++v) {
+        if (!mask[v]) continue;
+        int k = grid_neighbours(X, Y, Z, v, st, nst, nb);
+        for (int i = 0; i < k; ++i)
+            if (mask[nb[i]]) uf_union(label, v, nb[i]);
+    }
+    return uf_labels(label, mask, n, label);
+}
+
+/* Same components by breadth-first search from each unlabelled vertex in
+ * increasing id order (the first vertex reached is the component minimum).
+ * `queue` holds n entries. */
+int64_t orc_cc_grid_bfs(const uint8_t *mask, int64_t X, int64_t Y, int64_t Z,
+                        int64_t *label, int64_t *queue)
+{
+    int32_t st[14 * 3];
+    int nst = orc_stencil(st);
+    int64_t n = X * Y * Z, nb[32], comps = 0;
+    for (int64_t v = 0; v < n; ++v) label[v] = -1;
+    for (int64_t s = 0; s < n; ++s) {
+        if (!mask[s] || label[s] >= 0) continue;
+        int64_t head = 0, tail = 0;
+        queue[tail++] = s;
+        label[s] = s;
+        ++comps;
+        while (head < tail) {
+            int64_t v = queue[head++];
+            int k = grid_neighbours(X, Y, Z, v, st, nst, nb);
+            for (int i = 0; i < k; ++i) {
+                if (mask[nb[i]] && label[nb[i]] < 0) {
+                    label[nb[i]] = s;
+                    queue[tail++] = nb[i];
+                }
+            }
+        }
+    }
+    return comps;
+}
+
+/*
+ * Components of a graph in CSR form (row_ptr[n+1], col_idx[row_ptr[n]]),
+ * restricted to masked vertices when mask != NULL.  Edges are used in both
+ * directions, so a one-sided listing is also accepted.  Returns -2 if a
+ * column index is out of range.
+ */
+int64_t orc_cc_csr_uf(int64_t n, const int64_t *row_ptr, const int32_t *col_idx,
+                      const uint8_t *mask, int64_t *label)
+{
+    for (int64_t v = 0; v < n; ++v) label[v] = v;
+    for (int64_t v = 0; v < n; ++v) {
+        if (mask && !mask[v]) continue;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            int64_t u = col_idx[e];
+            if (u < 0 || u >= n) return -2;
+            if (mask && !mask[u]) continue;
+            uf_union(label, v, u);
+        }
+    }
+    return uf_labels(label, mask, n, label);
+}
+
+/* BFS on a symmetric CSR graph; same output convention as orc_cc_csr_uf. */
+int64_t orc_cc_csr_bfs(int64_t n, const int64_t *row_ptr,
+                       const int32_t *col_idx, const uint8_t *mask,
+                       int64_t *label, int64_t *queue)
+{
+    int64_t comps = 0;
+    for (int64_t v = 0; v < n; ++v) label[v] = -1;
+    for (int64_t s = 0; s < n; ++s) {
+        if ((mask && !mask[s]) || label[s] >= 0) continue;
+        int64_t head = 0, tail = 0;
+        queue[tail++] = s;
+        label[s] = s;
+        ++comps;
+        while (head < tail) {
+            int64_t v = queue[head++];
+            for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+                int64_t u = col_idx[e];
+                if (u < 0 || u >= n) return -2;
+                if ((mask && !mask[u]) || label[u] >= 0) continue;
+                label[u] = s;
+                queue[tail++] = u;
+            }
+        }
+    }
+    return comps;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Full-size local-consistency checker                                      */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Checks labels without walking: root[v] == v iff v is a fixed point of the
+ * steepest step in direction dir, and otherwise root[v] == root[S(v)].  The
+ * two conditions determine the root map uniquely (induction along strictly
+ * monotone paths), so a label array passing this check equals the walk.
+ * Vertices [v0, v1) are checked; returns the number of violations and the
+ * first offending vertex in *first_bad (or -1).
+ */
+int64_t orc_check_roots(const float *f, int64_t X, int64_t Y, int64_t Z,
+                        const int32_t *root, int dir, int64_t v0, int64_t v1,
+                        int64_t *first_bad)
+{
+    int32_t st[14 * 3];
+    int nst = orc_stencil(st);
+    int64_t bad = 0, first = -1;
+    int64_t n = X * Y * Z;
+    for (int64_t v = v0; v < v1; ++v) {
+        int64_t s = steepest(f, X, Y, Z, v, dir, st, nst);
+        int ok;
+        if (root[v] < 0 || root[v] >= n) ok = 0;
+        else if (s == v) ok = (root[v] == v);
+        else ok = (root[v] != v) && (root[v] == root[s]);
+        if (!ok) {
+            if (first < 0) first = v;
+            ++bad;
+        }
+    }
+    *first_bad = first;
+    return bad;
+}

@@ -1,0 +1,201 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle
+checks.  This module holds none of the segmentation or connected-components
+arithmetic: it only draws fields, masks, meshes and request traces.
+
+Field recipe (sum of Gaussian bumps plus uniform noise), evaluated in float64
+and rounded once to float32:
+
+    f(p) = sum_k A_k exp(-|p - c_k|^2 / (2 s_k^2)) + e(p)
+
+with, drawn in this order from ``numpy.random.default_rng(seed)``:
+  centres c_k ~ U[0, n_axis - 1] per axis (x, y, z), shape [nb, 3];
+  amplitudes A_k ~ U[-1, 1];
+  widths s_k ~ U[0.02, 0.1] * scale, scale = geometric mean of the dims;
+  noise e ~ U[-1e-4, 1e-4], one draw per vertex in id order.
+The Gaussian is evaluated as the product of its three 1-D factors.  The field
+is stored [Z][Y][X] (x fastest), so vertex (x, y, z) has id x + X*y + X*Y*z.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+NOISE = 1e-4
+
+
+def gaussian_params(dims, nbumps: int, seed: int):
+    X, Y, Z = (int(d) for d in dims)
+    rng = np.random.default_rng(seed)
+    hi = np.array([X - 1, Y - 1, Z - 1], np.float64)
+    centres = rng.uniform(0.0, 1.0, size=(nbumps, 3)) * hi
+    amps = rng.uniform(-1.0, 1.0, size=nbumps)
+    scale = (X * Y * Z) ** (1.0 / 3.0)
+    sigmas = rng.uniform(0.02, 0.1, size=nbumps) * scale
+    return rng, centres, amps, sigmas
+
+
+def _factors(n: int, c: np.ndarray, s: np.ndarray) -> np.ndarray:
+    t = np.arange(n, dtype=np.float64)[None, :] - c[:, None]
+    return np.exp(-(t * t) / (2.0 * s[:, None] ** 2))
+
+
+def gaussian_field(dims, nbumps: int, seed: int, noise: bool = True,
+                   z_chunk: int = 16) -> np.ndarray:
+    """float32 array of shape [Z, Y, X]."""
+    X, Y, Z = (int(d) for d in dims)
+    rng, c, a, s = gaussian_params((X, Y, Z), nbumps, seed)
+    gx = _factors(X, c[:, 0], s)          # [nb, X]
+    gy = _factors(Y, c[:, 1], s)          # [nb, Y]
+    gz = _factors(Z, c[:, 2], s) * a[:, None]  # [nb, Z], amplitude folded in
+    out = np.empty((Z, Y, X), np.float32)
+    for z0 in range(0, Z, z_chunk):
+        z1 = min(Z, z0 + z_chunk)
+        P = gz[:, z0:z1, None] * gy[:, None, :]              # [nb, zc, Y]
+        blk = P.reshape(P.shape[0], -1).T @ gx                # [zc*Y, X]
+        if noise:
+            blk += rng.uniform(-NOISE, NOISE, size=blk.shape)
+        out[z0:z1] = blk.reshape(z1 - z0, Y, X).astype(np.float32)
+    return out
+
+
+def config_field(name: str) -> np.ndarray:
+    """The named single-field workloads."""
+    if name == "c1":      # 64^3, 8 bumps, seed 0
+        return gaussian_field((64, 64, 64), 8, 0)
+    if name == "c2":      # 1024^3, 512 bumps, seed 1
+        return gaussian_field((1024, 1024, 1024), 512, 1)
+    raise KeyError(name)
+
+
+def threshold_mask(f: np.ndarray, quantile: float = 0.7) -> np.ndarray:
+    """uint8 mask f > tau, tau the k-th smallest value, k = floor(q*N)
+    (0-based): about (1-q) of the vertices are foreground."""
+    flat = f.reshape(-1)
+    k = int(math.floor(quantile * flat.size))
+    k = min(max(k, 0), flat.size - 1)
+    tau = np.partition(flat, k)[k]
+    return (f > tau).astype(np.uint8)
+
+
+def random_field(dims, seed: int, levels: int | None = None) -> np.ndarray:
+    """Small test fields: uniform float32, or integers in [0, levels) to
+    force ties (exercising the id tie-break)."""
+    X, Y, Z = (int(d) for d in dims)
+    rng = np.random.default_rng(seed)
+    if levels is None:
+        return rng.standard_normal((Z, Y, X)).astype(np.float32)
+    return rng.integers(0, levels, size=(Z, Y, X)).astype(np.float32)
+
+
+def batch_specs(count: int = 256, seed: int = 3, lo: int = 32, hi: int = 256):
+    """Uneven batch: per field (dims, nbumps, field seed); each axis
+    round(exp(U[ln lo, ln hi])), bumps ~ U{8..128}."""
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(count):
+        d = np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), size=3)))
+        nb = int(rng.integers(8, 129))
+        specs.append(((int(d[0]), int(d[1]), int(d[2])), nb, seed * 100003 + i))
+    return specs
+
+
+# ---------------------------------------------------------------------------
+# Unstructured input: jittered Kuhn tetrahedralisation as CSR adjacency
+# ---------------------------------------------------------------------------
+
+_KUHN_EDGES = np.array([[1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 0],
+                        [1, 0, 1], [0, 1, 1], [1, 1, 1]], np.int64)
+
+
+def kuhn_csr(n_axis: int, seed: int, nbumps: int | None = None,
+             quantile: float = 0.7, jitter: float = 0.25):
+    """Mesh input for CSR connected components.
+
+    Vertices of an n^3 grid, positions jittered by U[-jitter, jitter] per axis
+    (topology unchanged), edges of its Kuhn tetrahedralisation, vertex ids
+    randomly permuted.  A Gaussian-sum field is evaluated at the jittered
+    positions and thresholded at the quantile.  Returns a dict with
+    ``row_ptr`` (int64 [n+1]), ``col_idx`` (int32, symmetric, rows sorted),
+    ``mask`` (uint8 [n], in permuted ids), ``perm`` (new id of grid vertex
+    g) and the explicit-geometry CSR ``fg_row_ptr``/``fg_col_idx`` that
+    keeps only edges whose two endpoints are foreground.
+    """
+    n3 = n_axis ** 3
+    if nbumps is None:
+        nbumps = max(1, int(round(512 * (n_axis / 1024.0) ** 3)))
+    rng = np.random.default_rng(seed)
+    perm = rng.permutation(n3).astype(np.int64)             # grid -> new id
+    # Field at jittered positions (per-axis jitter, then the bump sum).
+    _, c, a, s = gaussian_params((n_axis,) * 3, nbumps, seed)
+    g = np.arange(n3, dtype=np.int64)
+    f = np.zeros(n3, np.float64)
+    chunk = 1 << 22
+    for g0 in range(0, n3, chunk):
+        gg = g[g0:g0 + chunk]
+        p = np.stack([gg % n_axis, (gg // n_axis) % n_axis,
+                      gg // (n_axis * n_axis)], 1).astype(np.float64)
+        p += rng.uniform(-jitter, jitter, size=p.shape)
+        acc = np.zeros(gg.shape[0], np.float64)
+        for k in range(nbumps):
+            d2 = ((p - c[k]) ** 2).sum(1)
+            acc += a[k] * np.exp(-d2 / (2.0 * s[k] ** 2))
+        f[g0:g0 + chunk] = acc
+    f32 = f.astype(np.float32)
+    kq = min(int(math.floor(quantile * n3)), n3 - 1)
+    tau = np.partition(f32, kq)[kq]
+    fg_grid = (f32 > tau)
+    mask = np.empty(n3, np.uint8)
+    mask[perm] = fg_grid.astype(np.uint8)
+
+    # Adjacency: for each grid vertex the up-to-14 neighbours.
+    offs = np.concatenate([_KUHN_EDGES, -_KUHN_EDGES])
+    inv = np.empty(n3, np.int64)
+    inv[perm] = g
+    rows = []
+    for g0 in range(0, n3, chunk):
+        new_ids = np.arange(g0, min(n3, g0 + chunk), dtype=np.int64)
+        gv = inv[new_ids]
+        x, y, z = gv % n_axis, (gv // n_axis) % n_axis, gv // (n_axis * n_axis)
+        nb = np.full((gv.shape[0], 14), -1, np.int64)
+        for k, (dx, dy, dz) in enumerate(offs):
+            xx, yy, zz = x + dx, y + dy, z + dz
+            ok = ((xx >= 0) & (xx < n_axis) & (yy >= 0) & (yy < n_axis) &
+                  (zz >= 0) & (zz < n_axis))
+            gid = xx + n_axis * yy + n_axis * n_axis * zz
+            nb[:, k] = np.where(ok, perm[np.where(ok, gid, 0)], -1)
+        rows.append(nb.astype(np.int32))
+    nbr = np.concatenate(rows)                               # [n3, 14]
+    nbr.sort(axis=1)                                         # -1 first
+    valid = nbr >= 0
+    deg = valid.sum(1)
+    row_ptr = np.zeros(n3 + 1, np.int64)
+    np.cumsum(deg, out=row_ptr[1:])
+    col_idx = nbr[valid]
+    # Explicit geometry: keep edges between two foreground vertices.
+    keep = valid & (mask[:, None] == 1) & (mask[np.where(valid, nbr, 0)] == 1)
+    fdeg = keep.sum(1)
+    fg_row_ptr = np.zeros(n3 + 1, np.int64)
+    np.cumsum(fdeg, out=fg_row_ptr[1:])
+    fg_col_idx = nbr[keep]
+    return dict(row_ptr=row_ptr, col_idx=np.ascontiguousarray(col_idx),
+                mask=mask, perm=perm, fg_row_ptr=fg_row_ptr,
+                fg_col_idx=np.ascontiguousarray(fg_col_idx), field=f32)
+
+
+def poisson_trace(rate: float, count: int, seed: int = 4, lo: int = 64,
+                  hi: int = 512, ms_frac: float = 0.7):
+    """Open-loop request trace: arrival times (s), kind ('ms' or 'cc'),
+    dims log-uniform per axis, per-request field seed."""
+    rng = np.random.default_rng(seed)
+    gaps = rng.exponential(1.0 / rate, size=count)
+    t = np.cumsum(gaps)
+    out = []
+    for i in range(count):
+        kind = "ms" if rng.uniform() < ms_frac else "cc"
+        d = np.rint(np.exp(rng.uniform(math.log(lo), math.log(hi), size=3)))
+        nb = int(rng.integers(8, 129))
+        out.append(dict(t=float(t[i]), kind=kind,
+                        dims=(int(d[0]), int(d[1]), int(d[2])), nbumps=nb,
+                        seed=seed * 1000003 + i))
+    return out
