@@ -1,0 +1,146 @@
+"""Benchmark: Morse-Smale segmentation throughput on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload gauss1024]
+
+A step is one msc_segment call (steepest pointers, pointer jumping, pairing
+into Morse-Smale cells) over a 1024^3 float32 field already resident in HBM.
+Prints one JSON line with Gvertices/s, the roofline of the dominant kernel
+(timed with HIP events on the call's stream by the library's own trace) and
+the CPU oracle timed on a bounded slab of the same field.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = ("Gvertices/s MS segmentation @1024^3 f32 (vs plain); "
+          "served p50/p99 latency")
+HBM_PEAK_GBS = 8000.0
+WORKLOAD_TEXT = {
+    "gauss1024": "gauss1024: 1024^3 float32, sum of 512 Gaussians "
+                 "(sigma U[0.02,0.1]*1024) + U[-1e-4,1e-4] noise, seed 1",
+    "gauss64": "gauss64: 64^3 float32, sum of 8 Gaussians + noise, seed 0",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(field_dev, depth: int):
+    """The oracle, single-threaded, on the first `depth` z-planes of the
+    field taken as a grid of their own."""
+    import numpy as np
+
+    from oracle import oracle as O
+    slab = field_dev[:depth].cpu().numpy()
+    n = slab.size
+    t0 = time.perf_counter()
+    O.segment(slab, memo=True)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt / 1e9, "unit": "Gvertices/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"first {depth} z-planes ({slab.shape[2]}x{slab.shape[1]}"
+                      f"x{depth} = {n} vertices) of the same field, "
+                      f"{dt:.1f} s, serial C oracle (successors, memoised "
+                      "walks, sort-based cells)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="gauss1024",
+                    choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--cpu-depth", type=int, default=40,
+                    help="z-planes of the field the CPU oracle is timed on")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): "
+              "the segmentation path is single-device; there is no multi-GPU "
+              "mode to measure.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2409_03771_amd import msc, synth
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    log(f"[bench] generating {args.workload} on {dev}")
+    t0 = time.perf_counter()
+    field = synth.config_field(args.workload, device=dev)
+    torch.cuda.synchronize()
+    log(f"[bench] field ready in {time.perf_counter() - t0:.1f} s, "
+        f"shape {tuple(field.shape)}")
+    n = field.numel()
+    asc = torch.empty(n, dtype=torch.int32, device=dev)
+    desc = torch.empty_like(asc)
+    ms = torch.empty_like(asc)
+    stream = torch.cuda.current_stream(dev)
+
+    for i in range(args.warmup):
+        msc.segment_into(field, asc, desc, ms, stream=stream)
+        log(f"[bench] warmup {i + 1}/{args.warmup}")
+    torch.cuda.synchronize()
+    stats = msc.last_stats()
+    log(f"[bench] stats {stats}")
+
+    msc.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        msc.segment_into(field, asc, desc, ms, stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    msc.profile(False)
+    prof = msc.profile_read()
+    ms_per_step = dt / args.steps * 1e3
+    value = n / (dt / args.steps) / 1e9
+    log(f"[bench] {args.steps} steps in {dt:.3f} s: {ms_per_step:.2f} ms/step")
+    for k, p in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"]):
+        avg = p["total_ms"] / max(1, p["launches"])
+        gbs = p["bytes"] / max(1, p["launches"]) / (avg * 1e-3) / 1e9 if avg else 0
+        log(f"[bench]   {k:16s} launches {p['launches']:5d} "
+            f"avg {avg:8.3f} ms  {gbs:8.1f} GB/s (algorithmic)")
+
+    dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
+    avg_ms = dom["total_ms"] / dom["launches"]
+    bytes_per_launch = dom["bytes"] / dom["launches"]
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": dom_name, "avg_ms": round(avg_ms, 4),
+                "bytes_per_launch": bytes_per_launch}
+
+    out = {
+        "metric": METRIC, "value": round(value, 3), "unit": "Gvertices/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
+                   "vertices": n, "outputs": "int32 asc, desc, ms",
+                   "maxima": stats["n_maxima"], "minima": stats["n_minima"],
+                   "cells": stats["n_cells"]},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        depth = min(args.cpu_depth, field.shape[0])
+        log(f"[bench] timing the CPU oracle on {depth} z-planes")
+        out["cpu_baseline"] = cpu_baseline(field, depth)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

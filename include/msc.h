@@ -1,0 +1,191 @@
+/*
+ * msc.h -- C-ABI of libmsc.so: path-compression Morse-Smale segmentation and
+ * connected components on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Will, Lukasczyk, Tierny, Garth, "Distributed Path Compression for
+ * Piecewise Linear Morse-Smale Segmentations and Connected Components",
+ * arXiv 2409.03771.
+ *
+ * General rules for every entry point:
+ *  - Buffers named "device" are device pointers on the context's GPU, owned
+ *    by the caller; the library never frees or keeps them past the call.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *    device work of a call is enqueued on it.  Calls may block the host while
+ *    they read small convergence counters back from the device; when a call
+ *    returns MSC_OK its outputs are complete once `stream` has completed.
+ *  - Outputs must not alias inputs or each other.
+ *  - Return value: MSC_OK (0) or one of the MSC_E* codes below; nothing is
+ *    thrown across the ABI.  On an error the contents of the outputs are
+ *    unspecified.  msc_strerror() names a code.
+ *  - A context is not thread-safe: one host thread at a time per context.
+ *
+ * Grids: dims = {X, Y, Z}, every entry >= 1.  Vertex (x, y, z) has id
+ * x + X*y + X*Y*z and arrays are stored in id order (x fastest).  The grid is
+ * triangulated by the Freudenthal (Kuhn) subdivision: vertex v is adjacent to
+ * v + (dx,dy,dz) for the 14 non-zero offsets with entries all in {0,1} or all
+ * in {0,-1}, when that vertex lies inside the grid.  Degenerate grids (Z = 1,
+ * or Y = Z = 1) are the 2-D and 1-D restrictions of the same rule.
+ */
+#ifndef MSC_H
+#define MSC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__)
+#define MSC_API __attribute__((visibility("default")))
+#else
+#define MSC_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  MSC_OK = 0,
+  MSC_EINVAL = 1,  /* bad dims, NULL required pointer, bad argument       */
+  MSC_ERANGE = 2,  /* vertex count does not fit the id type of an output  */
+  MSC_ENAN = 3,    /* NaN in the scalar field: there is no total order    */
+  MSC_ENOMEM = 4,  /* device workspace could not be allocated             */
+  MSC_EBUDGET = 5, /* request larger than a queue's memory budget         */
+  MSC_EHIP = 6,    /* a HIP runtime call failed                           */
+  MSC_ECANCELED = 7,/* request cancelled before it ran                     */
+  MSC_EBUSY = 8    /* ticket not finished (msc_poll)                      */
+};
+
+typedef struct msc_ctx msc_ctx;
+
+/* Static string for an error code (never NULL). */
+MSC_API const char *msc_strerror(int code);
+
+/* Create a context on HIP device `device`.  The context owns a growable
+ * device workspace (allocated lazily).  *out is NULL on failure. */
+MSC_API int msc_create(msc_ctx **out, int device);
+
+/* Release the context and its workspace.  Synchronises the device first.
+ * NULL is ignored. */
+MSC_API void msc_destroy(msc_ctx *ctx);
+
+/*
+ * Morse-Smale segmentation of a float32 scalar field on a grid.
+ *
+ * Paper: the input is a PL scalar field on a simplicial complex (background,
+ * "Scalar Fields"); vertices are totally ordered by (value, global id), the
+ * simulation-of-simplicity order of the preprocessing section.  Each vertex
+ * points to the largest vertex of its closed neighbourhood (Alg. 1,
+ * initialisation) and pointer jumping compresses every path onto its
+ * extremum (Alg. 1, main loop); the same is done downwards, and vertices
+ * whose two extrema agree form one Morse-Smale cell (methods, "Ascending and
+ * Descending Segmentation").
+ *
+ *  field  device, float32[N], N = X*Y*Z, read only.  No value may be NaN.
+ *         Values are compared as IEEE floats (-0.0 == +0.0, so the id
+ *         decides); they are never converted.
+ *  dims   host, int64[3] = {X, Y, Z}.
+ *  asc    device, int32[N] or NULL: id of the maximum reached by steepest
+ *         ascent from each vertex (the paper's "descending manifold").
+ *  desc   device, int32[N] or NULL: id of the minimum reached by steepest
+ *         descent (the paper's "ascending manifold").
+ *  ms     device, int32[N] or NULL: Morse-Smale cell id = smallest vertex id
+ *         u with asc[u] == asc[v] and desc[u] == desc[v].
+ *  Errors: MSC_EINVAL (dims < 1, field NULL, all outputs NULL),
+ *          MSC_ERANGE (N > INT32_MAX), MSC_ENAN, MSC_ENOMEM, MSC_EHIP.
+ */
+MSC_API int msc_segment(msc_ctx *ctx, const float *field, const int64_t dims[3],
+                int32_t *asc, int32_t *desc, int32_t *ms, void *stream);
+
+/* Counters of the last successful msc_segment on this context. */
+typedef struct msc_stats {
+  int64_t n_vertices;
+  int64_t n_maxima;      /* distinct ascent roots                     */
+  int64_t n_minima;      /* distinct descent roots                    */
+  int64_t n_cells;       /* distinct (asc, desc) pairs                */
+  int64_t n_exits;       /* tile-exit vertices resolved globally      */
+  int32_t jump_rounds;   /* pointer-jumping rounds on the exit graph  */
+  int32_t tile_x, tile_y, tile_z; /* tile of the fused local pass     */
+} msc_stats;
+
+MSC_API int msc_last_stats(const msc_ctx *ctx, msc_stats *out);
+
+/*
+ * Per-kernel timing (the library's own trace).  While enabled, every kernel
+ * launch of the calls on this context is bracketed by HIP events recorded on
+ * the call's stream, and its elapsed time is added to a per-kernel record
+ * together with the kernel's algorithmic HBM bytes (the bytes the algorithm
+ * must move: inputs read once, outputs written once, pointer gathers counted
+ * once per access).  Recording adds two event records per launch.
+ *
+ *  msc_profile: enable != 0 clears the records and starts recording;
+ *               enable == 0 stops recording (records are kept).
+ *  msc_profile_read: copies up to `max` records to `out` (host array) and
+ *               sets *count to the number of records available.
+ */
+typedef struct msc_phase {
+  char name[32];
+  int64_t launches;
+  double total_ms;
+  double bytes;
+} msc_phase;
+
+MSC_API int msc_profile(msc_ctx *ctx, int enable);
+MSC_API int msc_profile_read(const msc_ctx *ctx, msc_phase *out, int max,
+                             int *count);
+
+/*
+ * Connected components of the feature mask on a grid (Alg. 3, implicit
+ * thresholding): the graph is the Freudenthal grid restricted to vertices
+ * with mask != 0.
+ *
+ *  mask    device, uint8[N], read only; nonzero = feature.
+ *  dims    host, int64[3].
+ *  labels  device, int64[N]: smallest vertex id of the vertex's component,
+ *          -1 for vertices outside the mask (Alg. 3 gives them a negative
+ *          label; the paper names a component by its largest id, this
+ *          library by its smallest).
+ *  Errors: MSC_EINVAL, MSC_ENOMEM, MSC_EHIP.
+ */
+MSC_API int cc_label_grid(msc_ctx *ctx, const uint8_t *mask, const int64_t dims[3],
+                  int64_t *labels, void *stream);
+
+/*
+ * Connected components of an explicit graph in CSR form (the paper's
+ * "explicit" CC on extracted geometry).
+ *
+ *  n        number of vertices (>= 0; 0 is a no-op).
+ *  row_ptr  device, int64[n+1], row_ptr[0] = 0, non-decreasing.
+ *  col_idx  device, int32[row_ptr[n]], each in [0, n).  Edges are used in
+ *           both directions, so listing an edge once suffices; duplicates
+ *           and self-loops are allowed.
+ *  mask     device, uint8[n] or NULL (NULL = every vertex is a feature).
+ *  labels   device, int64[n]: smallest id of the component, -1 outside mask.
+ *  Errors: MSC_EINVAL (NULL pointers, n < 0, n > INT32_MAX), MSC_ENOMEM,
+ *          MSC_EHIP.  Out-of-range col_idx entries are reported as
+ *          MSC_EINVAL after the call's kernels have checked them.
+ */
+MSC_API int cc_label_csr(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,
+                 const int32_t *col_idx, const uint8_t *mask, int64_t *labels,
+                 void *stream);
+
+/*
+ * Path compression of a pointer forest in place (Alg. 1 main loop; the
+ * synchronous form is pointer doubling as tabulated in Fig. 2).
+ *
+ *  d        device, int64[n]: d[v] in [0, n); the pointers must form a forest
+ *           whose roots point to themselves (no longer cycles).
+ *  rounds   >= 1: number of rounds to run; 0 = until every vertex points to a
+ *           root.
+ *  synchronous  nonzero: each round computes d'[v] = d[d[v]] from the
+ *           previous round's array (double buffered, as in the worked
+ *           example); zero: rounds update d in place (the paper's production
+ *           form), which converges at least as fast.
+ *  Errors: MSC_EINVAL (d NULL, n < 0, rounds < 0), MSC_ENOMEM, MSC_EHIP.
+ */
+MSC_API int msc_pointer_jump(msc_ctx *ctx, int64_t *d, int64_t n, int rounds,
+                     int synchronous, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MSC_H */

@@ -1,0 +1,207 @@
+// C-ABI entry points of libmsc.so: argument checks, context and workspace.
+#include <climits>
+#include <cstring>
+#include <new>
+
+#include "msc_internal.hpp"
+
+namespace msc {
+
+int reserve(DevBuf &buf, size_t bytes) {
+  if (bytes <= buf.bytes) return MSC_OK;
+  // The old block may still be read by work queued on any stream.
+  MSC_HIP_TRY(hipDeviceSynchronize());
+  if (buf.ptr) {
+    MSC_HIP_TRY(hipFree(buf.ptr));
+    buf.ptr = nullptr;
+    buf.bytes = 0;
+  }
+  size_t want = bytes + bytes / 8 + (1 << 20);
+  void *p = nullptr;
+  if (hipMalloc(&p, want) != hipSuccess) {
+    (void)hipGetLastError();
+    return MSC_ENOMEM;
+  }
+  buf.ptr = static_cast<char *>(p);
+  buf.bytes = want;
+  return MSC_OK;
+}
+
+int clear_counters(msc_ctx *ctx, hipStream_t stream) {
+  MSC_HIP_TRY(hipMemsetAsync(ctx->dctr, 0,
+                             kNumCounters * sizeof(unsigned long long),
+                             stream));
+  return MSC_OK;
+}
+
+int read_counters(msc_ctx *ctx, hipStream_t stream) {
+  MSC_HIP_TRY(hipMemcpyAsync(ctx->hctr, ctx->dctr,
+                             kNumCounters * sizeof(unsigned long long),
+                             hipMemcpyDeviceToHost, stream));
+  MSC_HIP_TRY(hipStreamSynchronize(stream));
+  if (ctx->prof.on) ctx->prof.flush();
+  return MSC_OK;
+}
+
+}  // namespace msc
+
+namespace {
+
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = false;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) return;
+    ok = hipSetDevice(dev) == hipSuccess;
+  }
+  ~DeviceGuard() {
+    if (prev >= 0) (void)hipSetDevice(prev);
+  }
+};
+
+int check_dims(const int64_t dims[3], int64_t *n) {
+  if (!dims) return MSC_EINVAL;
+  for (int i = 0; i < 3; ++i)
+    if (dims[i] < 1) return MSC_EINVAL;
+  // Guard the product against overflow of int64.
+  const int64_t lim = INT64_C(1) << 40;
+  if (dims[0] > lim || dims[1] > lim || dims[2] > lim) return MSC_ERANGE;
+  if (dims[0] * dims[1] > lim || dims[0] * dims[1] * dims[2] > lim)
+    return MSC_ERANGE;
+  *n = dims[0] * dims[1] * dims[2];
+  return MSC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *msc_strerror(int code) {
+  switch (code) {
+    case MSC_OK: return "ok";
+    case MSC_EINVAL: return "invalid argument";
+    case MSC_ERANGE: return "size out of range for the id type";
+    case MSC_ENAN: return "NaN in scalar field";
+    case MSC_ENOMEM: return "device workspace allocation failed";
+    case MSC_EBUDGET: return "request exceeds the memory budget";
+    case MSC_EHIP: return "HIP runtime error";
+    case MSC_ECANCELED: return "request cancelled";
+    case MSC_EBUSY: return "request not finished";
+    default: return "unknown error";
+  }
+}
+
+int msc_create(msc_ctx **out, int device) {
+  if (!out) return MSC_EINVAL;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess) return MSC_EHIP;
+  if (device < 0 || device >= count) return MSC_EINVAL;
+  DeviceGuard g(device);
+  if (!g.ok) return MSC_EHIP;
+  msc_ctx *c = new (std::nothrow) msc_ctx();
+  if (!c) return MSC_ENOMEM;
+  c->device = device;
+  if (hipMalloc(&c->dctr, msc::kNumCounters * sizeof(unsigned long long)) !=
+      hipSuccess) {
+    delete c;
+    return MSC_ENOMEM;
+  }
+  if (hipHostMalloc(&c->hctr, msc::kNumCounters * sizeof(unsigned long long),
+                    hipHostMallocDefault) != hipSuccess) {
+    (void)hipFree(c->dctr);
+    delete c;
+    return MSC_ENOMEM;
+  }
+  std::memset(c->hctr, 0, msc::kNumCounters * sizeof(unsigned long long));
+  *out = c;
+  return MSC_OK;
+}
+
+void msc_destroy(msc_ctx *ctx) {
+  if (!ctx) return;
+  DeviceGuard g(ctx->device);
+  (void)hipDeviceSynchronize();
+  if (ctx->ws.ptr) (void)hipFree(ctx->ws.ptr);
+  if (ctx->tab.ptr) (void)hipFree(ctx->tab.ptr);
+  if (ctx->dctr) (void)hipFree(ctx->dctr);
+  if (ctx->hctr) (void)hipHostFree(ctx->hctr);
+  delete ctx;
+}
+
+int msc_segment(msc_ctx *ctx, const float *field, const int64_t dims[3],
+                int32_t *asc, int32_t *desc, int32_t *ms, void *stream) {
+  if (!ctx || !field) return MSC_EINVAL;
+  if (!asc && !desc && !ms) return MSC_EINVAL;
+  int64_t n = 0;
+  MSC_TRY(check_dims(dims, &n));
+  if (n > INT32_MAX) return MSC_ERANGE;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return MSC_EHIP;
+  return msc::segment_run(ctx, field, dims[0], dims[1], dims[2], asc, desc, ms,
+                          static_cast<hipStream_t>(stream));
+}
+
+int msc_last_stats(const msc_ctx *ctx, msc_stats *out) {
+  if (!ctx || !out) return MSC_EINVAL;
+  *out = ctx->stats;
+  return MSC_OK;
+}
+
+int msc_profile(msc_ctx *ctx, int enable) {
+  if (!ctx) return MSC_EINVAL;
+  if (enable) {
+    DeviceGuard g(ctx->device);
+    (void)hipDeviceSynchronize();
+    ctx->prof.pending.clear();
+    ctx->prof.next = 0;
+    ctx->prof.totals.clear();
+  }
+  ctx->prof.on = enable != 0;
+  return MSC_OK;
+}
+
+int msc_profile_read(const msc_ctx *ctx, msc_phase *out, int max, int *count) {
+  if (!ctx || !count || max < 0 || (max > 0 && !out)) return MSC_EINVAL;
+  int n = (int)ctx->prof.totals.size();
+  *count = n;
+  for (int i = 0; i < n && i < max; ++i) out[i] = ctx->prof.totals[i];
+  return MSC_OK;
+}
+
+int cc_label_grid(msc_ctx *ctx, const uint8_t *mask, const int64_t dims[3],
+                  int64_t *labels, void *stream) {
+  if (!ctx || !mask || !labels) return MSC_EINVAL;
+  int64_t n = 0;
+  MSC_TRY(check_dims(dims, &n));
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return MSC_EHIP;
+  return msc::cc_grid_run(ctx, mask, dims[0], dims[1], dims[2], labels,
+                          static_cast<hipStream_t>(stream));
+}
+
+int cc_label_csr(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,
+                 const int32_t *col_idx, const uint8_t *mask, int64_t *labels,
+                 void *stream) {
+  if (!ctx || n < 0) return MSC_EINVAL;
+  if (n == 0) return MSC_OK;
+  if (n > INT32_MAX) return MSC_EINVAL;
+  if (!row_ptr || !labels) return MSC_EINVAL;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return MSC_EHIP;
+  return msc::cc_csr_run(ctx, n, row_ptr, col_idx, mask, labels,
+                         static_cast<hipStream_t>(stream));
+}
+
+int msc_pointer_jump(msc_ctx *ctx, int64_t *d, int64_t n, int rounds,
+                     int synchronous, void *stream) {
+  if (!ctx || n < 0 || rounds < 0) return MSC_EINVAL;
+  if (n == 0) return MSC_OK;
+  if (!d) return MSC_EINVAL;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return MSC_EHIP;
+  return msc::jump_run(ctx, d, n, rounds, synchronous,
+                       static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,174 @@
+// Internal declarations shared by the translation units of libmsc.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <cstring>
+#include <vector>
+
+#include "../../include/msc.h"
+
+#define MSC_HIP_TRY(expr)                                                   \
+  do {                                                                      \
+    hipError_t e_ = (expr);                                                 \
+    if (e_ != hipSuccess) return MSC_EHIP;                                  \
+  } while (0)
+
+#define MSC_TRY(expr)                                                       \
+  do {                                                                      \
+    int s_ = (expr);                                                        \
+    if (s_ != MSC_OK) return s_;                                            \
+  } while (0)
+
+namespace msc {
+
+constexpr int kBlock = 256;
+
+// Slots of the small device counter block each context owns.
+enum Counter : int {
+  kCtrChanged = 0,   // set nonzero by a round that changed something
+  kCtrNaN = 1,       // NaN seen in the field
+  kCtrMaxima = 2,    // local maxima counted by the steepest pass
+  kCtrMinima = 3,    // local minima
+  kCtrCells = 4,     // distinct (asc, desc) pairs inserted
+  kCtrExits = 5,     // tile-exit list length
+  kCtrBadIndex = 6,  // out-of-range CSR column seen
+  kCtrOverflow = 7,  // hash table or list overflow
+  kCtrChanged2 = 8,
+  kNumCounters = 16
+};
+
+}  // namespace msc
+
+namespace msc {
+// Grow-only device buffer.
+struct DevBuf {
+  char *ptr = nullptr;
+  size_t bytes = 0;
+};
+
+// Event-bracketed per-kernel timing; see msc_profile in msc.h.
+struct Profiler {
+  struct Pending {
+    int slot;
+    hipEvent_t a, b;
+    double bytes;
+  };
+  bool on = false;
+  std::vector<hipEvent_t> pool;
+  size_t next = 0;
+  std::vector<Pending> pending;
+  std::vector<msc_phase> totals;
+
+  int slot_of(const char *name) {
+    for (size_t i = 0; i < totals.size(); ++i)
+      if (std::strncmp(totals[i].name, name, sizeof(totals[i].name)) == 0)
+        return (int)i;
+    msc_phase p{};
+    std::strncpy(p.name, name, sizeof(p.name) - 1);
+    totals.push_back(p);
+    return (int)totals.size() - 1;
+  }
+  hipEvent_t event() {
+    if (next == pool.size()) {
+      hipEvent_t e = nullptr;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      pool.push_back(e);
+    }
+    return pool[next++];
+  }
+  // Fold finished events into the totals; the stream must be complete.
+  void flush() {
+    for (const Pending &p : pending) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+        totals[p.slot].launches += 1;
+        totals[p.slot].total_ms += ms;
+        totals[p.slot].bytes += p.bytes;
+      }
+    }
+    pending.clear();
+    next = 0;
+  }
+  ~Profiler() {
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
+  }
+};
+}  // namespace msc
+
+struct msc_ctx {
+  int device = 0;
+  // Grow-only device workspaces carved per call: `ws` for per-vertex
+  // scratch, `tab` for hash tables and lists sized after a first pass.
+  msc::DevBuf ws, tab;
+  // Device counters and a pinned host mirror.
+  unsigned long long *dctr = nullptr;
+  unsigned long long *hctr = nullptr;
+  msc_stats stats{};
+  msc::Profiler prof;
+};
+
+namespace msc {
+
+// Make sure `buf` holds at least `bytes`.  Growing synchronises the device
+// (the old block may still be in use) and discards the old contents.
+int reserve(DevBuf &buf, size_t bytes);
+
+// Bump allocator over a DevBuf for the duration of one call.
+struct Carver {
+  char *base;
+  size_t cap, used = 0;
+  explicit Carver(const DevBuf &b) : base(b.ptr), cap(b.bytes) {}
+  template <class T>
+  T *take(size_t count) {
+    size_t off = (used + 255) & ~size_t(255);
+    used = off + count * sizeof(T);
+    return reinterpret_cast<T *>(base + off);
+  }
+};
+
+inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+
+// Read the counter block back to the host (synchronises `stream`).
+int read_counters(msc_ctx *ctx, hipStream_t stream);
+int clear_counters(msc_ctx *ctx, hipStream_t stream);
+
+// Launch `launch` (a statement) bracketed by profiling events when enabled.
+#define MSC_PHASE(ctx, stream, name, bytes, launch)                         \
+  do {                                                                      \
+    hipEvent_t pa_ = nullptr, pb_ = nullptr;                                \
+    if ((ctx)->prof.on) {                                                   \
+      pa_ = (ctx)->prof.event();                                            \
+      if (pa_) (void)hipEventRecord(pa_, stream);                           \
+    }                                                                       \
+    launch;                                                                 \
+    MSC_HIP_TRY(hipGetLastError());                                         \
+    if ((ctx)->prof.on && pa_) {                                            \
+      pb_ = (ctx)->prof.event();                                            \
+      if (pb_) {                                                            \
+        (void)hipEventRecord(pb_, stream);                                  \
+        (ctx)->prof.pending.push_back(                                      \
+            {(ctx)->prof.slot_of(name), pa_, pb_, (double)(bytes)});        \
+      }                                                                     \
+    }                                                                       \
+  } while (0)
+
+inline unsigned grid_for(int64_t n, int block = kBlock) {
+  int64_t g = (n + block - 1) / block;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+// Launchers implemented in the kernel translation units.
+int segment_run(msc_ctx *ctx, const float *f, int64_t X, int64_t Y, int64_t Z,
+                int32_t *asc, int32_t *desc, int32_t *ms, hipStream_t s);
+int cc_grid_run(msc_ctx *ctx, const uint8_t *mask, int64_t X, int64_t Y,
+                int64_t Z, int64_t *labels, hipStream_t s);
+int cc_csr_run(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,
+               const int32_t *col_idx, const uint8_t *mask, int64_t *labels,
+               hipStream_t s);
+int jump_run(msc_ctx *ctx, int64_t *d, int64_t n, int rounds, int sync,
+             hipStream_t s);
+
+}  // namespace msc

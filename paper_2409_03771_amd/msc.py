@@ -1,0 +1,225 @@
+"""Python binding of libmsc.so (ctypes).  Argument marshalling only: every
+step runs in the HIP library.  torch supplies device memory and streams.
+
+    asc, desc, ms = msc.segment(field)          # field: float32 [Z, Y, X] on GPU
+    labels = msc.cc_label_grid(mask)             # mask: uint8 [Z, Y, X]
+    labels = msc.cc_label_csr(row_ptr, col_idx)  # int64 [n+1], int32 [nnz]
+
+Importing this module loads the library and raises ImportError if it has not
+been built (``python -m paper_2409_03771_amd.build``); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmsc.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with "
+        "`python -m paper_2409_03771_amd.build` (hipcc, gfx950)")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+MSC_OK, MSC_EINVAL, MSC_ERANGE, MSC_ENAN, MSC_ENOMEM = 0, 1, 2, 3, 4
+MSC_EBUDGET, MSC_EHIP, MSC_ECANCELED, MSC_EBUSY = 5, 6, 7, 8
+
+_P = ctypes.c_void_p
+_I64 = ctypes.c_int64
+_I32 = ctypes.c_int
+
+
+class msc_stats(ctypes.Structure):
+    _fields_ = [("n_vertices", _I64), ("n_maxima", _I64), ("n_minima", _I64),
+                ("n_cells", _I64), ("n_exits", _I64), ("jump_rounds", _I32),
+                ("tile_x", _I32), ("tile_y", _I32), ("tile_z", _I32)]
+
+
+class msc_phase(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", _I64),
+                ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
+
+
+_SIGS = {
+    "msc_strerror": ([_I32], ctypes.c_char_p),
+    "msc_create": ([ctypes.POINTER(_P), _I32], _I32),
+    "msc_destroy": ([_P], None),
+    "msc_segment": ([_P, _P, ctypes.POINTER(_I64), _P, _P, _P, _P], _I32),
+    "msc_last_stats": ([_P, ctypes.POINTER(msc_stats)], _I32),
+    "msc_profile": ([_P, _I32], _I32),
+    "msc_profile_read": ([_P, ctypes.POINTER(msc_phase), _I32,
+                          ctypes.POINTER(_I32)], _I32),
+    "cc_label_grid": ([_P, _P, ctypes.POINTER(_I64), _P, _P], _I32),
+    "cc_label_csr": ([_P, _I64, _P, _P, _P, _P, _P], _I32),
+    "msc_pointer_jump": ([_P, _P, _I64, _I32, _I32, _P], _I32),
+}
+for _name, (_args, _res) in _SIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _res
+
+EXPORTS = tuple(_SIGS)
+
+
+class MscError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = _lib.msc_strerror(code).decode()
+        super().__init__(f"{where}: {msg} (code {code})")
+
+
+def _check(code: int, where: str):
+    if code != MSC_OK:
+        raise MscError(code, where)
+
+
+_ctx_lock = threading.Lock()
+_ctxs: dict[int, ctypes.c_void_p] = {}
+
+
+def context(device: int | None = None) -> ctypes.c_void_p:
+    """The library context of a device (created once, reused)."""
+    if device is None:
+        device = torch.cuda.current_device()
+    with _ctx_lock:
+        c = _ctxs.get(device)
+        if c is None:
+            c = _P()
+            _check(_lib.msc_create(ctypes.byref(c), int(device)), "msc_create")
+            _ctxs[device] = c
+        return c
+
+
+def _stream(t: torch.Tensor, stream=None):
+    if stream is None:
+        stream = torch.cuda.current_stream(t.device)
+    return _P(stream.cuda_stream)
+
+
+def _dev_ptr(t: torch.Tensor | None, dtype, name: str):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return _P(t.data_ptr())
+
+
+def grid_dims(shape) -> tuple[int, int, int]:
+    """(X, Y, Z) of an array stored [Z][Y][X]; 1-D and 2-D shapes are the
+    degenerate grids."""
+    shape = tuple(int(s) for s in shape)
+    if len(shape) == 1:
+        return shape[0], 1, 1
+    if len(shape) == 2:
+        return shape[1], shape[0], 1
+    if len(shape) == 3:
+        return shape[2], shape[1], shape[0]
+    raise ValueError("grid arrays are 1-D, 2-D or 3-D")
+
+
+def _dims_arg(dims):
+    return (_I64 * 3)(*[int(d) for d in dims])
+
+
+def segment_into(field, asc=None, desc=None, ms=None, dims=None, stream=None):
+    """Write ascent roots, descent roots and Morse-Smale cell ids into the
+    given int32 tensors (any may be None)."""
+    if dims is None:
+        dims = grid_dims(field.shape)
+    code = _lib.msc_segment(
+        context(field.device.index), _dev_ptr(field, torch.float32, "field"),
+        _dims_arg(dims), _dev_ptr(asc, torch.int32, "asc"),
+        _dev_ptr(desc, torch.int32, "desc"), _dev_ptr(ms, torch.int32, "ms"),
+        _stream(field, stream))
+    _check(code, "msc_segment")
+
+
+def segment(field: torch.Tensor, want=("asc", "desc", "ms"), stream=None):
+    """Morse-Smale segmentation of a float32 field on the GPU.  Returns a
+    tuple (asc, desc, ms) of flat int32 tensors (None where not wanted)."""
+    n = field.numel()
+    out = {k: (torch.empty(n, dtype=torch.int32, device=field.device)
+               if k in want else None) for k in ("asc", "desc", "ms")}
+    segment_into(field, out["asc"], out["desc"], out["ms"], stream=stream)
+    return out["asc"], out["desc"], out["ms"]
+
+
+def last_stats(device: int | None = None) -> dict:
+    s = msc_stats()
+    _check(_lib.msc_last_stats(context(device), ctypes.byref(s)),
+           "msc_last_stats")
+    return {k: getattr(s, k) for k, _ in msc_stats._fields_}
+
+
+def profile(enable: bool, device: int | None = None):
+    """Start (clearing old records) or stop per-kernel event timing."""
+    _check(_lib.msc_profile(context(device), int(bool(enable))), "msc_profile")
+
+
+def profile_read(device: int | None = None) -> dict:
+    """{kernel: {"launches", "total_ms", "bytes"}} recorded so far."""
+    cnt = _I32(0)
+    _check(_lib.msc_profile_read(context(device), None, 0, ctypes.byref(cnt)),
+           "msc_profile_read")
+    arr = (msc_phase * max(1, cnt.value))()
+    _check(_lib.msc_profile_read(context(device), arr, cnt.value,
+                                 ctypes.byref(cnt)), "msc_profile_read")
+    return {arr[i].name.decode(): dict(launches=arr[i].launches,
+                                       total_ms=arr[i].total_ms,
+                                       bytes=arr[i].bytes)
+            for i in range(cnt.value)}
+
+
+def cc_label_grid_into(mask, labels, dims=None, stream=None):
+    if dims is None:
+        dims = grid_dims(mask.shape)
+    code = _lib.cc_label_grid(
+        context(mask.device.index), _dev_ptr(mask, torch.uint8, "mask"),
+        _dims_arg(dims), _dev_ptr(labels, torch.int64, "labels"),
+        _stream(mask, stream))
+    _check(code, "cc_label_grid")
+
+
+def cc_label_grid(mask: torch.Tensor, stream=None) -> torch.Tensor:
+    """Components of a uint8 feature mask on the grid; int64 labels, flat."""
+    labels = torch.empty(mask.numel(), dtype=torch.int64, device=mask.device)
+    cc_label_grid_into(mask, labels, stream=stream)
+    return labels
+
+
+def cc_label_csr_into(row_ptr, col_idx, labels, mask=None, stream=None):
+    n = row_ptr.numel() - 1
+    code = _lib.cc_label_csr(
+        context(row_ptr.device.index), int(n),
+        _dev_ptr(row_ptr, torch.int64, "row_ptr"),
+        _dev_ptr(col_idx, torch.int32, "col_idx"),
+        _dev_ptr(mask, torch.uint8, "mask"),
+        _dev_ptr(labels, torch.int64, "labels"), _stream(row_ptr, stream))
+    _check(code, "cc_label_csr")
+
+
+def cc_label_csr(row_ptr, col_idx, mask=None, stream=None) -> torch.Tensor:
+    """Components of a CSR graph (optionally restricted to a mask)."""
+    n = row_ptr.numel() - 1
+    labels = torch.empty(n, dtype=torch.int64, device=row_ptr.device)
+    cc_label_csr_into(row_ptr, col_idx, labels, mask, stream)
+    return labels
+
+
+def pointer_jump(d: torch.Tensor, rounds: int = 0, synchronous: bool = False,
+                 stream=None) -> torch.Tensor:
+    """Compress an int64 pointer forest in place (see msc_pointer_jump)."""
+    code = _lib.msc_pointer_jump(
+        context(d.device.index), _dev_ptr(d, torch.int64, "d"), d.numel(),
+        int(rounds), int(bool(synchronous)), _stream(d, stream))
+    _check(code, "msc_pointer_jump")
+    return d

@@ -41,13 +41,31 @@ def _factors(n: int, c: np.ndarray, s: np.ndarray) -> np.ndarray:
 
 
 def gaussian_field(dims, nbumps: int, seed: int, noise: bool = True,
-                   z_chunk: int = 16) -> np.ndarray:
-    """float32 array of shape [Z, Y, X]."""
+                   z_chunk: int = 16, device=None):
+    """float32 field of shape [Z, Y, X]: a numpy array, or a torch tensor
+    on `device` when one is given (the bump sum is then evaluated there in
+    float64; the noise is the same numpy draw)."""
     X, Y, Z = (int(d) for d in dims)
     rng, c, a, s = gaussian_params((X, Y, Z), nbumps, seed)
     gx = _factors(X, c[:, 0], s)          # [nb, X]
     gy = _factors(Y, c[:, 1], s)          # [nb, Y]
     gz = _factors(Z, c[:, 2], s) * a[:, None]  # [nb, Z], amplitude folded in
+    if device is not None:
+        import torch
+        out_t = torch.empty((Z, Y, X), dtype=torch.float32, device=device)
+        gx_t = torch.from_numpy(gx).to(device)
+        gy_t = torch.from_numpy(gy).to(device)
+        gz_t = torch.from_numpy(gz).to(device)
+        zc = max(z_chunk, 64)
+        for z0 in range(0, Z, zc):
+            z1 = min(Z, z0 + zc)
+            P = gz_t[:, z0:z1, None] * gy_t[:, None, :]
+            blk = P.reshape(P.shape[0], -1).T @ gx_t
+            if noise:
+                e = rng.uniform(-NOISE, NOISE, size=tuple(blk.shape))
+                blk += torch.from_numpy(e).to(device)
+            out_t[z0:z1] = blk.reshape(z1 - z0, Y, X).to(torch.float32)
+        return out_t
     out = np.empty((Z, Y, X), np.float32)
     for z0 in range(0, Z, z_chunk):
         z1 = min(Z, z0 + z_chunk)
@@ -59,13 +77,19 @@ def gaussian_field(dims, nbumps: int, seed: int, noise: bool = True,
     return out
 
 
-def config_field(name: str) -> np.ndarray:
-    """The named single-field workloads."""
-    if name == "c1":      # 64^3, 8 bumps, seed 0
-        return gaussian_field((64, 64, 64), 8, 0)
-    if name == "c2":      # 1024^3, 512 bumps, seed 1
-        return gaussian_field((1024, 1024, 1024), 512, 1)
-    raise KeyError(name)
+WORKLOADS = {
+    # name: (dims, bumps, seed)
+    "gauss64": ((64, 64, 64), 8, 0),
+    "gauss1024": ((1024, 1024, 1024), 512, 1),
+}
+
+
+def config_field(name: str, device=None):
+    """The named single-field workloads: "gauss64" (64^3, 8 bumps, seed 0)
+    and "gauss1024" (1024^3, 512 bumps, seed 1)."""
+    alias = {"c1": "gauss64", "c2": "gauss1024"}
+    dims, nb, seed = WORKLOADS[alias.get(name, name)]
+    return gaussian_field(dims, nb, seed, device=device)
 
 
 def threshold_mask(f: np.ndarray, quantile: float = 0.7) -> np.ndarray:

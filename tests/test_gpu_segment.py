@@ -1,0 +1,147 @@
+"""Parity of the HIP segmentation (through the C-ABI) with the CPU oracle,
+bit-exact, on seeded inputs; degenerate grids, ties and error paths."""
+import itertools
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2409_03771_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def msc():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2409_03771_amd import msc as m
+    return m
+
+
+def gpu_segment(msc, f_np, **kw):
+    t = torch.from_numpy(np.ascontiguousarray(f_np)).cuda()
+    a, d, m = msc.segment(t, **kw)
+    torch.cuda.synchronize()
+    cpu = lambda x: None if x is None else x.cpu().numpy()
+    return cpu(a), cpu(d), cpu(m)
+
+
+def assert_parity(msc, f_np, tag=""):
+    want = O.segment(f_np)
+    got = gpu_segment(msc, f_np)
+    for name, g, w in zip(("asc", "desc", "ms"), got, want):
+        np.testing.assert_array_equal(g, w, err_msg=f"{tag} {name}")
+
+
+def test_gauss64_parity(msc):
+    f = synth.config_field("gauss64")
+    assert_parity(msc, f, "gauss64")
+    st = msc.last_stats()
+    assert st["n_maxima"] == 9911 and st["n_minima"] == 11008
+    assert st["n_cells"] == 50420
+
+
+@pytest.mark.parametrize("dims", [
+    (37, 29, 23), (128, 64, 17), (300, 7, 5), (1, 1, 1), (100, 1, 1),
+    (1, 100, 1), (1, 1, 100), (40, 30, 1), (1, 30, 40), (33, 1, 31),
+    (2, 2, 2), (257, 3, 2), (65, 65, 65)])
+@pytest.mark.parametrize("levels", [None, 3])
+def test_random_grids_parity(msc, dims, levels):
+    f = synth.random_field(dims, seed=sum(dims) + (levels or 0), levels=levels)
+    assert_parity(msc, f, f"{dims} levels={levels}")
+
+
+def test_gaussian_ragged_parity(msc):
+    f = synth.gaussian_field((203, 151, 77), 40, seed=11)
+    assert_parity(msc, f, "gauss ragged")
+
+
+def test_exhaustive_ties_2x2x2(msc):
+    """Every field over {0,1,2} on 2x2x2 (3^8) and a seeded sample of the
+    8! orderings of distinct values."""
+    F = list(itertools.product((0, 1, 2), repeat=8))
+    perms = list(itertools.permutations(range(8)))
+    rng = np.random.default_rng(0)
+    F += [perms[i] for i in rng.choice(len(perms), 3000, replace=False)]
+    for vals in F:
+        f = np.array(vals, np.float32).reshape(2, 2, 2)
+        want = O.segment(f)
+        got = gpu_segment(msc, f)
+        for g, w in zip(got, want):
+            assert np.array_equal(g, w), vals
+
+
+@pytest.mark.parametrize("dims", [(50, 40, 30), (16, 1, 1), (9, 7, 1)])
+def test_closed_forms(msc, dims):
+    X, Y, Z = dims
+    n = X * Y * Z
+    a, d, m = gpu_segment(msc, np.zeros((Z, Y, X), np.float32))
+    assert (a == n - 1).all() and (d == 0).all() and (m == 0).all()
+    ids = np.arange(n, dtype=np.float32).reshape(Z, Y, X)
+    a, d, m = gpu_segment(msc, ids)
+    assert (a == n - 1).all() and (d == 0).all() and (m == 0).all()
+    a, d, m = gpu_segment(msc, -ids)
+    assert (a == 0).all() and (d == n - 1).all() and (m == 0).all()
+
+
+def test_single_bump_one_ascending_manifold(msc):
+    n, c = 48, (30, 7, 19)
+    zz, yy, xx = np.meshgrid(np.arange(n), np.arange(n), np.arange(n),
+                             indexing="ij")
+    r2 = (xx - c[0]) ** 2 + (yy - c[1]) ** 2 + (zz - c[2]) ** 2
+    f = np.exp(-r2 / (2 * (n / 3) ** 2)).astype(np.float32)
+    a, _, _ = gpu_segment(msc, f)
+    assert (a == c[0] + n * c[1] + n * n * c[2]).all()
+    assert msc.last_stats()["n_maxima"] == 1
+
+
+def test_signed_zero_tie(msc):
+    f = np.array([[[0.0, -0.0, 0.0, -0.0]]], np.float32)
+    a, d, _ = gpu_segment(msc, f)
+    assert list(a) == [3] * 4 and list(d) == [0] * 4
+
+
+def test_partial_outputs_agree(msc):
+    f = synth.random_field((31, 17, 9), seed=5)
+    full = gpu_segment(msc, f)
+    for want in (("asc",), ("desc",), ("ms",), ("asc", "ms"), ("desc", "ms")):
+        got = gpu_segment(msc, f, want=want)
+        for k, g, w in zip(("asc", "desc", "ms"), got, full):
+            if k in want:
+                np.testing.assert_array_equal(g, w)
+            else:
+                assert g is None
+
+
+def test_nan_is_rejected(msc):
+    f = synth.random_field((20, 20, 20), seed=1)
+    f[3, 4, 5] = np.nan
+    with pytest.raises(msc.MscError) as e:
+        gpu_segment(msc, f)
+    assert e.value.code == msc.MSC_ENAN
+    # the context stays usable
+    assert_parity(msc, synth.random_field((20, 20, 20), seed=2))
+
+
+def test_bad_dims_rejected(msc):
+    t = torch.zeros(8, device="cuda")
+    out = torch.empty(8, dtype=torch.int32, device="cuda")
+    for dims in ((0, 1, 1), (2, -1, 4)):
+        with pytest.raises(msc.MscError) as e:
+            msc.segment_into(t, out, None, None, dims=dims)
+        assert e.value.code == msc.MSC_EINVAL
+    with pytest.raises(msc.MscError) as e:
+        msc.segment_into(t, out, None, None, dims=(1 << 16, 1 << 16, 1))
+    assert e.value.code == msc.MSC_ERANGE
+
+
+def test_side_stream_and_determinism(msc):
+    f = torch.from_numpy(synth.gaussian_field((96, 80, 64), 20, 7)).cuda()
+    a0, d0, m0 = msc.segment(f)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        a1, d1, m1 = msc.segment(f, stream=s)
+    s.synchronize()
+    torch.cuda.synchronize()
+    assert torch.equal(a0, a1) and torch.equal(d0, d1) and torch.equal(m0, m1)
