@@ -37,6 +37,7 @@ enum Counter : int {
   kCtrBadIndex = 6,  // out-of-range CSR column seen
   kCtrOverflow = 7,  // hash table or list overflow
   kCtrChanged2 = 8,
+  kCtrRounds = 9,    // longest exit chain walked
   kNumCounters = 16
 };
 
@@ -108,6 +109,7 @@ struct msc_ctx {
   unsigned long long *hctr = nullptr;
   msc_stats stats{};
   msc::Profiler prof;
+  uint64_t exit_cap_hint = 0;  // exit-list size that sufficed last time
 };
 
 namespace msc {
