@@ -62,7 +62,24 @@ def main():
     ap.add_argument("--cpu-depth", type=int, default=40,
                     help="z-planes of the field the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", default=None,
+                    help="tile shape of the fused pass, e.g. 32x16x16")
+    ap.add_argument("--calibrate-copy", type=float, default=None,
+                    metavar="GIB",
+                    help="only run torch's device copy of a GIB-sized float32 "
+                         "buffer 3 times (reference for HBM byte counters)")
     args = ap.parse_args()
+
+    if args.calibrate_copy:
+        import torch
+        n = int(args.calibrate_copy * (1 << 30)) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": 4 * n, "launches": 3}))
+        return
 
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): "
@@ -75,6 +92,8 @@ def main():
     from paper_2409_03771_amd import msc, synth
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.tile:
+        msc.set_tile(*(int(t) for t in args.tile.split("x")))
 
     log(f"[bench] generating {args.workload} on {dev}")
     t0 = time.perf_counter()

@@ -95,6 +95,17 @@ MSC_API void msc_destroy(msc_ctx *ctx);
 MSC_API int msc_segment(msc_ctx *ctx, const float *field, const int64_t dims[3],
                 int32_t *asc, int32_t *desc, int32_t *ms, void *stream);
 
+/*
+ * Tile shape of the segmentation's fused LDS pass (a tuning knob; results
+ * do not depend on it).  msc_tile_shapes writes up to `max` compiled shapes
+ * as {tx, ty, tz} triples to `out` (host int[3*max]) and returns their
+ * number; the first is the default.  msc_set_tile selects one for this
+ * context (MSC_EINVAL if it is not compiled in).  The environment variable
+ * MSC_TILE="TXxTYxTZ" sets the initial choice of new contexts.
+ */
+MSC_API int msc_tile_shapes(int *out, int max);
+MSC_API int msc_set_tile(msc_ctx *ctx, int tx, int ty, int tz);
+
 /* Counters of the last successful msc_segment on this context. */
 typedef struct msc_stats {
   int64_t n_vertices;

@@ -1,5 +1,7 @@
 // C-ABI entry points of libmsc.so: argument checks, context and workspace.
 #include <climits>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 
@@ -114,6 +116,14 @@ int msc_create(msc_ctx **out, int device) {
     return MSC_ENOMEM;
   }
   std::memset(c->hctr, 0, msc::kNumCounters * sizeof(unsigned long long));
+  // Tile shape override for tuning runs, e.g. MSC_TILE=32x16x16.
+  if (const char *t = std::getenv("MSC_TILE")) {
+    int tx = 0, ty = 0, tz = 0;
+    if (std::sscanf(t, "%dx%dx%d", &tx, &ty, &tz) == 3) {
+      int k = msc::tile_index(tx, ty, tz);
+      if (k >= 0) c->tile_choice = k;
+    }
+  }
   *out = c;
   return MSC_OK;
 }
@@ -140,6 +150,21 @@ int msc_segment(msc_ctx *ctx, const float *field, const int64_t dims[3],
   if (!g.ok) return MSC_EHIP;
   return msc::segment_run(ctx, field, dims[0], dims[1], dims[2], asc, desc, ms,
                           static_cast<hipStream_t>(stream));
+}
+
+int msc_tile_shapes(int *out, int max) {
+  const int n = msc::kNumTileShapes;
+  for (int i = 0; i < n && i < max && out; ++i)
+    for (int k = 0; k < 3; ++k) out[3 * i + k] = msc::kTileShapes[i][k];
+  return n;
+}
+
+int msc_set_tile(msc_ctx *ctx, int tx, int ty, int tz) {
+  if (!ctx) return MSC_EINVAL;
+  int k = msc::tile_index(tx, ty, tz);
+  if (k < 0) return MSC_EINVAL;
+  ctx->tile_choice = k;
+  return MSC_OK;
 }
 
 int msc_last_stats(const msc_ctx *ctx, msc_stats *out) {

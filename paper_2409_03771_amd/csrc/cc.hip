@@ -1,64 +1,33 @@
-// Connected components by hook-and-compress (gfx950).
+// Connected components (gfx950) and the pointer-forest compression entry.
 //
 // arXiv 2409.03771, Alg. 3 and methods "Connected Components": masked
-// vertices first point to a masked neighbour chosen by id, pointer jumping
-// compresses the resulting trees, and a stitching pass links trees that touch
-// before a second compression.  Here every pointer goes to a smaller (or
-// equal) id, so a component ends up named by its smallest id, and the stitch
-// (hook) is an atomicMin on the root that is repeated, each time followed by
-// compression, until no hook changes anything: a single stitch does not join
-// every pair of touching trees in general.
+// vertices point to a masked neighbour chosen by id, path compression turns
+// the pointers into per-component labels, and a stitching step merges the
+// partial trees that touch before a last compression.  Every pointer here
+// goes to a smaller (or equal) id, so a component ends up named by its
+// smallest id.  The paper's single racy stitch does not join every pair of
+// touching trees in general; here trees are joined with a lock-free union
+// (compare-and-swap of the larger root onto the smaller one, retried until
+// it sticks), whose result is the min-id labelling whatever the schedule.
+//
+// Grid masks use the same two levels as the segmentation, mirroring the
+// paper's rank-local pass plus exchange:
+//   cc_tile    one workgroup per tile: union-find over the tile's own edges
+//              in LDS; writes each vertex's tile-local root (16-bit) and
+//              makes every tile-local root its own parent in the global
+//              label array;
+//   cc_cross   unions across the tile faces (each cross-tile edge once, from
+//              the tile holding its lower endpoint) on the global array,
+//              touching tile-local roots only (the paper's ghost exchange);
+//   cc_final   label = root of the vertex's tile-local root.
+// CSR graphs have no locality to exploit: init to the smallest masked
+// neighbour, one union per listed edge, then a final find per vertex.
 #include <climits>
 
 #include "msc_internal.hpp"
 
 namespace msc {
 namespace {
-
-struct GridDims {
-  int64_t X, Y, Z, XY, N;
-};
-
-__device__ __forceinline__ void coords(const GridDims &d, int64_t v,
-                                       int64_t &x, int64_t &y, int64_t &z) {
-  if (d.N <= (int64_t)UINT32_MAX) {
-    uint32_t vv = (uint32_t)v, XY = (uint32_t)d.XY, X = (uint32_t)d.X;
-    uint32_t zz = vv / XY, r = vv - zz * XY, yy = r / X;
-    z = zz;
-    y = yy;
-    x = r - yy * X;
-  } else {
-    z = v / d.XY;
-    int64_t r = v - z * d.XY;
-    y = r / d.X;
-    x = r - y * d.X;
-  }
-}
-
-// Closed Freudenthal neighbourhood in increasing id order (self at k = 7).
-struct Stencil {
-  bool ok[15];
-  int64_t off[15];
-  __device__ __forceinline__ Stencil(const GridDims &d, int64_t x, int64_t y,
-                                     int64_t z) {
-    const bool xm = x > 0, xp = x + 1 < d.X;
-    const bool ym = y > 0, yp = y + 1 < d.Y;
-    const bool zm = z > 0, zp = z + 1 < d.Z;
-    const int64_t X = d.X, XY = d.XY;
-    const bool o[15] = {xm && ym && zm, ym && zm, xm && zm, zm,
-                        xm && ym,       ym,       xm,       true,
-                        xp,             yp,       xp && yp, zp,
-                        xp && zp,       yp && zp, xp && yp && zp};
-    const int64_t f[15] = {-XY - X - 1, -XY - X, -XY - 1, -XY, -X - 1, -X,
-                           -1,          0,       1,       X,   X + 1,  XY,
-                           XY + 1,      XY + X,  XY + X + 1};
-#pragma unroll
-    for (int k = 0; k < 15; ++k) {
-      ok[k] = o[k];
-      off[k] = f[k];
-    }
-  }
-};
 
 __device__ __forceinline__ int64_t gid() {
   return (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -68,28 +37,273 @@ __device__ __forceinline__ void flag_any(bool pred, unsigned long long *ctr) {
   if (__ballot(pred) && (threadIdx.x & 63) == 0) atomicOr(ctr, 1ull);
 }
 
-// L[v] = smallest masked id of the closed neighbourhood, or -1.
-__global__ void __launch_bounds__(kBlock)
-k_cc_init(const uint8_t *__restrict__ mask, GridDims d, int64_t *__restrict__ L) {
-  int64_t v = gid();
-  if (v >= d.N) return;
-  if (!mask[v]) {
-    L[v] = -1;
-    return;
+// ---------------------------------------------------------------------------
+// Lock-free union-find on a parent array whose pointers only decrease.
+// ---------------------------------------------------------------------------
+
+template <class T>
+__device__ __forceinline__ T uf_find(T *par, T x) {
+  for (;;) {
+    T p = __atomic_load_n(&par[x], __ATOMIC_RELAXED);
+    if (p == x) return x;
+    T g = __atomic_load_n(&par[p], __ATOMIC_RELAXED);
+    if (g == p) return p;
+    // Path halving: g is an ancestor of x, so this only shortens the path.
+    __atomic_store_n(&par[x], g, __ATOMIC_RELAXED);
+    x = g;
   }
-  int64_t x, y, z;
-  coords(d, v, x, y, z);
-  Stencil s(d, x, y, z);
-  int64_t best = v;
+}
+
+// Root of x without writing: used once no union is running, by the passes
+// in which every entry is also an output that only its owner may write.
+template <class T>
+__device__ __forceinline__ T uf_root(const T *par, T x) {
+  for (;;) {
+    T p = __atomic_load_n(&par[x], __ATOMIC_RELAXED);
+    if (p == x) return x;
+    x = p;
+  }
+}
+
+// Join the trees of a and b: the larger root is hung under the smaller one.
+template <class T>
+__device__ __forceinline__ bool uf_unite(T *par, T a, T b) {
+  bool changed = false;
+  for (;;) {
+    a = uf_find(par, a);
+    b = uf_find(par, b);
+    if (a == b) return changed;
+    if (a > b) {
+      T t = a;
+      a = b;
+      b = t;
+    }
+    T expect = b;
+    if (__atomic_compare_exchange_n(&par[b], &expect, a, false,
+                                    __ATOMIC_RELAXED, __ATOMIC_RELAXED))
+      return true;
+    changed = true;  // b moved meanwhile; retry from the new trees
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Grid masks
+// ---------------------------------------------------------------------------
+
+constexpr int CTX = 32, CTY = 16, CTZ = 16;      // tile; one thread per column
+constexpr int kCThreads = CTX * CTY;
+constexpr int kCOwned = CTX * CTY * CTZ;
+constexpr uint16_t kOutside = 0xffff;           // unmasked vertex
+static_assert(kCOwned < 65535, "tile-local roots are 16-bit");
+
+struct CGeo {
+  int64_t X, Y, Z, XY, N;
+  int64_t ntx, nty, ntz;
+};
+
+__device__ __forceinline__ uint32_t cc_tile_of_block(uint32_t b, uint32_t nb) {
+  const uint32_t per = nb / 8, rem = nb % 8, xcd = b % 8, idx = b / 8;
+  return xcd < rem ? xcd * (per + 1) + idx
+                   : rem * (per + 1) + (xcd - rem) * per + idx;
+}
+
+struct CTile {
+  int64_t x0, y0, z0;
+};
+
+__device__ __forceinline__ CTile ctile_at(const CGeo &g, int64_t t) {
+  int64_t tx = t % g.ntx, r = t / g.ntx;
+  int64_t ty = r % g.nty, tz = r / g.nty;
+  return CTile{tx * CTX, ty * CTY, tz * CTZ};
+}
+
+// Global id of the tile-local index l (lx + CTX*(ly + CTY*lz)).
+__device__ __forceinline__ int64_t ctile_global(const CGeo &g, const CTile &t,
+                                                int l) {
+  const int lz = l / (CTX * CTY), r = l - lz * (CTX * CTY);
+  const int ly = r / CTX, lx = r - ly * CTX;
+  return (t.x0 + lx) + g.X * (t.y0 + ly) + g.XY * (t.z0 + lz);
+}
+
+__global__ void __launch_bounds__(kCThreads)
+k_cc_tile(const uint8_t *__restrict__ mask, CGeo g, uint16_t *__restrict__ loc,
+          int64_t *__restrict__ L) {
+  __shared__ int32_t par[kCOwned];
+  const int tid = threadIdx.x;
+  const CTile t = ctile_at(g, cc_tile_of_block(blockIdx.x, gridDim.x));
+  const int cx = tid % CTX, cy = tid / CTX;
+  const int64_t gx = t.x0 + cx, gy = t.y0 + cy;
+  const bool col_in = gx < g.X && gy < g.Y;
+  int nz = (int)((g.Z - t.z0) < CTZ ? (g.Z - t.z0) : CTZ);
+  if (!col_in) nz = 0;
+  const int64_t v0 = gx + g.X * gy + g.XY * t.z0;
+
+  uint32_t m = 0;  // this column's mask bits
 #pragma unroll
-  for (int k = 0; k < 7; ++k) {
-    if (s.ok[k] && mask[v + s.off[k]]) {
-      best = v + s.off[k];
-      break;
+  for (int lz = 0; lz < CTZ; ++lz) {
+    const int l = cx + CTX * (cy + CTY * lz);
+    const bool in = lz < nz && mask[v0 + g.XY * lz];
+    m |= (uint32_t)in << lz;
+    par[l] = in ? l : -1;
+  }
+  __syncthreads();
+
+  // Union over the tile's own edges, each from its higher-id endpoint
+  // towards the 7 lower-id Freudenthal neighbours.
+  const int SX = 1, SY = CTX, SZ = CTX * CTY;
+  for (int lz = 0; lz < nz; ++lz) {
+    if (!((m >> lz) & 1)) continue;
+    const int l = cx + CTX * (cy + CTY * lz);
+    const bool xm = cx > 0, ym = cy > 0, zm = lz > 0;
+    const bool ok[7] = {xm, ym, xm && ym, zm, xm && zm, ym && zm,
+                        xm && ym && zm};
+    const int off[7] = {-SX, -SY, -SX - SY, -SZ, -SX - SZ, -SY - SZ,
+                        -SX - SY - SZ};
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+      if (!ok[k]) continue;
+      const int u = l + off[k];
+      if (__atomic_load_n(&par[u], __ATOMIC_RELAXED) < 0) continue;
+      uf_unite<int32_t>(par, l, u);
     }
   }
-  L[v] = best;
+  __syncthreads();
+
+  for (int lz = 0; lz < nz; ++lz) {
+    const int64_t v = v0 + g.XY * lz;
+    if (!((m >> lz) & 1)) {
+      loc[v] = kOutside;
+      continue;
+    }
+    const int l = cx + CTX * (cy + CTY * lz);
+    const int r = uf_find<int32_t>(par, l);
+    loc[v] = (uint16_t)r;
+    if (r == l) L[v] = v;  // tile-local roots start as global roots
+  }
 }
+
+// Unions across tile faces.  An edge between two tiles is handled by the tile
+// that owns its lower endpoint, which sees it as one of the 7 higher-id
+// neighbours leaving the tile through an upper face.
+__global__ void __launch_bounds__(kCThreads)
+k_cc_cross(const uint8_t *__restrict__ mask, CGeo g,
+           const uint16_t *__restrict__ loc, int64_t *L,
+           unsigned long long *ctr) {
+  const int tid = threadIdx.x;
+  const CTile t = ctile_at(g, cc_tile_of_block(blockIdx.x, gridDim.x));
+  const int cx = tid % CTX, cy = tid / CTX;
+  const int64_t gx = t.x0 + cx, gy = t.y0 + cy;
+  const bool col_in = gx < g.X && gy < g.Y;
+  int nz = (int)((g.Z - t.z0) < CTZ ? (g.Z - t.z0) : CTZ);
+  if (!col_in) nz = 0;
+  const bool xface = cx == CTX - 1 && gx + 1 < g.X;
+  const bool yface = cy == CTY - 1 && gy + 1 < g.Y;
+  bool changed = false;
+  for (int lz = 0; lz < nz; ++lz) {
+    const bool zface = lz == CTZ - 1 && t.z0 + lz + 1 < g.Z;
+    if (!(xface || yface || zface)) continue;
+    const int64_t v = gx + g.X * gy + g.XY * (t.z0 + lz);
+    if (!mask[v]) continue;
+    const int64_t rv = ctile_global(g, t, loc[v]);
+    const bool xp = gx + 1 < g.X, yp = gy + 1 < g.Y,
+               zp = t.z0 + lz + 1 < g.Z;
+    // (dx, dy, dz) of the 7 higher-id neighbours; keep those outside the tile.
+    const int dx[7] = {1, 0, 1, 0, 1, 0, 1};
+    const int dy[7] = {0, 1, 1, 0, 0, 1, 1};
+    const int dz[7] = {0, 0, 0, 1, 1, 1, 1};
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+      if ((dx[k] && !xp) || (dy[k] && !yp) || (dz[k] && !zp)) continue;
+      const bool leaves = (dx[k] && xface) || (dy[k] && yface) ||
+                          (dz[k] && zface);
+      if (!leaves) continue;
+      const int64_t u = v + dx[k] + g.X * dy[k] + g.XY * dz[k];
+      if (!mask[u]) continue;
+      // u's tile-local root, decoded with u's own tile origin.
+      const int64_t ux = gx + dx[k], uy = gy + dy[k], uz = t.z0 + lz + dz[k];
+      const CTile tu{ux - ux % CTX, uy - uy % CTY, uz - uz % CTZ};
+      const int64_t ru = ctile_global(g, tu, loc[u]);
+      changed |= uf_unite<int64_t>(L, rv, ru);
+    }
+  }
+  flag_any(changed, ctr + kCtrChanged);
+}
+
+__global__ void __launch_bounds__(kCThreads)
+k_cc_final(CGeo g, const uint16_t *__restrict__ loc, int64_t *L) {
+  const int tid = threadIdx.x;
+  const CTile t = ctile_at(g, cc_tile_of_block(blockIdx.x, gridDim.x));
+  const int cx = tid % CTX, cy = tid / CTX;
+  const int64_t gx = t.x0 + cx, gy = t.y0 + cy;
+  if (gx >= g.X || gy >= g.Y) return;
+  int nz = (int)((g.Z - t.z0) < CTZ ? (g.Z - t.z0) : CTZ);
+  for (int lz = 0; lz < nz; ++lz) {
+    const int64_t v = gx + g.X * gy + g.XY * (t.z0 + lz);
+    const uint16_t s = loc[v];
+    // Only tile-local roots are ever on a root path, and a root's entry is
+    // overwritten (by its owner only) with its own final root, so concurrent
+    // walks stay on ancestors and every entry ends as its final root.
+    const int64_t out =
+        s == kOutside ? -1 : uf_root<int64_t>(L, ctile_global(g, t, s));
+    __atomic_store_n(&L[v], out, __ATOMIC_RELAXED);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CSR graphs
+// ---------------------------------------------------------------------------
+
+__global__ void __launch_bounds__(kBlock)
+k_csr_init(int64_t n, const int64_t *__restrict__ rp,
+           const int32_t *__restrict__ ci, const uint8_t *__restrict__ mask,
+           int64_t *__restrict__ L, unsigned long long *ctr) {
+  int64_t v = gid();
+  bool bad = false;
+  if (v < n) {
+    if (mask && !mask[v]) {
+      L[v] = -1;
+    } else {
+      int64_t best = v;
+      for (int64_t e = rp[v], end = rp[v + 1]; e < end; ++e) {
+        int64_t u = ci[e];
+        if (u < 0 || u >= n) {
+          bad = true;
+          continue;
+        }
+        if (mask && !mask[u]) continue;
+        best = u < best ? u : best;
+      }
+      L[v] = best;
+    }
+  }
+  flag_any(bad, ctr + kCtrBadIndex);
+}
+
+// One union per listed edge between two masked vertices.
+__global__ void __launch_bounds__(kBlock)
+k_csr_union(int64_t n, const int64_t *__restrict__ rp,
+            const int32_t *__restrict__ ci, const uint8_t *__restrict__ mask,
+            int64_t *L) {
+  int64_t v = gid();
+  if (v >= n || (mask && !mask[v])) return;
+  for (int64_t e = rp[v], end = rp[v + 1]; e < end; ++e) {
+    const int64_t u = ci[e];
+    if (u == v || (mask && !mask[u])) continue;
+    uf_unite<int64_t>(L, v, u);
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_csr_final(int64_t n, int64_t *L) {
+  int64_t v = gid();
+  if (v >= n) return;
+  if (__atomic_load_n(&L[v], __ATOMIC_RELAXED) < 0) return;
+  __atomic_store_n(&L[v], uf_root<int64_t>(L, v), __ATOMIC_RELAXED);
+}
+
+// ---------------------------------------------------------------------------
+// Pointer forests
+// ---------------------------------------------------------------------------
 
 // One in-place jumping round; negative entries are not part of the forest.
 __global__ void __launch_bounds__(kBlock)
@@ -124,92 +338,12 @@ k_double64(const int64_t *__restrict__ in, int64_t *__restrict__ out,
   flag_any(changed, ctr + kCtrChanged);
 }
 
-// Hook: the root of v's tree takes the smallest label among v's masked
-// neighbours when that label is smaller than its own.
+// Every pointer must be an id in [0, n) before any kernel follows it.
 __global__ void __launch_bounds__(kBlock)
-k_cc_hook(const uint8_t *__restrict__ mask, GridDims d, int64_t *L,
-          unsigned long long *ctr) {
+k_check_range(const int64_t *__restrict__ d, int64_t n,
+              unsigned long long *ctr) {
   int64_t v = gid();
-  bool changed = false;
-  if (v < d.N && mask[v]) {
-    int64_t x, y, z;
-    coords(d, v, x, y, z);
-    Stencil s(d, x, y, z);
-    int64_t lv = __atomic_load_n(&L[v], __ATOMIC_RELAXED);
-    int64_t m = lv;
-#pragma unroll
-    for (int k = 0; k < 15; ++k) {
-      if (k == 7 || !s.ok[k]) continue;
-      int64_t u = v + s.off[k];
-      if (!mask[u]) continue;
-      int64_t lu = __atomic_load_n(&L[u], __ATOMIC_RELAXED);
-      m = lu < m ? lu : m;
-    }
-    if (m < lv) {
-      unsigned long long old = atomicMin((unsigned long long *)&L[lv],
-                                         (unsigned long long)m);
-      changed = (int64_t)old > m;
-    }
-  }
-  flag_any(changed, ctr + kCtrChanged);
-}
-
-__global__ void __launch_bounds__(kBlock)
-k_csr_init(int64_t n, const int64_t *__restrict__ rp,
-           const int32_t *__restrict__ ci, const uint8_t *__restrict__ mask,
-           int64_t *__restrict__ L, unsigned long long *ctr) {
-  int64_t v = gid();
-  bool bad = false;
-  if (v < n) {
-    if (mask && !mask[v]) {
-      L[v] = -1;
-    } else {
-      int64_t best = v;
-      for (int64_t e = rp[v], end = rp[v + 1]; e < end; ++e) {
-        int64_t u = ci[e];
-        if (u < 0 || u >= n) {
-          bad = true;
-          continue;
-        }
-        if (mask && !mask[u]) continue;
-        best = u < best ? u : best;
-      }
-      L[v] = best;
-    }
-  }
-  flag_any(bad, ctr + kCtrBadIndex);
-}
-
-// Hook over CSR rows in both directions of every listed edge, so a one-sided
-// listing still joins its endpoints.
-__global__ void __launch_bounds__(kBlock)
-k_csr_hook(int64_t n, const int64_t *__restrict__ rp,
-           const int32_t *__restrict__ ci, const uint8_t *__restrict__ mask,
-           int64_t *L, unsigned long long *ctr) {
-  int64_t v = gid();
-  bool changed = false;
-  if (v < n && (!mask || mask[v])) {
-    int64_t lv = __atomic_load_n(&L[v], __ATOMIC_RELAXED);
-    int64_t m = lv;
-    for (int64_t e = rp[v], end = rp[v + 1]; e < end; ++e) {
-      int64_t u = ci[e];
-      if (u < 0 || u >= n) continue;
-      if (mask && !mask[u]) continue;
-      int64_t lu = __atomic_load_n(&L[u], __ATOMIC_RELAXED);
-      if (lu < m) m = lu;
-      if (lu > lv) {
-        unsigned long long old = atomicMin((unsigned long long *)&L[lu],
-                                           (unsigned long long)lv);
-        changed |= (int64_t)old > lv;
-      }
-    }
-    if (m < lv) {
-      unsigned long long old = atomicMin((unsigned long long *)&L[lv],
-                                         (unsigned long long)m);
-      changed |= (int64_t)old > m;
-    }
-  }
-  flag_any(changed, ctr + kCtrChanged);
+  flag_any(v < n && (d[v] < 0 || d[v] >= n), ctr + kCtrBadIndex);
 }
 
 int clear_changed(msc_ctx *ctx, hipStream_t s) {
@@ -222,43 +356,32 @@ int clear_changed(msc_ctx *ctx, hipStream_t s) {
 // than this many means the pointers hold a cycle (not a forest).
 constexpr int kMaxRounds = 96;
 
-// Jump in place until no pointer moves; returns rounds through *rounds.
-int compress(msc_ctx *ctx, int64_t *L, int64_t n, hipStream_t s, int *rounds) {
-  for (int r = 0;; ++r) {
-    if (r == kMaxRounds) return MSC_EINVAL;
-    MSC_TRY(clear_changed(ctx, s));
-    MSC_PHASE(ctx, s, "cc_jump_round", 24.0 * n,
-              (k_jump64<<<grid_for(n), kBlock, 0, s>>>(L, n, ctx->dctr)));
-    if (rounds) ++*rounds;
-    MSC_TRY(read_counters(ctx, s));
-    if (!ctx->hctr[kCtrChanged]) return MSC_OK;
-  }
-}
-
 }  // namespace
 
 int cc_grid_run(msc_ctx *ctx, const uint8_t *mask, int64_t X, int64_t Y,
                 int64_t Z, int64_t *labels, hipStream_t s) {
-  GridDims d{X, Y, Z, X * Y, X * Y * Z};
+  CGeo g{X, Y, Z, X * Y, X * Y * Z, (X + CTX - 1) / CTX, (Y + CTY - 1) / CTY,
+         (Z + CTZ - 1) / CTZ};
+  const int64_t ntiles = g.ntx * g.nty * g.ntz;
+  if (ntiles > INT32_MAX) return MSC_ERANGE;
+  MSC_TRY(reserve(ctx->ws, align256(g.N * sizeof(uint16_t)) + 4096));
+  Carver cv(ctx->ws);
+  uint16_t *loc = cv.take<uint16_t>(g.N);
   MSC_TRY(clear_counters(ctx, s));
-  MSC_PHASE(ctx, s, "cc_init", 9.0 * d.N,
-            (k_cc_init<<<grid_for(d.N), kBlock, 0, s>>>(mask, d, labels)));
-  int rounds = 0, hooks = 0;
-  MSC_TRY(compress(ctx, labels, d.N, s, &rounds));
-  for (;;) {
-    MSC_TRY(clear_changed(ctx, s));
-    MSC_PHASE(ctx, s, "cc_hook", 9.0 * d.N,
-              (k_cc_hook<<<grid_for(d.N), kBlock, 0, s>>>(mask, d, labels,
-                                                          ctx->dctr)));
-    MSC_TRY(read_counters(ctx, s));
-    if (!ctx->hctr[kCtrChanged]) break;
-    ++hooks;
-    MSC_TRY(compress(ctx, labels, d.N, s, &rounds));
-  }
+  const unsigned nb = (unsigned)ntiles;
+  MSC_PHASE(ctx, s, "cc_tile", 3.0 * g.N,
+            (k_cc_tile<<<nb, kCThreads, 0, s>>>(mask, g, loc, labels)));
+  MSC_PHASE(ctx, s, "cc_cross", 0.5 * g.N,
+            (k_cc_cross<<<nb, kCThreads, 0, s>>>(mask, g, loc, labels,
+                                                 ctx->dctr)));
+  MSC_PHASE(ctx, s, "cc_final", 10.0 * g.N,
+            (k_cc_final<<<nb, kCThreads, 0, s>>>(g, loc, labels)));
+  MSC_TRY(read_counters(ctx, s));
   ctx->stats = msc_stats{};
-  ctx->stats.n_vertices = d.N;
-  ctx->stats.jump_rounds = rounds;
-  ctx->stats.n_exits = hooks;
+  ctx->stats.n_vertices = g.N;
+  ctx->stats.tile_x = CTX;
+  ctx->stats.tile_y = CTY;
+  ctx->stats.tile_z = CTZ;
   return MSC_OK;
 }
 
@@ -272,34 +395,34 @@ int cc_csr_run(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,
                                                        ctx->dctr)));
   MSC_TRY(read_counters(ctx, s));
   if (ctx->hctr[kCtrBadIndex]) return MSC_EINVAL;
-  int rounds = 0, hooks = 0;
-  MSC_TRY(compress(ctx, labels, n, s, &rounds));
-  for (;;) {
-    MSC_TRY(clear_changed(ctx, s));
-    MSC_PHASE(ctx, s, "csr_hook", 17.0 * n,
-              (k_csr_hook<<<grid_for(n), kBlock, 0, s>>>(n, row_ptr, col_idx,
-                                                         mask, labels,
-                                                         ctx->dctr)));
-    MSC_TRY(read_counters(ctx, s));
-    if (!ctx->hctr[kCtrChanged]) break;
-    ++hooks;
-    MSC_TRY(compress(ctx, labels, n, s, &rounds));
-  }
+  MSC_PHASE(ctx, s, "csr_union", 13.0 * n,
+            (k_csr_union<<<grid_for(n), kBlock, 0, s>>>(n, row_ptr, col_idx,
+                                                        mask, labels)));
+  MSC_PHASE(ctx, s, "csr_final", 16.0 * n,
+            (k_csr_final<<<grid_for(n), kBlock, 0, s>>>(n, labels)));
+  MSC_TRY(read_counters(ctx, s));
   ctx->stats = msc_stats{};
   ctx->stats.n_vertices = n;
-  ctx->stats.jump_rounds = rounds;
-  ctx->stats.n_exits = hooks;
   return MSC_OK;
 }
 
 int jump_run(msc_ctx *ctx, int64_t *d, int64_t n, int rounds, int sync,
              hipStream_t s) {
   MSC_TRY(clear_counters(ctx, s));
+  MSC_PHASE(ctx, s, "check_range", 8.0 * n,
+            (k_check_range<<<grid_for(n), kBlock, 0, s>>>(d, n, ctx->dctr)));
+  MSC_TRY(read_counters(ctx, s));
+  if (ctx->hctr[kCtrBadIndex]) return MSC_EINVAL;
   if (!sync) {
-    if (rounds == 0) return compress(ctx, d, n, s, nullptr);
-    for (int r = 0; r < rounds; ++r) {
+    for (int r = 0; rounds == 0 || r < rounds; ++r) {
+      if (rounds == 0 && r == kMaxRounds) return MSC_EINVAL;
+      MSC_TRY(clear_changed(ctx, s));
       MSC_PHASE(ctx, s, "jump64_round", 24.0 * n,
                 (k_jump64<<<grid_for(n), kBlock, 0, s>>>(d, n, ctx->dctr)));
+      if (rounds == 0) {
+        MSC_TRY(read_counters(ctx, s));
+        if (!ctx->hctr[kCtrChanged]) break;
+      }
     }
     return MSC_OK;
   }

@@ -110,6 +110,7 @@ struct msc_ctx {
   msc_stats stats{};
   msc::Profiler prof;
   uint64_t exit_cap_hint = 0;  // exit-list size that sufficed last time
+  int tile_choice = 0;         // segmentation tile shape (0 = default)
 };
 
 namespace msc {
@@ -160,6 +161,19 @@ int clear_counters(msc_ctx *ctx, hipStream_t stream);
 inline unsigned grid_for(int64_t n, int block = kBlock) {
   int64_t g = (n + block - 1) / block;
   return (unsigned)(g < 1 ? 1 : g);
+}
+
+// Segmentation tile shapes compiled in (index = ctx->tile_choice); the
+// first is the default.
+constexpr int kNumTileShapes = 5;
+constexpr int kTileShapes[kNumTileShapes][3] = {
+    {32, 32, 16}, {32, 16, 16}, {32, 8, 8}, {64, 16, 16}, {64, 8, 8}};
+inline int tile_index(int tx, int ty, int tz) {
+  for (int i = 0; i < kNumTileShapes; ++i)
+    if (kTileShapes[i][0] == tx && kTileShapes[i][1] == ty &&
+        kTileShapes[i][2] == tz)
+      return i;
+  return -1;
 }
 
 // Launchers implemented in the kernel translation units.

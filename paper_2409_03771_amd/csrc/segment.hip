@@ -11,36 +11,55 @@
 // leave a rank in one exchange step (Alg. 2).  Here the same two levels map
 // onto the GPU's memory hierarchy:
 //
-//   tile_local   one workgroup per 32x8x8 tile: the field plus a one-vertex
-//                halo is staged in LDS, both steepest pointers are computed
-//                from LDS, halo vertices point to themselves (the ghost
-//                rule), and pointer jumping runs in LDS until every owned
-//                vertex points to a tile-local extremum or to a halo vertex
-//                ("exit").  Writes one 16-bit tile-local pointer per vertex
-//                and direction, and appends the distinct exits to a list.
-//   exit_init    each exit gets its own tile's pointer as a global id.
-//   exit_jump    in-place pointer jumping over the exit list only (the
+//   tile_local   one workgroup per tile: the field plus a one-vertex halo is
+//                staged in LDS, both steepest pointers are computed from LDS
+//                (each thread walks a z-column with a three-plane register
+//                window), halo vertices point to themselves (the ghost rule),
+//                and pointer jumping runs in LDS until every owned vertex
+//                points to a tile-local extremum or to a halo vertex
+//                ("exit").  Writes one packed pair of 16-bit tile-local
+//                pointers per vertex, appends the tile's exits to a list in
+//                a fixed order (its segment), writes the global pointer of
+//                every shell vertex (the ones other tiles can exit to) and
+//                of every local extremum.
+//   exit_hist    exits are bucketed by field value (ascent chains climb, so
+//   exit_scan    ascent exits go high values first, descent exits low values
+//   exit_scatter first): a counting sort over value buckets.
+//   exit_jump    in-place pointer jumping over the exits only, in that order,
+//                so most chains find their next exit already resolved (the
 //                paper's compression of the ghost graph after the exchange).
-//   tile_pairs   decode every vertex's final extrema (local root or resolved
-//                exit) and insert its (asc, desc) pair into a hash table
-//                that keeps the smallest vertex id; per-tile LDS table first.
-//   tile_write   decode again, write asc, desc and the cell id (table
-//                lookup) per vertex (the paper's relabelling pass, Alg. 2).
+//                The result of list entry i goes to R[i].
+//   tile_pairs   per tile: rebuild the exit bitsets from the local pointers,
+//                stage the tile's resolved segment of R in LDS, decode every
+//                vertex's final extrema, and insert its (asc, desc) pair into
+//                a hash table keeping the smallest vertex id (per-tile LDS
+//                table first).
+//   tile_write   the same decode, then asc, desc and the cell id per vertex
+//                (the paper's relabelling pass, Alg. 2).
 #include <climits>
+#include <cstdlib>
+#include <cstring>
 
 #include "msc_internal.hpp"
 
 namespace msc {
 namespace {
 
-constexpr int TX = 32, TY = 8, TZ = 8;   // owned tile; one thread per column
-constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
-constexpr int HXY = HX * HY;
-constexpr int H = HX * HY * HZ;          // tile plus halo, in LDS
-constexpr int kThreads = TX * TY;
-constexpr int kPairSlots = 1024;         // per-tile LDS pair table
-static_assert(H < 32768, "tile-local pointers are 16-bit");
-static_assert(kThreads == kBlock, "one thread per tile column");
+template <int TX_, int TY_, int TZ_>
+struct Cfg {
+  static constexpr int TX = TX_, TY = TY_, TZ = TZ_;
+  static constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
+  static constexpr int HXY = HX * HY;
+  static constexpr int H = HXY * HZ;          // tile plus halo
+  static constexpr int kThreads = TX * TY;    // one thread per z-column
+  static constexpr int kWords = (H + 31) / 32;
+  static constexpr int kHalo = H - TX * TY * TZ;
+  static_assert(H <= 65535, "tile-local pointers are 16-bit");
+  static_assert(kThreads % 64 == 0 && kThreads <= 1024, "block shape");
+  static_assert(kWords <= kThreads, "one bitset word per thread");
+  static_assert(TX * TY * TZ <= 0x8000 && kHalo < 0x8000,
+                "local pointer codes are 15-bit");
+};
 
 constexpr unsigned long long kEmptyKey = ~0ull;
 constexpr uint32_t kTagDesc = 0x80000000u;
@@ -48,6 +67,13 @@ constexpr uint32_t kTagDesc = 0x80000000u;
 struct Geo {
   uint32_t X, Y, Z, XY, N;
   uint32_t ntx, nty, ntz, ntiles;
+};
+
+// A tile's exits in the list: `base`, then `na` ascent exits and `nd`
+// descent exits, each group in increasing halo-index order.
+struct Seg {
+  uint32_t base;
+  uint16_t na, nd;
 };
 
 // Spread consecutive tiles over one XCD: the hardware hands workgroups to
@@ -64,23 +90,54 @@ struct Tile {
   int x0, y0, z0;
 };
 
+template <class C>
 __device__ __forceinline__ Tile tile_at(const Geo &g, uint32_t t) {
   uint32_t tx = t % g.ntx, r = t / g.ntx;
   uint32_t ty = r % g.nty, tz = r / g.nty;
-  return Tile{(int)tx * TX, (int)ty * TY, (int)tz * TZ};
+  return Tile{(int)tx * C::TX, (int)ty * C::TY, (int)tz * C::TZ};
 }
 
+template <class C>
 __device__ __forceinline__ bool halo_owned(int p) {
-  int hz = p / HXY, r = p - hz * HXY, hy = r / HX, hx = r - hy * HX;
-  return hx >= 1 && hx <= TX && hy >= 1 && hy <= TY && hz >= 1 && hz <= TZ;
+  int hz = p / C::HXY, r = p - hz * C::HXY, hy = r / C::HX, hx = r - hy * C::HX;
+  return hx >= 1 && hx <= C::TX && hy >= 1 && hy <= C::TY && hz >= 1 &&
+         hz <= C::TZ;
 }
 
 // Global id of tile-local index p; p must lie inside the domain.
+template <class C>
 __device__ __forceinline__ uint32_t halo_global(const Geo &g, const Tile &t,
                                                 int p) {
-  int hz = p / HXY, r = p - hz * HXY, hy = r / HX, hx = r - hy * HX;
+  int hz = p / C::HXY, r = p - hz * C::HXY, hy = r / C::HX, hx = r - hy * C::HX;
   return (uint32_t)(t.x0 - 1 + hx) + g.X * (uint32_t)(t.y0 - 1 + hy) +
          g.XY * (uint32_t)(t.z0 - 1 + hz);
+}
+
+// Stored tile-local pointers are 16-bit codes: an owned target is
+// lx + TX*(ly + TY*lz) (bit 15 clear); an exit target is its number among the
+// tile's exits of that direction, with bit 15 set.
+constexpr uint32_t kExitCode = 0x8000u;
+
+template <class C>
+__device__ __forceinline__ uint32_t local_code(int p, const uint32_t *bits,
+                                               const uint32_t *prefix) {
+  int hz = p / C::HXY, r = p - hz * C::HXY, hy = r / C::HX, hx = r - hy * C::HX;
+  if (hx >= 1 && hx <= C::TX && hy >= 1 && hy <= C::TY && hz >= 1 &&
+      hz <= C::TZ)
+    return (uint32_t)((hx - 1) + C::TX * ((hy - 1) + C::TY * (hz - 1)));
+  const int w = p >> 5;
+  return kExitCode |
+         (prefix[w] + __popc(bits[w] & ((1u << (p & 31)) - 1u)));
+}
+
+// Global id of an owned code.
+template <class C>
+__device__ __forceinline__ uint32_t owned_global(const Geo &g, const Tile &t,
+                                                 uint32_t code) {
+  const uint32_t lx = code % C::TX, ly = (code / C::TX) % C::TY,
+                 lz = code / (C::TX * C::TY);
+  return ((uint32_t)t.x0 + lx) + g.X * ((uint32_t)t.y0 + ly) +
+         g.XY * ((uint32_t)t.z0 + lz);
 }
 
 __device__ __forceinline__ void wave_count(bool pred, unsigned long long *ctr) {
@@ -98,141 +155,271 @@ __device__ __forceinline__ uint64_t mix64(uint64_t k) {
   return k;
 }
 
+// Exclusive prefix sum over the block (at most 1024 threads = 16 waves).
+// `tmp` holds 16 words of LDS.  Returns the prefix; *total gets the sum.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x,
+                                                         uint32_t *tmp,
+                                                         uint32_t *total) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nwaves = (blockDim.x + 63) >> 6;
+  uint32_t inc = x;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    uint32_t y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) tmp[wave] = inc;
+  __syncthreads();
+  if (wave == 0) {
+    uint32_t s = lane < nwaves ? tmp[lane] : 0;
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) {
+      uint32_t y = __shfl_up(s, o);
+      if (lane >= o) s += y;
+    }
+    if (lane < 16) tmp[16 + lane] = s;  // inclusive wave totals
+  }
+  __syncthreads();
+  const uint32_t before = wave ? tmp[16 + wave - 1] : 0;
+  *total = tmp[16 + nwaves - 1];
+  __syncthreads();
+  return before + inc - x;
+}
+
 // ---------------------------------------------------------------------------
 // tile_local
 // ---------------------------------------------------------------------------
 
-__global__ void __launch_bounds__(kThreads)
-k_tile_local(const float *__restrict__ f, Geo g, int16_t *__restrict__ la,
-             int16_t *__restrict__ ld, uint32_t *__restrict__ exits,
-             uint32_t exit_cap, unsigned long long *ctr) {
-  __shared__ float sf[H];
-  __shared__ int16_t pa[H], pd[H];
-  __shared__ uint8_t ea[H], ed[H];
-  __shared__ unsigned s_cnt, s_cur;
+// The 7 values of one plane a column needs: (dx,dy) = (-1,-1), (0,-1),
+// (-1,0), (0,0), (1,0), (0,1), (1,1) -- the Freudenthal neighbours never use
+// the (1,-1) and (-1,1) corners.
+struct Plane {
+  float v[7];
+};
+
+template <class C>
+__device__ __forceinline__ Plane load_plane(const uint32_t *lds, int c) {
+  Plane p;
+  p.v[0] = __uint_as_float(lds[c - 1 - C::HX]);
+  p.v[1] = __uint_as_float(lds[c - C::HX]);
+  p.v[2] = __uint_as_float(lds[c - 1]);
+  p.v[3] = __uint_as_float(lds[c]);
+  p.v[4] = __uint_as_float(lds[c + 1]);
+  p.v[5] = __uint_as_float(lds[c + C::HX]);
+  p.v[6] = __uint_as_float(lds[c + C::HX + 1]);
+  return p;
+}
+
+struct ExitOut {
+  uint32_t *list;      // exit ids (bit 31: descent)
+  Seg *seg;            // per tile
+  uint32_t *tkey;      // per tile: order key of its mean value
+  uint32_t cap;
+};
+
+// Order-preserving map of a float to an unsigned key; only used to order
+// work, never to decide a result.
+__device__ __forceinline__ uint32_t float_key(float x) {
+  uint32_t u = __float_as_uint(x);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+template <class C>
+__global__ void __launch_bounds__(C::kThreads)
+k_tile_local(const float *__restrict__ f, Geo g, uint32_t *__restrict__ lp,
+             ExitOut xo, unsigned long long *ctr) {
+  constexpr int HX = C::HX, HXY = C::HXY, H = C::H, T = C::kThreads;
+  // Field bits while the steepest pointers are computed, then the packed
+  // pointers (ascent in the low 16 bits, descent in the high 16 bits).
+  __shared__ uint32_t lds[H];
+  __shared__ uint32_t xa[C::kWords], xd[C::kWords];  // exit bitsets
+  __shared__ uint32_t pra[C::kWords], prd[C::kWords];  // their word prefixes
+  __shared__ uint32_t scan_tmp[32];
+  __shared__ float s_wsum[16];
   __shared__ unsigned long long s_base;
 
   const int tid = threadIdx.x;
-  const Tile t = tile_at(g, tile_of_block(blockIdx.x, gridDim.x));
-  if (tid == 0) {
-    s_cnt = 0;
-    s_cur = 0;
+  const uint32_t tile = tile_of_block(blockIdx.x, gridDim.x);
+  const Tile t = tile_at<C>(g, tile);
+  for (int w = tid; w < C::kWords; w += T) {
+    xa[w] = 0;
+    xd[w] = 0;
   }
-
   // Stage the tile and its halo; positions outside the domain hold NaN,
   // which loses every comparison below and so is never chosen.
-  for (int i = tid; i < H; i += kThreads) {
+  const uint32_t kNaN = 0x7fc00000u;
+#pragma unroll 4
+  for (int i = tid; i < H; i += T) {
     int hz = i / HXY, r = i - hz * HXY, hy = r / HX, hx = r - hy * HX;
     int gx = t.x0 - 1 + hx, gy = t.y0 - 1 + hy, gz = t.z0 - 1 + hz;
     bool in = gx >= 0 && gx < (int)g.X && gy >= 0 && gy < (int)g.Y &&
               gz >= 0 && gz < (int)g.Z;
-    sf[i] = in ? f[(uint32_t)gx + g.X * (uint32_t)gy + g.XY * (uint32_t)gz]
-               : __builtin_nanf("");
-    pa[i] = (int16_t)i;   // halo vertices point to themselves
-    pd[i] = (int16_t)i;
-    ea[i] = 0;
-    ed[i] = 0;
+    lds[i] = in ? __float_as_uint(
+                      f[(uint32_t)gx + g.X * (uint32_t)gy + g.XY * (uint32_t)gz])
+                : kNaN;
   }
   __syncthreads();
 
-  const int cx = tid % TX, cy = tid / TX;
+  const int cx = tid % C::TX, cy = tid / C::TX;
   const int gx = t.x0 + cx, gy = t.y0 + cy;
   const bool col_in = gx < (int)g.X && gy < (int)g.Y;
   int nz = (int)g.Z - t.z0;
-  nz = col_in ? (nz < TZ ? nz : TZ) : 0;
-  const int i0 = (cx + 1) + HX * (cy + 1) + HXY;
+  nz = col_in ? (nz < C::TZ ? nz : C::TZ) : 0;
+  const int c0 = (cx + 1) + HX * (cy + 1);  // column index in plane 0
 
   // Steepest ascent / descent over the closed neighbourhood, ordered by
   // (value, id).  Starting from v itself, a lower-id neighbour must be
   // strictly above to win the max and at most equal to win the min; a
   // higher-id neighbour wins the max when at least equal and the min when
-  // strictly below.
-  // Neighbour offsets in the LDS tile: the 7 lower-id neighbours in
-  // decreasing id order and the 7 higher-id neighbours in increasing order.
-  const int kLo[7] = {-1,   -HX,      -HX - 1,  -HXY,
-                      -HXY - 1, -HXY - HX, -HXY - HX - 1};
-  const int kHi[7] = {1, HX, HX + 1, HXY, HXY + 1, HXY + HX, HXY + HX + 1};
+  // strictly below.  Lower-id neighbours are taken in decreasing id order,
+  // higher-id ones in increasing id order.
+  uint32_t ptr[C::TZ];
   bool any_nan = false;
-  for (int lz = 0; lz < TZ; ++lz) {
-    bool in = lz < nz;
-    bool ismax = false, ismin = false;
-    if (in) {
-      const int i = i0 + lz * HXY;
-      const float fv = sf[i];
-      any_nan |= fv != fv;
-      float bmax = fv, bmin = fv;
-      int omax = 0, omin = 0;
+  float fsum = 0.f;
+  Plane below = load_plane<C>(lds, c0);
+  Plane cur = load_plane<C>(lds, c0 + HXY);
 #pragma unroll
-      for (int k = 0; k < 7; ++k) {
-        const float fu = sf[i + kLo[k]];
-        if (fu > bmax) { bmax = fu; omax = kLo[k]; }
-        if (fu <= bmin) { bmin = fu; omin = kLo[k]; }
-      }
-#pragma unroll
-      for (int k = 0; k < 7; ++k) {
-        const float fu = sf[i + kHi[k]];
-        if (fu >= bmax) { bmax = fu; omax = kHi[k]; }
-        if (fu < bmin) { bmin = fu; omin = kHi[k]; }
-      }
-      pa[i] = (int16_t)(i + omax);
-      pd[i] = (int16_t)(i + omin);
-      ismax = omax == 0;
-      ismin = omin == 0;
-    }
-    wave_count(ismax, ctr + kCtrMaxima);
-    wave_count(ismin, ctr + kCtrMinima);
+  for (int lz = 0; lz < C::TZ; ++lz) {
+    const int i = c0 + (lz + 1) * HXY;
+    const Plane above = load_plane<C>(lds, i + HXY);
+    const float fv = cur.v[3];
+    float bmax = fv, bmin = fv;
+    int omax = 0, omin = 0;
+#define MSC_LO(val, off)                        \
+  {                                             \
+    const float fu = (val);                     \
+    if (fu > bmax) { bmax = fu; omax = (off); } \
+    if (fu <= bmin) { bmin = fu; omin = (off); } \
+  }
+#define MSC_HI(val, off)                        \
+  {                                             \
+    const float fu = (val);                     \
+    if (fu >= bmax) { bmax = fu; omax = (off); } \
+    if (fu < bmin) { bmin = fu; omin = (off); }  \
+  }
+    MSC_LO(cur.v[2], -1)
+    MSC_LO(cur.v[1], -HX)
+    MSC_LO(cur.v[0], -HX - 1)
+    MSC_LO(below.v[3], -HXY)
+    MSC_LO(below.v[2], -HXY - 1)
+    MSC_LO(below.v[1], -HXY - HX)
+    MSC_LO(below.v[0], -HXY - HX - 1)
+    MSC_HI(cur.v[4], 1)
+    MSC_HI(cur.v[5], HX)
+    MSC_HI(cur.v[6], HX + 1)
+    MSC_HI(above.v[3], HXY)
+    MSC_HI(above.v[4], HXY + 1)
+    MSC_HI(above.v[5], HXY + HX)
+    MSC_HI(above.v[6], HXY + HX + 1)
+#undef MSC_LO
+#undef MSC_HI
+    const bool in = lz < nz;
+    any_nan |= in && fv != fv;
+    fsum += in ? fv : 0.f;
+    ptr[lz] = in ? (uint32_t)(i + omax) | ((uint32_t)(i + omin) << 16)
+                 : (uint32_t)i | ((uint32_t)i << 16);
+    wave_count(in && omax == 0, ctr + kCtrMaxima);
+    wave_count(in && omin == 0, ctr + kCtrMinima);
+    below = cur;
+    cur = above;
   }
   wave_count(any_nan, ctr + kCtrNaN);
+  for (int o = 32; o > 0; o >>= 1) fsum += __shfl_xor(fsum, o);
+  if ((tid & 63) == 0) s_wsum[tid >> 6] = fsum;
+  __syncthreads();  // every thread is done reading the field
+
+  // Pointers replace the field: halo vertices point to themselves.
+#pragma unroll 4
+  for (int i = tid; i < H; i += T)
+    if (!halo_owned<C>(i)) lds[i] = (uint32_t)i | ((uint32_t)i << 16);
+#pragma unroll
+  for (int lz = 0; lz < C::TZ; ++lz) lds[c0 + (lz + 1) * HXY] = ptr[lz];
   __syncthreads();
 
-  // Pointer jumping inside the tile, in place.
+  // Pointer jumping inside the tile, in place.  Only the owner writes an
+  // entry, so the owner's copy in registers is always current; an entry
+  // whose two targets are fixed points is final and is skipped.
+  uint32_t live = nz >= 32 ? ~0u : ((1u << nz) - 1u);
   for (;;) {
     bool changed = false;
-    for (int lz = 0; lz < nz; ++lz) {
-      const int i = i0 + lz * HXY;
-      int p = pa[i], q = pa[p];
-      if (q != p) { pa[i] = (int16_t)q; changed = true; }
-      p = pd[i];
-      q = pd[p];
-      if (q != p) { pd[i] = (int16_t)q; changed = true; }
+#pragma unroll
+    for (int lz = 0; lz < C::TZ; ++lz) {
+      if ((live >> lz) & 1) {
+        const uint32_t w = ptr[lz];
+        const uint32_t pa = w & 0xffffu, pd = w >> 16;
+        const uint32_t qa = lds[pa] & 0xffffu, qd = lds[pd] >> 16;
+        if (qa != pa || qd != pd) {
+          ptr[lz] = qa | (qd << 16);
+          lds[c0 + (lz + 1) * HXY] = ptr[lz];
+          changed = true;
+        } else {
+          live &= ~(1u << lz);
+        }
+      }
     }
     if (!__syncthreads_or(changed)) break;
   }
 
-  // Tile-local results; mark the halo vertices that are pointed to.
-  for (int lz = 0; lz < nz; ++lz) {
-    const int i = i0 + lz * HXY;
-    const uint32_t v = (uint32_t)gx + g.X * (uint32_t)gy +
-                       g.XY * (uint32_t)(t.z0 + lz);
-    const int p = pa[i], q = pd[i];
-    la[v] = (int16_t)p;
-    ld[v] = (int16_t)q;
-    if (!halo_owned(p)) ea[p] = 1;
-    if (!halo_owned(q)) ed[q] = 1;
+  // Halo targets are the tile's exits.
+#pragma unroll
+  for (int lz = 0; lz < C::TZ; ++lz) {
+    if (lz < nz) {
+      const uint32_t w = ptr[lz];
+      const int pa = (int)(w & 0xffffu), pd = (int)(w >> 16);
+      if (!halo_owned<C>(pa)) atomicOr(&xa[pa >> 5], 1u << (pa & 31));
+      if (!halo_owned<C>(pd)) atomicOr(&xd[pd >> 5], 1u << (pd & 31));
+    }
   }
   __syncthreads();
 
-  // Append the marked halo vertices to the exit list (one global atomic per
-  // tile).
-  unsigned mine = 0;
-  for (int i = tid; i < H; i += kThreads) mine += ea[i] + ed[i];
-  if (mine) atomicAdd(&s_cnt, mine);
+  // Exits are numbered ascent then descent, each in increasing halo index.
+  const uint32_t wa = tid < C::kWords ? xa[tid] : 0u;
+  const uint32_t wd = tid < C::kWords ? xd[tid] : 0u;
+  uint32_t na = 0, nd = 0;
+  const uint32_t pa0 = block_exclusive_scan(__popc(wa), scan_tmp, &na);
+  const uint32_t pd0 = block_exclusive_scan(__popc(wd), scan_tmp, &nd);
+  if (tid < C::kWords) {
+    pra[tid] = pa0;
+    prd[tid] = pd0;
+  }
   __syncthreads();
-  if (tid == 0 && s_cnt)
-    s_base = atomicAdd(ctr + kCtrExits, (unsigned long long)s_cnt);
+
+  // The stored local pointer: an owned target by its owned index, an exit
+  // by its number (bit 15 set), so that later passes decode it with one
+  // lookup in the tile's resolved exits.
+#pragma unroll
+  for (int lz = 0; lz < C::TZ; ++lz) {
+    if (lz < nz) {
+      const uint32_t v = (uint32_t)gx + g.X * (uint32_t)gy +
+                         g.XY * (uint32_t)(t.z0 + lz);
+      const uint32_t w = ptr[lz];
+      lp[v] = local_code<C>((int)(w & 0xffffu), xa, pra) |
+              (local_code<C>((int)(w >> 16), xd, prd) << 16);
+    }
+  }
+
+  if (tid == 0) {
+    s_base = (na + nd) ? atomicAdd(ctr + kCtrExits,
+                                   (unsigned long long)(na + nd))
+                       : 0ull;
+    xo.seg[tile] = Seg{(uint32_t)s_base, (uint16_t)na, (uint16_t)nd};
+    // Mean value of the tile: the order in which exits get resolved.
+    float sum = 0.f;
+    for (int w = 0; w < T / 64; ++w) sum += s_wsum[w];
+    const int cnt = min(C::TX, (int)g.X - t.x0) * min(C::TY, (int)g.Y - t.y0) *
+                    min(C::TZ, (int)g.Z - t.z0);
+    xo.tkey[tile] = float_key(sum / (float)cnt);
+  }
   __syncthreads();
-  if (mine) {
-    for (int i = tid; i < H; i += kThreads) {
-      if (!(ea[i] | ed[i])) continue;
-      const uint32_t gid = halo_global(g, t, i);
-      if (ea[i]) {
-        unsigned long long pos = s_base + atomicAdd(&s_cur, 1u);
-        if (pos < exit_cap) exits[pos] = gid;
-      }
-      if (ed[i]) {
-        unsigned long long pos = s_base + atomicAdd(&s_cur, 1u);
-        if (pos < exit_cap) exits[pos] = gid | kTagDesc;
-      }
+  for (int k = 0; k < 2; ++k) {
+    uint32_t bits = k ? wd : wa;
+    unsigned long long at = s_base + (k ? na + pd0 : pa0);
+    while (bits) {
+      const int b = __ffs(bits) - 1;
+      bits &= bits - 1;
+      if (at < xo.cap)
+        xo.list[at] = halo_global<C>(g, t, tid * 32 + b) | (k ? kTagDesc : 0u);
+      ++at;
     }
   }
 }
@@ -241,75 +428,174 @@ k_tile_local(const float *__restrict__ f, Geo g, int16_t *__restrict__ la,
 // exit graph
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ Tile tile_of_vertex(const Geo &g, uint32_t v) {
+// Exit i (the k-th exit of its tile) lies on the shell of a neighbouring
+// tile, whose stored code for it names either an extremum of that tile
+// (final) or one of that tile's exits (the next node of the graph).  Nodes
+// are numbered by list position, so the graph is a dense array: next[i] is a
+// node index, or kRoot | vertex id once final.
+constexpr uint32_t kRoot = 0x80000000u;
+
+template <class C>
+__device__ __forceinline__ Tile tile_of_vertex(const Geo &g, uint32_t v,
+                                               uint32_t *tile) {
   uint32_t z = v / g.XY, r = v - z * g.XY, y = r / g.X, x = r - y * g.X;
-  return Tile{(int)(x - x % TX), (int)(y - y % TY), (int)(z - z % TZ)};
+  uint32_t tx = x / C::TX, ty = y / C::TY, tz = z / C::TZ;
+  *tile = tx + g.ntx * (ty + g.nty * tz);
+  return Tile{(int)(tx * C::TX), (int)(ty * C::TY), (int)(tz * C::TZ)};
 }
 
-// Each exit takes its own tile's pointer as a global id; a pointer to a
-// tile-local root makes that root point to itself in the same array.
+template <class C>
 __global__ void __launch_bounds__(kBlock)
-k_exit_init(const uint32_t *__restrict__ exits, uint32_t count, Geo g,
-            const int16_t *__restrict__ la, const int16_t *__restrict__ ld,
-            int32_t *A, int32_t *D) {
-  uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+k_exit_link(const uint32_t *__restrict__ list, uint32_t count, Geo g,
+            const uint32_t *__restrict__ lp, const Seg *__restrict__ seg,
+            uint32_t *__restrict__ next) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= count) return;
-  const uint32_t e = exits[i];
+  const uint32_t e = list[i];
   const bool desc = e & kTagDesc;
   const uint32_t v = e & ~kTagDesc;
-  const int p = desc ? ld[v] : la[v];
-  const uint32_t target = halo_global(g, tile_of_vertex(g, v), p);
-  int32_t *arr = desc ? D : A;
-  arr[v] = (int32_t)target;
-  if (halo_owned(p)) arr[target] = (int32_t)target;
+  uint32_t u;
+  const Tile t = tile_of_vertex<C>(g, v, &u);
+  const uint32_t w = lp[v];
+  const uint32_t code = desc ? (w >> 16) : (w & 0xffffu);
+  if (code & kExitCode) {
+    const Seg sg = seg[u];
+    next[i] = sg.base + (desc ? sg.na : 0u) + (code & (kExitCode - 1));
+  } else {
+    next[i] = kRoot | owned_global<C>(g, t, code);
+  }
 }
 
-// In-place jumping over the exit list: every entry follows its chain to a
-// fixed point; entries read by others only ever move further along their
-// path, so any interleaving ends at the same extremum.
+// Tiles are resolved in order of their mean value: ascent chains climb, so
+// a tile's ascent exits mostly lead into tiles of higher mean that were
+// resolved just before (their graph segments are still in cache); descent
+// runs the other way.  The order only affects speed: every chase follows
+// its own path to a final value, whatever has been resolved already.
+constexpr int kTileBuckets = 4096;
+
 __global__ void __launch_bounds__(kBlock)
-k_exit_jump(const uint32_t *__restrict__ exits, uint32_t count, uint32_t n,
-            int32_t *A, int32_t *D, unsigned long long *ctr) {
-  uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  unsigned steps = 0;
+k_key_minmax(const uint32_t *__restrict__ key, uint32_t n, uint32_t *mm) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  uint32_t lo = ~0u, hi = 0;
+  if (i < n) lo = hi = key[i];
+  for (int o = 32; o > 0; o >>= 1) {
+    const uint32_t a = __shfl_xor(lo, o), b = __shfl_xor(hi, o);
+    lo = a < lo ? a : lo;
+    hi = b > hi ? b : hi;
+  }
+  if ((threadIdx.x & 63) == 0 && lo <= hi) {
+    atomicMin(&mm[0], lo);
+    atomicMax(&mm[1], hi);
+  }
+}
+
+__device__ __forceinline__ uint32_t key_bucket(uint32_t key, const uint32_t *mm) {
+  const uint64_t span = (uint64_t)mm[1] - mm[0] + 1;
+  const uint64_t b = ((uint64_t)(key - mm[0]) * kTileBuckets) / span;
+  return b < kTileBuckets ? (uint32_t)b : kTileBuckets - 1;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_key_hist(const uint32_t *__restrict__ key, uint32_t n,
+           const uint32_t *__restrict__ mm, uint32_t *hist) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) atomicAdd(&hist[key_bucket(key[i], mm)], 1u);
+}
+
+// Exclusive scan of kTileBuckets counts in place (one block of 1024
+// threads, four counts each).
+__global__ void __launch_bounds__(1024) k_key_scan(uint32_t *hist) {
+  __shared__ uint32_t tmp[32];
+  const int b0 = threadIdx.x * 4;
+  const uint32_t c0 = hist[b0], c1 = hist[b0 + 1], c2 = hist[b0 + 2],
+                 c3 = hist[b0 + 3];
+  uint32_t total;
+  const uint32_t p = block_exclusive_scan(c0 + c1 + c2 + c3, tmp, &total);
+  hist[b0] = p;
+  hist[b0 + 1] = p + c0;
+  hist[b0 + 2] = p + c0 + c1;
+  hist[b0 + 3] = p + c0 + c1 + c2;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_key_scatter(const uint32_t *__restrict__ key, uint32_t n,
+              const uint32_t *__restrict__ mm, uint32_t *cursor,
+              uint32_t *__restrict__ order) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) order[atomicAdd(&cursor[key_bucket(key[i], mm)], 1u)] = i;
+}
+
+// Block b resolves one tile's exits of one direction: the first ntiles
+// blocks take ascent exits in decreasing mean, the rest descent exits in
+// increasing mean.  Each exit chases its successors until a final value.
+template <class C>
+__global__ void __launch_bounds__(C::kThreads)
+k_exit_resolve(const uint32_t *__restrict__ order, uint32_t ntiles,
+               const Seg *__restrict__ seg, uint32_t count, uint32_t *next,
+               unsigned long long *ctr) {
+  const bool desc = blockIdx.x >= ntiles;
+  const uint32_t tile =
+      desc ? order[blockIdx.x - ntiles] : order[ntiles - 1 - blockIdx.x];
+  const Seg sg = seg[tile];
+  const uint32_t first = sg.base + (desc ? sg.na : 0u);
+  const uint32_t cnt = desc ? sg.nd : sg.na;
+  unsigned steps_max = 0;
   bool bad = false;
-  if (i < count) {
-    const uint32_t e = exits[i];
-    int32_t *arr = (e & kTagDesc) ? D : A;
-    const uint32_t v = e & ~kTagDesc;
-    // Every pointer is a vertex id and a chain is at most n long; the checks
-    // only turn a broken invariant into an error instead of a bad access.
-    for (; steps <= n; ++steps) {
-      int32_t u = __atomic_load_n(&arr[v], __ATOMIC_RELAXED);
-      if ((uint32_t)u >= n) { bad = true; break; }
-      int32_t w = __atomic_load_n(&arr[u], __ATOMIC_RELAXED);
-      if ((uint32_t)w >= n) { bad = true; break; }
-      if (w == u) break;
-      __atomic_store_n(&arr[v], w, __ATOMIC_RELAXED);
+  for (uint32_t k = threadIdx.x; k < cnt; k += C::kThreads) {
+    uint32_t x = __atomic_load_n(&next[first + k], __ATOMIC_RELAXED);
+    unsigned steps = 0;
+    // Chains are acyclic and at most `count` long; the bound only turns a
+    // broken invariant into an error instead of a hang.
+    while (!(x & kRoot)) {
+      if (x >= count || ++steps > count) {
+        bad = true;
+        x = kRoot;
+        break;
+      }
+      x = __atomic_load_n(&next[x], __ATOMIC_RELAXED);
     }
-    if (steps > n) bad = true;
+    __atomic_store_n(&next[first + k], x, __ATOMIC_RELAXED);
+    steps_max = steps > steps_max ? steps : steps_max;
   }
   if (bad) atomicOr(ctr + kCtrOverflow, 2ull);
-  // Longest chain seen (reported as the jump-round count).
   for (int o = 32; o > 0; o >>= 1) {
-    unsigned other = __shfl_xor(steps, o);
-    steps = other > steps ? other : steps;
+    const unsigned other = __shfl_xor(steps_max, o);
+    steps_max = other > steps_max ? other : steps_max;
   }
-  if ((threadIdx.x & 63) == 0 && steps)
-    atomicMax(ctr + kCtrRounds, (unsigned long long)steps);
+  if ((threadIdx.x & 63) == 0 && steps_max)
+    atomicMax(ctr + kCtrRounds, (unsigned long long)steps_max);
 }
 
 // ---------------------------------------------------------------------------
 // pairs and output
 // ---------------------------------------------------------------------------
 
-// Final extremum of a vertex from its tile-local pointer p: a local root is
-// final; otherwise p is an exit whose resolved value sits in arr.
-__device__ __forceinline__ int32_t final_of(const Geo &g, const Tile &t, int p,
-                                            const int32_t *arr) {
-  const uint32_t target = halo_global(g, t, p);
-  if (halo_owned(p)) return (int32_t)target;
-  return __atomic_load_n(&arr[target], __ATOMIC_RELAXED);
+// A tile's resolved exits, staged in LDS: ascent exits first, then descent.
+template <class C>
+struct Decode {
+  int32_t res[2 * C::kHalo];
+  uint32_t na;
+};
+
+template <class C>
+__device__ __forceinline__ void decode_setup(Decode<C> &s, uint32_t tile,
+                                             const Seg *seg, const uint32_t *R) {
+  const Seg sg = seg[tile];
+  const uint32_t n = (uint32_t)sg.na + sg.nd;
+  for (uint32_t k = threadIdx.x; k < n; k += C::kThreads)
+    s.res[k] = (int32_t)(R[sg.base + k] & ~kRoot);
+  if (threadIdx.x == 0) s.na = sg.na;
+  __syncthreads();
+}
+
+// Final extremum of a stored local pointer code.
+template <class C>
+__device__ __forceinline__ int32_t decode_final(const Decode<C> &s,
+                                                const Geo &g, const Tile &t,
+                                                uint32_t code, bool desc) {
+  if (code & kExitCode)
+    return s.res[(desc ? s.na : 0u) + (code & (kExitCode - 1))];
+  return (int32_t)owned_global<C>(g, t, code);
 }
 
 __global__ void k_table_clear(unsigned long long *keys, int32_t *vals,
@@ -351,6 +637,25 @@ __device__ __forceinline__ unsigned long long pair_key(int32_t a, int32_t d) {
   return ((unsigned long long)(uint32_t)a << 32) | (uint32_t)d;
 }
 
+// Per-tile table of the distinct final (asc, desc) pairs: few per tile, so
+// the global insert and the cell lookup run once per distinct pair.
+constexpr int kPairSlots = 1024;
+
+__device__ __forceinline__ int pair_slot(unsigned long long *skey,
+                                         unsigned long long key) {
+  uint32_t h = (uint32_t)mix64(key) & (kPairSlots - 1);
+  for (int probe = 0; probe < 32; ++probe) {
+    unsigned long long cur = skey[h];
+    if (cur == kEmptyKey) {
+      cur = atomicCAS(&skey[h], kEmptyKey, key);
+      if (cur == kEmptyKey) return (int)h;
+    }
+    if (cur == key) return (int)h;
+    h = (h + 1) & (kPairSlots - 1);
+  }
+  return -1;  // table full: the caller takes the per-vertex path
+}
+
 __device__ __forceinline__ unsigned long long wave_bcast64(
     unsigned long long x, int lane) {
   uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, lane);
@@ -358,65 +663,94 @@ __device__ __forceinline__ unsigned long long wave_bcast64(
   return ((unsigned long long)hi << 32) | lo;
 }
 
-__global__ void __launch_bounds__(kThreads)
-k_tile_pairs(Geo g, const int16_t *__restrict__ la,
-             const int16_t *__restrict__ ld, const int32_t *A,
-             const int32_t *D, unsigned long long *keys, int32_t *vals,
-             uint32_t mask, unsigned long long *ctr) {
+// Slot of every lane's pair, merging equal pairs of a wave first; the
+// lowest lane of a group holds its smallest vertex id (ids grow with the lane
+// inside a wave: rows of the tile are consecutive in y).  With `sval`, the
+// group's smallest id is folded into the slot.
+__device__ __forceinline__ int wave_pair_slot(unsigned long long *skey,
+                                              int32_t *sval, bool in,
+                                              unsigned long long key,
+                                              int32_t id) {
+  const int lane = threadIdx.x & 63;
+  int slot = -1;
+  bool pending = in;
+  for (;;) {
+    const unsigned long long m = __ballot(pending);
+    if (!m) break;
+    const int leader = __ffsll((long long)m) - 1;
+    const unsigned long long lkey = wave_bcast64(key, leader);
+    int ls = 0;
+    if (lane == leader) {
+      ls = pair_slot(skey, lkey);
+      if (sval && ls >= 0) atomicMin(&sval[ls], id);
+    }
+    ls = __builtin_amdgcn_readlane(ls, leader);
+    if (pending && key == lkey) {
+      slot = ls;
+      pending = false;
+    }
+  }
+  return slot;
+}
+
+__device__ __forceinline__ int32_t table_lookup(
+    const unsigned long long *__restrict__ keys,
+    const int32_t *__restrict__ vals, uint32_t mask, unsigned long long key) {
+  uint32_t h = (uint32_t)mix64(key) & mask;
+  for (uint32_t probe = 0; probe <= mask; ++probe) {
+    const unsigned long long cur = keys[h];
+    if (cur == key) return vals[h];
+    if (cur == kEmptyKey) return -1;
+    h = (h + 1) & mask;
+  }
+  return -1;
+}
+
+template <class C>
+__global__ void __launch_bounds__(C::kThreads)
+k_tile_pairs(Geo g, const uint32_t *__restrict__ lp, const Seg *__restrict__ seg,
+             const uint32_t *__restrict__ R, unsigned long long *keys,
+             int32_t *vals, uint32_t mask, unsigned long long *ctr) {
+  __shared__ Decode<C> s;
   __shared__ unsigned long long skey[kPairSlots];
   __shared__ int32_t sval[kPairSlots];
-  const int tid = threadIdx.x, lane = tid & 63;
-  const Tile t = tile_at(g, tile_of_block(blockIdx.x, gridDim.x));
-  for (int i = tid; i < kPairSlots; i += kThreads) {
+  const int tid = threadIdx.x;
+  const uint32_t tile = tile_of_block(blockIdx.x, gridDim.x);
+  const Tile t = tile_at<C>(g, tile);
+  for (int i = tid; i < kPairSlots; i += C::kThreads) {
     skey[i] = kEmptyKey;
     sval[i] = INT32_MAX;
   }
-  __syncthreads();
-
-  const int cx = tid % TX, cy = tid / TX;
+  const int cx = tid % C::TX, cy = tid / C::TX;
   const int gx = t.x0 + cx, gy = t.y0 + cy;
   const bool col_in = gx < (int)g.X && gy < (int)g.Y;
+  int nz = (int)g.Z - t.z0;
+  nz = col_in ? (nz < C::TZ ? nz : C::TZ) : 0;
+  uint32_t code[C::TZ];
+#pragma unroll
+  for (int lz = 0; lz < C::TZ; ++lz)
+    code[lz] = lz < nz ? lp[(uint32_t)gx + g.X * (uint32_t)gy +
+                            g.XY * (uint32_t)(t.z0 + lz)]
+                       : 0u;
+  decode_setup<C>(s, tile, seg, R);
+
   unsigned fresh = 0;
   bool overflow = false;
-  for (int lz = 0; lz < TZ; ++lz) {
-    const bool in = col_in && t.z0 + lz < (int)g.Z;
+#pragma unroll
+  for (int lz = 0; lz < C::TZ; ++lz) {
+    const bool in = lz < nz;
     unsigned long long key = 0;
-    int32_t id = 0;
-    if (in) {
-      const uint32_t v = (uint32_t)gx + g.X * (uint32_t)gy +
-                         g.XY * (uint32_t)(t.z0 + lz);
-      key = pair_key(final_of(g, t, la[v], A), final_of(g, t, ld[v], D));
-      id = (int32_t)v;
-    }
-    // Lanes holding the same pair are merged: the lowest lane holds the
-    // smallest id of them (ids grow with the lane inside a row, and the
-    // second row of a wave has larger ids than the first).
-    bool pending = in;
-    for (;;) {
-      unsigned long long m = __ballot(pending);
-      if (!m) break;
-      const int leader = __ffsll((long long)m) - 1;
-      const unsigned long long lkey = wave_bcast64(key, leader);
-      if (lane == leader) {
-        uint32_t h = (uint32_t)mix64(lkey) & (kPairSlots - 1);
-        bool done = false;
-        for (int probe = 0; probe < 32 && !done; ++probe) {
-          unsigned long long cur = skey[h];
-          if (cur == kEmptyKey) cur = atomicCAS(&skey[h], kEmptyKey, lkey);
-          if (cur == kEmptyKey || cur == lkey) {
-            atomicMin(&sval[h], id);
-            done = true;
-          }
-          h = (h + 1) & (kPairSlots - 1);
-        }
-        if (!done && !table_insert(keys, vals, mask, lkey, id, &fresh))
-          overflow = true;
-      }
-      if (pending && key == lkey) pending = false;
-    }
+    if (in)
+      key = pair_key(decode_final<C>(s, g, t, code[lz] & 0xffffu, false),
+                     decode_final<C>(s, g, t, code[lz] >> 16, true));
+    const int32_t id = (int32_t)((uint32_t)gx + g.X * (uint32_t)gy +
+                                 g.XY * (uint32_t)(t.z0 + lz));
+    const int slot = wave_pair_slot(skey, sval, in, key, id);
+    if (in && slot < 0 && !table_insert(keys, vals, mask, key, id, &fresh))
+      overflow = true;
   }
   __syncthreads();
-  for (int i = tid; i < kPairSlots; i += kThreads) {
+  for (int i = tid; i < kPairSlots; i += C::kThreads) {
     if (skey[i] != kEmptyKey &&
         !table_insert(keys, vals, mask, skey[i], sval[i], &fresh))
       overflow = true;
@@ -425,60 +759,69 @@ k_tile_pairs(Geo g, const int16_t *__restrict__ la,
   if (overflow) atomicOr(ctr + kCtrOverflow, 1ull);
 }
 
-__global__ void __launch_bounds__(kThreads)
-k_tile_write(Geo g, const int16_t *__restrict__ la,
-             const int16_t *__restrict__ ld, int32_t *A, int32_t *D,
+template <class C>
+__global__ void __launch_bounds__(C::kThreads)
+k_tile_write(Geo g, const uint32_t *__restrict__ lp, const Seg *__restrict__ seg,
+             const uint32_t *__restrict__ R, int32_t *__restrict__ A,
+             int32_t *__restrict__ D,
              const unsigned long long *__restrict__ keys,
              const int32_t *__restrict__ vals, uint32_t mask,
              int32_t *__restrict__ ms) {
-  const int tid = threadIdx.x, lane = tid & 63;
-  const Tile t = tile_at(g, tile_of_block(blockIdx.x, gridDim.x));
-  const int cx = tid % TX, cy = tid / TX;
+  __shared__ Decode<C> s;
+  __shared__ unsigned long long skey[kPairSlots];
+  __shared__ int32_t scell[kPairSlots];
+  const int tid = threadIdx.x;
+  const uint32_t tile = tile_of_block(blockIdx.x, gridDim.x);
+  const Tile t = tile_at<C>(g, tile);
+  if (ms)
+    for (int i = tid; i < kPairSlots; i += C::kThreads) skey[i] = kEmptyKey;
+  const int cx = tid % C::TX, cy = tid / C::TX;
   const int gx = t.x0 + cx, gy = t.y0 + cy;
   const bool col_in = gx < (int)g.X && gy < (int)g.Y;
-  for (int lz = 0; lz < TZ; ++lz) {
-    const bool in = col_in && t.z0 + lz < (int)g.Z;
-    uint32_t v = 0;
+  int nz = (int)g.Z - t.z0;
+  nz = col_in ? (nz < C::TZ ? nz : C::TZ) : 0;
+  uint32_t code[C::TZ];
+#pragma unroll
+  for (int lz = 0; lz < C::TZ; ++lz)
+    code[lz] = lz < nz ? lp[(uint32_t)gx + g.X * (uint32_t)gy +
+                            g.XY * (uint32_t)(t.z0 + lz)]
+                       : 0u;
+  decode_setup<C>(s, tile, seg, R);
+
+  int16_t slot[C::TZ];
+#pragma unroll
+  for (int lz = 0; lz < C::TZ; ++lz) {
+    const bool in = lz < nz;
+    const uint32_t v =
+        (uint32_t)gx + g.X * (uint32_t)gy + g.XY * (uint32_t)(t.z0 + lz);
     int32_t a = 0, d = 0;
     if (in) {
-      v = (uint32_t)gx + g.X * (uint32_t)gy + g.XY * (uint32_t)(t.z0 + lz);
-      a = final_of(g, t, la[v], A);
-      d = final_of(g, t, ld[v], D);
+      a = decode_final<C>(s, g, t, code[lz] & 0xffffu, false);
+      d = decode_final<C>(s, g, t, code[lz] >> 16, true);
+      A[v] = a;
+      D[v] = d;
     }
-    if (ms) {
-      const unsigned long long key = pair_key(a, d);
-      int32_t cell = -1;
-      bool pending = in;
-      for (;;) {
-        unsigned long long m = __ballot(pending);
-        if (!m) break;
-        const int leader = __ffsll((long long)m) - 1;
-        const unsigned long long lkey = wave_bcast64(key, leader);
-        int32_t found = -1;
-        if (lane == leader) {
-          uint32_t h = (uint32_t)mix64(lkey) & mask;
-          for (uint32_t probe = 0; probe <= mask; ++probe) {
-            const unsigned long long cur = keys[h];
-            if (cur == lkey) { found = vals[h]; break; }
-            if (cur == kEmptyKey) break;
-            h = (h + 1) & mask;
-          }
-        }
-        found = __builtin_amdgcn_readlane(found, leader);
-        if (pending && key == lkey) {
-          cell = found;
-          pending = false;
-        }
-      }
-      if (in) ms[v] = cell;
-    }
-    if (in) {
-      // Same value an exit already holds, so concurrent readers of A/D see a
-      // final value either way.
-      __atomic_store_n(&A[v], a, __ATOMIC_RELAXED);
-      __atomic_store_n(&D[v], d, __ATOMIC_RELAXED);
-    }
+    slot[lz] = -1;
+    if (ms) slot[lz] = (int16_t)wave_pair_slot(skey, nullptr, in, pair_key(a, d), 0);
+    if (ms && in && slot[lz] < 0)  // table full: look this vertex up alone
+      ms[v] = table_lookup(keys, vals, mask, pair_key(a, d));
   }
+  if (!ms) return;
+  __syncthreads();
+  for (int i = tid; i < kPairSlots; i += C::kThreads)
+    if (skey[i] != kEmptyKey) scell[i] = table_lookup(keys, vals, mask, skey[i]);
+  __syncthreads();
+#pragma unroll
+  for (int lz = 0; lz < C::TZ; ++lz) {
+    if (lz < nz && slot[lz] >= 0)
+      ms[(uint32_t)gx + g.X * (uint32_t)gy + g.XY * (uint32_t)(t.z0 + lz)] =
+          scell[slot[lz]];
+  }
+}
+
+__global__ void k_fill_u32(uint32_t *p, uint32_t n, uint32_t value) {
+  uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = value;
 }
 
 uint32_t table_capacity(uint64_t n, uint64_t nmax, uint64_t nmin) {
@@ -489,10 +832,10 @@ uint32_t table_capacity(uint64_t n, uint64_t nmax, uint64_t nmin) {
   return (uint32_t)cap;
 }
 
-}  // namespace
-
-int segment_run(msc_ctx *ctx, const float *f, int64_t X, int64_t Y, int64_t Z,
-                int32_t *asc, int32_t *desc, int32_t *ms, hipStream_t s) {
+template <class C>
+int segment_tiles(msc_ctx *ctx, const float *f, int64_t X, int64_t Y,
+                  int64_t Z, int32_t *asc, int32_t *desc, int32_t *ms,
+                  hipStream_t s) {
   const int64_t n = X * Y * Z;
   Geo g{};
   g.X = (uint32_t)X;
@@ -500,46 +843,61 @@ int segment_run(msc_ctx *ctx, const float *f, int64_t X, int64_t Y, int64_t Z,
   g.Z = (uint32_t)Z;
   g.XY = (uint32_t)(X * Y);
   g.N = (uint32_t)n;
-  g.ntx = (uint32_t)((X + TX - 1) / TX);
-  g.nty = (uint32_t)((Y + TY - 1) / TY);
-  g.ntz = (uint32_t)((Z + TZ - 1) / TZ);
+  g.ntx = (uint32_t)((X + C::TX - 1) / C::TX);
+  g.nty = (uint32_t)((Y + C::TY - 1) / C::TY);
+  g.ntz = (uint32_t)((Z + C::TZ - 1) / C::TZ);
   const int64_t ntiles = (int64_t)g.ntx * g.nty * g.ntz;
   if (ntiles > INT32_MAX) return MSC_ERANGE;
   g.ntiles = (uint32_t)ntiles;
   unsigned long long *ctr = ctx->dctr;
 
-  // Workspace: 16-bit tile-local pointers, full-size arrays the caller did
-  // not ask for, and the exit list (grown if a run overflows it).
+  // Workspace: packed tile-local pointer codes, per-tile exit segments, the
+  // exit list and its graph (grown if a run overflows it), and full-size
+  // arrays the caller did not ask for.
   uint64_t exit_cap = ctx->exit_cap_hint;
   if (exit_cap < 4096) exit_cap = 4096;
-  if (exit_cap < (uint64_t)n / 16) exit_cap = (uint64_t)n / 16;
-  if (exit_cap > UINT32_MAX) exit_cap = UINT32_MAX;
+  if (exit_cap < (uint64_t)n / 8) exit_cap = (uint64_t)n / 8;
+  if (exit_cap > kRoot - 1) exit_cap = kRoot - 1;
   uint64_t exits = 0;
-  int16_t *la = nullptr, *ld = nullptr;
+  uint32_t *lp = nullptr, *list = nullptr, *next = nullptr;
+  uint32_t *tkey = nullptr, *torder = nullptr, *hist = nullptr, *mm = nullptr;
+  Seg *seg = nullptr;
   int32_t *A = asc, *D = desc;
-  uint32_t *list = nullptr;
   for (int attempt = 0;; ++attempt) {
-    size_t need = 2 * align256(n * sizeof(int16_t)) +
-                  align256(exit_cap * sizeof(uint32_t)) + 4096;
+    size_t need = align256(n * sizeof(uint32_t)) +
+                  2 * align256(exit_cap * sizeof(uint32_t)) +
+                  align256(ntiles * sizeof(Seg)) +
+                  2 * align256(ntiles * sizeof(uint32_t)) +
+                  align256((kTileBuckets + 2) * sizeof(uint32_t)) + 4096;
     if (!asc) need += align256(n * sizeof(int32_t));
     if (!desc) need += align256(n * sizeof(int32_t));
     MSC_TRY(reserve(ctx->ws, need));
     Carver cv(ctx->ws);
-    la = cv.take<int16_t>(n);
-    ld = cv.take<int16_t>(n);
+    lp = cv.take<uint32_t>(n);
     list = cv.take<uint32_t>(exit_cap);
+    next = cv.take<uint32_t>(exit_cap);
+    seg = cv.take<Seg>(ntiles);
+    tkey = cv.take<uint32_t>(ntiles);
+    torder = cv.take<uint32_t>(ntiles);
+    hist = cv.take<uint32_t>(kTileBuckets + 2);
+    mm = hist + kTileBuckets;
     A = asc ? asc : cv.take<int32_t>(n);
     D = desc ? desc : cv.take<int32_t>(n);
 
     MSC_TRY(clear_counters(ctx, s));
+    k_fill_u32<<<grid_for(kTileBuckets + 2), kBlock, 0, s>>>(
+        hist, kTileBuckets + 2, 0u);
+    k_fill_u32<<<1, kBlock, 0, s>>>(mm, 1, ~0u);
+    MSC_HIP_TRY(hipGetLastError());
+    ExitOut xo{list, seg, tkey, (uint32_t)exit_cap};
     MSC_PHASE(ctx, s, "tile_local", 8.0 * n,
-              (k_tile_local<<<g.ntiles, kThreads, 0, s>>>(
-                  f, g, la, ld, list, (uint32_t)exit_cap, ctr)));
+              (k_tile_local<C><<<g.ntiles, C::kThreads, 0, s>>>(f, g, lp, xo,
+                                                                ctr)));
     MSC_TRY(read_counters(ctx, s));
     if (ctx->hctr[kCtrNaN]) return MSC_ENAN;
     exits = ctx->hctr[kCtrExits];
     if (exits <= exit_cap) break;
-    if (attempt > 0 || exits > UINT32_MAX) return MSC_ENOMEM;
+    if (attempt > 0 || exits >= kRoot) return MSC_ENOMEM;
     exit_cap = exits + exits / 4;
   }
   ctx->exit_cap_hint = exit_cap;
@@ -547,12 +905,19 @@ int segment_run(msc_ctx *ctx, const float *f, int64_t X, int64_t Y, int64_t Z,
 
   if (exits) {
     const uint32_t ne = (uint32_t)exits;
-    MSC_PHASE(ctx, s, "exit_init", 14.0 * ne,
-              (k_exit_init<<<grid_for(ne), kBlock, 0, s>>>(list, ne, g, la, ld,
-                                                           A, D)));
-    MSC_PHASE(ctx, s, "exit_jump", 12.0 * ne,
-              (k_exit_jump<<<grid_for(ne), kBlock, 0, s>>>(list, ne, g.N, A,
-                                                           D, ctr)));
+    MSC_PHASE(ctx, s, "exit_link", 14.0 * ne,
+              (k_exit_link<C><<<grid_for(ne), kBlock, 0, s>>>(list, ne, g, lp,
+                                                              seg, next)));
+    const unsigned nt = (unsigned)g.ntiles;
+    MSC_PHASE(ctx, s, "tile_order", 12.0 * nt,
+              (k_key_minmax<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm),
+               k_key_hist<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm, hist),
+               k_key_scan<<<1, 1024, 0, s>>>(hist),
+               k_key_scatter<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm, hist,
+                                                             torder)));
+    MSC_PHASE(ctx, s, "exit_resolve", 12.0 * ne,
+              (k_exit_resolve<C><<<2 * nt, C::kThreads, 0, s>>>(
+                  torder, nt, seg, ne, next, ctr)));
   }
 
   unsigned long long *keys = nullptr;
@@ -569,12 +934,12 @@ int segment_run(msc_ctx *ctx, const float *f, int64_t X, int64_t Y, int64_t Z,
               (k_table_clear<<<grid_for(cap), kBlock, 0, s>>>(keys, vals,
                                                               cap)));
     MSC_PHASE(ctx, s, "tile_pairs", 4.0 * n,
-              (k_tile_pairs<<<g.ntiles, kThreads, 0, s>>>(
-                  g, la, ld, A, D, keys, vals, cap - 1, ctr)));
+              (k_tile_pairs<C><<<g.ntiles, C::kThreads, 0, s>>>(
+                  g, lp, seg, next, keys, vals, cap - 1, ctr)));
   }
   MSC_PHASE(ctx, s, "tile_write", (ms ? 16.0 : 12.0) * n,
-            (k_tile_write<<<g.ntiles, kThreads, 0, s>>>(
-                g, la, ld, A, D, keys, vals, cap ? cap - 1 : 0, ms)));
+            (k_tile_write<C><<<g.ntiles, C::kThreads, 0, s>>>(
+                g, lp, seg, next, A, D, keys, vals, cap ? cap - 1 : 0, ms)));
   MSC_TRY(read_counters(ctx, s));
   if (ctx->hctr[kCtrOverflow] & 2) return MSC_EHIP;
   if (ctx->hctr[kCtrOverflow]) return MSC_ENOMEM;
@@ -586,10 +951,35 @@ int segment_run(msc_ctx *ctx, const float *f, int64_t X, int64_t Y, int64_t Z,
   ctx->stats.n_cells = ms ? (int64_t)ctx->hctr[kCtrCells] : -1;
   ctx->stats.n_exits = (int64_t)exits;
   ctx->stats.jump_rounds = (int32_t)ctx->hctr[kCtrRounds];
-  ctx->stats.tile_x = TX;
-  ctx->stats.tile_y = TY;
-  ctx->stats.tile_z = TZ;
+  ctx->stats.tile_x = C::TX;
+  ctx->stats.tile_y = C::TY;
+  ctx->stats.tile_z = C::TZ;
   return MSC_OK;
+}
+
+// Tile shapes compiled in, in the order of kTileShapes.
+using Tile32x32x16 = Cfg<32, 32, 16>;
+using Tile32x16x16 = Cfg<32, 16, 16>;
+using Tile32x8x8 = Cfg<32, 8, 8>;
+using Tile64x16x16 = Cfg<64, 16, 16>;
+using Tile64x8x8 = Cfg<64, 8, 8>;
+
+}  // namespace
+
+int segment_run(msc_ctx *ctx, const float *f, int64_t X, int64_t Y, int64_t Z,
+                int32_t *asc, int32_t *desc, int32_t *ms, hipStream_t s) {
+  switch (ctx->tile_choice) {
+    case 1:
+      return segment_tiles<Tile32x16x16>(ctx, f, X, Y, Z, asc, desc, ms, s);
+    case 2:
+      return segment_tiles<Tile32x8x8>(ctx, f, X, Y, Z, asc, desc, ms, s);
+    case 3:
+      return segment_tiles<Tile64x16x16>(ctx, f, X, Y, Z, asc, desc, ms, s);
+    case 4:
+      return segment_tiles<Tile64x8x8>(ctx, f, X, Y, Z, asc, desc, ms, s);
+    default:
+      return segment_tiles<Tile32x32x16>(ctx, f, X, Y, Z, asc, desc, ms, s);
+  }
 }
 
 }  // namespace msc

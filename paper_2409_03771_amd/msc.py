@@ -51,6 +51,8 @@ _SIGS = {
     "msc_destroy": ([_P], None),
     "msc_segment": ([_P, _P, ctypes.POINTER(_I64), _P, _P, _P, _P], _I32),
     "msc_last_stats": ([_P, ctypes.POINTER(msc_stats)], _I32),
+    "msc_tile_shapes": ([ctypes.POINTER(_I32), _I32], _I32),
+    "msc_set_tile": ([_P, _I32, _I32, _I32], _I32),
     "msc_profile": ([_P, _I32], _I32),
     "msc_profile_read": ([_P, ctypes.POINTER(msc_phase), _I32,
                           ctypes.POINTER(_I32)], _I32),
@@ -158,6 +160,20 @@ def last_stats(device: int | None = None) -> dict:
     _check(_lib.msc_last_stats(context(device), ctypes.byref(s)),
            "msc_last_stats")
     return {k: getattr(s, k) for k, _ in msc_stats._fields_}
+
+
+def tile_shapes() -> list[tuple[int, int, int]]:
+    """Tile shapes of the fused segmentation pass compiled into the
+    library; the first is the default."""
+    n = _lib.msc_tile_shapes(None, 0)
+    buf = (_I32 * (3 * n))()
+    _lib.msc_tile_shapes(buf, n)
+    return [tuple(buf[3 * i:3 * i + 3]) for i in range(n)]
+
+
+def set_tile(tx: int, ty: int, tz: int, device: int | None = None):
+    """Select the segmentation tile shape of a device's context."""
+    _check(_lib.msc_set_tile(context(device), tx, ty, tz), "msc_set_tile")
 
 
 def profile(enable: bool, device: int | None = None):

@@ -136,6 +136,28 @@ def test_bad_dims_rejected(msc):
     assert e.value.code == msc.MSC_ERANGE
 
 
+def test_every_tile_shape_parity(msc):
+    """Results do not depend on the tile shape of the fused pass."""
+    cases = [synth.gaussian_field((131, 77, 45), 30, seed=3),
+             synth.random_field((70, 33, 37), seed=4, levels=3),
+             synth.random_field((200, 1, 1), seed=5),
+             synth.random_field((1, 45, 70), seed=6),
+             synth.random_field((65, 17, 1), seed=7, levels=2)]
+    want = [O.segment(f) for f in cases]
+    try:
+        for shape in msc.tile_shapes():
+            msc.set_tile(*shape)
+            for f, w in zip(cases, want):
+                got = gpu_segment(msc, f)
+                for name, g, ww in zip(("asc", "desc", "ms"), got, w):
+                    np.testing.assert_array_equal(
+                        g, ww, err_msg=f"tile {shape} dims {f.shape} {name}")
+            assert tuple(msc.last_stats()[k] for k in
+                         ("tile_x", "tile_y", "tile_z")) == shape
+    finally:
+        msc.set_tile(*msc.tile_shapes()[0])
+
+
 def test_side_stream_and_determinism(msc):
     f = torch.from_numpy(synth.gaussian_field((96, 80, 64), 20, 7)).cuda()
     a0, d0, m0 = msc.segment(f)
