@@ -22,6 +22,8 @@ sys.path.insert(0, ROOT)
 METRIC = ("Gvertices/s MS segmentation @1024^3 f32 (vs plain); "
           "served p50/p99 latency")
 HBM_PEAK_GBS = 8000.0
+BATCH_TEXT = ("batch256: 256 float32 fields, each axis round(exp(U[ln32, "
+              "ln256])), Gaussian sums with U{8..128} bumps, seed 3")
 WORKLOAD_TEXT = {
     "gauss1024": "gauss1024: 1024^3 float32, sum of 512 Gaussians "
                  "(sigma U[0.02,0.1]*1024) + U[-1e-4,1e-4] noise, seed 1",
@@ -52,13 +54,71 @@ def cpu_baseline(field_dev, depth: int):
                       "walks, sort-based cells)"}
 
 
+def bench_batch(args, msc, synth, torch, dev):
+    """256 uneven fields: one batched call per step vs. 256 plain calls."""
+    specs = synth.batch_specs(256, seed=3)
+    log("[bench] generating batch256")
+    fields = [synth.gaussian_field(d, nb, sd, device=dev) for d, nb, sd in specs]
+    torch.cuda.synchronize()
+    n = sum(f.numel() for f in fields)
+    outs = [tuple(torch.empty(f.numel(), dtype=torch.int32, device=dev)
+                  for _ in range(3)) for f in fields]
+    stream = torch.cuda.current_stream(dev)
+    tune = msc.autotune(fields, outs, stream=stream)
+    log(f"[bench] autotune {tune}")
+    for _ in range(args.warmup):
+        msc.segment_batched_into(fields, outs, stream=stream)
+    torch.cuda.synchronize()
+    msc.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        msc.segment_batched_into(fields, outs, stream=stream)
+    torch.cuda.synchronize()
+    dt_batch = (time.perf_counter() - t0) / args.steps
+    msc.profile(False)
+    prof = msc.profile_read()
+    # The same fields, one plain call each.
+    for f, (a, d, m) in zip(fields[:8], outs[:8]):
+        msc.segment_into(f, a, d, m, stream=stream)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for f, (a, d, m) in zip(fields, outs):
+            msc.segment_into(f, a, d, m, stream=stream)
+    torch.cuda.synchronize()
+    dt_plain = (time.perf_counter() - t0) / args.steps
+    log(f"[bench] batched {dt_batch * 1e3:.2f} ms vs plain {dt_plain * 1e3:.2f} ms"
+        f" for {n} vertices")
+    dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
+    avg_ms = dom["total_ms"] / dom["launches"]
+    achieved = dom["bytes"] / dom["launches"] / (avg_ms * 1e-3) / 1e9
+    out = {
+        "metric": "Gvertices/s batched MS segmentation (256 uneven fields)",
+        "value": round(n / dt_batch / 1e9, 3), "unit": "Gvertices/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt_batch * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": BATCH_TEXT, "vertices": n,
+                   "tile": list(tune["tile"]),
+                   "plain_ms_per_step": round(dt_plain * 1e3, 3),
+                   "speedup_vs_plain": round(dt_plain / dt_batch, 2)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None, "kernel": dom_name,
+                     "avg_ms": round(avg_ms, 4)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="gauss1024",
-                    choices=sorted(WORKLOAD_TEXT))
+                    choices=sorted(WORKLOAD_TEXT) + ["batch256"])
     ap.add_argument("--cpu-depth", type=int, default=40,
                     help="z-planes of the field the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -94,6 +154,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.tile:
         msc.set_tile(*(int(t) for t in args.tile.split("x")))
+
+    if args.workload == "batch256":
+        return bench_batch(args, msc, synth, torch, dev)
 
     log(f"[bench] generating {args.workload} on {dev}")
     t0 = time.perf_counter()

@@ -96,6 +96,44 @@ MSC_API int msc_segment(msc_ctx *ctx, const float *field, const int64_t dims[3],
                 int32_t *asc, int32_t *desc, int32_t *ms, void *stream);
 
 /*
+ * Segmentation of a batch of fields of independent shapes in one set of
+ * launches: every pass of msc_segment runs once over the tiles of all
+ * fields, so per-call launch and synchronisation costs are paid once per
+ * batch.  Each field's outputs are bit-identical to its own msc_segment call.
+ *
+ *  fields   host array of `nfields` descriptors; each is checked as the
+ *           arguments of msc_segment (same errors); outputs of different
+ *           fields must not overlap.
+ *  Per-field counters of the call: msc_last_field_stats(ctx, i, out).
+ */
+typedef struct msc_field {
+  const float *field;   /* device float32[X*Y*Z]                   */
+  int64_t dims[3];      /* X, Y, Z                                 */
+  int32_t *asc;         /* device int32[N] or NULL                 */
+  int32_t *desc;        /* device int32[N] or NULL                 */
+  int32_t *ms;          /* device int32[N] or NULL                 */
+} msc_field;
+
+MSC_API int msc_segment_batched(msc_ctx *ctx, int nfields,
+                                const msc_field *fields, void *stream);
+
+/*
+ * Autotuner: runs the batch once per compiled tile shape (one untimed run,
+ * then the best of two runs timed with HIP events on `stream`), selects the
+ * fastest shape for this context and reports every time.  The outputs hold
+ * the batch's results afterwards.  Blocks until the runs have finished.
+ */
+typedef struct msc_tune {
+  int best;             /* index into msc_tile_shapes              */
+  int tile[3];          /* the chosen shape                        */
+  int n_shapes;         /* shapes timed (entries of ms)            */
+  float ms[8];          /* best time per shape, milliseconds       */
+} msc_tune;
+
+MSC_API int msc_autotune(msc_ctx *ctx, int nfields, const msc_field *fields,
+                         void *stream, msc_tune *out);
+
+/*
  * Tile shape of the segmentation's fused LDS pass (a tuning knob; results
  * do not depend on it).  msc_tile_shapes writes up to `max` compiled shapes
  * as {tx, ty, tz} triples to `out` (host int[3*max]) and returns their
@@ -118,6 +156,11 @@ typedef struct msc_stats {
 } msc_stats;
 
 MSC_API int msc_last_stats(const msc_ctx *ctx, msc_stats *out);
+
+/* Counters of field `index` of the last successful segmentation call (a
+ * single msc_segment is a batch of one). */
+MSC_API int msc_last_field_stats(const msc_ctx *ctx, int index,
+                                 msc_stats *out);
 
 /*
  * Per-kernel timing (the library's own trace).  While enabled, every kernel

@@ -132,6 +132,7 @@ void msc_destroy(msc_ctx *ctx) {
   if (!ctx) return;
   DeviceGuard g(ctx->device);
   (void)hipDeviceSynchronize();
+  if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->ws.ptr) (void)hipFree(ctx->ws.ptr);
   if (ctx->tab.ptr) (void)hipFree(ctx->tab.ptr);
   if (ctx->dctr) (void)hipFree(ctx->dctr);
@@ -141,15 +142,86 @@ void msc_destroy(msc_ctx *ctx) {
 
 int msc_segment(msc_ctx *ctx, const float *field, const int64_t dims[3],
                 int32_t *asc, int32_t *desc, int32_t *ms, void *stream) {
-  if (!ctx || !field) return MSC_EINVAL;
-  if (!asc && !desc && !ms) return MSC_EINVAL;
-  int64_t n = 0;
-  MSC_TRY(check_dims(dims, &n));
-  if (n > INT32_MAX) return MSC_ERANGE;
+  if (!ctx || !dims) return MSC_EINVAL;
+  msc_field f{field, {dims[0], dims[1], dims[2]}, asc, desc, ms};
+  return msc_segment_batched(ctx, 1, &f, stream);
+}
+
+int msc_segment_batched(msc_ctx *ctx, int nfields, const msc_field *fields,
+                        void *stream) {
+  if (!ctx || nfields < 0 || (nfields > 0 && !fields)) return MSC_EINVAL;
+  if (nfields == 0) return MSC_OK;
+  for (int i = 0; i < nfields; ++i) {
+    const msc_field &f = fields[i];
+    if (!f.field || (!f.asc && !f.desc && !f.ms)) return MSC_EINVAL;
+    int64_t n = 0;
+    MSC_TRY(check_dims(f.dims, &n));
+    if (n > INT32_MAX) return MSC_ERANGE;
+  }
   DeviceGuard g(ctx->device);
   if (!g.ok) return MSC_EHIP;
-  return msc::segment_run(ctx, field, dims[0], dims[1], dims[2], asc, desc, ms,
-                          static_cast<hipStream_t>(stream));
+  return msc::segment_batch_run(ctx, nfields, fields,
+                                static_cast<hipStream_t>(stream));
+}
+
+int msc_last_field_stats(const msc_ctx *ctx, int index, msc_stats *out) {
+  if (!ctx || !out || index < 0 || index >= (int)ctx->field_stats.size())
+    return MSC_EINVAL;
+  *out = ctx->field_stats[index];
+  return MSC_OK;
+}
+
+int msc_autotune(msc_ctx *ctx, int nfields, const msc_field *fields,
+                 void *stream, msc_tune *out) {
+  if (!ctx || !out) return MSC_EINVAL;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return MSC_EHIP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  *out = msc_tune{};
+  const int prev = ctx->tile_choice;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    return MSC_EHIP;
+  }
+  int best = -1, rc = MSC_OK;
+  float best_ms = 0.f;
+  const int nshape = msc::kNumTileShapes < 8 ? msc::kNumTileShapes : 8;
+  for (int i = 0; i < nshape && rc == MSC_OK; ++i) {
+    ctx->tile_choice = i;
+    // One untimed run sizes the workspace; the best of two timed runs counts.
+    rc = msc_segment_batched(ctx, nfields, fields, stream);
+    float t_best = 0.f;
+    for (int r = 0; r < 2 && rc == MSC_OK; ++r) {
+      if (hipEventRecord(a, s) != hipSuccess) { rc = MSC_EHIP; break; }
+      rc = msc_segment_batched(ctx, nfields, fields, stream);
+      if (rc != MSC_OK) break;
+      float ms = 0.f;
+      if (hipEventRecord(b, s) != hipSuccess ||
+          hipEventSynchronize(b) != hipSuccess ||
+          hipEventElapsedTime(&ms, a, b) != hipSuccess) {
+        rc = MSC_EHIP;
+        break;
+      }
+      if (r == 0 || ms < t_best) t_best = ms;
+    }
+    out->ms[i] = t_best;
+    if (rc == MSC_OK && (best < 0 || t_best < best_ms)) {
+      best = i;
+      best_ms = t_best;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (rc != MSC_OK) {
+    ctx->tile_choice = prev;
+    return rc;
+  }
+  ctx->tile_choice = best;
+  out->n_shapes = nshape;
+  out->best = best;
+  for (int k = 0; k < 3; ++k) out->tile[k] = msc::kTileShapes[best][k];
+  return MSC_OK;
 }
 
 int msc_tile_shapes(int *out, int max) {

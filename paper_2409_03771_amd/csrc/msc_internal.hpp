@@ -111,6 +111,9 @@ struct msc_ctx {
   msc::Profiler prof;
   uint64_t exit_cap_hint = 0;  // exit-list size that sufficed last time
   int tile_choice = 0;         // segmentation tile shape (0 = default)
+  void *pinned = nullptr;      // grow-only pinned host staging
+  size_t pinned_bytes = 0;
+  std::vector<msc_stats> field_stats;  // per field of the last batch
 };
 
 namespace msc {
@@ -177,8 +180,8 @@ inline int tile_index(int tx, int ty, int tz) {
 }
 
 // Launchers implemented in the kernel translation units.
-int segment_run(msc_ctx *ctx, const float *f, int64_t X, int64_t Y, int64_t Z,
-                int32_t *asc, int32_t *desc, int32_t *ms, hipStream_t s);
+int segment_batch_run(msc_ctx *ctx, int nfields, const msc_field *fields,
+                      hipStream_t s);
 int cc_grid_run(msc_ctx *ctx, const uint8_t *mask, int64_t X, int64_t Y,
                 int64_t Z, int64_t *labels, hipStream_t s);
 int cc_csr_run(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,

@@ -1,4 +1,4 @@
-// Morse-Smale segmentation kernels (gfx950).
+// Morse-Smale segmentation kernels (gfx950), for one field or a batch.
 //
 // arXiv 2409.03771, Alg. 1 and methods "Ascending and Descending
 // Segmentation": every vertex points to the (value,id)-largest vertex of its
@@ -9,36 +9,35 @@
 // The paper splits the domain over ranks, compresses each rank's part with
 // ghost vertices treated as maxima (Alg. 1), then resolves the pointers that
 // leave a rank in one exchange step (Alg. 2).  Here the same two levels map
-// onto the GPU's memory hierarchy:
+// onto the GPU's memory hierarchy, and every pass runs once over the tiles
+// of all fields of a batch (one field is a batch of one):
 //
-//   tile_local   one workgroup per tile: the field plus a one-vertex halo is
-//                staged in LDS, both steepest pointers are computed from LDS
-//                (each thread walks a z-column with a three-plane register
-//                window), halo vertices point to themselves (the ghost rule),
-//                and pointer jumping runs in LDS until every owned vertex
-//                points to a tile-local extremum or to a halo vertex
-//                ("exit").  Writes one packed pair of 16-bit tile-local
-//                pointers per vertex, appends the tile's exits to a list in
-//                a fixed order (its segment), writes the global pointer of
-//                every shell vertex (the ones other tiles can exit to) and
-//                of every local extremum.
-//   exit_hist    exits are bucketed by field value (ascent chains climb, so
-//   exit_scan    ascent exits go high values first, descent exits low values
-//   exit_scatter first): a counting sort over value buckets.
-//   exit_jump    in-place pointer jumping over the exits only, in that order,
-//                so most chains find their next exit already resolved (the
-//                paper's compression of the ghost graph after the exchange).
-//                The result of list entry i goes to R[i].
-//   tile_pairs   per tile: rebuild the exit bitsets from the local pointers,
-//                stage the tile's resolved segment of R in LDS, decode every
-//                vertex's final extrema, and insert its (asc, desc) pair into
-//                a hash table keeping the smallest vertex id (per-tile LDS
-//                table first).
-//   tile_write   the same decode, then asc, desc and the cell id per vertex
-//                (the paper's relabelling pass, Alg. 2).
+//   tile_local    one workgroup per tile: the field plus a one-vertex halo is
+//                 staged in LDS, both steepest pointers are computed from LDS
+//                 (each thread walks a z-column with a three-plane register
+//                 window), halo vertices point to themselves (the ghost
+//                 rule), and pointer jumping runs in LDS until every owned
+//                 vertex points to a tile-local extremum or to a halo vertex
+//                 ("exit").  Writes a 16-bit code per vertex and direction
+//                 (an owned extremum, or the number of an exit of the tile)
+//                 and appends the tile's exits to a list (its segment).
+//   exit_link     an exit lies on a neighbouring tile's shell; that tile's
+//                 code for it gives the exit's successor: a final extremum or
+//                 another tile's exit.  The exits form a dense graph.
+//   tile_order    tiles sorted by mean value;
+//   exit_resolve  one workgroup per tile and direction, in that order
+//                 (ascent: high mean first; descent: low mean first), chases
+//                 every exit's successors to a final value -- the paper's
+//                 compression of the ghost graph after the exchange.
+//   tile_pairs    per tile: decode every vertex's final (asc, desc) pair from
+//                 its codes and the tile's resolved exits, dedupe in LDS, and
+//                 insert into the field's hash table keeping the smallest id;
+//   tile_write    the same decode, then asc, desc and the cell id per vertex
+//                 (the paper's relabelling pass, Alg. 2).
 #include <climits>
 #include <cstdlib>
 #include <cstring>
+#include <vector>
 
 #include "msc_internal.hpp"
 
@@ -64,9 +63,25 @@ struct Cfg {
 constexpr unsigned long long kEmptyKey = ~0ull;
 constexpr uint32_t kTagDesc = 0x80000000u;
 
+// Per-field counters (kFieldCtrs per field).
+enum FieldCtr : int { kFMaxima = 0, kFMinima = 1, kFCells = 2, kFNaN = 3,
+                      kFieldCtrs = 4 };
+
 struct Geo {
   uint32_t X, Y, Z, XY, N;
   uint32_t ntx, nty, ntz, ntiles;
+};
+
+// One field of a batch as the kernels see it.
+struct FieldDev {
+  const float *f;
+  uint32_t *lp;                // packed codes, one per vertex
+  int32_t *A, *D, *ms;         // outputs (A/D may be library scratch)
+  unsigned long long *keys;    // the field's pair table
+  int32_t *vals;
+  uint32_t mask;               // table capacity - 1
+  uint32_t tile0;              // first global tile of the field
+  Geo g;
 };
 
 // A tile's exits in the list: `base`, then `na` ascent exits and `nd`
@@ -155,8 +170,15 @@ __device__ __forceinline__ uint64_t mix64(uint64_t k) {
   return k;
 }
 
+// Order-preserving map of a float to an unsigned key; only used to order
+// work, never to decide a result.
+__device__ __forceinline__ uint32_t float_key(float x) {
+  uint32_t u = __float_as_uint(x);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
 // Exclusive prefix sum over the block (at most 1024 threads = 16 waves).
-// `tmp` holds 16 words of LDS.  Returns the prefix; *total gets the sum.
+// `tmp` holds 32 words of LDS.  Returns the prefix; *total gets the sum.
 __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x,
                                                          uint32_t *tmp,
                                                          uint32_t *total) {
@@ -186,6 +208,22 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t x,
   return before + inc - x;
 }
 
+// The block's tile: global tile index, its field and the field's geometry.
+struct BlockTile {
+  uint32_t gt, fi, tile;
+  FieldDev fd;
+};
+
+__device__ __forceinline__ BlockTile block_tile(const FieldDev *fds,
+                                                const uint32_t *tfield) {
+  BlockTile b;
+  b.gt = tile_of_block(blockIdx.x, gridDim.x);
+  b.fi = tfield[b.gt];
+  b.fd = fds[b.fi];
+  b.tile = b.gt - b.fd.tile0;
+  return b;
+}
+
 // ---------------------------------------------------------------------------
 // tile_local
 // ---------------------------------------------------------------------------
@@ -211,23 +249,18 @@ __device__ __forceinline__ Plane load_plane(const uint32_t *lds, int c) {
 }
 
 struct ExitOut {
-  uint32_t *list;      // exit ids (bit 31: descent)
-  Seg *seg;            // per tile
-  uint32_t *tkey;      // per tile: order key of its mean value
+  uint32_t *list;      // exit vertex ids (bit 31: descent)
+  uint32_t *lfield;    // field of each exit
+  Seg *seg;            // per global tile
+  uint32_t *tkey;      // per global tile: order key of its mean value
   uint32_t cap;
 };
 
-// Order-preserving map of a float to an unsigned key; only used to order
-// work, never to decide a result.
-__device__ __forceinline__ uint32_t float_key(float x) {
-  uint32_t u = __float_as_uint(x);
-  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
-}
-
 template <class C>
 __global__ void __launch_bounds__(C::kThreads)
-k_tile_local(const float *__restrict__ f, Geo g, uint32_t *__restrict__ lp,
-             ExitOut xo, unsigned long long *ctr) {
+k_tile_local(const FieldDev *__restrict__ fds,
+             const uint32_t *__restrict__ tfield, ExitOut xo,
+             unsigned long long *ctr, unsigned long long *fctr) {
   constexpr int HX = C::HX, HXY = C::HXY, H = C::H, T = C::kThreads;
   // Field bits while the steepest pointers are computed, then the packed
   // pointers (ascent in the low 16 bits, descent in the high 16 bits).
@@ -239,8 +272,11 @@ k_tile_local(const float *__restrict__ f, Geo g, uint32_t *__restrict__ lp,
   __shared__ unsigned long long s_base;
 
   const int tid = threadIdx.x;
-  const uint32_t tile = tile_of_block(blockIdx.x, gridDim.x);
-  const Tile t = tile_at<C>(g, tile);
+  const BlockTile bt = block_tile(fds, tfield);
+  const Geo &g = bt.fd.g;
+  const float *__restrict__ f = bt.fd.f;
+  unsigned long long *fc = fctr + (size_t)bt.fi * kFieldCtrs;
+  const Tile t = tile_at<C>(g, bt.tile);
   for (int w = tid; w < C::kWords; w += T) {
     xa[w] = 0;
     xd[w] = 0;
@@ -318,12 +354,12 @@ k_tile_local(const float *__restrict__ f, Geo g, uint32_t *__restrict__ lp,
     fsum += in ? fv : 0.f;
     ptr[lz] = in ? (uint32_t)(i + omax) | ((uint32_t)(i + omin) << 16)
                  : (uint32_t)i | ((uint32_t)i << 16);
-    wave_count(in && omax == 0, ctr + kCtrMaxima);
-    wave_count(in && omin == 0, ctr + kCtrMinima);
+    wave_count(in && omax == 0, fc + kFMaxima);
+    wave_count(in && omin == 0, fc + kFMinima);
     below = cur;
     cur = above;
   }
-  wave_count(any_nan, ctr + kCtrNaN);
+  wave_count(any_nan, fc + kFNaN);
   for (int o = 32; o > 0; o >>= 1) fsum += __shfl_xor(fsum, o);
   if ((tid & 63) == 0) s_wsum[tid >> 6] = fsum;
   __syncthreads();  // every thread is done reading the field
@@ -387,6 +423,7 @@ k_tile_local(const float *__restrict__ f, Geo g, uint32_t *__restrict__ lp,
   // The stored local pointer: an owned target by its owned index, an exit
   // by its number (bit 15 set), so that later passes decode it with one
   // lookup in the tile's resolved exits.
+  uint32_t *__restrict__ lp = bt.fd.lp;
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz) {
     if (lz < nz) {
@@ -402,13 +439,13 @@ k_tile_local(const float *__restrict__ f, Geo g, uint32_t *__restrict__ lp,
     s_base = (na + nd) ? atomicAdd(ctr + kCtrExits,
                                    (unsigned long long)(na + nd))
                        : 0ull;
-    xo.seg[tile] = Seg{(uint32_t)s_base, (uint16_t)na, (uint16_t)nd};
+    xo.seg[bt.gt] = Seg{(uint32_t)s_base, (uint16_t)na, (uint16_t)nd};
     // Mean value of the tile: the order in which exits get resolved.
     float sum = 0.f;
     for (int w = 0; w < T / 64; ++w) sum += s_wsum[w];
     const int cnt = min(C::TX, (int)g.X - t.x0) * min(C::TY, (int)g.Y - t.y0) *
                     min(C::TZ, (int)g.Z - t.z0);
-    xo.tkey[tile] = float_key(sum / (float)cnt);
+    xo.tkey[bt.gt] = float_key(sum / (float)cnt);
   }
   __syncthreads();
   for (int k = 0; k < 2; ++k) {
@@ -417,8 +454,10 @@ k_tile_local(const float *__restrict__ f, Geo g, uint32_t *__restrict__ lp,
     while (bits) {
       const int b = __ffs(bits) - 1;
       bits &= bits - 1;
-      if (at < xo.cap)
+      if (at < xo.cap) {
         xo.list[at] = halo_global<C>(g, t, tid * 32 + b) | (k ? kTagDesc : 0u);
+        xo.lfield[at] = bt.fi;
+      }
       ++at;
     }
   }
@@ -446,23 +485,25 @@ __device__ __forceinline__ Tile tile_of_vertex(const Geo &g, uint32_t v,
 
 template <class C>
 __global__ void __launch_bounds__(kBlock)
-k_exit_link(const uint32_t *__restrict__ list, uint32_t count, Geo g,
-            const uint32_t *__restrict__ lp, const Seg *__restrict__ seg,
+k_exit_link(const uint32_t *__restrict__ list,
+            const uint32_t *__restrict__ lfield, uint32_t count,
+            const FieldDev *__restrict__ fds, const Seg *__restrict__ seg,
             uint32_t *__restrict__ next) {
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
   if (i >= count) return;
   const uint32_t e = list[i];
   const bool desc = e & kTagDesc;
   const uint32_t v = e & ~kTagDesc;
+  const FieldDev &fd = fds[lfield[i]];
   uint32_t u;
-  const Tile t = tile_of_vertex<C>(g, v, &u);
-  const uint32_t w = lp[v];
+  const Tile t = tile_of_vertex<C>(fd.g, v, &u);
+  const uint32_t w = fd.lp[v];
   const uint32_t code = desc ? (w >> 16) : (w & 0xffffu);
   if (code & kExitCode) {
-    const Seg sg = seg[u];
+    const Seg sg = seg[fd.tile0 + u];
     next[i] = sg.base + (desc ? sg.na : 0u) + (code & (kExitCode - 1));
   } else {
-    next[i] = kRoot | owned_global<C>(g, t, code);
+    next[i] = kRoot | owned_global<C>(fd.g, t, code);
   }
 }
 
@@ -489,7 +530,8 @@ k_key_minmax(const uint32_t *__restrict__ key, uint32_t n, uint32_t *mm) {
   }
 }
 
-__device__ __forceinline__ uint32_t key_bucket(uint32_t key, const uint32_t *mm) {
+__device__ __forceinline__ uint32_t key_bucket(uint32_t key,
+                                               const uint32_t *mm) {
   const uint64_t span = (uint64_t)mm[1] - mm[0] + 1;
   const uint64_t b = ((uint64_t)(key - mm[0]) * kTileBuckets) / span;
   return b < kTileBuckets ? (uint32_t)b : kTileBuckets - 1;
@@ -578,9 +620,10 @@ struct Decode {
 };
 
 template <class C>
-__device__ __forceinline__ void decode_setup(Decode<C> &s, uint32_t tile,
-                                             const Seg *seg, const uint32_t *R) {
-  const Seg sg = seg[tile];
+__device__ __forceinline__ void decode_setup(Decode<C> &s, uint32_t gt,
+                                             const Seg *seg,
+                                             const uint32_t *R) {
+  const Seg sg = seg[gt];
   const uint32_t n = (uint32_t)sg.na + sg.nd;
   for (uint32_t k = threadIdx.x; k < n; k += C::kThreads)
     s.res[k] = (int32_t)(R[sg.base + k] & ~kRoot);
@@ -599,8 +642,8 @@ __device__ __forceinline__ int32_t decode_final(const Decode<C> &s,
 }
 
 __global__ void k_table_clear(unsigned long long *keys, int32_t *vals,
-                              uint32_t cap) {
-  uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+                              uint64_t cap) {
+  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i < cap) {
     keys[i] = kEmptyKey;
     vals[i] = INT32_MAX;
@@ -708,15 +751,18 @@ __device__ __forceinline__ int32_t table_lookup(
 
 template <class C>
 __global__ void __launch_bounds__(C::kThreads)
-k_tile_pairs(Geo g, const uint32_t *__restrict__ lp, const Seg *__restrict__ seg,
-             const uint32_t *__restrict__ R, unsigned long long *keys,
-             int32_t *vals, uint32_t mask, unsigned long long *ctr) {
+k_tile_pairs(const FieldDev *__restrict__ fds,
+             const uint32_t *__restrict__ tfield, const Seg *__restrict__ seg,
+             const uint32_t *__restrict__ R, unsigned long long *ctr,
+             unsigned long long *fctr) {
   __shared__ Decode<C> s;
   __shared__ unsigned long long skey[kPairSlots];
   __shared__ int32_t sval[kPairSlots];
   const int tid = threadIdx.x;
-  const uint32_t tile = tile_of_block(blockIdx.x, gridDim.x);
-  const Tile t = tile_at<C>(g, tile);
+  const BlockTile bt = block_tile(fds, tfield);
+  if (!bt.fd.ms) return;
+  const Geo &g = bt.fd.g;
+  const Tile t = tile_at<C>(g, bt.tile);
   for (int i = tid; i < kPairSlots; i += C::kThreads) {
     skey[i] = kEmptyKey;
     sval[i] = INT32_MAX;
@@ -729,10 +775,10 @@ k_tile_pairs(Geo g, const uint32_t *__restrict__ lp, const Seg *__restrict__ seg
   uint32_t code[C::TZ];
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz)
-    code[lz] = lz < nz ? lp[(uint32_t)gx + g.X * (uint32_t)gy +
-                            g.XY * (uint32_t)(t.z0 + lz)]
+    code[lz] = lz < nz ? bt.fd.lp[(uint32_t)gx + g.X * (uint32_t)gy +
+                                  g.XY * (uint32_t)(t.z0 + lz)]
                        : 0u;
-  decode_setup<C>(s, tile, seg, R);
+  decode_setup<C>(s, bt.gt, seg, R);
 
   unsigned fresh = 0;
   bool overflow = false;
@@ -746,33 +792,38 @@ k_tile_pairs(Geo g, const uint32_t *__restrict__ lp, const Seg *__restrict__ seg
     const int32_t id = (int32_t)((uint32_t)gx + g.X * (uint32_t)gy +
                                  g.XY * (uint32_t)(t.z0 + lz));
     const int slot = wave_pair_slot(skey, sval, in, key, id);
-    if (in && slot < 0 && !table_insert(keys, vals, mask, key, id, &fresh))
+    if (in && slot < 0 &&
+        !table_insert(bt.fd.keys, bt.fd.vals, bt.fd.mask, key, id, &fresh))
       overflow = true;
   }
   __syncthreads();
   for (int i = tid; i < kPairSlots; i += C::kThreads) {
     if (skey[i] != kEmptyKey &&
-        !table_insert(keys, vals, mask, skey[i], sval[i], &fresh))
+        !table_insert(bt.fd.keys, bt.fd.vals, bt.fd.mask, skey[i], sval[i],
+                      &fresh))
       overflow = true;
   }
-  if (fresh) atomicAdd(ctr + kCtrCells, (unsigned long long)fresh);
+  if (fresh)
+    atomicAdd(fctr + (size_t)bt.fi * kFieldCtrs + kFCells,
+              (unsigned long long)fresh);
   if (overflow) atomicOr(ctr + kCtrOverflow, 1ull);
 }
 
 template <class C>
 __global__ void __launch_bounds__(C::kThreads)
-k_tile_write(Geo g, const uint32_t *__restrict__ lp, const Seg *__restrict__ seg,
-             const uint32_t *__restrict__ R, int32_t *__restrict__ A,
-             int32_t *__restrict__ D,
-             const unsigned long long *__restrict__ keys,
-             const int32_t *__restrict__ vals, uint32_t mask,
-             int32_t *__restrict__ ms) {
+k_tile_write(const FieldDev *__restrict__ fds,
+             const uint32_t *__restrict__ tfield, const Seg *__restrict__ seg,
+             const uint32_t *__restrict__ R) {
   __shared__ Decode<C> s;
   __shared__ unsigned long long skey[kPairSlots];
   __shared__ int32_t scell[kPairSlots];
   const int tid = threadIdx.x;
-  const uint32_t tile = tile_of_block(blockIdx.x, gridDim.x);
-  const Tile t = tile_at<C>(g, tile);
+  const BlockTile bt = block_tile(fds, tfield);
+  const Geo &g = bt.fd.g;
+  int32_t *__restrict__ A = bt.fd.A;
+  int32_t *__restrict__ D = bt.fd.D;
+  int32_t *__restrict__ ms = bt.fd.ms;
+  const Tile t = tile_at<C>(g, bt.tile);
   if (ms)
     for (int i = tid; i < kPairSlots; i += C::kThreads) skey[i] = kEmptyKey;
   const int cx = tid % C::TX, cy = tid / C::TX;
@@ -783,10 +834,10 @@ k_tile_write(Geo g, const uint32_t *__restrict__ lp, const Seg *__restrict__ seg
   uint32_t code[C::TZ];
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz)
-    code[lz] = lz < nz ? lp[(uint32_t)gx + g.X * (uint32_t)gy +
-                            g.XY * (uint32_t)(t.z0 + lz)]
+    code[lz] = lz < nz ? bt.fd.lp[(uint32_t)gx + g.X * (uint32_t)gy +
+                                  g.XY * (uint32_t)(t.z0 + lz)]
                        : 0u;
-  decode_setup<C>(s, tile, seg, R);
+  decode_setup<C>(s, bt.gt, seg, R);
 
   int16_t slot[C::TZ];
 #pragma unroll
@@ -802,14 +853,16 @@ k_tile_write(Geo g, const uint32_t *__restrict__ lp, const Seg *__restrict__ seg
       D[v] = d;
     }
     slot[lz] = -1;
-    if (ms) slot[lz] = (int16_t)wave_pair_slot(skey, nullptr, in, pair_key(a, d), 0);
+    if (ms)
+      slot[lz] = (int16_t)wave_pair_slot(skey, nullptr, in, pair_key(a, d), 0);
     if (ms && in && slot[lz] < 0)  // table full: look this vertex up alone
-      ms[v] = table_lookup(keys, vals, mask, pair_key(a, d));
+      ms[v] = table_lookup(bt.fd.keys, bt.fd.vals, bt.fd.mask, pair_key(a, d));
   }
-  if (!ms) return;
+  if (!ms) return;  // uniform over the block: ms belongs to the field
   __syncthreads();
   for (int i = tid; i < kPairSlots; i += C::kThreads)
-    if (skey[i] != kEmptyKey) scell[i] = table_lookup(keys, vals, mask, skey[i]);
+    if (skey[i] != kEmptyKey)
+      scell[i] = table_lookup(bt.fd.keys, bt.fd.vals, bt.fd.mask, skey[i]);
   __syncthreads();
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz) {
@@ -824,6 +877,12 @@ __global__ void k_fill_u32(uint32_t *p, uint32_t n, uint32_t value) {
   if (i < n) p[i] = value;
 }
 
+__global__ void k_fill_u64(unsigned long long *p, uint32_t n,
+                           unsigned long long value) {
+  uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = value;
+}
+
 uint32_t table_capacity(uint64_t n, uint64_t nmax, uint64_t nmin) {
   uint64_t bound = nmax * nmin;
   if (bound > n) bound = n;
@@ -832,83 +891,142 @@ uint32_t table_capacity(uint64_t n, uint64_t nmax, uint64_t nmin) {
   return (uint32_t)cap;
 }
 
+// Grow-only pinned host staging owned by the context.
+template <class T>
+int stage(msc_ctx *ctx, size_t count, T **out) {
+  const size_t bytes = count * sizeof(T);
+  if (bytes > ctx->pinned_bytes) {
+    if (ctx->pinned) (void)hipHostFree(ctx->pinned);
+    ctx->pinned = nullptr;
+    ctx->pinned_bytes = 0;
+    const size_t want = bytes + bytes / 4 + 4096;
+    if (hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault) != hipSuccess)
+      return MSC_ENOMEM;
+    ctx->pinned_bytes = want;
+  }
+  *out = static_cast<T *>(ctx->pinned);
+  return MSC_OK;
+}
+
 template <class C>
-int segment_tiles(msc_ctx *ctx, const float *f, int64_t X, int64_t Y,
-                  int64_t Z, int32_t *asc, int32_t *desc, int32_t *ms,
+int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
                   hipStream_t s) {
-  const int64_t n = X * Y * Z;
-  Geo g{};
-  g.X = (uint32_t)X;
-  g.Y = (uint32_t)Y;
-  g.Z = (uint32_t)Z;
-  g.XY = (uint32_t)(X * Y);
-  g.N = (uint32_t)n;
-  g.ntx = (uint32_t)((X + C::TX - 1) / C::TX);
-  g.nty = (uint32_t)((Y + C::TY - 1) / C::TY);
-  g.ntz = (uint32_t)((Z + C::TZ - 1) / C::TZ);
-  const int64_t ntiles = (int64_t)g.ntx * g.nty * g.ntz;
-  if (ntiles > INT32_MAX) return MSC_ERANGE;
-  g.ntiles = (uint32_t)ntiles;
+  // Geometry, tile ranges and workspace layout of every field.
+  std::vector<FieldDev> fd(nfields);
+  uint64_t total_tiles = 0, total_n = 0;
+  size_t need_lp = 0, need_scratch = 0;
+  for (int i = 0; i < nfields; ++i) {
+    const int64_t X = fields[i].dims[0], Y = fields[i].dims[1],
+                  Z = fields[i].dims[2];
+    Geo &g = fd[i].g;
+    g.X = (uint32_t)X;
+    g.Y = (uint32_t)Y;
+    g.Z = (uint32_t)Z;
+    g.XY = (uint32_t)(X * Y);
+    g.N = (uint32_t)(X * Y * Z);
+    g.ntx = (uint32_t)((X + C::TX - 1) / C::TX);
+    g.nty = (uint32_t)((Y + C::TY - 1) / C::TY);
+    g.ntz = (uint32_t)((Z + C::TZ - 1) / C::TZ);
+    const uint64_t nt = (uint64_t)g.ntx * g.nty * g.ntz;
+    g.ntiles = (uint32_t)nt;
+    fd[i].tile0 = (uint32_t)total_tiles;
+    total_tiles += nt;
+    total_n += g.N;
+    need_lp += align256((size_t)g.N * sizeof(uint32_t));
+    if (!fields[i].asc) need_scratch += align256((size_t)g.N * sizeof(int32_t));
+    if (!fields[i].desc) need_scratch += align256((size_t)g.N * sizeof(int32_t));
+    if (total_tiles > INT32_MAX / 2) return MSC_ERANGE;
+  }
+  const uint32_t nt = (uint32_t)total_tiles;
   unsigned long long *ctr = ctx->dctr;
 
-  // Workspace: packed tile-local pointer codes, per-tile exit segments, the
-  // exit list and its graph (grown if a run overflows it), and full-size
-  // arrays the caller did not ask for.
   uint64_t exit_cap = ctx->exit_cap_hint;
   if (exit_cap < 4096) exit_cap = 4096;
-  if (exit_cap < (uint64_t)n / 8) exit_cap = (uint64_t)n / 8;
+  if (exit_cap < total_n / 8) exit_cap = total_n / 8;
   if (exit_cap > kRoot - 1) exit_cap = kRoot - 1;
   uint64_t exits = 0;
-  uint32_t *lp = nullptr, *list = nullptr, *next = nullptr;
+  uint32_t *list = nullptr, *lfield = nullptr, *next = nullptr;
   uint32_t *tkey = nullptr, *torder = nullptr, *hist = nullptr, *mm = nullptr;
+  uint32_t *tfield = nullptr;
+  unsigned long long *fctr = nullptr;
+  FieldDev *fds = nullptr;
   Seg *seg = nullptr;
-  int32_t *A = asc, *D = desc;
+  std::vector<uint32_t> tf_host(nt);
+  for (int i = 0; i < nfields; ++i)
+    for (uint32_t k = 0; k < fd[i].g.ntiles; ++k) tf_host[fd[i].tile0 + k] = i;
+
   for (int attempt = 0;; ++attempt) {
-    size_t need = align256(n * sizeof(uint32_t)) +
-                  2 * align256(exit_cap * sizeof(uint32_t)) +
-                  align256(ntiles * sizeof(Seg)) +
-                  2 * align256(ntiles * sizeof(uint32_t)) +
-                  align256((kTileBuckets + 2) * sizeof(uint32_t)) + 4096;
-    if (!asc) need += align256(n * sizeof(int32_t));
-    if (!desc) need += align256(n * sizeof(int32_t));
+    const size_t need =
+        need_lp + need_scratch + 3 * align256(exit_cap * sizeof(uint32_t)) +
+        align256(nt * sizeof(Seg)) + 3 * align256(nt * sizeof(uint32_t)) +
+        align256((kTileBuckets + 2) * sizeof(uint32_t)) +
+        align256(nfields * sizeof(FieldDev)) +
+        align256(nfields * kFieldCtrs * sizeof(unsigned long long)) + 8192;
     MSC_TRY(reserve(ctx->ws, need));
     Carver cv(ctx->ws);
-    lp = cv.take<uint32_t>(n);
+    for (int i = 0; i < nfields; ++i) {
+      fd[i].f = fields[i].field;
+      fd[i].lp = cv.take<uint32_t>(fd[i].g.N);
+      fd[i].A = fields[i].asc ? fields[i].asc : cv.take<int32_t>(fd[i].g.N);
+      fd[i].D = fields[i].desc ? fields[i].desc : cv.take<int32_t>(fd[i].g.N);
+      fd[i].ms = fields[i].ms;
+      fd[i].keys = nullptr;
+      fd[i].vals = nullptr;
+      fd[i].mask = 0;
+    }
     list = cv.take<uint32_t>(exit_cap);
+    lfield = cv.take<uint32_t>(exit_cap);
     next = cv.take<uint32_t>(exit_cap);
-    seg = cv.take<Seg>(ntiles);
-    tkey = cv.take<uint32_t>(ntiles);
-    torder = cv.take<uint32_t>(ntiles);
+    seg = cv.take<Seg>(nt);
+    tkey = cv.take<uint32_t>(nt);
+    torder = cv.take<uint32_t>(nt);
+    tfield = cv.take<uint32_t>(nt);
     hist = cv.take<uint32_t>(kTileBuckets + 2);
     mm = hist + kTileBuckets;
-    A = asc ? asc : cv.take<int32_t>(n);
-    D = desc ? desc : cv.take<int32_t>(n);
+    fds = cv.take<FieldDev>(nfields);
+    fctr = cv.take<unsigned long long>((size_t)nfields * kFieldCtrs);
 
+    // Descriptors and the tile -> field map go up through pinned staging.
+    char *st = nullptr;
+    const size_t fbytes = nfields * sizeof(FieldDev), tbytes = nt * 4ull;
+    MSC_TRY(stage(ctx, fbytes + tbytes, &st));
+    std::memcpy(st, fd.data(), fbytes);
+    std::memcpy(st + fbytes, tf_host.data(), tbytes);
+    MSC_HIP_TRY(hipMemcpyAsync(fds, st, fbytes, hipMemcpyHostToDevice, s));
+    MSC_HIP_TRY(hipMemcpyAsync(tfield, st + fbytes, tbytes,
+                               hipMemcpyHostToDevice, s));
     MSC_TRY(clear_counters(ctx, s));
+    k_fill_u64<<<grid_for((uint64_t)nfields * kFieldCtrs), kBlock, 0, s>>>(
+        fctr, (uint32_t)(nfields * kFieldCtrs), 0ull);
     k_fill_u32<<<grid_for(kTileBuckets + 2), kBlock, 0, s>>>(
         hist, kTileBuckets + 2, 0u);
     k_fill_u32<<<1, kBlock, 0, s>>>(mm, 1, ~0u);
     MSC_HIP_TRY(hipGetLastError());
-    ExitOut xo{list, seg, tkey, (uint32_t)exit_cap};
-    MSC_PHASE(ctx, s, "tile_local", 8.0 * n,
-              (k_tile_local<C><<<g.ntiles, C::kThreads, 0, s>>>(f, g, lp, xo,
-                                                                ctr)));
+    ExitOut xo{list, lfield, seg, tkey, (uint32_t)exit_cap};
+    MSC_PHASE(ctx, s, "tile_local", 8.0 * total_n,
+              (k_tile_local<C><<<nt, C::kThreads, 0, s>>>(fds, tfield, xo, ctr,
+                                                          fctr)));
     MSC_TRY(read_counters(ctx, s));
-    if (ctx->hctr[kCtrNaN]) return MSC_ENAN;
     exits = ctx->hctr[kCtrExits];
     if (exits <= exit_cap) break;
     if (attempt > 0 || exits >= kRoot) return MSC_ENOMEM;
     exit_cap = exits + exits / 4;
   }
   ctx->exit_cap_hint = exit_cap;
-  const uint64_t nmax = ctx->hctr[kCtrMaxima], nmin = ctx->hctr[kCtrMinima];
+
+  // Per-field counters: NaN check and table sizes.
+  std::vector<unsigned long long> fc((size_t)nfields * kFieldCtrs);
+  MSC_HIP_TRY(hipMemcpyAsync(fc.data(), fctr, fc.size() * 8,
+                             hipMemcpyDeviceToHost, s));
+  MSC_HIP_TRY(hipStreamSynchronize(s));
+  for (int i = 0; i < nfields; ++i)
+    if (fc[(size_t)i * kFieldCtrs + kFNaN]) return MSC_ENAN;
 
   if (exits) {
     const uint32_t ne = (uint32_t)exits;
-    MSC_PHASE(ctx, s, "exit_link", 14.0 * ne,
-              (k_exit_link<C><<<grid_for(ne), kBlock, 0, s>>>(list, ne, g, lp,
-                                                              seg, next)));
-    const unsigned nt = (unsigned)g.ntiles;
+    MSC_PHASE(ctx, s, "exit_link", 18.0 * ne,
+              (k_exit_link<C><<<grid_for(ne), kBlock, 0, s>>>(
+                  list, lfield, ne, fds, seg, next)));
     MSC_PHASE(ctx, s, "tile_order", 12.0 * nt,
               (k_key_minmax<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm),
                k_key_hist<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm, hist),
@@ -920,35 +1038,70 @@ int segment_tiles(msc_ctx *ctx, const float *f, int64_t X, int64_t Y,
                   torder, nt, seg, ne, next, ctr)));
   }
 
-  unsigned long long *keys = nullptr;
-  int32_t *vals = nullptr;
-  uint32_t cap = 0;
-  if (ms) {
-    cap = table_capacity(n, nmax, nmin);
-    size_t tbytes = align256((size_t)cap * 8) + align256((size_t)cap * 4);
-    MSC_TRY(reserve(ctx->tab, tbytes + 4096));
-    Carver tc(ctx->tab);
-    keys = tc.take<unsigned long long>(cap);
-    vals = tc.take<int32_t>(cap);
-    MSC_PHASE(ctx, s, "table_clear", 12.0 * cap,
-              (k_table_clear<<<grid_for(cap), kBlock, 0, s>>>(keys, vals,
-                                                              cap)));
-    MSC_PHASE(ctx, s, "tile_pairs", 4.0 * n,
-              (k_tile_pairs<C><<<g.ntiles, C::kThreads, 0, s>>>(
-                  g, lp, seg, next, keys, vals, cap - 1, ctr)));
+  // Pair tables of the fields that want cells, in one block of `tab`.
+  uint64_t total_cap = 0;
+  std::vector<uint64_t> off(nfields, 0);
+  for (int i = 0; i < nfields; ++i) {
+    if (!fields[i].ms) continue;
+    off[i] = total_cap;
+    total_cap += table_capacity(fd[i].g.N, fc[(size_t)i * kFieldCtrs + kFMaxima],
+                                fc[(size_t)i * kFieldCtrs + kFMinima]);
   }
-  MSC_PHASE(ctx, s, "tile_write", (ms ? 16.0 : 12.0) * n,
-            (k_tile_write<C><<<g.ntiles, C::kThreads, 0, s>>>(
-                g, lp, seg, next, A, D, keys, vals, cap ? cap - 1 : 0, ms)));
+  bool any_ms = total_cap > 0;
+  if (any_ms) {
+    MSC_TRY(reserve(ctx->tab, align256(total_cap * 8) + align256(total_cap * 4) +
+                                  4096));
+    Carver tc(ctx->tab);
+    unsigned long long *keys = tc.take<unsigned long long>(total_cap);
+    int32_t *vals = tc.take<int32_t>(total_cap);
+    for (int i = 0; i < nfields; ++i) {
+      if (!fields[i].ms) continue;
+      fd[i].keys = keys + off[i];
+      fd[i].vals = vals + off[i];
+      fd[i].mask = table_capacity(fd[i].g.N,
+                                  fc[(size_t)i * kFieldCtrs + kFMaxima],
+                                  fc[(size_t)i * kFieldCtrs + kFMinima]) - 1;
+    }
+    char *st = nullptr;
+    MSC_TRY(stage(ctx, nfields * sizeof(FieldDev), &st));
+    std::memcpy(st, fd.data(), nfields * sizeof(FieldDev));
+    MSC_HIP_TRY(hipMemcpyAsync(fds, st, nfields * sizeof(FieldDev),
+                               hipMemcpyHostToDevice, s));
+    MSC_PHASE(ctx, s, "table_clear", 12.0 * total_cap,
+              (k_table_clear<<<(unsigned)((total_cap + kBlock - 1) / kBlock),
+                               kBlock, 0, s>>>(keys, vals, total_cap)));
+    MSC_PHASE(ctx, s, "tile_pairs", 4.0 * total_n,
+              (k_tile_pairs<C><<<nt, C::kThreads, 0, s>>>(fds, tfield, seg,
+                                                          next, ctr, fctr)));
+  }
+  MSC_PHASE(ctx, s, "tile_write", (any_ms ? 16.0 : 12.0) * total_n,
+            (k_tile_write<C><<<nt, C::kThreads, 0, s>>>(fds, tfield, seg,
+                                                        next)));
   MSC_TRY(read_counters(ctx, s));
   if (ctx->hctr[kCtrOverflow] & 2) return MSC_EHIP;
   if (ctx->hctr[kCtrOverflow]) return MSC_ENOMEM;
+  MSC_HIP_TRY(hipMemcpyAsync(fc.data(), fctr, fc.size() * 8,
+                             hipMemcpyDeviceToHost, s));
+  MSC_HIP_TRY(hipStreamSynchronize(s));
 
   ctx->stats = msc_stats{};
-  ctx->stats.n_vertices = n;
-  ctx->stats.n_maxima = (int64_t)nmax;
-  ctx->stats.n_minima = (int64_t)nmin;
-  ctx->stats.n_cells = ms ? (int64_t)ctx->hctr[kCtrCells] : -1;
+  ctx->field_stats.assign(nfields, msc_stats{});
+  for (int i = 0; i < nfields; ++i) {
+    msc_stats &st = ctx->field_stats[i];
+    st.n_vertices = fd[i].g.N;
+    st.n_maxima = (int64_t)fc[(size_t)i * kFieldCtrs + kFMaxima];
+    st.n_minima = (int64_t)fc[(size_t)i * kFieldCtrs + kFMinima];
+    st.n_cells =
+        fields[i].ms ? (int64_t)fc[(size_t)i * kFieldCtrs + kFCells] : -1;
+    st.tile_x = C::TX;
+    st.tile_y = C::TY;
+    st.tile_z = C::TZ;
+    ctx->stats.n_vertices += st.n_vertices;
+    ctx->stats.n_maxima += st.n_maxima;
+    ctx->stats.n_minima += st.n_minima;
+    ctx->stats.n_cells += st.n_cells > 0 ? st.n_cells : 0;
+  }
+  if (nfields == 1) ctx->stats.n_cells = ctx->field_stats[0].n_cells;
   ctx->stats.n_exits = (int64_t)exits;
   ctx->stats.jump_rounds = (int32_t)ctx->hctr[kCtrRounds];
   ctx->stats.tile_x = C::TX;
@@ -966,19 +1119,19 @@ using Tile64x8x8 = Cfg<64, 8, 8>;
 
 }  // namespace
 
-int segment_run(msc_ctx *ctx, const float *f, int64_t X, int64_t Y, int64_t Z,
-                int32_t *asc, int32_t *desc, int32_t *ms, hipStream_t s) {
+int segment_batch_run(msc_ctx *ctx, int nfields, const msc_field *fields,
+                      hipStream_t s) {
   switch (ctx->tile_choice) {
     case 1:
-      return segment_tiles<Tile32x16x16>(ctx, f, X, Y, Z, asc, desc, ms, s);
+      return segment_batch<Tile32x16x16>(ctx, nfields, fields, s);
     case 2:
-      return segment_tiles<Tile32x8x8>(ctx, f, X, Y, Z, asc, desc, ms, s);
+      return segment_batch<Tile32x8x8>(ctx, nfields, fields, s);
     case 3:
-      return segment_tiles<Tile64x16x16>(ctx, f, X, Y, Z, asc, desc, ms, s);
+      return segment_batch<Tile64x16x16>(ctx, nfields, fields, s);
     case 4:
-      return segment_tiles<Tile64x8x8>(ctx, f, X, Y, Z, asc, desc, ms, s);
+      return segment_batch<Tile64x8x8>(ctx, nfields, fields, s);
     default:
-      return segment_tiles<Tile32x32x16>(ctx, f, X, Y, Z, asc, desc, ms, s);
+      return segment_batch<Tile32x32x16>(ctx, nfields, fields, s);
   }
 }
 

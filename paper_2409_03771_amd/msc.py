@@ -45,12 +45,26 @@ class msc_phase(ctypes.Structure):
                 ("total_ms", ctypes.c_double), ("bytes", ctypes.c_double)]
 
 
+class msc_field(ctypes.Structure):
+    _fields_ = [("field", _P), ("dims", _I64 * 3), ("asc", _P), ("desc", _P),
+                ("ms", _P)]
+
+
+class msc_tune(ctypes.Structure):
+    _fields_ = [("best", _I32), ("tile", _I32 * 3), ("n_shapes", _I32),
+                ("ms", ctypes.c_float * 8)]
+
+
 _SIGS = {
     "msc_strerror": ([_I32], ctypes.c_char_p),
     "msc_create": ([ctypes.POINTER(_P), _I32], _I32),
     "msc_destroy": ([_P], None),
     "msc_segment": ([_P, _P, ctypes.POINTER(_I64), _P, _P, _P, _P], _I32),
     "msc_last_stats": ([_P, ctypes.POINTER(msc_stats)], _I32),
+    "msc_segment_batched": ([_P, _I32, ctypes.POINTER(msc_field), _P], _I32),
+    "msc_last_field_stats": ([_P, _I32, ctypes.POINTER(msc_stats)], _I32),
+    "msc_autotune": ([_P, _I32, ctypes.POINTER(msc_field), _P,
+                      ctypes.POINTER(msc_tune)], _I32),
     "msc_tile_shapes": ([ctypes.POINTER(_I32), _I32], _I32),
     "msc_set_tile": ([_P, _I32, _I32, _I32], _I32),
     "msc_profile": ([_P, _I32], _I32),
@@ -153,6 +167,67 @@ def segment(field: torch.Tensor, want=("asc", "desc", "ms"), stream=None):
                if k in want else None) for k in ("asc", "desc", "ms")}
     segment_into(field, out["asc"], out["desc"], out["ms"], stream=stream)
     return out["asc"], out["desc"], out["ms"]
+
+
+def _field_array(fields, outs, dims_list):
+    arr = (msc_field * len(fields))()
+    for i, (f, (a, d, m), dims) in enumerate(zip(fields, outs, dims_list)):
+        arr[i].field = _dev_ptr(f, torch.float32, f"fields[{i}]")
+        for k in range(3):
+            arr[i].dims[k] = int(dims[k])
+        arr[i].asc = _dev_ptr(a, torch.int32, "asc")
+        arr[i].desc = _dev_ptr(d, torch.int32, "desc")
+        arr[i].ms = _dev_ptr(m, torch.int32, "ms")
+    return arr
+
+
+def _batch_outputs(fields, want):
+    return [tuple(torch.empty(f.numel(), dtype=torch.int32, device=f.device)
+                  if k in want else None for k in ("asc", "desc", "ms"))
+            for f in fields]
+
+
+def segment_batched_into(fields, outs, dims=None, stream=None):
+    """Segment several fields in one set of launches; `outs` holds an
+    (asc, desc, ms) tuple of int32 tensors (or None) per field."""
+    if not fields:
+        return
+    dims = dims or [grid_dims(f.shape) for f in fields]
+    arr = _field_array(fields, outs, dims)
+    code = _lib.msc_segment_batched(context(fields[0].device.index),
+                                    len(fields), arr,
+                                    _stream(fields[0], stream))
+    _check(code, "msc_segment_batched")
+
+
+def segment_batched(fields, want=("asc", "desc", "ms"), stream=None):
+    """Batched segmentation of a list of float32 fields (any shapes).
+    Returns one (asc, desc, ms) tuple per field."""
+    outs = _batch_outputs(fields, want)
+    segment_batched_into(fields, outs, stream=stream)
+    return outs
+
+
+def last_field_stats(index: int, device: int | None = None) -> dict:
+    s = msc_stats()
+    _check(_lib.msc_last_field_stats(context(device), int(index),
+                                     ctypes.byref(s)), "msc_last_field_stats")
+    return {k: getattr(s, k) for k, _ in msc_stats._fields_}
+
+
+def autotune(fields, outs=None, stream=None) -> dict:
+    """Time every compiled tile shape on this batch, keep the fastest for
+    the device's context; returns {"tile", "best", "ms": {shape: ms}}."""
+    outs = outs or _batch_outputs(fields, ("asc", "desc", "ms"))
+    dims = [grid_dims(f.shape) for f in fields]
+    arr = _field_array(fields, outs, dims)
+    t = msc_tune()
+    _check(_lib.msc_autotune(context(fields[0].device.index), len(fields), arr,
+                             _stream(fields[0], stream), ctypes.byref(t)),
+           "msc_autotune")
+    shapes = tile_shapes()
+    return {"tile": tuple(t.tile), "best": t.best,
+            "ms": {shapes[i]: t.ms[i] for i in range(t.n_shapes)}}
 
 
 def last_stats(device: int | None = None) -> dict:
