@@ -112,16 +112,168 @@ def bench_batch(args, msc, synth, torch, dev):
     print(json.dumps(out), flush=True)
 
 
+SERVE_TEXT = ("served: open-loop Poisson arrivals (seed 4), 70% MS segmentation"
+              " / 30% mask CC (mask above the 70th percentile), each axis "
+              "round(exp(U[ln64, ln512])), Gaussian sums with U{{8..128}} bumps; "
+              "inputs from a pool of {pool} pre-generated page-locked host "
+              "fields (request i uses entry i mod {pool}); H2D copy counted in "
+              "latency (arrival -> results resident on the device); "
+              "{budget} GiB HBM budget, at most {max_batch} fields per launch")
+
+
+def serve_pool(synth, torch, dev, size):
+    """Page-locked host inputs: a float32 field and its mask per entry."""
+    import numpy as np
+    pool = []
+    for spec in synth.poisson_trace(1.0, size, seed=4):
+        f = synth.gaussian_field(spec["dims"], spec["nbumps"], spec["seed"],
+                                 device=dev).cpu().numpy()
+        fh = torch.from_numpy(f).pin_memory()
+        mh = torch.from_numpy(synth.threshold_mask(f, 0.7)).pin_memory()
+        pool.append((fh, mh))
+    return pool
+
+
+def _percentiles(lat_ms):
+    import numpy as np
+    a = np.asarray(lat_ms)
+    return round(float(np.percentile(a, 50)), 3), round(float(np.percentile(a, 99)), 3)
+
+
+def run_served(msc, pool, trace, warm, budget, max_batch):
+    """Open loop through the request queue: a submitter thread at the trace's
+    arrival times, this thread collecting and releasing results in order."""
+    import queue
+    import threading
+    srv = msc.Server(hbm_budget=budget, max_batch=max_batch)
+    handoff = queue.Queue()
+    t0 = time.monotonic_ns() + 20_000_000
+
+    def submitter():
+        for i, req in enumerate(trace):
+            at = t0 + int(req["t"] * 1e9)
+            dt = (at - time.monotonic_ns()) / 1e9
+            if dt > 0:
+                time.sleep(dt)
+            fh, mh = pool[i % len(pool)]
+            kind = msc.REQ_SEGMENT if req["kind"] == "ms" else msc.REQ_CC_GRID
+            t = srv.submit(kind, fh if kind == msc.REQ_SEGMENT else mh)
+            handoff.put((t, at, fh.numel()))
+        handoff.put(None)
+
+    th = threading.Thread(target=submitter)
+    th.start()
+    lat, verts, first, last, batches, k = [], 0, None, 0, [], 0
+    while True:
+        item = handoff.get()
+        if item is None:
+            break
+        t, at, n = item
+        rc = srv.wait(t)
+        if rc != msc.MSC_OK:
+            raise msc.MscError(rc, f"served request {k}")
+        r = srv.result(t)
+        srv.release(t)
+        if k >= warm:
+            lat.append((r["t_done_ns"] - at) / 1e6)
+            verts += n
+            first = at if first is None else first
+            last = max(last, r["t_done_ns"])
+            batches.append(r["batch_size"])
+        k += 1
+    th.join()
+    srv.close()
+    p50, p99 = _percentiles(lat)
+    return {"p50_ms": p50, "p99_ms": p99,
+            "gvps": round(verts / ((last - first) / 1e9) / 1e9, 3),
+            "mean_batch": round(sum(batches) / len(batches), 2)}
+
+
+def run_plain(msc, torch, dev, pool, trace, warm):
+    """The same trace served one request at a time in arrival order: copy the
+    input to the device, one plain call, wait for it."""
+    stream = torch.cuda.current_stream(dev)
+    t0 = time.monotonic_ns() + 20_000_000
+    lat, verts, first, last = [], 0, None, 0
+    for i, req in enumerate(trace):
+        at = t0 + int(req["t"] * 1e9)
+        dt = (at - time.monotonic_ns()) / 1e9
+        if dt > 0:
+            time.sleep(dt)
+        fh, mh = pool[i % len(pool)]
+        if req["kind"] == "ms":
+            f = fh.to(dev, non_blocking=True)
+            a = torch.empty(f.numel(), dtype=torch.int32, device=dev)
+            d, m = torch.empty_like(a), torch.empty_like(a)
+            msc.segment_into(f, a, d, m, stream=stream)
+        else:
+            msc.cc_label_grid(mh.to(dev, non_blocking=True), stream=stream)
+        torch.cuda.synchronize()
+        done = time.monotonic_ns()
+        if i >= warm:
+            lat.append((done - at) / 1e6)
+            verts += fh.numel()
+            first = at if first is None else first
+            last = done
+    p50, p99 = _percentiles(lat)
+    return {"p50_ms": p50, "p99_ms": p99,
+            "gvps": round(verts / ((last - first) / 1e9) / 1e9, 3)}
+
+
+def served_sweep(msc, synth, torch, dev, rates, warm, count, pool_size,
+                 budget_gib=64, max_batch=64):
+    log(f"[bench] serve pool of {pool_size} fields")
+    pool = serve_pool(synth, torch, dev, pool_size)
+    out = {}
+    for rate in rates:
+        trace = synth.poisson_trace(float(rate), warm + count, seed=4)
+        srv = run_served(msc, pool, trace, warm, budget_gib << 30, max_batch)
+        plain = run_plain(msc, torch, dev, pool, trace, warm)
+        log(f"[bench] {rate:5d} req/s served {srv} plain {plain}")
+        out[str(rate)] = {**srv, "plain_p50_ms": plain["p50_ms"],
+                          "plain_p99_ms": plain["p99_ms"],
+                          "plain_gvps": plain["gvps"]}
+    text = SERVE_TEXT.format(pool=pool_size, budget=budget_gib,
+                             max_batch=max_batch)
+    return text, out
+
+
+def bench_serve(args, msc, synth, torch, dev):
+    rates = [int(r) for r in args.rates.split(",")]
+    text, res = served_sweep(msc, synth, torch, dev, rates, args.serve_warmup,
+                             args.serve_requests, args.serve_pool)
+    top = res[str(rates[-1])]
+    out = {
+        "metric": "Gvertices/s served MS segmentation + mask CC; "
+                  "p50/p99 latency",
+        "value": top["gvps"], "unit": "Gvertices/s", "n_gpus": 1,
+        "steps": args.serve_requests, "warmup": args.serve_warmup,
+        "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": text, "requests_per_rate": args.serve_requests,
+                   "rates": res,
+                   "speedup_vs_plain": round(top["gvps"] / top["plain_gvps"], 2)},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="gauss1024",
-                    choices=sorted(WORKLOAD_TEXT) + ["batch256"])
+                    choices=sorted(WORKLOAD_TEXT) + ["batch256", "serve"])
     ap.add_argument("--cpu-depth", type=int, default=40,
                     help="z-planes of the field the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--rates", default="50,100,200,500,1000,2000",
+                    help="served mode: arrival rates (req/s)")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--serve-warmup", type=int, default=100)
+    ap.add_argument("--serve-pool", type=int, default=48)
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the short served leg of the default run")
     ap.add_argument("--tile", default=None,
                     help="tile shape of the fused pass, e.g. 32x16x16")
     ap.add_argument("--calibrate-copy", type=float, default=None,
@@ -157,6 +309,8 @@ def main():
 
     if args.workload == "batch256":
         return bench_batch(args, msc, synth, torch, dev)
+    if args.workload == "serve":
+        return bench_serve(args, msc, synth, torch, dev)
 
     log(f"[bench] generating {args.workload} on {dev}")
     t0 = time.perf_counter()
@@ -221,6 +375,14 @@ def main():
         depth = min(args.cpu_depth, field.shape[0])
         log(f"[bench] timing the CPU oracle on {depth} z-planes")
         out["cpu_baseline"] = cpu_baseline(field, depth)
+    if not args.no_serve:
+        # Short served leg: one light and one saturating arrival rate.
+        del field, asc, desc, ms
+        torch.cuda.empty_cache()
+        text, res = served_sweep(msc, synth, torch, dev, [200, 2000], 50, 300,
+                                 24)
+        out["served"] = {"workload": text, "requests_per_rate": 300,
+                         "rates": res}
     print(json.dumps(out), flush=True)
 
 

@@ -238,6 +238,87 @@ MSC_API int cc_label_csr(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,
 MSC_API int msc_pointer_jump(msc_ctx *ctx, int64_t *d, int64_t n, int rounds,
                      int synchronous, void *stream);
 
+/*
+ * Serving: a request queue with continuous batching.
+ *
+ * A queue reserves `hbm_budget` bytes of device memory as an arena for
+ * request-resident buffers (each request's input and outputs) and admits
+ * requests in arrival order while the arena holds their buffers and the
+ * resident bytes plus an estimate of the workspace of every admitted,
+ * unfinished request (8 bytes per vertex for a segmentation, 2 for a CC)
+ * stay within the budget.  That workspace is held by the queue's two
+ * library contexts outside the arena; it grows to the largest launch and is
+ * kept until msc_queue_destroy.  Admitted inputs are copied to the device
+ * on a copy stream; segmentation requests that are staged while a launch is
+ * running all join the next launch (one msc_segment_batched call of at most
+ * `max_batch` fields), and mask-CC requests run on their own stream, so the
+ * two kinds overlap on the device.  Results stay on the device until
+ * msc_release; a finished request that is never released keeps its arena
+ * space, so the requests behind it wait.  Every call is thread-safe.  A
+ * request that fails (e.g. NaN in its field) fails alone: its batch is rerun
+ * field by field.
+ *
+ *  msc_queue_create: `device` is the HIP device index, `hbm_budget` at least
+ *  1 MiB, `max_batch` >= 1 (1 = one field per launch).  MSC_EINVAL,
+ *  MSC_ENOMEM (arena allocation failed), MSC_EHIP.  Starts three host
+ *  threads; msc_queue_destroy joins them after the running launches end and
+ *  frees everything, including unreleased results.
+ *  msc_request.host_input: host memory the queue reads until the request
+ *  is staged (page-locked memory makes the copy asynchronous); float32[N]
+ *  for MSC_REQ_SEGMENT, uint8 mask[N] for MSC_REQ_CC_GRID.
+ *  msc_submit: MSC_EBUDGET if the request alone exceeds the budget,
+ *  MSC_EINVAL / MSC_ERANGE as msc_segment.  *ticket names the request.
+ *  msc_poll: *status = MSC_EBUSY while queued or running, MSC_ECANCELED, or
+ *  the request's own result code.
+ *  msc_wait: blocks until the request is finished; returns its result code.
+ *  msc_get_result: device pointers of the outputs (valid until msc_release) and
+ *  host steady-clock times (ns) of submission, launch start and completion.
+ *  msc_cancel: removes a request that is still waiting for admission
+ *  (MSC_EBUSY once admitted).
+ *  msc_release: frees a finished or cancelled request's device memory.
+ */
+enum { MSC_REQ_SEGMENT = 1, MSC_REQ_CC_GRID = 2 };
+
+typedef struct msc_queue msc_queue;
+
+typedef struct msc_request {
+  int kind;                /* MSC_REQ_SEGMENT or MSC_REQ_CC_GRID      */
+  int64_t dims[3];         /* X, Y, Z                                 */
+  const void *host_input;  /* float32 field or uint8 mask, host       */
+} msc_request;
+
+typedef struct msc_result {
+  int kind;
+  int status;              /* the request's result code               */
+  int64_t n;               /* vertices                                */
+  int32_t *asc, *desc, *ms;/* device outputs of a segmentation        */
+  int64_t *labels;         /* device output of a mask CC              */
+  int64_t t_submit_ns, t_start_ns, t_done_ns;
+  int batch_size;          /* requests in the launch that ran it      */
+} msc_result;
+
+typedef struct msc_queue_stats {
+  size_t budget, arena_used, workspace_reserved;
+  int64_t pending, running, finished;
+} msc_queue_stats;
+
+MSC_API int msc_queue_create(int device, size_t hbm_budget, int max_batch,
+                             msc_queue **out);
+MSC_API void msc_queue_destroy(msc_queue *q);
+MSC_API int msc_submit(msc_queue *q, const msc_request *req,
+                       uint64_t *ticket);
+MSC_API int msc_poll(msc_queue *q, uint64_t ticket, int *status);
+MSC_API int msc_wait(msc_queue *q, uint64_t ticket);
+MSC_API int msc_get_result(msc_queue *q, uint64_t ticket, msc_result *out);
+/* Copies output `which` (0 asc, 1 desc, 2 ms of a segmentation; 3 labels of
+ * a CC) of a finished request to `dst` (host or device memory, at least
+ * n * 4 bytes, n * 8 for labels).  Blocks until the copy is done. */
+MSC_API int msc_copy_result(msc_queue *q, uint64_t ticket, int which,
+                            void *dst);
+MSC_API int msc_cancel(msc_queue *q, uint64_t ticket);
+MSC_API int msc_release(msc_queue *q, uint64_t ticket);
+MSC_API int msc_queue_info(msc_queue *q, msc_queue_stats *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libmsc.so")
-SOURCES = ["api.hip", "segment.hip", "cc.hip"]
+SOURCES = ["api.hip", "segment.hip", "cc.hip", "serve.cpp"]
 ARCH = os.environ.get("MSC_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

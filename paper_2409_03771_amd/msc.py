@@ -314,3 +314,149 @@ def pointer_jump(d: torch.Tensor, rounds: int = 0, synchronous: bool = False,
         int(rounds), int(bool(synchronous)), _stream(d, stream))
     _check(code, "msc_pointer_jump")
     return d
+
+
+# ---------------------------------------------------------------------------
+# Serving: request queue with continuous batching (msc_queue_* in msc.h)
+# ---------------------------------------------------------------------------
+
+REQ_SEGMENT, REQ_CC_GRID = 1, 2
+
+
+class msc_request(ctypes.Structure):
+    _fields_ = [("kind", _I32), ("dims", _I64 * 3), ("host_input", _P)]
+
+
+class msc_result(ctypes.Structure):
+    _fields_ = [("kind", _I32), ("status", _I32), ("n", _I64), ("asc", _P),
+                ("desc", _P), ("ms", _P), ("labels", _P),
+                ("t_submit_ns", _I64), ("t_start_ns", _I64),
+                ("t_done_ns", _I64), ("batch_size", _I32)]
+
+
+class msc_queue_stats(ctypes.Structure):
+    _fields_ = [("budget", ctypes.c_size_t), ("arena_used", ctypes.c_size_t),
+                ("workspace_reserved", ctypes.c_size_t), ("pending", _I64),
+                ("running", _I64), ("finished", _I64)]
+
+
+_U64 = ctypes.c_uint64
+_QSIGS = {
+    "msc_queue_create": ([_I32, ctypes.c_size_t, _I32, ctypes.POINTER(_P)],
+                         _I32),
+    "msc_queue_destroy": ([_P], None),
+    "msc_submit": ([_P, ctypes.POINTER(msc_request), ctypes.POINTER(_U64)],
+                   _I32),
+    "msc_poll": ([_P, _U64, ctypes.POINTER(_I32)], _I32),
+    "msc_wait": ([_P, _U64], _I32),
+    "msc_get_result": ([_P, _U64, ctypes.POINTER(msc_result)], _I32),
+    "msc_copy_result": ([_P, _U64, _I32, _P], _I32),
+    "msc_cancel": ([_P, _U64], _I32),
+    "msc_release": ([_P, _U64], _I32),
+    "msc_queue_info": ([_P, ctypes.POINTER(msc_queue_stats)], _I32),
+}
+for _name, (_args, _res) in _QSIGS.items():
+    _fn = getattr(_lib, _name)
+    _fn.argtypes = _args
+    _fn.restype = _res
+EXPORTS = EXPORTS + tuple(_QSIGS)
+
+
+class Server:
+    """Client of a device-side request queue.  Inputs are host arrays
+    (page-locked torch tensors are copied asynchronously); results stay on
+    the device until `release`."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 8 << 30,
+                 max_batch: int = 64):
+        self._q = _P()
+        _check(_lib.msc_queue_create(int(device), int(hbm_budget),
+                                     int(max_batch), ctypes.byref(self._q)),
+               "msc_queue_create")
+        self._keep = {}
+
+    def submit(self, kind: int, host_input) -> int:
+        """Queue a segmentation (float32 field) or mask-CC (uint8 mask)
+        request; `host_input` is a C-contiguous numpy array or CPU tensor of
+        shape [Z, Y, X] (or 1-D / 2-D)."""
+        if isinstance(host_input, torch.Tensor):
+            if host_input.is_cuda or not host_input.is_contiguous():
+                raise ValueError("host_input must be a contiguous host tensor")
+            want = torch.float32 if kind == REQ_SEGMENT else torch.uint8
+            if host_input.dtype != want:
+                raise TypeError(f"host_input must be {want}")
+            ptr = host_input.data_ptr()
+        else:
+            import numpy as np
+            want = np.float32 if kind == REQ_SEGMENT else np.uint8
+            if host_input.dtype != want or not host_input.flags["C_CONTIGUOUS"]:
+                raise TypeError(f"host_input must be contiguous {want}")
+            ptr = host_input.ctypes.data
+        req = msc_request()
+        req.kind = int(kind)
+        for k, d in enumerate(grid_dims(host_input.shape)):
+            req.dims[k] = d
+        req.host_input = ptr
+        t = _U64(0)
+        _check(_lib.msc_submit(self._q, ctypes.byref(req), ctypes.byref(t)),
+               "msc_submit")
+        self._keep[t.value] = host_input
+        return t.value
+
+    def poll(self, ticket: int) -> int:
+        st = _I32(0)
+        _check(_lib.msc_poll(self._q, ticket, ctypes.byref(st)), "msc_poll")
+        return st.value
+
+    def wait(self, ticket: int) -> int:
+        return _lib.msc_wait(self._q, ticket)
+
+    def result(self, ticket: int) -> dict:
+        r = msc_result()
+        _check(_lib.msc_get_result(self._q, ticket, ctypes.byref(r)),
+               "msc_get_result")
+        return {k: getattr(r, k) for k, _ in msc_result._fields_}
+
+    def copy_output(self, ticket: int, which: int):
+        """Host copy of one output of a finished request: 0 asc, 1 desc,
+        2 ms (int32) of a segmentation, 3 labels (int64) of a CC."""
+        import numpy as np
+        r = self.result(ticket)
+        a = np.empty(r["n"], np.int64 if which == 3 else np.int32)
+        _check(_lib.msc_copy_result(self._q, ticket, int(which),
+                                    a.ctypes.data_as(_P)), "msc_copy_result")
+        return a
+
+    def fetch(self, ticket: int):
+        """Host copies of a finished request's outputs: (asc, desc, ms) for a
+        segmentation, labels for a CC."""
+        r = self.result(ticket)
+        if r["status"] != MSC_OK:
+            raise MscError(r["status"], "request")
+        if r["kind"] == REQ_CC_GRID:
+            return self.copy_output(ticket, 3)
+        return tuple(self.copy_output(ticket, w) for w in range(3))
+
+    def cancel(self, ticket: int):
+        _check(_lib.msc_cancel(self._q, ticket), "msc_cancel")
+
+    def release(self, ticket: int):
+        _check(_lib.msc_release(self._q, ticket), "msc_release")
+        self._keep.pop(ticket, None)
+
+    def info(self) -> dict:
+        s = msc_queue_stats()
+        _check(_lib.msc_queue_info(self._q, ctypes.byref(s)), "msc_queue_info")
+        return {k: getattr(s, k) for k, _ in msc_queue_stats._fields_}
+
+    def close(self):
+        if self._q:
+            _lib.msc_queue_destroy(self._q)
+            self._q = _P()
+            self._keep.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

@@ -1,0 +1,167 @@
+"""Request queue with continuous batching: every result is bit-identical to
+the CPU oracle and to the plain call, alone and in a mix of kinds and sizes;
+admission respects the HBM budget; cancellation, errors and NaN requests
+stay local to their request."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2409_03771_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def msc():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2409_03771_amd import msc as m
+    return m
+
+
+def _requests(count, seed, lo=8, hi=64):
+    """Mixed trace: 70 % segmentation (some tie-heavy), 30 % mask CC."""
+    rng = np.random.default_rng(seed)
+    specs = synth.batch_specs(count, seed=seed, lo=lo, hi=hi)
+    out = []
+    for k, (dims, nb, fseed) in enumerate(specs):
+        if rng.random() < 0.7:
+            f = (synth.random_field(dims, seed=fseed, levels=4) if k % 4 == 1
+                 else synth.gaussian_field(dims, nb, fseed))
+            out.append((1, f))
+        else:
+            f = synth.gaussian_field(dims, nb, fseed)
+            out.append((2, synth.threshold_mask(f, 0.7)))
+    return out
+
+
+def _check(kind, arr, got, tag):
+    if kind == 1:
+        want = O.segment(arr)
+        for name, g, w in zip(("asc", "desc", "ms"), got, want):
+            np.testing.assert_array_equal(g, w, err_msg=f"{tag} {name}")
+    else:
+        np.testing.assert_array_equal(got, O.cc_grid(arr)[0], err_msg=tag)
+
+
+def test_mix_matches_oracle_alone_and_plain(msc):
+    reqs = _requests(40, seed=11)
+    with msc.Server(hbm_budget=1 << 30, max_batch=16) as srv:
+        tickets = [srv.submit(k, a) for k, a in reqs]
+        batches = []
+        for t, (k, a) in zip(tickets, reqs):
+            assert srv.wait(t) == msc.MSC_OK
+            r = srv.result(t)
+            assert r["t_submit_ns"] <= r["t_start_ns"] <= r["t_done_ns"]
+            batches.append(r["batch_size"])
+            _check(k, a, srv.fetch(t), f"ticket {t} {a.shape}")
+            srv.release(t)
+        info = srv.info()
+        assert info["arena_used"] == 0 and info["workspace_reserved"] == 0
+        assert info["pending"] == info["running"] == info["finished"] == 0
+    # Requests submitted together were packed into shared launches.
+    assert max(batches) > 1
+    # The same requests alone, each in a fresh queue, and as plain calls.
+    with msc.Server(hbm_budget=1 << 30, max_batch=16) as srv:
+        for k, a in reqs[:6]:
+            t = srv.submit(k, a)
+            assert srv.wait(t) == msc.MSC_OK
+            assert srv.result(t)["batch_size"] == 1
+            got = srv.fetch(t)
+            if k == 1:
+                plain = msc.segment(torch.from_numpy(a).cuda())
+                torch.cuda.synchronize()
+                for g, p in zip(got, plain):
+                    np.testing.assert_array_equal(g, p.cpu().numpy())
+            else:
+                lab = msc.cc_label_grid(torch.from_numpy(a).cuda())
+                torch.cuda.synchronize()
+                np.testing.assert_array_equal(got, lab.cpu().numpy())
+            srv.release(t)
+
+
+def test_budget_backpressure(msc):
+    """A budget that holds about three requests: later ones wait for
+    releases, arrival order is kept and every result is still exact."""
+    dims = (40, 36, 32)
+    n = dims[0] * dims[1] * dims[2]
+    per = 16 * n + 256 + 8 * n + (1 << 20)      # resident + workspace estimate
+    budget = 3 * per + per // 2
+    fields = [synth.gaussian_field(dims, 6, 100 + i) for i in range(10)]
+    with msc.Server(hbm_budget=budget, max_batch=8) as srv:
+        tickets = [srv.submit(1, f) for f in fields]
+        starts = []
+        for t, f in zip(tickets, fields):
+            info = srv.info()
+            assert info["arena_used"] + info["workspace_reserved"] <= budget
+            assert srv.wait(t) == msc.MSC_OK
+            starts.append(srv.result(t)["t_start_ns"])
+            _check(1, f, srv.fetch(t), f"ticket {t}")
+            srv.release(t)
+        assert starts == sorted(starts)
+        assert srv.info()["arena_used"] == 0
+
+
+def test_rejects_and_cancel(msc):
+    big = np.zeros((128, 128, 128), np.float32)
+    fa = synth.gaussian_field((60, 50, 40), 6, 5)       # 120000 vertices
+    fb = synth.gaussian_field((50, 40, 30), 4, 6)       # 60000 vertices
+    # Room for fa alone (resident 16 B/vertex + 8 B/vertex workspace + 1 MiB),
+    # but not for fb beside fa's unreleased result.
+    budget = 24 * 120000 + (1 << 20) + (64 << 10)
+    with msc.Server(hbm_budget=budget, max_batch=4) as srv:
+        with pytest.raises(msc.MscError) as e:
+            srv.submit(1, big)                      # alone exceeds the budget
+        assert e.value.code == msc.MSC_EBUDGET
+        with pytest.raises(TypeError):
+            srv.submit(1, fa.astype(np.float64))
+        with pytest.raises(msc.MscError):
+            srv.poll(987654)                        # unknown ticket
+        ta = srv.submit(1, fa)
+        assert srv.wait(ta) == msc.MSC_OK
+        tb = srv.submit(1, fb)                      # waits for fa's release
+        assert srv.poll(tb) == msc.MSC_EBUSY
+        assert srv.info()["pending"] == 1
+        srv.cancel(tb)
+        assert srv.poll(tb) == msc.MSC_ECANCELED
+        assert srv.wait(tb) == msc.MSC_ECANCELED
+        with pytest.raises(msc.MscError):
+            srv.fetch(tb)
+        srv.release(tb)
+        with pytest.raises(msc.MscError):           # labels of a segmentation
+            srv.copy_output(ta, 3)
+        tc = srv.submit(1, fb)
+        assert srv.poll(tc) == msc.MSC_EBUSY
+        _check(1, fa, srv.fetch(ta), "held")
+        srv.release(ta)                             # lets fb in
+        assert srv.wait(tc) == msc.MSC_OK
+        _check(1, fb, srv.fetch(tc), "after release")
+        with pytest.raises(msc.MscError):
+            srv.cancel(tc)                          # already finished
+        srv.release(tc)
+        t = srv.submit(2, synth.threshold_mask(fb, 0.5))
+        assert srv.wait(t) == msc.MSC_OK
+        with pytest.raises(msc.MscError):           # outputs of a CC
+            srv.copy_output(t, 0)
+        srv.release(t)
+        assert srv.info()["arena_used"] == 0
+
+
+def test_nan_request_fails_alone(msc):
+    reqs = [(1, synth.gaussian_field((30, 22, 18), 5, 200 + i)) for i in range(8)]
+    bad = reqs[3][1].copy()
+    bad.reshape(-1)[17] = np.nan
+    reqs[3] = (1, bad)
+    reqs.insert(5, (2, synth.threshold_mask(reqs[0][1], 0.6)))
+    with msc.Server(hbm_budget=256 << 20, max_batch=16) as srv:
+        tickets = [srv.submit(k, a) for k, a in reqs]
+        for i, (t, (k, a)) in enumerate(zip(tickets, reqs)):
+            rc = srv.wait(t)
+            if i == 3:
+                assert rc == msc.MSC_ENAN
+                with pytest.raises(msc.MscError):
+                    srv.fetch(t)
+            else:
+                assert rc == msc.MSC_OK
+                _check(k, a, srv.fetch(t), f"request {i}")
+            srv.release(t)
