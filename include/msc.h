@@ -153,6 +153,7 @@ typedef struct msc_stats {
   int64_t n_exits;       /* tile-exit vertices resolved globally      */
   int32_t jump_rounds;   /* pointer-jumping rounds on the exit graph  */
   int32_t tile_x, tile_y, tile_z; /* tile of the fused local pass     */
+  int64_t exit_steps;    /* exit-graph links followed in total        */
 } msc_stats;
 
 MSC_API int msc_last_stats(const msc_ctx *ctx, msc_stats *out);

@@ -187,8 +187,7 @@ k_cc_tile(const uint8_t *__restrict__ mask, CGeo g, uint16_t *__restrict__ loc,
 // neighbours leaving the tile through an upper face.
 __global__ void __launch_bounds__(kCThreads)
 k_cc_cross(const uint8_t *__restrict__ mask, CGeo g,
-           const uint16_t *__restrict__ loc, int64_t *L,
-           unsigned long long *ctr) {
+           const uint16_t *__restrict__ loc, int64_t *L) {
   const int tid = threadIdx.x;
   const CTile t = ctile_at(g, cc_tile_of_block(blockIdx.x, gridDim.x));
   const int cx = tid % CTX, cy = tid / CTX;
@@ -198,7 +197,6 @@ k_cc_cross(const uint8_t *__restrict__ mask, CGeo g,
   if (!col_in) nz = 0;
   const bool xface = cx == CTX - 1 && gx + 1 < g.X;
   const bool yface = cy == CTY - 1 && gy + 1 < g.Y;
-  bool changed = false;
   for (int lz = 0; lz < nz; ++lz) {
     const bool zface = lz == CTZ - 1 && t.z0 + lz + 1 < g.Z;
     if (!(xface || yface || zface)) continue;
@@ -223,10 +221,9 @@ k_cc_cross(const uint8_t *__restrict__ mask, CGeo g,
       const int64_t ux = gx + dx[k], uy = gy + dy[k], uz = t.z0 + lz + dz[k];
       const CTile tu{ux - ux % CTX, uy - uy % CTY, uz - uz % CTZ};
       const int64_t ru = ctile_global(g, tu, loc[u]);
-      changed |= uf_unite<int64_t>(L, rv, ru);
+      uf_unite<int64_t>(L, rv, ru);
     }
   }
-  flag_any(changed, ctr + kCtrChanged);
 }
 
 __global__ void __launch_bounds__(kCThreads)
@@ -372,8 +369,7 @@ int cc_grid_run(msc_ctx *ctx, const uint8_t *mask, int64_t X, int64_t Y,
   MSC_PHASE(ctx, s, "cc_tile", 3.0 * g.N,
             (k_cc_tile<<<nb, kCThreads, 0, s>>>(mask, g, loc, labels)));
   MSC_PHASE(ctx, s, "cc_cross", 0.5 * g.N,
-            (k_cc_cross<<<nb, kCThreads, 0, s>>>(mask, g, loc, labels,
-                                                 ctx->dctr)));
+            (k_cc_cross<<<nb, kCThreads, 0, s>>>(mask, g, loc, labels)));
   MSC_PHASE(ctx, s, "cc_final", 10.0 * g.N,
             (k_cc_final<<<nb, kCThreads, 0, s>>>(g, loc, labels)));
   MSC_TRY(read_counters(ctx, s));

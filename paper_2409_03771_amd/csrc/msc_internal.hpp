@@ -38,6 +38,7 @@ enum Counter : int {
   kCtrOverflow = 7,  // hash table or list overflow
   kCtrChanged2 = 8,
   kCtrRounds = 9,    // longest exit chain walked
+  kCtrSteps = 10,    // exit-graph links followed in total
   kNumCounters = 16
 };
 
@@ -168,9 +169,10 @@ inline unsigned grid_for(int64_t n, int block = kBlock) {
 
 // Segmentation tile shapes compiled in (index = ctx->tile_choice); the
 // first is the default.
-constexpr int kNumTileShapes = 5;
+constexpr int kNumTileShapes = 6;
 constexpr int kTileShapes[kNumTileShapes][3] = {
-    {32, 32, 16}, {32, 16, 16}, {32, 8, 8}, {64, 16, 16}, {64, 8, 8}};
+    {32, 16, 16}, {32, 32, 16}, {32, 8, 8}, {64, 16, 16}, {64, 8, 8},
+    {32, 32, 32}};
 inline int tile_index(int tx, int ty, int tz) {
   for (int i = 0; i < kNumTileShapes; ++i)
     if (kTileShapes[i][0] == tx && kTileShapes[i][1] == ty &&

@@ -52,10 +52,11 @@ struct Cfg {
   static constexpr int H = HXY * HZ;          // tile plus halo
   static constexpr int kThreads = TX * TY;    // one thread per z-column
   static constexpr int kWords = (H + 31) / 32;
+  static constexpr int kWordsPerThread = (kWords + kThreads - 1) / kThreads;
   static constexpr int kHalo = H - TX * TY * TZ;
   static_assert(H <= 65535, "tile-local pointers are 16-bit");
   static_assert(kThreads % 64 == 0 && kThreads <= 1024, "block shape");
-  static_assert(kWords <= kThreads, "one bitset word per thread");
+  static_assert(4 * kWords <= H, "exit bitsets alias the pointer array");
   static_assert(TX * TY * TZ <= 0x8000 && kHalo < 0x8000,
                 "local pointer codes are 15-bit");
 };
@@ -253,8 +254,53 @@ struct ExitOut {
   uint32_t *lfield;    // field of each exit
   Seg *seg;            // per global tile
   uint32_t *tkey;      // per global tile: order key of its mean value
+  uint32_t *tstat;     // per global tile: maxima, minima, cells, unused
   uint32_t cap;
 };
+
+// Counters are summed per block and written per tile, then folded by these
+// small kernels: atomics on one device address are serialised across the
+// chip and cost far more than the kernels' own work at one per wave.
+// tstat[4 * tile + k] summed per field into fctr[field][which]; a wave whose
+// tiles all belong to one field adds once.
+__global__ void __launch_bounds__(kBlock)
+k_tile_stat_reduce(const uint32_t *__restrict__ tstat, int k, uint32_t nt,
+                   const uint32_t *__restrict__ tfield,
+                   unsigned long long *fctr, int which) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  const bool in = i < nt;
+  const uint32_t v = in ? tstat[4 * (size_t)i + k] : 0u;
+  const uint32_t fi = in ? tfield[i] : 0u;
+  const uint32_t f0 = __builtin_amdgcn_readlane(fi, 0);
+  if (__ballot(in && fi != f0) == 0) {
+    uint32_t sum = v;
+    for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+    if ((threadIdx.x & 63) == 0 && sum)
+      atomicAdd(fctr + (size_t)f0 * kFieldCtrs + which,
+                (unsigned long long)sum);
+  } else if (in && v) {
+    atomicAdd(fctr + (size_t)fi * kFieldCtrs + which, (unsigned long long)v);
+  }
+}
+
+// Per-block (longest chain, links followed) of the exit resolution into the
+// global counters.
+__global__ void __launch_bounds__(kBlock)
+k_steps_reduce(const unsigned long long *__restrict__ rstat, uint32_t nb,
+               unsigned long long *ctr) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  unsigned long long mx = i < nb ? rstat[2 * (size_t)i] : 0ull;
+  unsigned long long sum = i < nb ? rstat[2 * (size_t)i + 1] : 0ull;
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long a = __shfl_xor(mx, o);
+    mx = a > mx ? a : mx;
+    sum += __shfl_xor(sum, o);
+  }
+  if ((threadIdx.x & 63) == 0 && sum) {
+    atomicMax(ctr + kCtrRounds, mx);
+    atomicAdd(ctr + kCtrSteps, sum);
+  }
+}
 
 template <class C>
 __global__ void __launch_bounds__(C::kThreads)
@@ -265,10 +311,13 @@ k_tile_local(const FieldDev *__restrict__ fds,
   // Field bits while the steepest pointers are computed, then the packed
   // pointers (ascent in the low 16 bits, descent in the high 16 bits).
   __shared__ uint32_t lds[H];
-  __shared__ uint32_t xa[C::kWords], xd[C::kWords];  // exit bitsets
-  __shared__ uint32_t pra[C::kWords], prd[C::kWords];  // their word prefixes
+  // Exit bitsets over the tile-plus-halo index and their word prefixes,
+  // placed in `lds` once the pointers there are no longer read.
+  uint32_t *const xa = lds, *const xd = lds + C::kWords;
+  uint32_t *const pra = lds + 2 * C::kWords, *const prd = lds + 3 * C::kWords;
   __shared__ uint32_t scan_tmp[32];
   __shared__ float s_wsum[16];
+  __shared__ uint32_t s_wext[16];  // per wave: maxima | minima << 16
   __shared__ unsigned long long s_base;
 
   const int tid = threadIdx.x;
@@ -277,10 +326,6 @@ k_tile_local(const FieldDev *__restrict__ fds,
   const float *__restrict__ f = bt.fd.f;
   unsigned long long *fc = fctr + (size_t)bt.fi * kFieldCtrs;
   const Tile t = tile_at<C>(g, bt.tile);
-  for (int w = tid; w < C::kWords; w += T) {
-    xa[w] = 0;
-    xd[w] = 0;
-  }
   // Stage the tile and its halo; positions outside the domain hold NaN,
   // which loses every comparison below and so is never chosen.
   const uint32_t kNaN = 0x7fc00000u;
@@ -312,6 +357,7 @@ k_tile_local(const FieldDev *__restrict__ fds,
   uint32_t ptr[C::TZ];
   bool any_nan = false;
   float fsum = 0.f;
+  unsigned nmax = 0, nmin = 0;
   Plane below = load_plane<C>(lds, c0);
   Plane cur = load_plane<C>(lds, c0 + HXY);
 #pragma unroll
@@ -354,15 +400,24 @@ k_tile_local(const FieldDev *__restrict__ fds,
     fsum += in ? fv : 0.f;
     ptr[lz] = in ? (uint32_t)(i + omax) | ((uint32_t)(i + omin) << 16)
                  : (uint32_t)i | ((uint32_t)i << 16);
-    wave_count(in && omax == 0, fc + kFMaxima);
-    wave_count(in && omin == 0, fc + kFMinima);
+    nmax += __popcll(__ballot(in && omax == 0));
+    nmin += __popcll(__ballot(in && omin == 0));
     below = cur;
     cur = above;
   }
   wave_count(any_nan, fc + kFNaN);
+  // Extremum counts (wave totals above) of the tile.
   for (int o = 32; o > 0; o >>= 1) fsum += __shfl_xor(fsum, o);
-  if ((tid & 63) == 0) s_wsum[tid >> 6] = fsum;
+  if ((tid & 63) == 0) {
+    s_wsum[tid >> 6] = fsum;
+    s_wext[tid >> 6] = nmax | (nmin << 16);
+  }
   __syncthreads();  // every thread is done reading the field
+  if (tid < 2) {
+    unsigned c = 0;
+    for (int w = 0; w < T / 64; ++w) c += (s_wext[w] >> (16 * tid)) & 0xffffu;
+    xo.tstat[4 * (size_t)bt.gt + tid] = c;
+  }
 
   // Pointers replace the field: halo vertices point to themselves.
 #pragma unroll 4
@@ -395,6 +450,9 @@ k_tile_local(const FieldDev *__restrict__ fds,
     }
     if (!__syncthreads_or(changed)) break;
   }
+  // Every pointer is final in registers: `lds` becomes the exit bitsets.
+  for (int w = tid; w < 2 * C::kWords; w += T) lds[w] = 0;
+  __syncthreads();
 
   // Halo targets are the tile's exits.
 #pragma unroll
@@ -409,14 +467,33 @@ k_tile_local(const FieldDev *__restrict__ fds,
   __syncthreads();
 
   // Exits are numbered ascent then descent, each in increasing halo index.
-  const uint32_t wa = tid < C::kWords ? xa[tid] : 0u;
-  const uint32_t wd = tid < C::kWords ? xd[tid] : 0u;
+  // Thread tid owns the consecutive words tid*W .. tid*W+W-1.
+  constexpr int W = C::kWordsPerThread;
+  uint32_t wa[W], wd[W];
+  uint32_t ca = 0, cd = 0;
+#pragma unroll
+  for (int j = 0; j < W; ++j) {
+    const int w = tid * W + j;
+    wa[j] = w < C::kWords ? xa[w] : 0u;
+    wd[j] = w < C::kWords ? xd[w] : 0u;
+    ca += __popc(wa[j]);
+    cd += __popc(wd[j]);
+  }
   uint32_t na = 0, nd = 0;
-  const uint32_t pa0 = block_exclusive_scan(__popc(wa), scan_tmp, &na);
-  const uint32_t pd0 = block_exclusive_scan(__popc(wd), scan_tmp, &nd);
-  if (tid < C::kWords) {
-    pra[tid] = pa0;
-    prd[tid] = pd0;
+  const uint32_t pa0 = block_exclusive_scan(ca, scan_tmp, &na);
+  const uint32_t pd0 = block_exclusive_scan(cd, scan_tmp, &nd);
+  {
+    uint32_t ra = pa0, rd = pd0;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const int w = tid * W + j;
+      if (w < C::kWords) {
+        pra[w] = ra;
+        prd[w] = rd;
+      }
+      ra += __popc(wa[j]);
+      rd += __popc(wd[j]);
+    }
   }
   __syncthreads();
 
@@ -449,16 +526,20 @@ k_tile_local(const FieldDev *__restrict__ fds,
   }
   __syncthreads();
   for (int k = 0; k < 2; ++k) {
-    uint32_t bits = k ? wd : wa;
     unsigned long long at = s_base + (k ? na + pd0 : pa0);
-    while (bits) {
-      const int b = __ffs(bits) - 1;
-      bits &= bits - 1;
-      if (at < xo.cap) {
-        xo.list[at] = halo_global<C>(g, t, tid * 32 + b) | (k ? kTagDesc : 0u);
-        xo.lfield[at] = bt.fi;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      uint32_t bits = k ? wd[j] : wa[j];
+      while (bits) {
+        const int b = __ffs(bits) - 1;
+        bits &= bits - 1;
+        if (at < xo.cap) {
+          xo.list[at] = halo_global<C>(g, t, (tid * W + j) * 32 + b) |
+                        (k ? kTagDesc : 0u);
+          xo.lfield[at] = bt.fi;
+        }
+        ++at;
       }
-      ++at;
     }
   }
 }
@@ -574,14 +655,15 @@ template <class C>
 __global__ void __launch_bounds__(C::kThreads)
 k_exit_resolve(const uint32_t *__restrict__ order, uint32_t ntiles,
                const Seg *__restrict__ seg, uint32_t count, uint32_t *next,
-               unsigned long long *ctr) {
+               unsigned long long *ctr, unsigned long long *rstat) {
+  __shared__ unsigned long long s_red[2][C::kThreads / 64];
   const bool desc = blockIdx.x >= ntiles;
   const uint32_t tile =
       desc ? order[blockIdx.x - ntiles] : order[ntiles - 1 - blockIdx.x];
   const Seg sg = seg[tile];
   const uint32_t first = sg.base + (desc ? sg.na : 0u);
   const uint32_t cnt = desc ? sg.nd : sg.na;
-  unsigned steps_max = 0;
+  unsigned steps_max = 0, steps_sum = 0;
   bool bad = false;
   for (uint32_t k = threadIdx.x; k < cnt; k += C::kThreads) {
     uint32_t x = __atomic_load_n(&next[first + k], __ATOMIC_RELAXED);
@@ -598,14 +680,28 @@ k_exit_resolve(const uint32_t *__restrict__ order, uint32_t ntiles,
     }
     __atomic_store_n(&next[first + k], x, __ATOMIC_RELAXED);
     steps_max = steps > steps_max ? steps : steps_max;
+    steps_sum += steps;
   }
   if (bad) atomicOr(ctr + kCtrOverflow, 2ull);
   for (int o = 32; o > 0; o >>= 1) {
     const unsigned other = __shfl_xor(steps_max, o);
     steps_max = other > steps_max ? other : steps_max;
+    steps_sum += __shfl_xor(steps_sum, o);
   }
-  if ((threadIdx.x & 63) == 0 && steps_max)
-    atomicMax(ctr + kCtrRounds, (unsigned long long)steps_max);
+  if ((threadIdx.x & 63) == 0) {
+    s_red[0][threadIdx.x >> 6] = steps_max;
+    s_red[1][threadIdx.x >> 6] = steps_sum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long mx = 0, sum = 0;
+    for (int w = 0; w < C::kThreads / 64; ++w) {
+      mx = s_red[0][w] > mx ? s_red[0][w] : mx;
+      sum += s_red[1][w];
+    }
+    rstat[2 * (size_t)blockIdx.x] = mx;
+    rstat[2 * (size_t)blockIdx.x + 1] = sum;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -680,23 +776,35 @@ __device__ __forceinline__ unsigned long long pair_key(int32_t a, int32_t d) {
   return ((unsigned long long)(uint32_t)a << 32) | (uint32_t)d;
 }
 
-// Per-tile table of the distinct final (asc, desc) pairs: few per tile, so
-// the global insert and the cell lookup run once per distinct pair.
-constexpr int kPairSlots = 1024;
+// Per-tile table of the distinct final (asc, desc) pairs: in smooth regions
+// a tile holds few, so the global insert and the cell lookup run once per
+// distinct pair.  Noise-dominated tiles hold thousands (a cell of pure noise
+// has about three vertices); once half the slots are taken the table accepts
+// no new pair, probes stay short, and the remaining vertices take the
+// per-vertex path.  Linear probing without deletion: a pair that is in the
+// table is found before any empty slot.
+constexpr int kPairSlots = 2048;
+constexpr unsigned kPairLimit = kPairSlots / 2;
+constexpr int kPairProbes = 16;
 
 __device__ __forceinline__ int pair_slot(unsigned long long *skey,
+                                         unsigned *fill,
                                          unsigned long long key) {
   uint32_t h = (uint32_t)mix64(key) & (kPairSlots - 1);
-  for (int probe = 0; probe < 32; ++probe) {
+  for (int probe = 0; probe < kPairProbes; ++probe) {
     unsigned long long cur = skey[h];
     if (cur == kEmptyKey) {
+      if (*fill >= kPairLimit) return -1;
       cur = atomicCAS(&skey[h], kEmptyKey, key);
-      if (cur == kEmptyKey) return (int)h;
+      if (cur == kEmptyKey) {
+        atomicAdd(fill, 1u);
+        return (int)h;
+      }
     }
     if (cur == key) return (int)h;
     h = (h + 1) & (kPairSlots - 1);
   }
-  return -1;  // table full: the caller takes the per-vertex path
+  return -1;
 }
 
 __device__ __forceinline__ unsigned long long wave_bcast64(
@@ -706,32 +814,41 @@ __device__ __forceinline__ unsigned long long wave_bcast64(
   return ((unsigned long long)hi << 32) | lo;
 }
 
-// Slot of every lane's pair, merging equal pairs of a wave first; the
-// lowest lane of a group holds its smallest vertex id (ids grow with the lane
-// inside a wave: rows of the tile are consecutive in y).  With `sval`, the
-// group's smallest id is folded into the slot.
+// Slot of every lane's pair (-1: not in the table).  Leader rounds first:
+// the lanes sharing the first pending lane's pair take one insert by that
+// lane, which holds their smallest vertex id (ids grow with the lane inside
+// a wave: rows of the tile are consecutive in y).  Smooth regions have a few
+// large groups per wave and end here; once a round merges fewer than 8
+// lanes (noise), the remaining lanes insert their own pairs in parallel.
+// With `sval`, each lane's id is folded into its slot's minimum.
 __device__ __forceinline__ int wave_pair_slot(unsigned long long *skey,
-                                              int32_t *sval, bool in,
-                                              unsigned long long key,
+                                              int32_t *sval, unsigned *fill,
+                                              bool in, unsigned long long key,
                                               int32_t id) {
   const int lane = threadIdx.x & 63;
   int slot = -1;
   bool pending = in;
-  for (;;) {
+  for (int round = 0; round < 4; ++round) {
     const unsigned long long m = __ballot(pending);
-    if (!m) break;
+    if (!m) return slot;
     const int leader = __ffsll((long long)m) - 1;
     const unsigned long long lkey = wave_bcast64(key, leader);
     int ls = 0;
     if (lane == leader) {
-      ls = pair_slot(skey, lkey);
+      ls = pair_slot(skey, fill, lkey);
       if (sval && ls >= 0) atomicMin(&sval[ls], id);
     }
     ls = __builtin_amdgcn_readlane(ls, leader);
-    if (pending && key == lkey) {
+    const bool mine = pending && key == lkey;
+    if (mine) {
       slot = ls;
       pending = false;
     }
+    if (__popcll(__ballot(mine)) < 8) break;
+  }
+  if (pending) {
+    slot = pair_slot(skey, fill, key);
+    if (sval && slot >= 0) atomicMin(&sval[slot], id);
   }
   return slot;
 }
@@ -754,10 +871,12 @@ __global__ void __launch_bounds__(C::kThreads)
 k_tile_pairs(const FieldDev *__restrict__ fds,
              const uint32_t *__restrict__ tfield, const Seg *__restrict__ seg,
              const uint32_t *__restrict__ R, unsigned long long *ctr,
-             unsigned long long *fctr) {
+             uint32_t *tstat) {
   __shared__ Decode<C> s;
+  __shared__ uint32_t s_fresh[C::kThreads / 64];
   __shared__ unsigned long long skey[kPairSlots];
   __shared__ int32_t sval[kPairSlots];
+  __shared__ unsigned sfill;
   const int tid = threadIdx.x;
   const BlockTile bt = block_tile(fds, tfield);
   if (!bt.fd.ms) return;
@@ -767,6 +886,7 @@ k_tile_pairs(const FieldDev *__restrict__ fds,
     skey[i] = kEmptyKey;
     sval[i] = INT32_MAX;
   }
+  if (tid == 0) sfill = 0;
   const int cx = tid % C::TX, cy = tid / C::TX;
   const int gx = t.x0 + cx, gy = t.y0 + cy;
   const bool col_in = gx < (int)g.X && gy < (int)g.Y;
@@ -791,7 +911,7 @@ k_tile_pairs(const FieldDev *__restrict__ fds,
                      decode_final<C>(s, g, t, code[lz] >> 16, true));
     const int32_t id = (int32_t)((uint32_t)gx + g.X * (uint32_t)gy +
                                  g.XY * (uint32_t)(t.z0 + lz));
-    const int slot = wave_pair_slot(skey, sval, in, key, id);
+    const int slot = wave_pair_slot(skey, sval, &sfill, in, key, id);
     if (in && slot < 0 &&
         !table_insert(bt.fd.keys, bt.fd.vals, bt.fd.mask, key, id, &fresh))
       overflow = true;
@@ -803,9 +923,15 @@ k_tile_pairs(const FieldDev *__restrict__ fds,
                       &fresh))
       overflow = true;
   }
-  if (fresh)
-    atomicAdd(fctr + (size_t)bt.fi * kFieldCtrs + kFCells,
-              (unsigned long long)fresh);
+  // New pairs this tile inserted: summed per tile, folded per field later.
+  for (int o = 32; o > 0; o >>= 1) fresh += __shfl_xor(fresh, o);
+  if ((tid & 63) == 0) s_fresh[tid >> 6] = fresh;
+  __syncthreads();
+  if (tid == 0) {
+    uint32_t c = 0;
+    for (int w = 0; w < C::kThreads / 64; ++w) c += s_fresh[w];
+    tstat[4 * (size_t)bt.gt + 2] = c;
+  }
   if (overflow) atomicOr(ctr + kCtrOverflow, 1ull);
 }
 
@@ -817,6 +943,7 @@ k_tile_write(const FieldDev *__restrict__ fds,
   __shared__ Decode<C> s;
   __shared__ unsigned long long skey[kPairSlots];
   __shared__ int32_t scell[kPairSlots];
+  __shared__ unsigned sfill;
   const int tid = threadIdx.x;
   const BlockTile bt = block_tile(fds, tfield);
   const Geo &g = bt.fd.g;
@@ -826,6 +953,7 @@ k_tile_write(const FieldDev *__restrict__ fds,
   const Tile t = tile_at<C>(g, bt.tile);
   if (ms)
     for (int i = tid; i < kPairSlots; i += C::kThreads) skey[i] = kEmptyKey;
+  if (tid == 0) sfill = 0;
   const int cx = tid % C::TX, cy = tid / C::TX;
   const int gx = t.x0 + cx, gy = t.y0 + cy;
   const bool col_in = gx < (int)g.X && gy < (int)g.Y;
@@ -854,7 +982,8 @@ k_tile_write(const FieldDev *__restrict__ fds,
     }
     slot[lz] = -1;
     if (ms)
-      slot[lz] = (int16_t)wave_pair_slot(skey, nullptr, in, pair_key(a, d), 0);
+      slot[lz] = (int16_t)wave_pair_slot(skey, nullptr, &sfill, in,
+                                         pair_key(a, d), 0);
     if (ms && in && slot[lz] < 0)  // table full: look this vertex up alone
       ms[v] = table_lookup(bt.fd.keys, bt.fd.vals, bt.fd.mask, pair_key(a, d));
   }
@@ -948,7 +1077,8 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
   uint32_t *list = nullptr, *lfield = nullptr, *next = nullptr;
   uint32_t *tkey = nullptr, *torder = nullptr, *hist = nullptr, *mm = nullptr;
   uint32_t *tfield = nullptr;
-  unsigned long long *fctr = nullptr;
+  unsigned long long *fctr = nullptr, *rstat = nullptr;
+  uint32_t *tstat = nullptr;
   FieldDev *fds = nullptr;
   Seg *seg = nullptr;
   std::vector<uint32_t> tf_host(nt);
@@ -961,7 +1091,9 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
         align256(nt * sizeof(Seg)) + 3 * align256(nt * sizeof(uint32_t)) +
         align256((kTileBuckets + 2) * sizeof(uint32_t)) +
         align256(nfields * sizeof(FieldDev)) +
-        align256(nfields * kFieldCtrs * sizeof(unsigned long long)) + 8192;
+        align256(nfields * kFieldCtrs * sizeof(unsigned long long)) +
+        align256(4ull * nt * sizeof(uint32_t)) +
+        align256(4ull * nt * sizeof(unsigned long long)) + 8192;
     MSC_TRY(reserve(ctx->ws, need));
     Carver cv(ctx->ws);
     for (int i = 0; i < nfields; ++i) {
@@ -985,6 +1117,8 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
     mm = hist + kTileBuckets;
     fds = cv.take<FieldDev>(nfields);
     fctr = cv.take<unsigned long long>((size_t)nfields * kFieldCtrs);
+    tstat = cv.take<uint32_t>(4ull * nt);
+    rstat = cv.take<unsigned long long>(4ull * nt);
 
     // Descriptors and the tile -> field map go up through pinned staging.
     char *st = nullptr;
@@ -1002,10 +1136,14 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
         hist, kTileBuckets + 2, 0u);
     k_fill_u32<<<1, kBlock, 0, s>>>(mm, 1, ~0u);
     MSC_HIP_TRY(hipGetLastError());
-    ExitOut xo{list, lfield, seg, tkey, (uint32_t)exit_cap};
+    k_fill_u32<<<grid_for(4ull * nt), kBlock, 0, s>>>(tstat, 4 * nt, 0u);
+    ExitOut xo{list, lfield, seg, tkey, tstat, (uint32_t)exit_cap};
     MSC_PHASE(ctx, s, "tile_local", 8.0 * total_n,
               (k_tile_local<C><<<nt, C::kThreads, 0, s>>>(fds, tfield, xo, ctr,
                                                           fctr)));
+    for (int k = 0; k < 2; ++k)
+      k_tile_stat_reduce<<<grid_for(nt), kBlock, 0, s>>>(
+          tstat, k, nt, tfield, fctr, k ? kFMinima : kFMaxima);
     MSC_TRY(read_counters(ctx, s));
     exits = ctx->hctr[kCtrExits];
     if (exits <= exit_cap) break;
@@ -1035,7 +1173,8 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
                                                              torder)));
     MSC_PHASE(ctx, s, "exit_resolve", 12.0 * ne,
               (k_exit_resolve<C><<<2 * nt, C::kThreads, 0, s>>>(
-                  torder, nt, seg, ne, next, ctr)));
+                  torder, nt, seg, ne, next, ctr, rstat)));
+    k_steps_reduce<<<grid_for(2ull * nt), kBlock, 0, s>>>(rstat, 2 * nt, ctr);
   }
 
   // Pair tables of the fields that want cells, in one block of `tab`.
@@ -1072,7 +1211,9 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
                                kBlock, 0, s>>>(keys, vals, total_cap)));
     MSC_PHASE(ctx, s, "tile_pairs", 4.0 * total_n,
               (k_tile_pairs<C><<<nt, C::kThreads, 0, s>>>(fds, tfield, seg,
-                                                          next, ctr, fctr)));
+                                                          next, ctr, tstat)));
+    k_tile_stat_reduce<<<grid_for(nt), kBlock, 0, s>>>(tstat, 2, nt, tfield,
+                                                       fctr, kFCells);
   }
   MSC_PHASE(ctx, s, "tile_write", (any_ms ? 16.0 : 12.0) * total_n,
             (k_tile_write<C><<<nt, C::kThreads, 0, s>>>(fds, tfield, seg,
@@ -1104,6 +1245,7 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
   if (nfields == 1) ctx->stats.n_cells = ctx->field_stats[0].n_cells;
   ctx->stats.n_exits = (int64_t)exits;
   ctx->stats.jump_rounds = (int32_t)ctx->hctr[kCtrRounds];
+  ctx->stats.exit_steps = (int64_t)ctx->hctr[kCtrSteps];
   ctx->stats.tile_x = C::TX;
   ctx->stats.tile_y = C::TY;
   ctx->stats.tile_z = C::TZ;
@@ -1116,6 +1258,7 @@ using Tile32x16x16 = Cfg<32, 16, 16>;
 using Tile32x8x8 = Cfg<32, 8, 8>;
 using Tile64x16x16 = Cfg<64, 16, 16>;
 using Tile64x8x8 = Cfg<64, 8, 8>;
+using Tile32x32x32 = Cfg<32, 32, 32>;
 
 }  // namespace
 
@@ -1123,15 +1266,17 @@ int segment_batch_run(msc_ctx *ctx, int nfields, const msc_field *fields,
                       hipStream_t s) {
   switch (ctx->tile_choice) {
     case 1:
-      return segment_batch<Tile32x16x16>(ctx, nfields, fields, s);
+      return segment_batch<Tile32x32x16>(ctx, nfields, fields, s);
     case 2:
       return segment_batch<Tile32x8x8>(ctx, nfields, fields, s);
     case 3:
       return segment_batch<Tile64x16x16>(ctx, nfields, fields, s);
     case 4:
       return segment_batch<Tile64x8x8>(ctx, nfields, fields, s);
+    case 5:
+      return segment_batch<Tile32x32x32>(ctx, nfields, fields, s);
     default:
-      return segment_batch<Tile32x32x16>(ctx, nfields, fields, s);
+      return segment_batch<Tile32x16x16>(ctx, nfields, fields, s);
   }
 }
 

@@ -37,7 +37,8 @@ _I32 = ctypes.c_int
 class msc_stats(ctypes.Structure):
     _fields_ = [("n_vertices", _I64), ("n_maxima", _I64), ("n_minima", _I64),
                 ("n_cells", _I64), ("n_exits", _I64), ("jump_rounds", _I32),
-                ("tile_x", _I32), ("tile_y", _I32), ("tile_z", _I32)]
+                ("tile_x", _I32), ("tile_y", _I32), ("tile_z", _I32),
+                ("exit_steps", _I64)]
 
 
 class msc_phase(ctypes.Structure):

@@ -142,7 +142,12 @@ def test_every_tile_shape_parity(msc):
              synth.random_field((70, 33, 37), seed=4, levels=3),
              synth.random_field((200, 1, 1), seed=5),
              synth.random_field((1, 45, 70), seed=6),
-             synth.random_field((65, 17, 1), seed=7, levels=2)]
+             synth.random_field((65, 17, 1), seed=7, levels=2),
+             # noise-dominated: thousands of cells per tile, more than the
+             # per-tile pair table takes, so most vertices take the
+             # per-vertex path of the pair and write passes
+             synth.random_field((96, 80, 40), seed=8),
+             synth.gaussian_field((150, 90, 50), 4, seed=9)]
     want = [O.segment(f) for f in cases]
     try:
         for shape in msc.tile_shapes():
@@ -152,6 +157,7 @@ def test_every_tile_shape_parity(msc):
                 for name, g, ww in zip(("asc", "desc", "ms"), got, w):
                     np.testing.assert_array_equal(
                         g, ww, err_msg=f"tile {shape} dims {f.shape} {name}")
+                assert msc.last_stats()["n_cells"] == len(np.unique(w[2]))
             assert tuple(msc.last_stats()[k] for k in
                          ("tile_x", "tile_y", "tile_z")) == shape
     finally:
