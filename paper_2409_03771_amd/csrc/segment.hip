@@ -113,13 +113,6 @@ __device__ __forceinline__ Tile tile_at(const Geo &g, uint32_t t) {
   return Tile{(int)tx * C::TX, (int)ty * C::TY, (int)tz * C::TZ};
 }
 
-template <class C>
-__device__ __forceinline__ bool halo_owned(int p) {
-  int hz = p / C::HXY, r = p - hz * C::HXY, hy = r / C::HX, hx = r - hy * C::HX;
-  return hx >= 1 && hx <= C::TX && hy >= 1 && hy <= C::TY && hz >= 1 &&
-         hz <= C::TZ;
-}
-
 // Global id of tile-local index p; p must lie inside the domain.
 template <class C>
 __device__ __forceinline__ uint32_t halo_global(const Geo &g, const Tile &t,
@@ -134,16 +127,24 @@ __device__ __forceinline__ uint32_t halo_global(const Geo &g, const Tile &t,
 // tile's exits of that direction, with bit 15 set.
 constexpr uint32_t kExitCode = 0x8000u;
 
+// Tile-plus-halo index p as the owned code of its vertex, or p itself with
+// bit 16 set when it lies in the halo (one decode per pointer target).
 template <class C>
-__device__ __forceinline__ uint32_t local_code(int p, const uint32_t *bits,
-                                               const uint32_t *prefix) {
+__device__ __forceinline__ uint32_t classify(int p) {
   int hz = p / C::HXY, r = p - hz * C::HXY, hy = r / C::HX, hx = r - hy * C::HX;
   if (hx >= 1 && hx <= C::TX && hy >= 1 && hy <= C::TY && hz >= 1 &&
       hz <= C::TZ)
     return (uint32_t)((hx - 1) + C::TX * ((hy - 1) + C::TY * (hz - 1)));
-  const int w = p >> 5;
-  return kExitCode |
-         (prefix[w] + __popc(bits[w] & ((1u << (p & 31)) - 1u)));
+  return 0x10000u | (uint32_t)p;
+}
+
+// Stored code of a classified target: owned codes pass through; a halo index
+// becomes its number among the tile's exits of that direction.
+__device__ __forceinline__ uint32_t exit_code(uint32_t c, const uint32_t *bits,
+                                              const uint32_t *prefix) {
+  if (!(c & 0x10000u)) return c;
+  const uint32_t p = c & 0xffffu, w = p >> 5;
+  return kExitCode | (prefix[w] + __popc(bits[w] & ((1u << (p & 31)) - 1u)));
 }
 
 // Global id of an owned code.
@@ -326,18 +327,23 @@ k_tile_local(const FieldDev *__restrict__ fds,
   const float *__restrict__ f = bt.fd.f;
   unsigned long long *fc = fctr + (size_t)bt.fi * kFieldCtrs;
   const Tile t = tile_at<C>(g, bt.tile);
-  // Stage the tile and its halo; positions outside the domain hold NaN,
-  // which loses every comparison below and so is never chosen.
+  // Stage the tile and its halo, one z-column of the tile-plus-halo box at a
+  // time (consecutive threads take consecutive x: coalesced rows); positions
+  // outside the domain hold NaN, which loses every comparison below and so
+  // is never chosen.
   const uint32_t kNaN = 0x7fc00000u;
-#pragma unroll 4
-  for (int i = tid; i < H; i += T) {
-    int hz = i / HXY, r = i - hz * HXY, hy = r / HX, hx = r - hy * HX;
-    int gx = t.x0 - 1 + hx, gy = t.y0 - 1 + hy, gz = t.z0 - 1 + hz;
-    bool in = gx >= 0 && gx < (int)g.X && gy >= 0 && gy < (int)g.Y &&
-              gz >= 0 && gz < (int)g.Z;
-    lds[i] = in ? __float_as_uint(
-                      f[(uint32_t)gx + g.X * (uint32_t)gy + g.XY * (uint32_t)gz])
-                : kNaN;
+  for (int col = tid; col < HXY; col += T) {
+    const int hy = col / HX, hx = col - hy * HX;
+    const int gx = t.x0 - 1 + hx, gy = t.y0 - 1 + hy;
+    const bool in_xy = gx >= 0 && gx < (int)g.X && gy >= 0 && gy < (int)g.Y;
+    const float *src = f + (in_xy ? (uint32_t)gx + g.X * (uint32_t)gy : 0u);
+#pragma unroll
+    for (int hz = 0; hz < C::HZ; ++hz) {
+      const int gz = t.z0 - 1 + hz;
+      const bool in = in_xy && gz >= 0 && gz < (int)g.Z;
+      lds[col + hz * HXY] =
+          in ? __float_as_uint(src[g.XY * (uint32_t)gz]) : kNaN;
+    }
   }
   __syncthreads();
 
@@ -419,10 +425,19 @@ k_tile_local(const FieldDev *__restrict__ fds,
     xo.tstat[4 * (size_t)bt.gt + tid] = c;
   }
 
-  // Pointers replace the field: halo vertices point to themselves.
-#pragma unroll 4
-  for (int i = tid; i < H; i += T)
-    if (!halo_owned<C>(i)) lds[i] = (uint32_t)i | ((uint32_t)i << 16);
+  // Pointers replace the field: halo vertices point to themselves (whole
+  // halo columns, and the bottom and top entries of the tile's columns).
+  for (int col = tid; col < HXY; col += T) {
+    const int hy = col / HX, hx = col - hy * HX;
+    const bool edge = hx == 0 || hx == HX - 1 || hy == 0 || hy == C::HY - 1;
+#pragma unroll
+    for (int hz = 0; hz < C::HZ; ++hz) {
+      if (edge || hz == 0 || hz == C::HZ - 1) {
+        const uint32_t i = (uint32_t)(col + hz * HXY);
+        lds[i] = i | (i << 16);
+      }
+    }
+  }
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz) lds[c0 + (lz + 1) * HXY] = ptr[lz];
   __syncthreads();
@@ -454,14 +469,23 @@ k_tile_local(const FieldDev *__restrict__ fds,
   for (int w = tid; w < 2 * C::kWords; w += T) lds[w] = 0;
   __syncthreads();
 
-  // Halo targets are the tile's exits.
+  // Halo targets are the tile's exits.  Each target is classified once:
+  // ptr keeps owned code or halo index, hmask_* flags the halo ones.
+  uint32_t hmask_a = 0, hmask_d = 0;
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz) {
     if (lz < nz) {
-      const uint32_t w = ptr[lz];
-      const int pa = (int)(w & 0xffffu), pd = (int)(w >> 16);
-      if (!halo_owned<C>(pa)) atomicOr(&xa[pa >> 5], 1u << (pa & 31));
-      if (!halo_owned<C>(pd)) atomicOr(&xd[pd >> 5], 1u << (pd & 31));
+      const uint32_t ca = classify<C>((int)(ptr[lz] & 0xffffu));
+      const uint32_t cd = classify<C>((int)(ptr[lz] >> 16));
+      if (ca & 0x10000u) {
+        atomicOr(&xa[(ca & 0xffffu) >> 5], 1u << (ca & 31));
+        hmask_a |= 1u << lz;
+      }
+      if (cd & 0x10000u) {
+        atomicOr(&xd[(cd & 0xffffu) >> 5], 1u << (cd & 31));
+        hmask_d |= 1u << lz;
+      }
+      ptr[lz] = (ca & 0xffffu) | (cd << 16);
     }
   }
   __syncthreads();
@@ -507,8 +531,9 @@ k_tile_local(const FieldDev *__restrict__ fds,
       const uint32_t v = (uint32_t)gx + g.X * (uint32_t)gy +
                          g.XY * (uint32_t)(t.z0 + lz);
       const uint32_t w = ptr[lz];
-      lp[v] = local_code<C>((int)(w & 0xffffu), xa, pra) |
-              (local_code<C>((int)(w >> 16), xd, prd) << 16);
+      const uint32_t ca = (w & 0xffffu) | (((hmask_a >> lz) & 1u) << 16);
+      const uint32_t cd = (w >> 16) | (((hmask_d >> lz) & 1u) << 16);
+      lp[v] = exit_code(ca, xa, pra) | (exit_code(cd, xd, prd) << 16);
     }
   }
 
@@ -902,19 +927,25 @@ k_tile_pairs(const FieldDev *__restrict__ fds,
 
   unsigned fresh = 0;
   bool overflow = false;
+  // A column's pair seldom changes from one z to the next; a repeated pair
+  // has a larger id than the one already recorded and needs nothing.
+  unsigned long long last = kEmptyKey;
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz) {
-    const bool in = lz < nz;
-    unsigned long long key = 0;
-    if (in)
+    unsigned long long key = kEmptyKey;
+    if (lz < nz)
       key = pair_key(decode_final<C>(s, g, t, code[lz] & 0xffffu, false),
                      decode_final<C>(s, g, t, code[lz] >> 16, true));
-    const int32_t id = (int32_t)((uint32_t)gx + g.X * (uint32_t)gy +
-                                 g.XY * (uint32_t)(t.z0 + lz));
-    const int slot = wave_pair_slot(skey, sval, &sfill, in, key, id);
-    if (in && slot < 0 &&
-        !table_insert(bt.fd.keys, bt.fd.vals, bt.fd.mask, key, id, &fresh))
-      overflow = true;
+    const bool fresh_key = key != last && key != kEmptyKey;
+    if (__ballot(fresh_key)) {
+      const int32_t id = (int32_t)((uint32_t)gx + g.X * (uint32_t)gy +
+                                   g.XY * (uint32_t)(t.z0 + lz));
+      const int slot = wave_pair_slot(skey, sval, &sfill, fresh_key, key, id);
+      if (fresh_key && slot < 0 &&
+          !table_insert(bt.fd.keys, bt.fd.vals, bt.fd.mask, key, id, &fresh))
+        overflow = true;
+    }
+    if (fresh_key) last = key;
   }
   __syncthreads();
   for (int i = tid; i < kPairSlots; i += C::kThreads) {
@@ -968,6 +999,10 @@ k_tile_write(const FieldDev *__restrict__ fds,
   decode_setup<C>(s, bt.gt, seg, R);
 
   int16_t slot[C::TZ];
+  // The slot (or, off the table, the cell) of the column's previous pair.
+  unsigned long long last = kEmptyKey;
+  int last_slot = -1;
+  int32_t last_cell = -1;
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz) {
     const bool in = lz < nz;
@@ -981,11 +1016,23 @@ k_tile_write(const FieldDev *__restrict__ fds,
       D[v] = d;
     }
     slot[lz] = -1;
-    if (ms)
-      slot[lz] = (int16_t)wave_pair_slot(skey, nullptr, &sfill, in,
-                                         pair_key(a, d), 0);
-    if (ms && in && slot[lz] < 0)  // table full: look this vertex up alone
-      ms[v] = table_lookup(bt.fd.keys, bt.fd.vals, bt.fd.mask, pair_key(a, d));
+    if (ms) {  // uniform over the block: ms belongs to the field
+      const unsigned long long key = pair_key(a, d);
+      const bool fresh_key = in && key != last;
+      if (__ballot(fresh_key)) {
+        const int sl = wave_pair_slot(skey, nullptr, &sfill, fresh_key, key, 0);
+        if (fresh_key) {
+          last_slot = sl;
+          if (sl < 0)  // not in the tile's table: look this pair up alone
+            last_cell = table_lookup(bt.fd.keys, bt.fd.vals, bt.fd.mask, key);
+        }
+      }
+      if (fresh_key) last = key;
+      if (in) {
+        slot[lz] = (int16_t)last_slot;
+        if (last_slot < 0) ms[v] = last_cell;
+      }
+    }
   }
   if (!ms) return;  // uniform over the block: ms belongs to the field
   __syncthreads();
