@@ -54,6 +54,97 @@ def cpu_baseline(field_dev, depth: int):
                       "walks, sort-based cells)"}
 
 
+def roofline_of(prof):
+    """Roofline object of the kernel with the most device time in `prof`
+    (the library's own event trace: per-kernel launches, milliseconds and
+    algorithmic bytes)."""
+    name, dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
+    avg_ms = dom["total_ms"] / dom["launches"]
+    bpl = dom["bytes"] / dom["launches"]
+    achieved = bpl / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "kernel": name, "avg_ms": round(avg_ms, 4),
+            "bytes_per_launch": bpl}
+
+
+def log_prof(prof):
+    for k, p in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"]):
+        avg = p["total_ms"] / max(1, p["launches"])
+        gbs = p["bytes"] / max(1, p["launches"]) / (avg * 1e-3) / 1e9 if avg else 0
+        log(f"[bench]   {k:16s} launches {p['launches']:5d} "
+            f"avg {avg:8.3f} ms  {gbs:8.1f} GB/s (algorithmic)")
+
+
+CC_TEXT = {
+    "cc1024": "cc1024: mask = gauss1024 field (1024^3 float32, 512 Gaussians, "
+              "seed 1) above its 70th percentile (k = floor(0.7 N)-th smallest "
+              "value), Freudenthal connectivity, int64 labels",
+    "csr50m": "csr50m: 368^3 = 49.8M-vertex jittered Kuhn tetrahedralisation "
+              "as symmetric CSR (int64 row_ptr, int32 col_idx), vertex ids "
+              "randomly permuted, seed 2; mask = Gaussian sum (24 bumps) at "
+              "the jittered positions above its 70th percentile; int64 labels",
+}
+
+
+def bench_cc(args, msc, synth, torch, dev):
+    """Connected components: the grid mask at 1024^3 or the 50M-vertex CSR
+    mesh, one labelling call per step, inputs resident on the device."""
+    stream = torch.cuda.current_stream(dev)
+    if args.workload == "cc1024":
+        log("[bench] generating gauss1024 and its 70th-percentile mask")
+        f = synth.config_field("gauss1024", device=dev)
+        n = f.numel()
+        k = int(0.7 * n)
+        tau = torch.sort(f.reshape(-1)).values[k]
+        mask = (f > tau).to(torch.uint8)
+        del f
+        torch.cuda.empty_cache()
+        labels = torch.empty(n, dtype=torch.int64, device=dev)
+        run = lambda: msc.cc_label_grid_into(mask, labels, stream=stream)
+        fg = int(mask.sum().item())
+    else:
+        log("[bench] generating the 368^3 Kuhn CSR mesh on the host")
+        t0 = time.perf_counter()
+        d = synth.kuhn_csr(368, seed=2)
+        log(f"[bench] mesh ready in {time.perf_counter() - t0:.1f} s")
+        rp = torch.from_numpy(d["row_ptr"]).to(dev)
+        ci = torch.from_numpy(d["col_idx"]).to(dev)
+        mask = torch.from_numpy(d["mask"]).to(dev)
+        del d
+        n = rp.numel() - 1
+        labels = torch.empty(n, dtype=torch.int64, device=dev)
+        run = lambda: msc.cc_label_csr_into(rp, ci, labels, mask, stream=stream)
+        fg = int(mask.sum().item())
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    msc.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    msc.profile(False)
+    prof = msc.profile_read()
+    log(f"[bench] {args.steps} steps: {dt * 1e3:.2f} ms/step")
+    log_prof(prof)
+    ncomp = int((labels == torch.arange(n, device=dev)).sum().item())
+    out = {
+        "metric": "Gvertices/s connected components (" + args.workload + ")",
+        "value": round(n / dt / 1e9, 3), "unit": "Gvertices/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": CC_TEXT[args.workload], "vertices": n,
+                   "foreground": fg, "components": ncomp},
+        "roofline": roofline_of(prof),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_batch(args, msc, synth, torch, dev):
     """256 uneven fields: one batched call per step vs. 256 plain calls."""
     specs = synth.batch_specs(256, seed=3)
@@ -89,9 +180,6 @@ def bench_batch(args, msc, synth, torch, dev):
     dt_plain = (time.perf_counter() - t0) / args.steps
     log(f"[bench] batched {dt_batch * 1e3:.2f} ms vs plain {dt_plain * 1e3:.2f} ms"
         f" for {n} vertices")
-    dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
-    avg_ms = dom["total_ms"] / dom["launches"]
-    achieved = dom["bytes"] / dom["launches"] / (avg_ms * 1e-3) / 1e9
     out = {
         "metric": "Gvertices/s batched MS segmentation (256 uneven fields)",
         "value": round(n / dt_batch / 1e9, 3), "unit": "Gvertices/s",
@@ -103,11 +191,7 @@ def bench_batch(args, msc, synth, torch, dev):
                    "tile": list(tune["tile"]),
                    "plain_ms_per_step": round(dt_plain * 1e3, 3),
                    "speedup_vs_plain": round(dt_plain / dt_batch, 2)},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1),
-                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": dom_name,
-                     "avg_ms": round(avg_ms, 4)},
+        "roofline": roofline_of(prof),
     }
     print(json.dumps(out), flush=True)
 
@@ -263,7 +347,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="gauss1024",
-                    choices=sorted(WORKLOAD_TEXT) + ["batch256", "serve"])
+                    choices=sorted(WORKLOAD_TEXT) + ["batch256", "serve",
+                                                     "cc1024", "csr50m"])
     ap.add_argument("--cpu-depth", type=int, default=40,
                     help="z-planes of the field the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -311,6 +396,8 @@ def main():
         return bench_batch(args, msc, synth, torch, dev)
     if args.workload == "serve":
         return bench_serve(args, msc, synth, torch, dev)
+    if args.workload in CC_TEXT:
+        return bench_cc(args, msc, synth, torch, dev)
 
     log(f"[bench] generating {args.workload} on {dev}")
     t0 = time.perf_counter()
@@ -343,21 +430,8 @@ def main():
     ms_per_step = dt / args.steps * 1e3
     value = n / (dt / args.steps) / 1e9
     log(f"[bench] {args.steps} steps in {dt:.3f} s: {ms_per_step:.2f} ms/step")
-    for k, p in sorted(prof.items(), key=lambda kv: -kv[1]["total_ms"]):
-        avg = p["total_ms"] / max(1, p["launches"])
-        gbs = p["bytes"] / max(1, p["launches"]) / (avg * 1e-3) / 1e9 if avg else 0
-        log(f"[bench]   {k:16s} launches {p['launches']:5d} "
-            f"avg {avg:8.3f} ms  {gbs:8.1f} GB/s (algorithmic)")
-
-    dom_name, dom = max(prof.items(), key=lambda kv: kv[1]["total_ms"])
-    avg_ms = dom["total_ms"] / dom["launches"]
-    bytes_per_launch = dom["bytes"] / dom["launches"]
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": dom_name, "avg_ms": round(avg_ms, 4),
-                "bytes_per_launch": bytes_per_launch}
+    log_prof(prof)
+    roofline = roofline_of(prof)
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gvertices/s",

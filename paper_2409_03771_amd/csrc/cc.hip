@@ -149,23 +149,33 @@ k_cc_tile(const uint8_t *__restrict__ mask, CGeo g, uint16_t *__restrict__ loc,
   __syncthreads();
 
   // Union over the tile's own edges, each from its higher-id endpoint
-  // towards the 7 lower-id Freudenthal neighbours.
+  // towards the 7 lower-id Freudenthal neighbours.  The three axis edges are
+  // always taken; a diagonal one is implied, and skipped, when an axis
+  // neighbour on its side is in the mask: e.g. with v-x in the mask, v-x-y
+  // is v-x's own -y neighbour, so v ~ v-x ~ v-x-y (by induction on id, as
+  // v-x < v settles its own lower edges the same way).
   const int SX = 1, SY = CTX, SZ = CTX * CTY;
   for (int lz = 0; lz < nz; ++lz) {
     if (!((m >> lz) & 1)) continue;
     const int l = cx + CTX * (cy + CTY * lz);
     const bool xm = cx > 0, ym = cy > 0, zm = lz > 0;
-    const bool ok[7] = {xm, ym, xm && ym, zm, xm && zm, ym && zm,
-                        xm && ym && zm};
-    const int off[7] = {-SX, -SY, -SX - SY, -SZ, -SX - SZ, -SY - SZ,
-                        -SX - SY - SZ};
-#pragma unroll
-    for (int k = 0; k < 7; ++k) {
-      if (!ok[k]) continue;
-      const int u = l + off[k];
-      if (__atomic_load_n(&par[u], __ATOMIC_RELAXED) < 0) continue;
-      uf_unite<int32_t>(par, l, u);
-    }
+    auto in_mask = [&](int u) {
+      return __atomic_load_n(&par[u], __ATOMIC_RELAXED) >= 0;
+    };
+    const bool mx = xm && in_mask(l - SX);
+    const bool my = ym && in_mask(l - SY);
+    const bool mz = zm && ((m >> (lz - 1)) & 1);
+    if (mx) uf_unite<int32_t>(par, l, l - SX);
+    if (my) uf_unite<int32_t>(par, l, l - SY);
+    if (mz) uf_unite<int32_t>(par, l, l - SZ);
+    if (xm && ym && !mx && !my && in_mask(l - SX - SY))
+      uf_unite<int32_t>(par, l, l - SX - SY);
+    if (xm && zm && !mx && !mz && in_mask(l - SX - SZ))
+      uf_unite<int32_t>(par, l, l - SX - SZ);
+    if (ym && zm && !my && !mz && in_mask(l - SY - SZ))
+      uf_unite<int32_t>(par, l, l - SY - SZ);
+    if (xm && ym && zm && !mx && !my && !mz && in_mask(l - SX - SY - SZ))
+      uf_unite<int32_t>(par, l, l - SX - SY - SZ);
   }
   __syncthreads();
 
@@ -184,11 +194,38 @@ k_cc_tile(const uint8_t *__restrict__ mask, CGeo g, uint16_t *__restrict__ loc,
 
 // Unions across tile faces.  An edge between two tiles is handled by the tile
 // that owns its lower endpoint, which sees it as one of the 7 higher-id
-// neighbours leaving the tile through an upper face.
+// neighbours leaving the tile through an upper face.  Both endpoints are
+// replaced by their tile-local roots, and each distinct (local root,
+// neighbour tile, its local root) triple is united once: a face of a smooth
+// mask carries thousands of edges but only a few such triples.
+constexpr int kCrossSlots = 2048;
+constexpr int kCrossProbes = 16;
+
+// Inserts key into the block's set; true if this call inserted it (or the
+// set is full and the caller must act on the key itself).
+__device__ __forceinline__ bool cross_first(uint32_t *set, uint32_t key) {
+  uint32_t h = (key * 0x9e3779b1u) >> (32 - 11);
+  for (int probe = 0; probe < kCrossProbes; ++probe) {
+    uint32_t cur = set[h];
+    if (cur == key) return false;
+    if (cur == 0xffffffffu) {
+      cur = atomicCAS(&set[h], 0xffffffffu, key);
+      if (cur == 0xffffffffu) return true;
+      if (cur == key) return false;
+    }
+    h = (h + 1) & (kCrossSlots - 1);
+  }
+  return true;
+}
+
 __global__ void __launch_bounds__(kCThreads)
 k_cc_cross(const uint8_t *__restrict__ mask, CGeo g,
            const uint16_t *__restrict__ loc, int64_t *L) {
+  static_assert(kCOwned <= (1 << 13), "13-bit local roots in the keys");
+  __shared__ uint32_t set[kCrossSlots];
   const int tid = threadIdx.x;
+  for (int i = tid; i < kCrossSlots; i += kCThreads) set[i] = 0xffffffffu;
+  __syncthreads();
   const CTile t = ctile_at(g, cc_tile_of_block(blockIdx.x, gridDim.x));
   const int cx = tid % CTX, cy = tid / CTX;
   const int64_t gx = t.x0 + cx, gy = t.y0 + cy;
@@ -202,7 +239,7 @@ k_cc_cross(const uint8_t *__restrict__ mask, CGeo g,
     if (!(xface || yface || zface)) continue;
     const int64_t v = gx + g.X * gy + g.XY * (t.z0 + lz);
     if (!mask[v]) continue;
-    const int64_t rv = ctile_global(g, t, loc[v]);
+    const uint32_t lv = loc[v];
     const bool xp = gx + 1 < g.X, yp = gy + 1 < g.Y,
                zp = t.z0 + lz + 1 < g.Z;
     // (dx, dy, dz) of the 7 higher-id neighbours; keep those outside the tile.
@@ -220,8 +257,13 @@ k_cc_cross(const uint8_t *__restrict__ mask, CGeo g,
       // u's tile-local root, decoded with u's own tile origin.
       const int64_t ux = gx + dx[k], uy = gy + dy[k], uz = t.z0 + lz + dz[k];
       const CTile tu{ux - ux % CTX, uy - uy % CTY, uz - uz % CTZ};
-      const int64_t ru = ctile_global(g, tu, loc[u]);
-      uf_unite<int64_t>(L, rv, ru);
+      const uint32_t lu = loc[u];
+      const uint32_t nbr = (uint32_t)(tu.x0 != t.x0) |
+                           ((uint32_t)(tu.y0 != t.y0) << 1) |
+                           ((uint32_t)(tu.z0 != t.z0) << 2);
+      if (cross_first(set, lv | (nbr << 13) | (lu << 16)))
+        uf_unite<int64_t>(L, ctile_global(g, t, (int)lv),
+                          ctile_global(g, tu, (int)lu));
     }
   }
 }
@@ -234,15 +276,20 @@ k_cc_final(CGeo g, const uint16_t *__restrict__ loc, int64_t *L) {
   const int64_t gx = t.x0 + cx, gy = t.y0 + cy;
   if (gx >= g.X || gy >= g.Y) return;
   int nz = (int)((g.Z - t.z0) < CTZ ? (g.Z - t.z0) : CTZ);
+  uint16_t last = kOutside;
+  int64_t last_out = -1;
   for (int lz = 0; lz < nz; ++lz) {
     const int64_t v = gx + g.X * gy + g.XY * (t.z0 + lz);
     const uint16_t s = loc[v];
     // Only tile-local roots are ever on a root path, and a root's entry is
     // overwritten (by its owner only) with its own final root, so concurrent
-    // walks stay on ancestors and every entry ends as its final root.
-    const int64_t out =
-        s == kOutside ? -1 : uf_root<int64_t>(L, ctile_global(g, t, s));
-    __atomic_store_n(&L[v], out, __ATOMIC_RELAXED);
+    // walks stay on ancestors and every entry ends as its final root.  A
+    // column mostly repeats its local root: its final root is reused.
+    if (s != last && s != kOutside) {
+      last = s;
+      last_out = uf_root<int64_t>(L, ctile_global(g, t, s));
+    }
+    __atomic_store_n(&L[v], s == kOutside ? -1 : last_out, __ATOMIC_RELAXED);
   }
 }
 
