@@ -54,7 +54,37 @@ def cpu_baseline(field_dev, depth: int):
                       "walks, sort-based cells)"}
 
 
-def roofline_of(prof):
+def traffic_of(workload, kernel):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    record of this workload, or None when there is none or the kernel
+    sources changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    from paper_2409_03771_amd.profsum import source_hash
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != source_hash():
+        return None
+    k = rec["kernels"].get(kernel)
+    return None if k is None else int(round(k["hbm_bytes"]))
+
+
+def path_traffic(workload):
+    """HBM bytes of one call summed over all kernels of the committed
+    counter record, or None when absent or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    from paper_2409_03771_amd.profsum import source_hash
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("source_sha256") != source_hash():
+        return None
+    return int(round(sum(k["hbm_bytes"] for k in rec["kernels"].values())))
+
+
+def roofline_of(prof, workload=None, tile=None):
     """Roofline object of the kernel with the most device time in `prof`
     (the library's own event trace: per-kernel launches, milliseconds and
     algorithmic bytes)."""
@@ -62,10 +92,12 @@ def roofline_of(prof):
     avg_ms = dom["total_ms"] / dom["launches"]
     bpl = dom["bytes"] / dom["launches"]
     achieved = bpl / (avg_ms * 1e-3) / 1e9
+    kname = "k_" + name + ("<%d,%d,%d>" % tile if tile else "")
     return {"bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "kernel": name, "avg_ms": round(avg_ms, 4),
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic_of(workload, kname) if workload else None,
+            "kernel": kname, "avg_ms": round(avg_ms, 4),
             "bytes_per_launch": bpl}
 
 
@@ -140,7 +172,7 @@ def bench_cc(args, msc, synth, torch, dev):
         "data": "synthetic",
         "config": {"workload": CC_TEXT[args.workload], "vertices": n,
                    "foreground": fg, "components": ncomp},
-        "roofline": roofline_of(prof),
+        "roofline": roofline_of(prof, args.workload),
     }
     print(json.dumps(out), flush=True)
 
@@ -431,7 +463,8 @@ def main():
     value = n / (dt / args.steps) / 1e9
     log(f"[bench] {args.steps} steps in {dt:.3f} s: {ms_per_step:.2f} ms/step")
     log_prof(prof)
-    roofline = roofline_of(prof)
+    tile = (stats["tile_x"], stats["tile_y"], stats["tile_z"])
+    roofline = roofline_of(prof, args.workload, tile)
 
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gvertices/s",
@@ -444,7 +477,19 @@ def main():
                    "maxima": stats["n_maxima"], "minima": stats["n_minima"],
                    "cells": stats["n_cells"]},
         "roofline": roofline,
+        # Whole call: the compulsory 16 B per vertex (read f, write asc, desc,
+        # ms) and the rocprofv3-measured HBM bytes of all kernels, per step.
+        "path_roofline": {
+            "compulsory_bytes": 16 * n,
+            "compulsory_frac": round(16 * n / (ms_per_step * 1e-3) /
+                                     (HBM_PEAK_GBS * 1e9), 4),
+            "measured_bytes": path_traffic(args.workload),
+            "measured_frac": None},
     }
+    pr = out["path_roofline"]
+    if pr["measured_bytes"]:
+        pr["measured_frac"] = round(pr["measured_bytes"] / (ms_per_step * 1e-3)
+                                    / (HBM_PEAK_GBS * 1e9), 4)
     if not args.no_cpu_baseline:
         depth = min(args.cpu_depth, field.shape[0])
         log(f"[bench] timing the CPU oracle on {depth} z-planes")

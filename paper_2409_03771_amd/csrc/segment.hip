@@ -443,24 +443,23 @@ k_tile_local(const FieldDev *__restrict__ fds,
   __syncthreads();
 
   // Pointer jumping inside the tile, in place.  Only the owner writes an
-  // entry, so the owner's copy in registers is always current; an entry
-  // whose two targets are fixed points is final and is skipped.
-  uint32_t live = nz >= 32 ? ~0u : ((1u << nz) - 1u);
+  // entry, so the owner's copy in registers is always current, and any value
+  // read from another entry is an ancestor of it.  Each round gathers the
+  // successors of all the column's entries first (one wait for the lot),
+  // then updates; finished entries gather themselves and stay unchanged.
   for (;;) {
+    uint32_t q[C::TZ];
+#pragma unroll
+    for (int lz = 0; lz < C::TZ; ++lz)
+      q[lz] = (lds[ptr[lz] & 0xffffu] & 0xffffu) |
+              (lds[ptr[lz] >> 16] & 0xffff0000u);
     bool changed = false;
 #pragma unroll
     for (int lz = 0; lz < C::TZ; ++lz) {
-      if ((live >> lz) & 1) {
-        const uint32_t w = ptr[lz];
-        const uint32_t pa = w & 0xffffu, pd = w >> 16;
-        const uint32_t qa = lds[pa] & 0xffffu, qd = lds[pd] >> 16;
-        if (qa != pa || qd != pd) {
-          ptr[lz] = qa | (qd << 16);
-          lds[c0 + (lz + 1) * HXY] = ptr[lz];
-          changed = true;
-        } else {
-          live &= ~(1u << lz);
-        }
+      if (q[lz] != ptr[lz]) {
+        ptr[lz] = q[lz];
+        lds[c0 + (lz + 1) * HXY] = q[lz];
+        changed = true;
       }
     }
     if (!__syncthreads_or(changed)) break;
