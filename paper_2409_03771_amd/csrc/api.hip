@@ -135,6 +135,7 @@ void msc_destroy(msc_ctx *ctx) {
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
   if (ctx->ws.ptr) (void)hipFree(ctx->ws.ptr);
   if (ctx->tab.ptr) (void)hipFree(ctx->tab.ptr);
+  if (ctx->xg.ptr) (void)hipFree(ctx->xg.ptr);
   if (ctx->dctr) (void)hipFree(ctx->dctr);
   if (ctx->hctr) (void)hipHostFree(ctx->hctr);
   delete ctx;

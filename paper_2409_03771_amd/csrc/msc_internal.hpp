@@ -104,13 +104,12 @@ struct msc_ctx {
   int device = 0;
   // Grow-only device workspaces carved per call: `ws` for per-vertex
   // scratch, `tab` for hash tables and lists sized after a first pass.
-  msc::DevBuf ws, tab;
+  msc::DevBuf ws, tab, xg;  // workspace, pair tables, exit graph
   // Device counters and a pinned host mirror.
   unsigned long long *dctr = nullptr;
   unsigned long long *hctr = nullptr;
   msc_stats stats{};
   msc::Profiler prof;
-  uint64_t exit_cap_hint = 0;  // exit-list size that sufficed last time
   int tile_choice = 0;         // segmentation tile shape (0 = default)
   void *pinned = nullptr;      // grow-only pinned host staging
   size_t pinned_bytes = 0;

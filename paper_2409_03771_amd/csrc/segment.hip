@@ -56,13 +56,13 @@ struct Cfg {
   static constexpr int kHalo = H - TX * TY * TZ;
   static_assert(H <= 65535, "tile-local pointers are 16-bit");
   static_assert(kThreads % 64 == 0 && kThreads <= 1024, "block shape");
-  static_assert(4 * kWords <= H, "exit bitsets alias the pointer array");
+  static_assert((2 * H + 3) / 4 + 3 * kWords <= H,
+                "exit flags and bitsets alias the pointer array");
   static_assert(TX * TY * TZ <= 0x8000 && kHalo < 0x8000,
                 "local pointer codes are 15-bit");
 };
 
 constexpr unsigned long long kEmptyKey = ~0ull;
-constexpr uint32_t kTagDesc = 0x80000000u;
 
 // Per-field counters (kFieldCtrs per field).
 enum FieldCtr : int { kFMaxima = 0, kFMinima = 1, kFCells = 2, kFNaN = 3,
@@ -139,12 +139,15 @@ __device__ __forceinline__ uint32_t classify(int p) {
 }
 
 // Stored code of a classified target: owned codes pass through; a halo index
-// becomes its number among the tile's exits of that direction.
+// becomes its number among the tile's exits of that direction (the word
+// prefixes of that direction sit at bit `shift` of `prefix`).
 __device__ __forceinline__ uint32_t exit_code(uint32_t c, const uint32_t *bits,
-                                              const uint32_t *prefix) {
+                                              const uint32_t *prefix,
+                                              int shift) {
   if (!(c & 0x10000u)) return c;
   const uint32_t p = c & 0xffffu, w = p >> 5;
-  return kExitCode | (prefix[w] + __popc(bits[w] & ((1u << (p & 31)) - 1u)));
+  return kExitCode | (((prefix[w] >> shift) & 0xffffu) +
+                      __popc(bits[w] & ((1u << (p & 31)) - 1u)));
 }
 
 // Global id of an owned code.
@@ -251,12 +254,11 @@ __device__ __forceinline__ Plane load_plane(const uint32_t *lds, int c) {
 }
 
 struct ExitOut {
-  uint32_t *list;      // exit vertex ids (bit 31: descent)
-  uint32_t *lfield;    // field of each exit
-  Seg *seg;            // per global tile
+  Seg *seg;            // per global tile: exit counts (base set later)
   uint32_t *tkey;      // per global tile: order key of its mean value
-  uint32_t *tstat;     // per global tile: maxima, minima, cells, unused
-  uint32_t cap;
+  uint32_t *tstat;     // per global tile: maxima, minima, cells, exits
+  uint16_t *tlist;     // per global tile, 2*kHalo slots: halo index of each
+                       // exit, ascent exits first (numbers are tile-local)
 };
 
 // Counters are summed per block and written per tile, then folded by these
@@ -312,14 +314,15 @@ k_tile_local(const FieldDev *__restrict__ fds,
   // Field bits while the steepest pointers are computed, then the packed
   // pointers (ascent in the low 16 bits, descent in the high 16 bits).
   __shared__ uint32_t lds[H];
-  // Exit bitsets over the tile-plus-halo index and their word prefixes,
-  // placed in `lds` once the pointers there are no longer read.
-  uint32_t *const xa = lds, *const xd = lds + C::kWords;
-  uint32_t *const pra = lds + 2 * C::kWords, *const prd = lds + 3 * C::kWords;
+  // Once the pointers in `lds` are no longer read it holds: one flag byte
+  // per tile-plus-halo index and direction, then the exit bitsets over that
+  // index and their word prefixes (ascent | descent << 16).
+  uint8_t *const flg = reinterpret_cast<uint8_t *>(lds);
+  uint32_t *const xa = lds + (2 * H + 3) / 4, *const xd = xa + C::kWords;
+  uint32_t *const pre = xd + C::kWords;
   __shared__ uint32_t scan_tmp[32];
   __shared__ float s_wsum[16];
   __shared__ uint32_t s_wext[16];  // per wave: maxima | minima << 16
-  __shared__ unsigned long long s_base;
 
   const int tid = threadIdx.x;
   const BlockTile bt = block_tile(fds, tfield);
@@ -464,12 +467,13 @@ k_tile_local(const FieldDev *__restrict__ fds,
     }
     if (!__syncthreads_or(changed)) break;
   }
-  // Every pointer is final in registers: `lds` becomes the exit bitsets.
-  for (int w = tid; w < 2 * C::kWords; w += T) lds[w] = 0;
+  // Every pointer is final in registers: `lds` becomes flags and bitsets.
+  for (int w = tid; w < (2 * H + 3) / 4; w += T) lds[w] = 0;
   __syncthreads();
 
-  // Halo targets are the tile's exits.  Each target is classified once:
-  // ptr keeps owned code or halo index, hmask_* flags the halo ones.
+  // Halo targets are the tile's exits.  Each target is classified once
+  // (ptr keeps owned code or halo index, hmask_* flags the halo ones) and
+  // flagged with a plain byte store: every writer stores the same 1.
   uint32_t hmask_a = 0, hmask_d = 0;
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz) {
@@ -477,46 +481,53 @@ k_tile_local(const FieldDev *__restrict__ fds,
       const uint32_t ca = classify<C>((int)(ptr[lz] & 0xffffu));
       const uint32_t cd = classify<C>((int)(ptr[lz] >> 16));
       if (ca & 0x10000u) {
-        atomicOr(&xa[(ca & 0xffffu) >> 5], 1u << (ca & 31));
+        flg[ca & 0xffffu] = 1;
         hmask_a |= 1u << lz;
       }
       if (cd & 0x10000u) {
-        atomicOr(&xd[(cd & 0xffffu) >> 5], 1u << (cd & 31));
+        flg[H + (cd & 0xffffu)] = 1;
         hmask_d |= 1u << lz;
       }
       ptr[lz] = (ca & 0xffffu) | (cd << 16);
     }
   }
   __syncthreads();
+  // Flags to bitsets: a wave ballots 64 consecutive indices into two words.
+  {
+    const int lane = tid & 63;
+    for (int b = tid - lane; b < H; b += T) {
+      const int p = b + lane;
+      const unsigned long long ma = __ballot(p < H && flg[p]);
+      const unsigned long long md = __ballot(p < H && flg[H + p]);
+      if (lane < 2 && (b >> 5) + lane < C::kWords) {
+        xa[(b >> 5) + lane] = (uint32_t)(ma >> (32 * lane));
+        xd[(b >> 5) + lane] = (uint32_t)(md >> (32 * lane));
+      }
+    }
+  }
+  __syncthreads();
 
   // Exits are numbered ascent then descent, each in increasing halo index.
-  // Thread tid owns the consecutive words tid*W .. tid*W+W-1.
+  // Thread tid owns the consecutive words tid*W .. tid*W+W-1; one scan of
+  // packed counts (ascent | descent << 16, each below 2^16) serves both.
   constexpr int W = C::kWordsPerThread;
   uint32_t wa[W], wd[W];
-  uint32_t ca = 0, cd = 0;
+  uint32_t cnt = 0;
 #pragma unroll
   for (int j = 0; j < W; ++j) {
     const int w = tid * W + j;
     wa[j] = w < C::kWords ? xa[w] : 0u;
     wd[j] = w < C::kWords ? xd[w] : 0u;
-    ca += __popc(wa[j]);
-    cd += __popc(wd[j]);
+    cnt += __popc(wa[j]) | ((uint32_t)__popc(wd[j]) << 16);
   }
-  uint32_t na = 0, nd = 0;
-  const uint32_t pa0 = block_exclusive_scan(ca, scan_tmp, &na);
-  const uint32_t pd0 = block_exclusive_scan(cd, scan_tmp, &nd);
-  {
-    uint32_t ra = pa0, rd = pd0;
+  uint32_t tot = 0;
+  uint32_t run = block_exclusive_scan(cnt, scan_tmp, &tot);
+  const uint32_t na = tot & 0xffffu, nd = tot >> 16;
 #pragma unroll
-    for (int j = 0; j < W; ++j) {
-      const int w = tid * W + j;
-      if (w < C::kWords) {
-        pra[w] = ra;
-        prd[w] = rd;
-      }
-      ra += __popc(wa[j]);
-      rd += __popc(wd[j]);
-    }
+  for (int j = 0; j < W; ++j) {
+    const int w = tid * W + j;
+    if (w < C::kWords) pre[w] = run;
+    run += __popc(wa[j]) | ((uint32_t)__popc(wd[j]) << 16);
   }
   __syncthreads();
 
@@ -532,39 +543,35 @@ k_tile_local(const FieldDev *__restrict__ fds,
       const uint32_t w = ptr[lz];
       const uint32_t ca = (w & 0xffffu) | (((hmask_a >> lz) & 1u) << 16);
       const uint32_t cd = (w >> 16) | (((hmask_d >> lz) & 1u) << 16);
-      lp[v] = exit_code(ca, xa, pra) | (exit_code(cd, xd, prd) << 16);
+      lp[v] = exit_code(ca, xa, pre, 0) | (exit_code(cd, xd, pre, 16) << 16);
     }
   }
 
+  // The tile's exits for the exit graph, by their tile-local numbers (the
+  // numbers become global with a scan over tiles afterwards): a wave takes
+  // 64 consecutive halo indices, so each lane reads the same two words.
+  {
+    uint16_t *tl = xo.tlist + (size_t)bt.gt * (2 * C::kHalo);
+    const int lane = tid & 63;
+    for (int b = tid - lane; b < H; b += T) {
+      const int p = b + lane;
+      if (p >= H) continue;
+      const uint32_t w = (uint32_t)p >> 5, below = (1u << (p & 31)) - 1u;
+      const uint32_t ba = xa[w], bd = xd[w];
+      if ((ba >> (p & 31)) & 1u)
+        tl[(pre[w] & 0xffffu) + __popc(ba & below)] = (uint16_t)p;
+      if ((bd >> (p & 31)) & 1u)
+        tl[na + (pre[w] >> 16) + __popc(bd & below)] = (uint16_t)p;
+    }
+  }
   if (tid == 0) {
-    s_base = (na + nd) ? atomicAdd(ctr + kCtrExits,
-                                   (unsigned long long)(na + nd))
-                       : 0ull;
-    xo.seg[bt.gt] = Seg{(uint32_t)s_base, (uint16_t)na, (uint16_t)nd};
-    // Mean value of the tile: the order in which exits get resolved.
+    xo.seg[bt.gt] = Seg{0u, (uint16_t)na, (uint16_t)nd};
+      // Mean value of the tile: the order in which exits get resolved.
     float sum = 0.f;
     for (int w = 0; w < T / 64; ++w) sum += s_wsum[w];
     const int cnt = min(C::TX, (int)g.X - t.x0) * min(C::TY, (int)g.Y - t.y0) *
                     min(C::TZ, (int)g.Z - t.z0);
     xo.tkey[bt.gt] = float_key(sum / (float)cnt);
-  }
-  __syncthreads();
-  for (int k = 0; k < 2; ++k) {
-    unsigned long long at = s_base + (k ? na + pd0 : pa0);
-#pragma unroll
-    for (int j = 0; j < W; ++j) {
-      uint32_t bits = k ? wd[j] : wa[j];
-      while (bits) {
-        const int b = __ffs(bits) - 1;
-        bits &= bits - 1;
-        if (at < xo.cap) {
-          xo.list[at] = halo_global<C>(g, t, (tid * W + j) * 32 + b) |
-                        (k ? kTagDesc : 0u);
-          xo.lfield[at] = bt.fi;
-        }
-        ++at;
-      }
-    }
   }
 }
 
@@ -588,27 +595,78 @@ __device__ __forceinline__ Tile tile_of_vertex(const Geo &g, uint32_t v,
   return Tile{(int)(tx * C::TX), (int)(ty * C::TY), (int)(tz * C::TZ)};
 }
 
+// Exit numbers: an exclusive scan of the tiles' exit counts in tile order,
+// so that the exits of tile t are nodes seg[t].base .. + na + nd - 1.
+__global__ void __launch_bounds__(1024)
+k_seg_scan_blocks(Seg *seg, uint32_t nt, uint32_t *bsum) {
+  __shared__ uint32_t tmp[32];
+  const uint32_t i = blockIdx.x * 1024 + threadIdx.x;
+  const uint32_t c = i < nt ? (uint32_t)seg[i].na + seg[i].nd : 0u;
+  uint32_t tot = 0;
+  const uint32_t ex = block_exclusive_scan(c, tmp, &tot);
+  if (i < nt) seg[i].base = ex;
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+__global__ void __launch_bounds__(1024)
+k_seg_scan_sums(uint32_t *bsum, uint32_t nb, unsigned long long *ctr) {
+  __shared__ uint32_t tmp[32];
+  uint32_t carry = 0;
+  for (uint32_t b0 = 0; b0 < nb; b0 += 1024) {
+    const uint32_t i = b0 + threadIdx.x;
+    const uint32_t c = i < nb ? bsum[i] : 0u;
+    uint32_t tot = 0;
+    const uint32_t ex = block_exclusive_scan(c, tmp, &tot);
+    if (i < nb) bsum[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) ctr[kCtrExits] = carry;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_seg_scan_add(Seg *seg, uint32_t nt, const uint32_t *__restrict__ bsum) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < nt) seg[i].base += bsum[i / 1024];
+}
+
+// One block per tile links the tile's exits: exit k is the halo vertex v at
+// tile-plus-halo index tlist[k]; its successor is the code that v's owner
+// tile (a face, edge or corner neighbour, found from the index) stored for
+// v -- an extremum of that tile (final) or one of that tile's exits (the
+// next node of the graph).
 template <class C>
 __global__ void __launch_bounds__(kBlock)
-k_exit_link(const uint32_t *__restrict__ list,
-            const uint32_t *__restrict__ lfield, uint32_t count,
-            const FieldDev *__restrict__ fds, const Seg *__restrict__ seg,
-            uint32_t *__restrict__ next) {
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i >= count) return;
-  const uint32_t e = list[i];
-  const bool desc = e & kTagDesc;
-  const uint32_t v = e & ~kTagDesc;
-  const FieldDev &fd = fds[lfield[i]];
-  uint32_t u;
-  const Tile t = tile_of_vertex<C>(fd.g, v, &u);
-  const uint32_t w = fd.lp[v];
-  const uint32_t code = desc ? (w >> 16) : (w & 0xffffu);
-  if (code & kExitCode) {
-    const Seg sg = seg[fd.tile0 + u];
-    next[i] = sg.base + (desc ? sg.na : 0u) + (code & (kExitCode - 1));
-  } else {
-    next[i] = kRoot | owned_global<C>(fd.g, t, code);
+k_exit_link(const FieldDev *__restrict__ fds,
+            const uint32_t *__restrict__ tfield, const Seg *__restrict__ seg,
+            const uint16_t *__restrict__ tlist, uint32_t *__restrict__ next) {
+  const BlockTile bt = block_tile(fds, tfield);
+  const Seg sg = seg[bt.gt];
+  const uint32_t n = (uint32_t)sg.na + sg.nd;
+  const uint16_t *tl = tlist + (size_t)bt.gt * (2 * C::kHalo);
+  const Geo &g = bt.fd.g;
+  const Tile t = tile_at<C>(g, bt.tile);
+  const int ttx = t.x0 / C::TX, tty = t.y0 / C::TY, ttz = t.z0 / C::TZ;
+  for (uint32_t k = threadIdx.x; k < n; k += kBlock) {
+    const int p = tl[k];
+    const int hz = p / C::HXY, r = p - hz * C::HXY, hy = r / C::HX,
+              hx = r - hy * C::HX;
+    const int dx = hx == 0 ? -1 : (hx == C::HX - 1 ? 1 : 0);
+    const int dy = hy == 0 ? -1 : (hy == C::HY - 1 ? 1 : 0);
+    const int dz = hz == 0 ? -1 : (hz == C::HZ - 1 ? 1 : 0);
+    const uint32_t u = (uint32_t)(ttx + dx) +
+                       g.ntx * ((uint32_t)(tty + dy) + g.nty * (uint32_t)(ttz + dz));
+    const Tile tu{t.x0 + dx * C::TX, t.y0 + dy * C::TY, t.z0 + dz * C::TZ};
+    const uint32_t v = (uint32_t)(t.x0 - 1 + hx) + g.X * (uint32_t)(t.y0 - 1 + hy) +
+                       g.XY * (uint32_t)(t.z0 - 1 + hz);
+    const bool desc = k >= sg.na;
+    const uint32_t lw = bt.fd.lp[v];
+    const uint32_t code = desc ? (lw >> 16) : (lw & 0xffffu);
+    if (code & kExitCode) {
+      const Seg su = seg[bt.fd.tile0 + u];
+      next[sg.base + k] = su.base + (desc ? su.na : 0u) + (code & (kExitCode - 1));
+    } else {
+      next[sg.base + k] = kRoot | owned_global<C>(g, tu, code);
+    }
   }
 }
 
@@ -1115,12 +1173,9 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
   const uint32_t nt = (uint32_t)total_tiles;
   unsigned long long *ctr = ctx->dctr;
 
-  uint64_t exit_cap = ctx->exit_cap_hint;
-  if (exit_cap < 4096) exit_cap = 4096;
-  if (exit_cap < total_n / 8) exit_cap = total_n / 8;
-  if (exit_cap > kRoot - 1) exit_cap = kRoot - 1;
   uint64_t exits = 0;
-  uint32_t *list = nullptr, *lfield = nullptr, *next = nullptr;
+  uint32_t *next = nullptr, *bsum = nullptr;
+  uint16_t *tlist = nullptr;
   uint32_t *tkey = nullptr, *torder = nullptr, *hist = nullptr, *mm = nullptr;
   uint32_t *tfield = nullptr;
   unsigned long long *fctr = nullptr, *rstat = nullptr;
@@ -1130,43 +1185,45 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
   std::vector<uint32_t> tf_host(nt);
   for (int i = 0; i < nfields; ++i)
     for (uint32_t k = 0; k < fd[i].g.ntiles; ++k) tf_host[fd[i].tile0 + k] = i;
+  const uint32_t nsb = (nt + 1023) / 1024;  // scan blocks over tiles
 
-  for (int attempt = 0;; ++attempt) {
-    const size_t need =
-        need_lp + need_scratch + 3 * align256(exit_cap * sizeof(uint32_t)) +
-        align256(nt * sizeof(Seg)) + 3 * align256(nt * sizeof(uint32_t)) +
-        align256((kTileBuckets + 2) * sizeof(uint32_t)) +
-        align256(nfields * sizeof(FieldDev)) +
-        align256(nfields * kFieldCtrs * sizeof(unsigned long long)) +
-        align256(4ull * nt * sizeof(uint32_t)) +
-        align256(4ull * nt * sizeof(unsigned long long)) + 8192;
-    MSC_TRY(reserve(ctx->ws, need));
-    Carver cv(ctx->ws);
-    for (int i = 0; i < nfields; ++i) {
-      fd[i].f = fields[i].field;
-      fd[i].lp = cv.take<uint32_t>(fd[i].g.N);
-      fd[i].A = fields[i].asc ? fields[i].asc : cv.take<int32_t>(fd[i].g.N);
-      fd[i].D = fields[i].desc ? fields[i].desc : cv.take<int32_t>(fd[i].g.N);
-      fd[i].ms = fields[i].ms;
-      fd[i].keys = nullptr;
-      fd[i].vals = nullptr;
-      fd[i].mask = 0;
-    }
-    list = cv.take<uint32_t>(exit_cap);
-    lfield = cv.take<uint32_t>(exit_cap);
-    next = cv.take<uint32_t>(exit_cap);
-    seg = cv.take<Seg>(nt);
-    tkey = cv.take<uint32_t>(nt);
-    torder = cv.take<uint32_t>(nt);
-    tfield = cv.take<uint32_t>(nt);
-    hist = cv.take<uint32_t>(kTileBuckets + 2);
-    mm = hist + kTileBuckets;
-    fds = cv.take<FieldDev>(nfields);
-    fctr = cv.take<unsigned long long>((size_t)nfields * kFieldCtrs);
-    tstat = cv.take<uint32_t>(4ull * nt);
-    rstat = cv.take<unsigned long long>(4ull * nt);
+  const size_t need =
+      need_lp + need_scratch + align256(nt * sizeof(Seg)) +
+      3 * align256(nt * sizeof(uint32_t)) +
+      align256((kTileBuckets + 2) * sizeof(uint32_t)) +
+      align256(nfields * sizeof(FieldDev)) +
+      align256(nfields * kFieldCtrs * sizeof(unsigned long long)) +
+      align256(4ull * nt * sizeof(uint32_t)) +
+      align256(4ull * nt * sizeof(unsigned long long)) +
+      align256(2ull * C::kHalo * nt * sizeof(uint16_t)) +
+      align256(nsb * sizeof(uint32_t)) + 8192;
+  MSC_TRY(reserve(ctx->ws, need));
+  Carver cv(ctx->ws);
+  for (int i = 0; i < nfields; ++i) {
+    fd[i].f = fields[i].field;
+    fd[i].lp = cv.take<uint32_t>(fd[i].g.N);
+    fd[i].A = fields[i].asc ? fields[i].asc : cv.take<int32_t>(fd[i].g.N);
+    fd[i].D = fields[i].desc ? fields[i].desc : cv.take<int32_t>(fd[i].g.N);
+    fd[i].ms = fields[i].ms;
+    fd[i].keys = nullptr;
+    fd[i].vals = nullptr;
+    fd[i].mask = 0;
+  }
+  seg = cv.take<Seg>(nt);
+  tkey = cv.take<uint32_t>(nt);
+  torder = cv.take<uint32_t>(nt);
+  tfield = cv.take<uint32_t>(nt);
+  hist = cv.take<uint32_t>(kTileBuckets + 2);
+  mm = hist + kTileBuckets;
+  fds = cv.take<FieldDev>(nfields);
+  fctr = cv.take<unsigned long long>((size_t)nfields * kFieldCtrs);
+  tstat = cv.take<uint32_t>(4ull * nt);
+  rstat = cv.take<unsigned long long>(4ull * nt);
+  tlist = cv.take<uint16_t>(2ull * C::kHalo * nt);
+  bsum = cv.take<uint32_t>(nsb);
 
-    // Descriptors and the tile -> field map go up through pinned staging.
+  // Descriptors and the tile -> field map go up through pinned staging.
+  {
     char *st = nullptr;
     const size_t fbytes = nfields * sizeof(FieldDev), tbytes = nt * 4ull;
     MSC_TRY(stage(ctx, fbytes + tbytes, &st));
@@ -1175,28 +1232,29 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
     MSC_HIP_TRY(hipMemcpyAsync(fds, st, fbytes, hipMemcpyHostToDevice, s));
     MSC_HIP_TRY(hipMemcpyAsync(tfield, st + fbytes, tbytes,
                                hipMemcpyHostToDevice, s));
-    MSC_TRY(clear_counters(ctx, s));
-    k_fill_u64<<<grid_for((uint64_t)nfields * kFieldCtrs), kBlock, 0, s>>>(
-        fctr, (uint32_t)(nfields * kFieldCtrs), 0ull);
-    k_fill_u32<<<grid_for(kTileBuckets + 2), kBlock, 0, s>>>(
-        hist, kTileBuckets + 2, 0u);
-    k_fill_u32<<<1, kBlock, 0, s>>>(mm, 1, ~0u);
-    MSC_HIP_TRY(hipGetLastError());
-    k_fill_u32<<<grid_for(4ull * nt), kBlock, 0, s>>>(tstat, 4 * nt, 0u);
-    ExitOut xo{list, lfield, seg, tkey, tstat, (uint32_t)exit_cap};
-    MSC_PHASE(ctx, s, "tile_local", 8.0 * total_n,
-              (k_tile_local<C><<<nt, C::kThreads, 0, s>>>(fds, tfield, xo, ctr,
-                                                          fctr)));
-    for (int k = 0; k < 2; ++k)
-      k_tile_stat_reduce<<<grid_for(nt), kBlock, 0, s>>>(
-          tstat, k, nt, tfield, fctr, k ? kFMinima : kFMaxima);
-    MSC_TRY(read_counters(ctx, s));
-    exits = ctx->hctr[kCtrExits];
-    if (exits <= exit_cap) break;
-    if (attempt > 0 || exits >= kRoot) return MSC_ENOMEM;
-    exit_cap = exits + exits / 4;
   }
-  ctx->exit_cap_hint = exit_cap;
+  MSC_TRY(clear_counters(ctx, s));
+  k_fill_u64<<<grid_for((uint64_t)nfields * kFieldCtrs), kBlock, 0, s>>>(
+      fctr, (uint32_t)(nfields * kFieldCtrs), 0ull);
+  k_fill_u32<<<grid_for(kTileBuckets + 2), kBlock, 0, s>>>(
+      hist, kTileBuckets + 2, 0u);
+  k_fill_u32<<<1, kBlock, 0, s>>>(mm, 1, ~0u);
+  k_fill_u32<<<grid_for(4ull * nt), kBlock, 0, s>>>(tstat, 4 * nt, 0u);
+  MSC_HIP_TRY(hipGetLastError());
+  ExitOut xo{seg, tkey, tstat, tlist};
+  MSC_PHASE(ctx, s, "tile_local", 8.0 * total_n,
+            (k_tile_local<C><<<nt, C::kThreads, 0, s>>>(fds, tfield, xo, ctr,
+                                                        fctr)));
+  for (int k = 0; k < 2; ++k)
+    k_tile_stat_reduce<<<grid_for(nt), kBlock, 0, s>>>(
+        tstat, k, nt, tfield, fctr, k ? kFMinima : kFMaxima);
+  MSC_PHASE(ctx, s, "exit_scan", 12.0 * nt,
+            (k_seg_scan_blocks<<<nsb, 1024, 0, s>>>(seg, nt, bsum),
+             k_seg_scan_sums<<<1, 1024, 0, s>>>(bsum, nsb, ctr),
+             k_seg_scan_add<<<grid_for(nt), kBlock, 0, s>>>(seg, nt, bsum)));
+  MSC_TRY(read_counters(ctx, s));
+  exits = ctx->hctr[kCtrExits];
+  if (exits >= kRoot) return MSC_ENOMEM;
 
   // Per-field counters: NaN check and table sizes.
   std::vector<unsigned long long> fc((size_t)nfields * kFieldCtrs);
@@ -1208,9 +1266,11 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
 
   if (exits) {
     const uint32_t ne = (uint32_t)exits;
+    MSC_TRY(reserve(ctx->xg, align256(ne * sizeof(uint32_t))));
+    next = reinterpret_cast<uint32_t *>(ctx->xg.ptr);
     MSC_PHASE(ctx, s, "exit_link", 18.0 * ne,
-              (k_exit_link<C><<<grid_for(ne), kBlock, 0, s>>>(
-                  list, lfield, ne, fds, seg, next)));
+              (k_exit_link<C><<<nt, kBlock, 0, s>>>(fds, tfield, seg, tlist,
+                                                    next)));
     MSC_PHASE(ctx, s, "tile_order", 12.0 * nt,
               (k_key_minmax<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm),
                k_key_hist<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm, hist),
