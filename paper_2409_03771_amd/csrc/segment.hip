@@ -58,6 +58,7 @@ struct Cfg {
   static_assert(kThreads % 64 == 0 && kThreads <= 1024, "block shape");
   static_assert((2 * H + 3) / 4 + 3 * kWords <= H,
                 "exit flags and bitsets alias the pointer array");
+  static_assert(kHalo <= (2 * H + 3) / 4, "the exit list fits the flag bytes");
   static_assert(TX * TY * TZ <= 0x8000 && kHalo < 0x8000,
                 "local pointer codes are 15-bit");
 };
@@ -406,7 +407,6 @@ k_tile_local(const FieldDev *__restrict__ fds,
 #undef MSC_HI
     const bool in = lz < nz;
     any_nan |= in && fv != fv;
-    fsum += in ? fv : 0.f;
     ptr[lz] = in ? (uint32_t)(i + omax) | ((uint32_t)(i + omin) << 16)
                  : (uint32_t)i | ((uint32_t)i << 16);
     nmax += __popcll(__ballot(in && omax == 0));
@@ -416,6 +416,11 @@ k_tile_local(const FieldDev *__restrict__ fds,
   }
   wave_count(any_nan, fc + kFNaN);
   // Extremum counts (wave totals above) of the tile.
+  // The column's sum for the tile mean, in a pass of its own: accumulating
+  // it inside the steepest loop above costs that loop dozens of registers.
+#pragma unroll
+  for (int lz = 0; lz < C::TZ; ++lz)
+    if (lz < nz) fsum += __uint_as_float(lds[c0 + (lz + 1) * HXY]);
   for (int o = 32; o > 0; o >>= 1) fsum += __shfl_xor(fsum, o);
   if ((tid & 63) == 0) {
     s_wsum[tid >> 6] = fsum;
@@ -426,6 +431,14 @@ k_tile_local(const FieldDev *__restrict__ fds,
     unsigned c = 0;
     for (int w = 0; w < T / 64; ++w) c += (s_wext[w] >> (16 * tid)) & 0xffffu;
     xo.tstat[4 * (size_t)bt.gt + tid] = c;
+  } else if (tid == 64) {
+    // Mean value of the tile: the order in which exits get resolved.  Taken
+    // here, so that nothing it needs stays live through the later phases.
+    float sum = 0.f;
+    for (int w = 0; w < T / 64; ++w) sum += s_wsum[w];
+    const int cnt = min(C::TX, (int)g.X - t.x0) * min(C::TY, (int)g.Y - t.y0) *
+                    min(C::TZ, (int)g.Z - t.z0);
+    xo.tkey[bt.gt] = float_key(sum / (float)cnt);
   }
 
   // Pointers replace the field: halo vertices point to themselves (whole
@@ -548,10 +561,11 @@ k_tile_local(const FieldDev *__restrict__ fds,
   }
 
   // The tile's exits for the exit graph, by their tile-local numbers (the
-  // numbers become global with a scan over tiles afterwards): a wave takes
-  // 64 consecutive halo indices, so each lane reads the same two words.
+  // numbers become global with a scan over tiles afterwards).  The list is
+  // built in the flag bytes, no longer read, and copied out in dwords; a
+  // wave takes 64 consecutive halo indices, so its lanes share two words.
   {
-    uint16_t *tl = xo.tlist + (size_t)bt.gt * (2 * C::kHalo);
+    uint16_t *sl = reinterpret_cast<uint16_t *>(lds);
     const int lane = tid & 63;
     for (int b = tid - lane; b < H; b += T) {
       const int p = b + lane;
@@ -559,20 +573,16 @@ k_tile_local(const FieldDev *__restrict__ fds,
       const uint32_t w = (uint32_t)p >> 5, below = (1u << (p & 31)) - 1u;
       const uint32_t ba = xa[w], bd = xd[w];
       if ((ba >> (p & 31)) & 1u)
-        tl[(pre[w] & 0xffffu) + __popc(ba & below)] = (uint16_t)p;
+        sl[(pre[w] & 0xffffu) + __popc(ba & below)] = (uint16_t)p;
       if ((bd >> (p & 31)) & 1u)
-        tl[na + (pre[w] >> 16) + __popc(bd & below)] = (uint16_t)p;
+        sl[na + (pre[w] >> 16) + __popc(bd & below)] = (uint16_t)p;
     }
+    __syncthreads();
+    uint32_t *tl = reinterpret_cast<uint32_t *>(xo.tlist +
+                                                (size_t)bt.gt * (2 * C::kHalo));
+    for (uint32_t w = tid; w < (na + nd + 1) / 2; w += T) tl[w] = lds[w];
   }
-  if (tid == 0) {
-    xo.seg[bt.gt] = Seg{0u, (uint16_t)na, (uint16_t)nd};
-      // Mean value of the tile: the order in which exits get resolved.
-    float sum = 0.f;
-    for (int w = 0; w < T / 64; ++w) sum += s_wsum[w];
-    const int cnt = min(C::TX, (int)g.X - t.x0) * min(C::TY, (int)g.Y - t.y0) *
-                    min(C::TZ, (int)g.Z - t.z0);
-    xo.tkey[bt.gt] = float_key(sum / (float)cnt);
-  }
+  if (tid == 0) xo.seg[bt.gt] = Seg{0u, (uint16_t)na, (uint16_t)nd};
 }
 
 // ---------------------------------------------------------------------------
