@@ -71,8 +71,8 @@ def cmd_stats(args):
             f"{float(r['AverageNs']) / 1e6:.3f} | {float(r['MinNs']) / 1e6:.3f}"
             f" | {float(r['MaxNs']) / 1e6:.3f} | "
             f"{100 * float(r['TotalDurationNs']) / total:.1f}% |")
-    lines += ["", f"Library kernels total per call of the traced program: "
-              f"{total / 1e6:.3f} ms over all calls listed."]
+    lines += ["", f"Sum over all launches of the library's kernels in the traced "
+              f"run: {total / 1e6:.3f} ms."]
     _write(args.out, lines)
 
 
