@@ -337,27 +337,39 @@ def run_plain(msc, torch, dev, pool, trace, warm):
 
 
 def served_sweep(msc, synth, torch, dev, rates, warm, count, pool_size,
-                 budget_gib=64, max_batch=64):
+                 budget_gib=64, max_batch=64, resident_rates=()):
+    """Per rate: the queue and plain sequential calls on the same trace with
+    host inputs (the H2D copy is part of each request); per resident rate,
+    the same with the inputs already in device memory."""
     log(f"[bench] serve pool of {pool_size} fields")
     pool = serve_pool(synth, torch, dev, pool_size)
-    out = {}
-    for rate in rates:
-        trace = synth.poisson_trace(float(rate), warm + count, seed=4)
-        srv = run_served(msc, pool, trace, warm, budget_gib << 30, max_batch)
-        plain = run_plain(msc, torch, dev, pool, trace, warm)
-        log(f"[bench] {rate:5d} req/s served {srv} plain {plain}")
-        out[str(rate)] = {**srv, "plain_p50_ms": plain["p50_ms"],
-                          "plain_p99_ms": plain["p99_ms"],
-                          "plain_gvps": plain["gvps"]}
+    out, out_res = {}, {}
+    for rates_, pool_, dst, tag in ((rates, pool, out, "host"),
+                                    (resident_rates, None, out_res,
+                                     "resident")):
+        if tag == "resident" and resident_rates:
+            pool_ = [(fh.to(dev), mh.to(dev)) for fh, mh in pool]
+        for rate in rates_:
+            trace = synth.poisson_trace(float(rate), warm + count, seed=4)
+            srv = run_served(msc, pool_, trace, warm, budget_gib << 30,
+                             max_batch)
+            plain = run_plain(msc, torch, dev, pool_, trace, warm)
+            log(f"[bench] {rate:5d} req/s {tag} served {srv} plain {plain}")
+            dst[str(rate)] = {**srv, "plain_p50_ms": plain["p50_ms"],
+                              "plain_p99_ms": plain["p99_ms"],
+                              "plain_gvps": plain["gvps"],
+                              "speedup_vs_plain": round(
+                                  srv["gvps"] / plain["gvps"], 2)}
     text = SERVE_TEXT.format(pool=pool_size, budget=budget_gib,
                              max_batch=max_batch)
-    return text, out
+    return text, out, out_res
 
 
 def bench_serve(args, msc, synth, torch, dev):
     rates = [int(r) for r in args.rates.split(",")]
-    text, res = served_sweep(msc, synth, torch, dev, rates, args.serve_warmup,
-                             args.serve_requests, args.serve_pool)
+    text, res, res_dev = served_sweep(
+        msc, synth, torch, dev, rates, args.serve_warmup, args.serve_requests,
+        args.serve_pool, resident_rates=rates)
     top = res[str(rates[-1])]
     out = {
         "metric": "Gvertices/s served MS segmentation + mask CC; "
@@ -367,7 +379,7 @@ def bench_serve(args, msc, synth, torch, dev):
         "ms_per_step": None, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": text, "requests_per_rate": args.serve_requests,
-                   "rates": res,
+                   "rates": res, "rates_device_resident_inputs": res_dev,
                    "speedup_vs_plain": round(top["gvps"] / top["plain_gvps"], 2)},
     }
     print(json.dumps(out), flush=True)
@@ -381,7 +393,7 @@ def main():
     ap.add_argument("--workload", default="gauss1024",
                     choices=sorted(WORKLOAD_TEXT) + ["batch256", "serve",
                                                      "cc1024", "csr50m"])
-    ap.add_argument("--cpu-depth", type=int, default=40,
+    ap.add_argument("--cpu-depth", type=int, default=100,
                     help="z-planes of the field the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--rates", default="50,100,200,500,1000,2000",
@@ -498,10 +510,11 @@ def main():
         # Short served leg: one light and one saturating arrival rate.
         del field, asc, desc, ms
         torch.cuda.empty_cache()
-        text, res = served_sweep(msc, synth, torch, dev, [200, 2000], 50, 300,
-                                 24)
+        text, res, res_dev = served_sweep(msc, synth, torch, dev, [200, 2000],
+                                          50, 300, 24, resident_rates=[2000])
         out["served"] = {"workload": text, "requests_per_rate": 300,
-                         "rates": res}
+                         "rates": res,
+                         "rates_device_resident_inputs": res_dev}
     print(json.dumps(out), flush=True)
 
 

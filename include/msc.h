@@ -264,9 +264,10 @@ MSC_API int msc_pointer_jump(msc_ctx *ctx, int64_t *d, int64_t n, int rounds,
  *  MSC_ENOMEM (arena allocation failed), MSC_EHIP.  Starts three host
  *  threads; msc_queue_destroy joins them after the running launches end and
  *  frees everything, including unreleased results.
- *  msc_request.host_input: host memory the queue reads until the request
- *  is staged (page-locked memory makes the copy asynchronous); float32[N]
- *  for MSC_REQ_SEGMENT, uint8 mask[N] for MSC_REQ_CC_GRID.
+ *  msc_request.host_input: the input, read until the request is staged:
+ *  host memory (page-locked memory makes the copy asynchronous) or device
+ *  memory of the queue's device; float32[N] for MSC_REQ_SEGMENT, uint8
+ *  mask[N] for MSC_REQ_CC_GRID.  It is copied into the queue's arena.
  *  msc_submit: MSC_EBUDGET if the request alone exceeds the budget,
  *  MSC_EINVAL / MSC_ERANGE as msc_segment.  *ticket names the request.
  *  msc_poll: *status = MSC_EBUSY while queued or running, MSC_ECANCELED, or
@@ -285,7 +286,7 @@ typedef struct msc_queue msc_queue;
 typedef struct msc_request {
   int kind;                /* MSC_REQ_SEGMENT or MSC_REQ_CC_GRID      */
   int64_t dims[3];         /* X, Y, Z                                 */
-  const void *host_input;  /* float32 field or uint8 mask, host       */
+  const void *host_input;  /* float32 field or uint8 mask (host or device) */
 } msc_request;
 
 typedef struct msc_result {

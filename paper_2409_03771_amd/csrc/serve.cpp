@@ -7,7 +7,8 @@
 //   dispatcher   admits pending requests in arrival order while their
 //                footprint (resident buffers plus the workspace their launch
 //                needs) fits the budget, places their buffers in the arena and
-//                copies their inputs to the device on a copy stream;
+//                copies their inputs to the device, round-robin over a few
+//                copy streams so that several DMA engines share the link;
 //   seg worker   takes every admitted segmentation request whose launch slot
 //                is free -- requests that arrived while the previous launch
 //                ran join the next one -- and segments them in one batched
@@ -111,7 +112,9 @@ struct msc_queue {
   Arena alloc;
   size_t inflight_ws = 0;
   msc_ctx *ctx_seg = nullptr, *ctx_cc = nullptr;
-  hipStream_t s_copy = nullptr, s_seg = nullptr, s_cc = nullptr;
+  static constexpr int kCopyStreams = 4;  // copies spread over DMA engines
+  hipStream_t s_copy[kCopyStreams] = {}, s_seg = nullptr, s_cc = nullptr;
+  int next_copy = 0;
   std::mutex mu;
   std::condition_variable cv;
   std::deque<Request *> pending, ready_seg, ready_cc;
@@ -149,11 +152,14 @@ void dispatcher_loop(msc_queue *q) {
       r->off = off;
       r->dev = q->arena + off;
       q->inflight_ws += r->ws_bytes;
+      hipStream_t cs = q->s_copy[q->next_copy];
+      q->next_copy = (q->next_copy + 1) % msc_queue::kCopyStreams;
       lk.unlock();
       int rc = MSC_OK;
-      if (hipMemcpyAsync(r->dev, r->host_in, r->in_bytes,
-                         hipMemcpyHostToDevice, q->s_copy) != hipSuccess ||
-          hipEventRecord(r->copied, q->s_copy) != hipSuccess)
+      // The input may be host or device memory (unified addressing).
+      if (hipMemcpyAsync(r->dev, r->host_in, r->in_bytes, hipMemcpyDefault,
+                         cs) != hipSuccess ||
+          hipEventRecord(r->copied, cs) != hipSuccess)
         rc = MSC_EHIP;
       lk.lock();
       if (rc != MSC_OK) {
@@ -275,13 +281,15 @@ int msc_queue_create(int device, size_t hbm_budget, int max_batch,
   if (rc == MSC_OK) {
     int prev = -1;
     (void)hipGetDevice(&prev);
-    if (hipSetDevice(device) != hipSuccess ||
-        hipStreamCreateWithFlags(&q->s_copy, hipStreamNonBlocking) !=
-            hipSuccess ||
-        hipStreamCreateWithFlags(&q->s_seg, hipStreamNonBlocking) !=
-            hipSuccess ||
-        hipStreamCreateWithFlags(&q->s_cc, hipStreamNonBlocking) !=
-            hipSuccess)
+    bool ok = hipSetDevice(device) == hipSuccess;
+    for (int k = 0; ok && k < msc_queue::kCopyStreams; ++k)
+      ok = hipStreamCreateWithFlags(&q->s_copy[k], hipStreamNonBlocking) ==
+           hipSuccess;
+    ok = ok &&
+         hipStreamCreateWithFlags(&q->s_seg, hipStreamNonBlocking) ==
+             hipSuccess &&
+         hipStreamCreateWithFlags(&q->s_cc, hipStreamNonBlocking) == hipSuccess;
+    if (!ok)
       rc = MSC_EHIP;
     else if (hipMalloc(&q->arena, hbm_budget) != hipSuccess)
       rc = MSC_ENOMEM;
@@ -318,7 +326,8 @@ void msc_queue_destroy(msc_queue *q) {
     delete kv.second;
   }
   if (q->arena) (void)hipFree(q->arena);
-  if (q->s_copy) (void)hipStreamDestroy(q->s_copy);
+  for (hipStream_t cs : q->s_copy)
+    if (cs) (void)hipStreamDestroy(cs);
   if (q->s_seg) (void)hipStreamDestroy(q->s_seg);
   if (q->s_cc) (void)hipStreamDestroy(q->s_cc);
   if (prev >= 0) (void)hipSetDevice(prev);

@@ -378,11 +378,11 @@ class Server:
 
     def submit(self, kind: int, host_input) -> int:
         """Queue a segmentation (float32 field) or mask-CC (uint8 mask)
-        request; `host_input` is a C-contiguous numpy array or CPU tensor of
-        shape [Z, Y, X] (or 1-D / 2-D)."""
+        request; `host_input` is a C-contiguous numpy array, or a host or
+        device tensor, of shape [Z, Y, X] (or 1-D / 2-D)."""
         if isinstance(host_input, torch.Tensor):
-            if host_input.is_cuda or not host_input.is_contiguous():
-                raise ValueError("host_input must be a contiguous host tensor")
+            if not host_input.is_contiguous():
+                raise ValueError("the input must be a contiguous tensor")
             want = torch.float32 if kind == REQ_SEGMENT else torch.uint8
             if host_input.dtype != want:
                 raise TypeError(f"host_input must be {want}")

@@ -165,3 +165,23 @@ def test_nan_request_fails_alone(msc):
                 assert rc == msc.MSC_OK
                 _check(k, a, srv.fetch(t), f"request {i}")
             srv.release(t)
+
+
+def test_device_inputs_match_host_inputs(msc):
+    """Inputs already in device memory are copied within the device and give
+    the same results as host inputs."""
+    reqs = _requests(12, seed=21)
+    with msc.Server(hbm_budget=512 << 20, max_batch=8) as srv:
+        host = [srv.submit(k, a) for k, a in reqs]
+        dev = [srv.submit(k, torch.from_numpy(a).cuda()) for k, a in reqs]
+        for th, td, (k, a) in zip(host, dev, reqs):
+            assert srv.wait(th) == msc.MSC_OK and srv.wait(td) == msc.MSC_OK
+            gh, gd = srv.fetch(th), srv.fetch(td)
+            if k == 1:
+                for x, y in zip(gh, gd):
+                    np.testing.assert_array_equal(x, y)
+            else:
+                np.testing.assert_array_equal(gh, gd)
+            _check(k, a, gd, f"device input {a.shape}")
+            srv.release(th)
+            srv.release(td)
