@@ -819,14 +819,17 @@ __device__ __forceinline__ void decode_setup(Decode<C> &s, uint32_t gt,
   __syncthreads();
 }
 
-// Final extremum of a stored local pointer code.
+// Final extremum of a stored local pointer code, without branches (this is
+// unrolled over a whole column): both readings are formed, one is kept.
 template <class C>
 __device__ __forceinline__ int32_t decode_final(const Decode<C> &s,
                                                 const Geo &g, const Tile &t,
                                                 uint32_t code, bool desc) {
-  if (code & kExitCode)
-    return s.res[(desc ? s.na : 0u) + (code & (kExitCode - 1))];
-  return (int32_t)owned_global<C>(g, t, code);
+  const bool ex = (code & kExitCode) != 0u;
+  const uint32_t low = code & (kExitCode - 1);
+  const int32_t r = s.res[ex ? (desc ? s.na : 0u) + low : 0u];
+  const int32_t o = (int32_t)owned_global<C>(g, t, low);
+  return ex ? r : o;
 }
 
 __global__ void k_table_clear(unsigned long long *keys, int32_t *vals,
@@ -845,6 +848,7 @@ __device__ __forceinline__ bool table_insert(unsigned long long *keys,
                                              unsigned long long key,
                                              int32_t id, unsigned *fresh) {
   uint32_t h = (uint32_t)mix64(key) & mask;
+#pragma unroll 1
   for (uint32_t probe = 0; probe <= mask; ++probe) {
     unsigned long long cur = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
     if (cur == kEmptyKey) {
@@ -874,7 +878,11 @@ __device__ __forceinline__ unsigned long long pair_key(int32_t a, int32_t d) {
 // has about three vertices); once half the slots are taken the table accepts
 // no new pair, probes stay short, and the remaining vertices take the
 // per-vertex path.  Linear probing without deletion: a pair that is in the
-// table is found before any empty slot.
+// table is found before any empty slot.  A lane consults the table only when
+// its column's pair changes from one z to the next (a repeated pair has a
+// larger id than the one already recorded), which in smooth regions is once
+// or twice per column; concurrent inserts of one pair meet in one slot
+// through the compare-and-swap.
 constexpr int kPairSlots = 2048;
 constexpr unsigned kPairLimit = kPairSlots / 2;
 constexpr int kPairProbes = 16;
@@ -883,6 +891,7 @@ __device__ __forceinline__ int pair_slot(unsigned long long *skey,
                                          unsigned *fill,
                                          unsigned long long key) {
   uint32_t h = (uint32_t)mix64(key) & (kPairSlots - 1);
+#pragma unroll 1
   for (int probe = 0; probe < kPairProbes; ++probe) {
     unsigned long long cur = skey[h];
     if (cur == kEmptyKey) {
@@ -899,56 +908,11 @@ __device__ __forceinline__ int pair_slot(unsigned long long *skey,
   return -1;
 }
 
-__device__ __forceinline__ unsigned long long wave_bcast64(
-    unsigned long long x, int lane) {
-  uint32_t lo = __builtin_amdgcn_readlane((uint32_t)x, lane);
-  uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(x >> 32), lane);
-  return ((unsigned long long)hi << 32) | lo;
-}
-
-// Slot of every lane's pair (-1: not in the table).  Leader rounds first:
-// the lanes sharing the first pending lane's pair take one insert by that
-// lane, which holds their smallest vertex id (ids grow with the lane inside
-// a wave: rows of the tile are consecutive in y).  Smooth regions have a few
-// large groups per wave and end here; once a round merges fewer than 8
-// lanes (noise), the remaining lanes insert their own pairs in parallel.
-// With `sval`, each lane's id is folded into its slot's minimum.
-__device__ __forceinline__ int wave_pair_slot(unsigned long long *skey,
-                                              int32_t *sval, unsigned *fill,
-                                              bool in, unsigned long long key,
-                                              int32_t id) {
-  const int lane = threadIdx.x & 63;
-  int slot = -1;
-  bool pending = in;
-  for (int round = 0; round < 4; ++round) {
-    const unsigned long long m = __ballot(pending);
-    if (!m) return slot;
-    const int leader = __ffsll((long long)m) - 1;
-    const unsigned long long lkey = wave_bcast64(key, leader);
-    int ls = 0;
-    if (lane == leader) {
-      ls = pair_slot(skey, fill, lkey);
-      if (sval && ls >= 0) atomicMin(&sval[ls], id);
-    }
-    ls = __builtin_amdgcn_readlane(ls, leader);
-    const bool mine = pending && key == lkey;
-    if (mine) {
-      slot = ls;
-      pending = false;
-    }
-    if (__popcll(__ballot(mine)) < 8) break;
-  }
-  if (pending) {
-    slot = pair_slot(skey, fill, key);
-    if (sval && slot >= 0) atomicMin(&sval[slot], id);
-  }
-  return slot;
-}
-
 __device__ __forceinline__ int32_t table_lookup(
     const unsigned long long *__restrict__ keys,
     const int32_t *__restrict__ vals, uint32_t mask, unsigned long long key) {
   uint32_t h = (uint32_t)mix64(key) & mask;
+#pragma unroll 1
   for (uint32_t probe = 0; probe <= mask; ++probe) {
     const unsigned long long cur = keys[h];
     if (cur == key) return vals[h];
@@ -1003,16 +967,17 @@ k_tile_pairs(const FieldDev *__restrict__ fds,
     if (lz < nz)
       key = pair_key(decode_final<C>(s, g, t, code[lz] & 0xffffu, false),
                      decode_final<C>(s, g, t, code[lz] >> 16, true));
-    const bool fresh_key = key != last && key != kEmptyKey;
-    if (__ballot(fresh_key)) {
+    if (key != last && key != kEmptyKey) {
+      last = key;
       const int32_t id = (int32_t)((uint32_t)gx + g.X * (uint32_t)gy +
                                    g.XY * (uint32_t)(t.z0 + lz));
-      const int slot = wave_pair_slot(skey, sval, &sfill, fresh_key, key, id);
-      if (fresh_key && slot < 0 &&
-          !table_insert(bt.fd.keys, bt.fd.vals, bt.fd.mask, key, id, &fresh))
+      const int slot = pair_slot(skey, &sfill, key);
+      if (slot >= 0)
+        atomicMin(&sval[slot], id);
+      else if (!table_insert(bt.fd.keys, bt.fd.vals, bt.fd.mask, key, id,
+                             &fresh))
         overflow = true;
     }
-    if (fresh_key) last = key;
   }
   __syncthreads();
   for (int i = tid; i < kPairSlots; i += C::kThreads) {
@@ -1085,16 +1050,12 @@ k_tile_write(const FieldDev *__restrict__ fds,
     slot[lz] = -1;
     if (ms) {  // uniform over the block: ms belongs to the field
       const unsigned long long key = pair_key(a, d);
-      const bool fresh_key = in && key != last;
-      if (__ballot(fresh_key)) {
-        const int sl = wave_pair_slot(skey, nullptr, &sfill, fresh_key, key, 0);
-        if (fresh_key) {
-          last_slot = sl;
-          if (sl < 0)  // not in the tile's table: look this pair up alone
-            last_cell = table_lookup(bt.fd.keys, bt.fd.vals, bt.fd.mask, key);
-        }
+      if (in && key != last) {
+        last = key;
+        last_slot = pair_slot(skey, &sfill, key);
+        if (last_slot < 0)  // not in the tile's table: look this pair up alone
+          last_cell = table_lookup(bt.fd.keys, bt.fd.vals, bt.fd.mask, key);
       }
-      if (fresh_key) last = key;
       if (in) {
         slot[lz] = (int16_t)last_slot;
         if (last_slot < 0) ms[v] = last_cell;
