@@ -331,23 +331,29 @@ k_tile_local(const FieldDev *__restrict__ fds,
   const float *__restrict__ f = bt.fd.f;
   unsigned long long *fc = fctr + (size_t)bt.fi * kFieldCtrs;
   const Tile t = tile_at<C>(g, bt.tile);
-  // Stage the tile and its halo, one z-column of the tile-plus-halo box at a
-  // time (consecutive threads take consecutive x: coalesced rows); positions
-  // outside the domain hold NaN, which loses every comparison below and so
-  // is never chosen.
-  const uint32_t kNaN = 0x7fc00000u;
-  for (int col = tid; col < HXY; col += T) {
-    const int hy = col / HX, hx = col - hy * HX;
-    const int gx = t.x0 - 1 + hx, gy = t.y0 - 1 + hy;
-    const bool in_xy = gx >= 0 && gx < (int)g.X && gy >= 0 && gy < (int)g.Y;
-    const float *src = f + (in_xy ? (uint32_t)gx + g.X * (uint32_t)gy : 0u);
+  // Stage the tile and its halo: each thread issues all its loads before
+  // the first LDS store, so the block waits for one memory round trip
+  // (consecutive threads take consecutive indices: coalesced rows).
+  // Positions outside the domain hold NaN, which loses every comparison
+  // below and so is never chosen.
+  {
+    constexpr int K = (H + T - 1) / T;
+    const uint32_t kNaN = 0x7fc00000u;
+    uint32_t val[K];
 #pragma unroll
-    for (int hz = 0; hz < C::HZ; ++hz) {
-      const int gz = t.z0 - 1 + hz;
-      const bool in = in_xy && gz >= 0 && gz < (int)g.Z;
-      lds[col + hz * HXY] =
-          in ? __float_as_uint(src[g.XY * (uint32_t)gz]) : kNaN;
+    for (int k = 0; k < K; ++k) {
+      const int i = tid + k * T;
+      const int hz = i / HXY, r = i - hz * HXY, hy = r / HX, hx = r - hy * HX;
+      const int gx = t.x0 - 1 + hx, gy = t.y0 - 1 + hy, gz = t.z0 - 1 + hz;
+      const bool in = i < H && gx >= 0 && gx < (int)g.X && gy >= 0 &&
+                      gy < (int)g.Y && gz >= 0 && gz < (int)g.Z;
+      val[k] = in ? __float_as_uint(f[(uint32_t)gx + g.X * (uint32_t)gy +
+                                      g.XY * (uint32_t)gz])
+                  : kNaN;
     }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (tid + k * T < H) lds[tid + k * T] = val[k];
   }
   __syncthreads();
 
