@@ -196,75 +196,108 @@ k_cc_tile(const uint8_t *__restrict__ mask, CGeo g, uint16_t *__restrict__ loc,
 // that owns its lower endpoint, which sees it as one of the 7 higher-id
 // neighbours leaving the tile through an upper face.  Both endpoints are
 // replaced by their tile-local roots, and each distinct (local root,
-// neighbour tile, its local root) triple is united once: a face of a smooth
-// mask carries thousands of edges but only a few such triples.
+// neighbour tile, its local root) triple is united once, after the block has
+// collected them: a face of a smooth mask carries thousands of edges but
+// only a few such triples.
 constexpr int kCrossSlots = 2048;
 constexpr int kCrossProbes = 16;
 
-// Inserts key into the block's set; true if this call inserted it (or the
-// set is full and the caller must act on the key itself).
-__device__ __forceinline__ bool cross_first(uint32_t *set, uint32_t key) {
+constexpr uint32_t kNoKey = 0xffffffffu;
+
+// Inserts key into the block's set; false only when the set has no room
+// for it (the caller then unites the pair itself).
+__device__ __forceinline__ bool cross_insert(uint32_t *set, uint32_t key) {
   uint32_t h = (key * 0x9e3779b1u) >> (32 - 11);
+#pragma unroll 1
   for (int probe = 0; probe < kCrossProbes; ++probe) {
     uint32_t cur = set[h];
-    if (cur == key) return false;
-    if (cur == 0xffffffffu) {
-      cur = atomicCAS(&set[h], 0xffffffffu, key);
-      if (cur == 0xffffffffu) return true;
-      if (cur == key) return false;
+    if (cur == key) return true;
+    if (cur == kNoKey) {
+      cur = atomicCAS(&set[h], kNoKey, key);
+      if (cur == kNoKey || cur == key) return true;
     }
     h = (h + 1) & (kCrossSlots - 1);
   }
-  return true;
+  return false;
+}
+
+// The two global ids a key stands for: the local root lv of tile t and the
+// local root lu of the neighbour tile (bit k of nbr: one tile up along axis k).
+__device__ __forceinline__ void cross_unite(const CGeo &g, const CTile &t,
+                                            uint32_t key, int64_t *L) {
+  const uint32_t lv = key & 0x1fffu, nbr = (key >> 13) & 7u, lu = key >> 16;
+  const CTile tu{t.x0 + (nbr & 1u ? CTX : 0), t.y0 + (nbr & 2u ? CTY : 0),
+                 t.z0 + (nbr & 4u ? CTZ : 0)};
+  uf_unite<int64_t>(L, ctile_global(g, t, (int)lv),
+                    ctile_global(g, tu, (int)lu));
 }
 
 __global__ void __launch_bounds__(kCThreads)
-k_cc_cross(const uint8_t *__restrict__ mask, CGeo g,
-           const uint16_t *__restrict__ loc, int64_t *L) {
+k_cc_cross(CGeo g, const uint16_t *__restrict__ loc, int64_t *L) {
   static_assert(kCOwned <= (1 << 13), "13-bit local roots in the keys");
+  // The tile grown by one vertex on its upper sides; only the two upper
+  // layers of each side are read: the tile's upper faces and the vertices
+  // just beyond them.  Entries hold tile-local roots (kOutside: unmasked or
+  // outside the domain), decoded with their own tile's origin later.
+  constexpr int BX = CTX + 1, BY = CTY + 1, BZ = CTZ + 1, BXY = BX * BY;
+  constexpr int BN = BXY * BZ, K = (BN + kCThreads - 1) / kCThreads;
+  __shared__ uint16_t box[BN];
   __shared__ uint32_t set[kCrossSlots];
   const int tid = threadIdx.x;
-  for (int i = tid; i < kCrossSlots; i += kCThreads) set[i] = 0xffffffffu;
-  __syncthreads();
+  for (int i = tid; i < kCrossSlots; i += kCThreads) set[i] = kNoKey;
   const CTile t = ctile_at(g, cc_tile_of_block(blockIdx.x, gridDim.x));
+  {
+    uint16_t val[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int i = tid + k * kCThreads;
+      const int bz = i / BXY, r = i - bz * BXY, by = r / BX, bx = r - by * BX;
+      const bool shell = bx >= CTX - 1 || by >= CTY - 1 || bz >= CTZ - 1;
+      const int64_t x = t.x0 + bx, y = t.y0 + by, z = t.z0 + bz;
+      const bool in = i < BN && shell && x < g.X && y < g.Y && z < g.Z;
+      val[k] = in ? loc[x + g.X * y + g.XY * z] : kOutside;
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+      if (tid + k * kCThreads < BN) box[tid + k * kCThreads] = val[k];
+  }
+  __syncthreads();
+  // Every masked vertex on an upper face, with each of its higher-id
+  // Freudenthal neighbours that lies beyond the face (and in the mask).
   const int cx = tid % CTX, cy = tid / CTX;
-  const int64_t gx = t.x0 + cx, gy = t.y0 + cy;
-  const bool col_in = gx < g.X && gy < g.Y;
-  int nz = (int)((g.Z - t.z0) < CTZ ? (g.Z - t.z0) : CTZ);
-  if (!col_in) nz = 0;
-  const bool xface = cx == CTX - 1 && gx + 1 < g.X;
-  const bool yface = cy == CTY - 1 && gy + 1 < g.Y;
-  for (int lz = 0; lz < nz; ++lz) {
-    const bool zface = lz == CTZ - 1 && t.z0 + lz + 1 < g.Z;
+  const bool xface = cx == CTX - 1, yface = cy == CTY - 1;
+  uint32_t last = kNoKey;
+  for (int lz = 0; lz < CTZ; ++lz) {
+    const bool zface = lz == CTZ - 1;
     if (!(xface || yface || zface)) continue;
-    const int64_t v = gx + g.X * gy + g.XY * (t.z0 + lz);
-    if (!mask[v]) continue;
-    const uint32_t lv = loc[v];
-    const bool xp = gx + 1 < g.X, yp = gy + 1 < g.Y,
-               zp = t.z0 + lz + 1 < g.Z;
-    // (dx, dy, dz) of the 7 higher-id neighbours; keep those outside the tile.
+    const int bv = cx + BX * (cy + BY * lz);
+    const uint32_t lv = box[bv];
+    if (lv == kOutside) continue;
     const int dx[7] = {1, 0, 1, 0, 1, 0, 1};
     const int dy[7] = {0, 1, 1, 0, 0, 1, 1};
     const int dz[7] = {0, 0, 0, 1, 1, 1, 1};
 #pragma unroll
     for (int k = 0; k < 7; ++k) {
-      if ((dx[k] && !xp) || (dy[k] && !yp) || (dz[k] && !zp)) continue;
       const bool leaves = (dx[k] && xface) || (dy[k] && yface) ||
                           (dz[k] && zface);
       if (!leaves) continue;
-      const int64_t u = v + dx[k] + g.X * dy[k] + g.XY * dz[k];
-      if (!mask[u]) continue;
-      // u's tile-local root, decoded with u's own tile origin.
-      const int64_t ux = gx + dx[k], uy = gy + dy[k], uz = t.z0 + lz + dz[k];
-      const CTile tu{ux - ux % CTX, uy - uy % CTY, uz - uz % CTZ};
-      const uint32_t lu = loc[u];
-      const uint32_t nbr = (uint32_t)(tu.x0 != t.x0) |
-                           ((uint32_t)(tu.y0 != t.y0) << 1) |
-                           ((uint32_t)(tu.z0 != t.z0) << 2);
-      if (cross_first(set, lv | (nbr << 13) | (lu << 16)))
-        uf_unite<int64_t>(L, ctile_global(g, t, (int)lv),
-                          ctile_global(g, tu, (int)lu));
+      const uint32_t lu = box[bv + dx[k] + BX * (dy[k] + BY * dz[k])];
+      if (lu == kOutside) continue;
+      // Which neighbour tile u lies in: one up along each axis it crossed.
+      const uint32_t nbr = (uint32_t)(dx[k] && xface) |
+                           ((uint32_t)(dy[k] && yface) << 1) |
+                           ((uint32_t)(dz[k] && zface) << 2);
+      const uint32_t key = lv | (nbr << 13) | (lu << 16);
+      if (key == last) continue;  // a lane's edges mostly repeat their roots
+      last = key;
+      if (!cross_insert(set, key)) cross_unite(g, t, key, L);
     }
+  }
+  // Each distinct triple once, spread over the block.
+  __syncthreads();
+  for (int i = tid; i < kCrossSlots; i += kCThreads) {
+    const uint32_t key = set[i];
+    if (key != kNoKey) cross_unite(g, t, key, L);
   }
 }
 
@@ -416,7 +449,7 @@ int cc_grid_run(msc_ctx *ctx, const uint8_t *mask, int64_t X, int64_t Y,
   MSC_PHASE(ctx, s, "cc_tile", 3.0 * g.N,
             (k_cc_tile<<<nb, kCThreads, 0, s>>>(mask, g, loc, labels)));
   MSC_PHASE(ctx, s, "cc_cross", 0.5 * g.N,
-            (k_cc_cross<<<nb, kCThreads, 0, s>>>(mask, g, loc, labels)));
+            (k_cc_cross<<<nb, kCThreads, 0, s>>>(g, loc, labels)));
   MSC_PHASE(ctx, s, "cc_final", 10.0 * g.N,
             (k_cc_final<<<nb, kCThreads, 0, s>>>(g, loc, labels)));
   MSC_TRY(read_counters(ctx, s));
