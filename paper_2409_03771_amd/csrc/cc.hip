@@ -125,10 +125,17 @@ __device__ __forceinline__ int64_t ctile_global(const CGeo &g, const CTile &t,
   return (t.x0 + lx) + g.X * (t.y0 + ly) + g.XY * (t.z0 + lz);
 }
 
+// First z of the run of consecutive set bits of `bits` that contains bit z.
+__device__ __forceinline__ int run_start(uint32_t bits, int z) {
+  const uint32_t zeros = ~bits & ((1u << z) - 1u);
+  return zeros ? 32 - __clz(zeros) : 0;
+}
+
 __global__ void __launch_bounds__(kCThreads)
 k_cc_tile(const uint8_t *__restrict__ mask, CGeo g, uint16_t *__restrict__ loc,
           int64_t *__restrict__ L) {
   __shared__ int32_t par[kCOwned];
+  __shared__ uint32_t cols[kCThreads];  // mask bits of every column
   const int tid = threadIdx.x;
   const CTile t = ctile_at(g, cc_tile_of_block(blockIdx.x, gridDim.x));
   const int cx = tid % CTX, cy = tid / CTX;
@@ -137,58 +144,76 @@ k_cc_tile(const uint8_t *__restrict__ mask, CGeo g, uint16_t *__restrict__ loc,
   int nz = (int)((g.Z - t.z0) < CTZ ? (g.Z - t.z0) : CTZ);
   if (!col_in) nz = 0;
   const int64_t v0 = gx + g.X * gy + g.XY * t.z0;
+  auto local = [](int x, int y, int z) { return x + CTX * (y + CTY * z); };
 
   uint32_t m = 0;  // this column's mask bits
 #pragma unroll
+  for (int lz = 0; lz < CTZ; ++lz)
+    m |= (uint32_t)(lz < nz && mask[v0 + g.XY * lz]) << lz;
+  // The column's runs of consecutive masked z: every vertex of a run points
+  // at the run's first vertex, which settles every -z edge of the tile.
+#pragma unroll
+  for (int lz = 0; lz < CTZ; ++lz)
+    par[local(cx, cy, lz)] =
+        ((m >> lz) & 1u) ? local(cx, cy, run_start(m, lz)) : -1;
+  cols[tid] = m;
+  __syncthreads();
+
+  // The other lower-id Freudenthal edges of each masked vertex, united run
+  // head to run head.  The -x and -y edges are always taken; a diagonal one
+  // is implied, and skipped, when an axis neighbour on its side is in the
+  // mask: e.g. with v-x in the mask, v-x-y is v-x's own -y neighbour, so
+  // v ~ v-x ~ v-x-y (by induction on id, as v-x < v settles its own lower
+  // edges the same way; v ~ v-z through their run).  A lane skips a union of
+  // the same two heads as its previous one in that direction, so runs that
+  // lie side by side are united once.
+  const uint32_t mx_ = cx > 0 ? cols[tid - 1] : 0u;
+  const uint32_t my_ = cy > 0 ? cols[tid - CTX] : 0u;
+  const uint32_t mxy = cx > 0 && cy > 0 ? cols[tid - CTX - 1] : 0u;
+  uint32_t last[6] = {~0u, ~0u, ~0u, ~0u, ~0u, ~0u};
+  auto unite = [&](int dir, int hl, int hu) {
+    const uint32_t key = (uint32_t)hl | ((uint32_t)hu << 13);
+    if (key == last[dir]) return;
+    last[dir] = key;
+    uf_unite<int32_t>(par, hl, hu);
+  };
+#pragma unroll
   for (int lz = 0; lz < CTZ; ++lz) {
-    const int l = cx + CTX * (cy + CTY * lz);
-    const bool in = lz < nz && mask[v0 + g.XY * lz];
-    m |= (uint32_t)in << lz;
-    par[l] = in ? l : -1;
+    if (!((m >> lz) & 1u)) continue;
+    const int hl = local(cx, cy, run_start(m, lz));
+    const bool mx = (mx_ >> lz) & 1u, my = (my_ >> lz) & 1u;
+    const bool mz = lz > 0 && ((m >> (lz - 1)) & 1u);
+    if (mx) unite(0, hl, local(cx - 1, cy, run_start(mx_, lz)));
+    if (my) unite(1, hl, local(cx, cy - 1, run_start(my_, lz)));
+    if (!mx && !my && ((mxy >> lz) & 1u))
+      unite(2, hl, local(cx - 1, cy - 1, run_start(mxy, lz)));
+    if (lz > 0 && !mz) {
+      if (!mx && ((mx_ >> (lz - 1)) & 1u))
+        unite(3, hl, local(cx - 1, cy, run_start(mx_, lz - 1)));
+      if (!my && ((my_ >> (lz - 1)) & 1u))
+        unite(4, hl, local(cx, cy - 1, run_start(my_, lz - 1)));
+      if (!mx && !my && ((mxy >> (lz - 1)) & 1u))
+        unite(5, hl, local(cx - 1, cy - 1, run_start(mxy, lz - 1)));
+    }
   }
   __syncthreads();
 
-  // Union over the tile's own edges, each from its higher-id endpoint
-  // towards the 7 lower-id Freudenthal neighbours.  The three axis edges are
-  // always taken; a diagonal one is implied, and skipped, when an axis
-  // neighbour on its side is in the mask: e.g. with v-x in the mask, v-x-y
-  // is v-x's own -y neighbour, so v ~ v-x ~ v-x-y (by induction on id, as
-  // v-x < v settles its own lower edges the same way).
-  const int SX = 1, SY = CTX, SZ = CTX * CTY;
-  for (int lz = 0; lz < nz; ++lz) {
-    if (!((m >> lz) & 1)) continue;
-    const int l = cx + CTX * (cy + CTY * lz);
-    const bool xm = cx > 0, ym = cy > 0, zm = lz > 0;
-    auto in_mask = [&](int u) {
-      return __atomic_load_n(&par[u], __ATOMIC_RELAXED) >= 0;
-    };
-    const bool mx = xm && in_mask(l - SX);
-    const bool my = ym && in_mask(l - SY);
-    const bool mz = zm && ((m >> (lz - 1)) & 1);
-    if (mx) uf_unite<int32_t>(par, l, l - SX);
-    if (my) uf_unite<int32_t>(par, l, l - SY);
-    if (mz) uf_unite<int32_t>(par, l, l - SZ);
-    if (xm && ym && !mx && !my && in_mask(l - SX - SY))
-      uf_unite<int32_t>(par, l, l - SX - SY);
-    if (xm && zm && !mx && !mz && in_mask(l - SX - SZ))
-      uf_unite<int32_t>(par, l, l - SX - SZ);
-    if (ym && zm && !my && !mz && in_mask(l - SY - SZ))
-      uf_unite<int32_t>(par, l, l - SY - SZ);
-    if (xm && ym && zm && !mx && !my && !mz && in_mask(l - SX - SY - SZ))
-      uf_unite<int32_t>(par, l, l - SX - SY - SZ);
-  }
-  __syncthreads();
-
+  // Tile-local roots, once per run.
+  int run_head = -1, run_root = -1;
   for (int lz = 0; lz < nz; ++lz) {
     const int64_t v = v0 + g.XY * lz;
-    if (!((m >> lz) & 1)) {
+    if (!((m >> lz) & 1u)) {
       loc[v] = kOutside;
       continue;
     }
-    const int l = cx + CTX * (cy + CTY * lz);
-    const int r = uf_find<int32_t>(par, l);
-    loc[v] = (uint16_t)r;
-    if (r == l) L[v] = v;  // tile-local roots start as global roots
+    const int l = local(cx, cy, lz);
+    const int h = local(cx, cy, run_start(m, lz));
+    if (h != run_head) {
+      run_head = h;
+      run_root = uf_find<int32_t>(par, h);
+    }
+    loc[v] = (uint16_t)run_root;
+    if (run_root == l) L[v] = v;  // tile-local roots start as global roots
   }
 }
 
