@@ -56,10 +56,13 @@ __device__ __forceinline__ T uf_find(T *par, T x) {
 
 // Root of x without writing: used once no union is running, by the passes
 // in which every entry is also an output that only its owner may write.
+// The loads are cached (workgroup scope): a value older than another
+// workgroup's write is still an ancestor on the path to the same root.
 template <class T>
 __device__ __forceinline__ T uf_root(const T *par, T x) {
   for (;;) {
-    T p = __atomic_load_n(&par[x], __ATOMIC_RELAXED);
+    T p = __hip_atomic_load(&par[x], __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_WORKGROUP);
     if (p == x) return x;
     x = p;
   }
@@ -355,6 +358,9 @@ k_cc_final(CGeo g, const uint16_t *__restrict__ loc, int64_t *L) {
 // CSR graphs
 // ---------------------------------------------------------------------------
 
+// Edges of a CSR row handled together, so that their gathers overlap.
+constexpr int kEdgeChunk = 8;
+
 __global__ void __launch_bounds__(kBlock)
 k_csr_init(int64_t n, const int64_t *__restrict__ rp,
            const int32_t *__restrict__ ci, const uint8_t *__restrict__ mask,
@@ -365,15 +371,21 @@ k_csr_init(int64_t n, const int64_t *__restrict__ rp,
     if (mask && !mask[v]) {
       L[v] = -1;
     } else {
+      // A row's edges in chunks whose loads are all in flight together.
       int64_t best = v;
-      for (int64_t e = rp[v], end = rp[v + 1]; e < end; ++e) {
-        int64_t u = ci[e];
-        if (u < 0 || u >= n) {
-          bad = true;
-          continue;
+      const int64_t end = rp[v + 1];
+      for (int64_t e0 = rp[v]; e0 < end; e0 += kEdgeChunk) {
+        int64_t u[kEdgeChunk];
+        bool ok[kEdgeChunk];
+#pragma unroll
+        for (int j = 0; j < kEdgeChunk; ++j) {
+          u[j] = e0 + j < end ? (int64_t)ci[e0 + j] : v;
+          ok[j] = u[j] >= 0 && u[j] < n;
+          bad |= !ok[j];
         }
-        if (mask && !mask[u]) continue;
-        best = u < best ? u : best;
+#pragma unroll
+        for (int j = 0; j < kEdgeChunk; ++j)
+          if (ok[j] && (!mask || mask[u[j]])) best = u[j] < best ? u[j] : best;
       }
       L[v] = best;
     }
@@ -381,17 +393,46 @@ k_csr_init(int64_t n, const int64_t *__restrict__ rp,
   flag_any(bad, ctr + kCtrBadIndex);
 }
 
-// One union per listed edge between two masked vertices.
+// Every vertex straight to its root (after the hooks of k_csr_init).
+__global__ void __launch_bounds__(kBlock)
+k_csr_compress(int64_t n, int64_t *L) {
+  const int64_t v = gid();
+  if (v >= n) return;
+  if (__hip_atomic_load(&L[v], __ATOMIC_RELAXED,
+                        __HIP_MEMORY_SCOPE_WORKGROUP) < 0)
+    return;
+  __atomic_store_n(&L[v], uf_root<int64_t>(L, v), __ATOMIC_RELAXED);
+}
+
+// One union per listed edge between two masked vertices.  Most edges join
+// vertices that already share a root after the hooks and the compression: a
+// cached read of both entries shows it (an old value is still an ancestor,
+// so equal values prove the two are connected), and only the rest take the
+// lock-free union.
 __global__ void __launch_bounds__(kBlock)
 k_csr_union(int64_t n, const int64_t *__restrict__ rp,
             const int32_t *__restrict__ ci, const uint8_t *__restrict__ mask,
             int64_t *L) {
-  int64_t v = gid();
+  const int64_t v = gid();
   if (v >= n || (mask && !mask[v])) return;
-  for (int64_t e = rp[v], end = rp[v + 1]; e < end; ++e) {
-    const int64_t u = ci[e];
-    if (u == v || (mask && !mask[u])) continue;
-    uf_unite<int64_t>(L, v, u);
+  const int64_t lv =
+      __hip_atomic_load(&L[v], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  const int64_t end = rp[v + 1];
+  for (int64_t e0 = rp[v]; e0 < end; e0 += kEdgeChunk) {
+    int64_t u[kEdgeChunk], lu[kEdgeChunk];
+#pragma unroll
+    for (int j = 0; j < kEdgeChunk; ++j) {
+      u[j] = e0 + j < end ? (int64_t)ci[e0 + j] : v;
+      if (u[j] != v && mask && !mask[u[j]]) u[j] = v;
+    }
+#pragma unroll
+    for (int j = 0; j < kEdgeChunk; ++j)
+      lu[j] = u[j] == v ? lv
+                        : __hip_atomic_load(&L[u[j]], __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+    for (int j = 0; j < kEdgeChunk; ++j)
+      if (lu[j] != lv) uf_unite<int64_t>(L, v, u[j]);
   }
 }
 
@@ -399,7 +440,9 @@ __global__ void __launch_bounds__(kBlock)
 k_csr_final(int64_t n, int64_t *L) {
   int64_t v = gid();
   if (v >= n) return;
-  if (__atomic_load_n(&L[v], __ATOMIC_RELAXED) < 0) return;
+  if (__hip_atomic_load(&L[v], __ATOMIC_RELAXED,
+                        __HIP_MEMORY_SCOPE_WORKGROUP) < 0)
+    return;
   __atomic_store_n(&L[v], uf_root<int64_t>(L, v), __ATOMIC_RELAXED);
 }
 
@@ -496,6 +539,8 @@ int cc_csr_run(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,
                                                        ctx->dctr)));
   MSC_TRY(read_counters(ctx, s));
   if (ctx->hctr[kCtrBadIndex]) return MSC_EINVAL;
+  MSC_PHASE(ctx, s, "csr_compress", 16.0 * n,
+            (k_csr_compress<<<grid_for(n), kBlock, 0, s>>>(n, labels)));
   MSC_PHASE(ctx, s, "csr_union", 13.0 * n,
             (k_csr_union<<<grid_for(n), kBlock, 0, s>>>(n, row_ptr, col_idx,
                                                         mask, labels)));
