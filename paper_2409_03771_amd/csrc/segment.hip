@@ -54,6 +54,12 @@ struct Cfg {
   static constexpr int kWords = (H + 31) / 32;
   static constexpr int kWordsPerThread = (kWords + kThreads - 1) / kThreads;
   static constexpr int kHalo = H - TX * TY * TZ;
+  // When the box indices fit in 15 bits, bit 15 of a 16-bit pointer marks a
+  // halo target: halo vertices start as flagged self-pointers and jumping
+  // carries the flag to every pointer that ends in the halo.
+  static constexpr bool kHaloBit = H <= 0x8000;
+  static constexpr uint32_t kHB = kHaloBit ? 0x8000u : 0u;
+  static constexpr uint32_t kIdx = kHaloBit ? 0x7fffu : 0xffffu;
   static_assert(H <= 65535, "tile-local pointers are 16-bit");
   static_assert(kThreads % 64 == 0 && kThreads <= 1024, "block shape");
   static_assert((2 * H + 3) / 4 + 3 * kWords <= H,
@@ -455,8 +461,8 @@ k_tile_local(const FieldDev *__restrict__ fds,
 #pragma unroll
     for (int hz = 0; hz < C::HZ; ++hz) {
       if (edge || hz == 0 || hz == C::HZ - 1) {
-        const uint32_t i = (uint32_t)(col + hz * HXY);
-        lds[i] = i | (i << 16);
+        const uint32_t i = (uint32_t)(col + hz * HXY) | C::kHB;
+        lds[i & C::kIdx] = i | (i << 16);
       }
     }
   }
@@ -473,8 +479,8 @@ k_tile_local(const FieldDev *__restrict__ fds,
     uint32_t q[C::TZ];
 #pragma unroll
     for (int lz = 0; lz < C::TZ; ++lz)
-      q[lz] = (lds[ptr[lz] & 0xffffu] & 0xffffu) |
-              (lds[ptr[lz] >> 16] & 0xffff0000u);
+      q[lz] = (lds[ptr[lz] & C::kIdx] & 0xffffu) |
+              (lds[(ptr[lz] >> 16) & C::kIdx] & 0xffff0000u);
     bool changed = false;
 #pragma unroll
     for (int lz = 0; lz < C::TZ; ++lz) {
@@ -492,13 +498,18 @@ k_tile_local(const FieldDev *__restrict__ fds,
 
   // Halo targets are the tile's exits.  Each target is classified once
   // (ptr keeps owned code or halo index, hmask_* flags the halo ones) and
-  // flagged with a plain byte store: every writer stores the same 1.
+  // flagged with a plain byte store: every writer stores the same 1.  With
+  // the halo bit only the rare in-tile extremum targets need a decode.
+  auto cls = [](uint32_t h) -> uint32_t {
+    if (C::kHaloBit && (h & C::kHB)) return 0x10000u | (h & C::kIdx);
+    return classify<C>((int)h);
+  };
   uint32_t hmask_a = 0, hmask_d = 0;
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz) {
     if (lz < nz) {
-      const uint32_t ca = classify<C>((int)(ptr[lz] & 0xffffu));
-      const uint32_t cd = classify<C>((int)(ptr[lz] >> 16));
+      const uint32_t ca = cls(ptr[lz] & 0xffffu);
+      const uint32_t cd = cls(ptr[lz] >> 16);
       if (ca & 0x10000u) {
         flg[ca & 0xffffu] = 1;
         hmask_a |= 1u << lz;
