@@ -19,8 +19,9 @@
 //                 rule), and pointer jumping runs in LDS until every owned
 //                 vertex points to a tile-local extremum or to a halo vertex
 //                 ("exit").  Writes a 16-bit code per vertex and direction
-//                 (an owned extremum, or the number of an exit of the tile)
-//                 and appends the tile's exits to a list (its segment).
+//                 (an owned extremum, or the tile-local number of an exit)
+//                 and the tile's exit list at the tile's fixed slots.
+//   exit_scan     exclusive scan of the tiles' exit counts: global numbers.
 //   exit_link     an exit lies on a neighbouring tile's shell; that tile's
 //                 code for it gives the exit's successor: a final extremum or
 //                 another tile's exit.  The exits form a dense graph.
@@ -294,21 +295,40 @@ k_tile_stat_reduce(const uint32_t *__restrict__ tstat, int k, uint32_t nt,
 }
 
 // Per-block (longest chain, links followed) of the exit resolution into the
-// global counters.
-__global__ void __launch_bounds__(kBlock)
+// global counters: each thread folds a strided share, then the block, then
+// one atomic pair per block.
+constexpr int kStepsBlocks = 64;
+
+__global__ void __launch_bounds__(1024)
 k_steps_reduce(const unsigned long long *__restrict__ rstat, uint32_t nb,
                unsigned long long *ctr) {
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  unsigned long long mx = i < nb ? rstat[2 * (size_t)i] : 0ull;
-  unsigned long long sum = i < nb ? rstat[2 * (size_t)i + 1] : 0ull;
+  __shared__ unsigned long long smx[16], ssum[16];
+  unsigned long long mx = 0, sum = 0;
+  for (uint32_t i = blockIdx.x * 1024 + threadIdx.x; i < nb;
+       i += kStepsBlocks * 1024) {
+    const unsigned long long m = rstat[2 * (size_t)i];
+    mx = m > mx ? m : mx;
+    sum += rstat[2 * (size_t)i + 1];
+  }
   for (int o = 32; o > 0; o >>= 1) {
     const unsigned long long a = __shfl_xor(mx, o);
     mx = a > mx ? a : mx;
     sum += __shfl_xor(sum, o);
   }
-  if ((threadIdx.x & 63) == 0 && sum) {
-    atomicMax(ctr + kCtrRounds, mx);
-    atomicAdd(ctr + kCtrSteps, sum);
+  if ((threadIdx.x & 63) == 0) {
+    smx[threadIdx.x >> 6] = mx;
+    ssum[threadIdx.x >> 6] = sum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 16; ++w) {
+      mx = smx[w] > mx ? smx[w] : mx;
+      sum += ssum[w];
+    }
+    if (sum) {
+      atomicMax(ctr + kCtrRounds, mx);
+      atomicAdd(ctr + kCtrSteps, sum);
+    }
   }
 }
 
@@ -1268,7 +1288,7 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
     MSC_PHASE(ctx, s, "exit_resolve", 12.0 * ne,
               (k_exit_resolve<C><<<2 * nt, C::kThreads, 0, s>>>(
                   torder, nt, seg, ne, next, ctr, rstat)));
-    k_steps_reduce<<<grid_for(2ull * nt), kBlock, 0, s>>>(rstat, 2 * nt, ctr);
+    k_steps_reduce<<<kStepsBlocks, 1024, 0, s>>>(rstat, 2 * nt, ctr);
   }
 
   // Pair tables of the fields that want cells, in one block of `tab`.
