@@ -168,10 +168,10 @@ inline unsigned grid_for(int64_t n, int block = kBlock) {
 
 // Segmentation tile shapes compiled in (index = ctx->tile_choice); the
 // first is the default.
-constexpr int kNumTileShapes = 6;
+constexpr int kNumTileShapes = 8;
 constexpr int kTileShapes[kNumTileShapes][3] = {
     {32, 16, 16}, {32, 32, 16}, {32, 8, 8}, {64, 16, 16}, {64, 8, 8},
-    {32, 32, 32}};
+    {32, 32, 32}, {32, 8, 16}, {64, 8, 16}};
 inline int tile_index(int tx, int ty, int tz) {
   for (int i = 0; i < kNumTileShapes; ++i)
     if (kTileShapes[i][0] == tx && kTileShapes[i][1] == ty &&

@@ -1373,6 +1373,8 @@ using Tile32x8x8 = Cfg<32, 8, 8>;
 using Tile64x16x16 = Cfg<64, 16, 16>;
 using Tile64x8x8 = Cfg<64, 8, 8>;
 using Tile32x32x32 = Cfg<32, 32, 32>;
+using Tile32x8x16 = Cfg<32, 8, 16>;
+using Tile64x8x16 = Cfg<64, 8, 16>;
 
 }  // namespace
 
@@ -1389,6 +1391,10 @@ int segment_batch_run(msc_ctx *ctx, int nfields, const msc_field *fields,
       return segment_batch<Tile64x8x8>(ctx, nfields, fields, s);
     case 5:
       return segment_batch<Tile32x32x32>(ctx, nfields, fields, s);
+    case 6:
+      return segment_batch<Tile32x8x16>(ctx, nfields, fields, s);
+    case 7:
+      return segment_batch<Tile64x8x16>(ctx, nfields, fields, s);
     default:
       return segment_batch<Tile32x16x16>(ctx, nfields, fields, s);
   }
