@@ -920,7 +920,7 @@ __device__ __forceinline__ unsigned long long pair_key(int32_t a, int32_t d) {
 // larger id than the one already recorded), which in smooth regions is once
 // or twice per column; concurrent inserts of one pair meet in one slot
 // through the compare-and-swap.
-constexpr int kPairSlots = 2048;
+constexpr int kPairSlots = 1024;
 constexpr unsigned kPairLimit = kPairSlots / 2;
 constexpr int kPairProbes = 16;
 
