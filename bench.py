@@ -54,11 +54,12 @@ def cpu_baseline(field_dev, depth: int):
                       "walks, sort-based cells)"}
 
 
-def traffic_of(workload, kernel):
+def traffic_of(workload, kernel, folder=None):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
     record of this workload, or None when there is none or the kernel
     sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    path = os.path.join(folder or os.path.join(ROOT, "profiles"),
+                        f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     from paper_2409_03771_amd.profsum import source_hash
@@ -70,10 +71,11 @@ def traffic_of(workload, kernel):
     return None if k is None else int(round(k["hbm_bytes"]))
 
 
-def path_traffic(workload):
+def path_traffic(workload, folder=None):
     """HBM bytes of one call summed over all kernels of the committed
     counter record, or None when absent or taken on other kernel sources."""
-    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    path = os.path.join(folder or os.path.join(ROOT, "profiles"),
+                        f"traffic_{workload}.json")
     if not os.path.exists(path):
         return None
     from paper_2409_03771_amd.profsum import source_hash

@@ -150,8 +150,8 @@ typedef struct msc_stats {
   int64_t n_maxima;      /* distinct ascent roots                     */
   int64_t n_minima;      /* distinct descent roots                    */
   int64_t n_cells;       /* distinct (asc, desc) pairs                */
-  int64_t n_exits;       /* tile-exit vertices resolved globally      */
-  int32_t jump_rounds;   /* pointer-jumping rounds on the exit graph  */
+  int64_t n_exits;       /* tile exits (halo targets), both directions */
+  int32_t jump_rounds;   /* longest exit-graph chain one exit followed */
   int32_t tile_x, tile_y, tile_z; /* tile of the fused local pass     */
   int64_t exit_steps;    /* exit-graph links followed in total        */
 } msc_stats;

@@ -29,14 +29,9 @@ constexpr int kBlock = 256;
 // Slots of the small device counter block each context owns.
 enum Counter : int {
   kCtrChanged = 0,   // set nonzero by a round that changed something
-  kCtrNaN = 1,       // NaN seen in the field
-  kCtrMaxima = 2,    // local maxima counted by the steepest pass
-  kCtrMinima = 3,    // local minima
-  kCtrCells = 4,     // distinct (asc, desc) pairs inserted
-  kCtrExits = 5,     // tile-exit list length
+  kCtrExits = 5,     // exits over all tiles (from the scan)
   kCtrBadIndex = 6,  // out-of-range CSR column seen
-  kCtrOverflow = 7,  // hash table or list overflow
-  kCtrChanged2 = 8,
+  kCtrOverflow = 7,  // pair table full (bit 0), broken exit chain (bit 1)
   kCtrRounds = 9,    // longest exit chain walked
   kCtrSteps = 10,    // exit-graph links followed in total
   kNumCounters = 16
