@@ -37,6 +37,7 @@
  *
  * Parity pins for every function live in tests/test_oracle_*.py.
  */
+#define _GNU_SOURCE /* qsort_r */
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -198,13 +199,16 @@ int64_t orc_walk_from(const float *f, int64_t X, int64_t Y, int64_t Z,
 /* Morse-Smale cells                                                        */
 /* ------------------------------------------------------------------------ */
 
-static const int32_t *g_asc, *g_desc;
+struct pair_maps {
+    const int32_t *asc, *desc;
+};
 
-static int pair_then_id(const void *pa, const void *pb)
+static int pair_then_id(const void *pa, const void *pb, void *ctx)
 {
+    const struct pair_maps *m = (const struct pair_maps *)ctx;
     int64_t a = *(const int64_t *)pa, b = *(const int64_t *)pb;
-    if (g_asc[a] != g_asc[b]) return g_asc[a] < g_asc[b] ? -1 : 1;
-    if (g_desc[a] != g_desc[b]) return g_desc[a] < g_desc[b] ? -1 : 1;
+    if (m->asc[a] != m->asc[b]) return m->asc[a] < m->asc[b] ? -1 : 1;
+    if (m->desc[a] != m->desc[b]) return m->desc[a] < m->desc[b] ? -1 : 1;
     return a < b ? -1 : (a > b);
 }
 
@@ -212,15 +216,14 @@ static int pair_then_id(const void *pa, const void *pb)
  * ms[v] = min{u : asc[u]==asc[v] && desc[u]==desc[v]}.  Sorts the vertex ids
  * by (asc, desc, id); the first id of each run is the class minimum.
  * `order` must hold n int64 entries.  Returns the number of classes.
- * Not thread-safe (qsort comparator state).
+ * Re-entrant: the comparator gets the two maps through qsort_r's argument.
  */
 int64_t orc_ms_cells(const int32_t *asc, const int32_t *desc, int64_t n,
                      int32_t *ms, int64_t *order)
 {
     for (int64_t v = 0; v < n; ++v) order[v] = v;
-    g_asc = asc;
-    g_desc = desc;
-    qsort(order, (size_t)n, sizeof(int64_t), pair_then_id);
+    struct pair_maps m = {asc, desc};
+    qsort_r(order, (size_t)n, sizeof(int64_t), pair_then_id, &m);
     int64_t classes = 0, first = -1;
     for (int64_t i = 0; i < n; ++i) {
         int64_t v = order[i];

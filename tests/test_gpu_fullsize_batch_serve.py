@@ -1,0 +1,103 @@
+"""Parity at the full batched and served workloads, in the configurations
+the benchmark times.
+
+batch256: the 256 uneven fields segmented in one batched call with the
+autotuned tile; every field's extremum and cell counts are checked against
+its own labels, and a seeded sample of fields is compared label by label
+with the oracle (the oracle runs on a thread pool: its C calls release the
+GIL).  Served: requests drawn from the served size distribution (each axis
+64..512) go through the queue all at once; every result is bit-identical to
+the same request's plain call, and a sample is compared with the oracle.
+"""
+from concurrent.futures import ThreadPoolExecutor
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2409_03771_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def msc():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2409_03771_amd import msc as m
+    return m
+
+
+def test_batch256_full(msc):
+    specs = synth.batch_specs(256, seed=3)
+    print("[batch256] generating", flush=True)
+    fields = [synth.gaussian_field(d, nb, sd, device="cuda")
+              for d, nb, sd in specs]
+    outs = [tuple(torch.empty(f.numel(), dtype=torch.int32, device="cuda")
+                  for _ in range(3)) for f in fields]
+    try:
+        tune = msc.autotune(fields, outs)
+        print(f"[batch256] tile {tune['tile']}", flush=True)
+        msc.segment_batched_into(fields, outs)
+        torch.cuda.synchronize()
+        stats = [msc.last_field_stats(i) for i in range(len(fields))]
+        for i, (a, d, m) in enumerate(outs):
+            assert stats[i]["n_maxima"] == torch.unique(a).numel(), i
+            assert stats[i]["n_minima"] == torch.unique(d).numel(), i
+            assert stats[i]["n_cells"] == torch.unique(m).numel(), i
+        rng = np.random.default_rng(12)
+        sample = sorted(rng.choice(len(fields), 40, replace=False).tolist())
+        host = {i: fields[i].cpu().numpy() for i in sample}
+        print(f"[batch256] oracle on {len(sample)} fields", flush=True)
+        with ThreadPoolExecutor(16) as pool:
+            wants = dict(zip(sample, pool.map(O.segment,
+                                              [host[i] for i in sample])))
+        for i in sample:
+            for name, g, w in zip(("asc", "desc", "ms"), outs[i], wants[i]):
+                np.testing.assert_array_equal(
+                    g.cpu().numpy(), w, err_msg=f"field {i} {specs[i][0]} {name}")
+    finally:
+        msc.set_tile(*msc.tile_shapes()[0])
+
+
+def test_served_full_sizes(msc):
+    trace = synth.poisson_trace(1.0, 48, seed=4)
+    pool_specs = synth.poisson_trace(1.0, 16, seed=4)
+    pool = []
+    for sp in pool_specs:
+        f = synth.gaussian_field(sp["dims"], sp["nbumps"], sp["seed"])
+        pool.append((f, synth.threshold_mask(f, 0.7)))
+    reqs = [(1 if r["kind"] == "ms" else 2, pool[i % len(pool)][0 if
+             r["kind"] == "ms" else 1]) for i, r in enumerate(trace)]
+    print(f"[served] {len(reqs)} requests, "
+          f"{sum(a.size for _, a in reqs) / 1e6:.0f}M vertices", flush=True)
+    plain = []
+    for k, a in reqs:
+        t = torch.from_numpy(a).cuda()
+        if k == 1:
+            plain.append(tuple(x.cpu().numpy() for x in msc.segment(t)))
+        else:
+            plain.append(msc.cc_label_grid(t).cpu().numpy())
+    torch.cuda.synchronize()
+    with msc.Server(hbm_budget=64 << 30, max_batch=64) as srv:
+        tickets = [srv.submit(k, torch.from_numpy(a).pin_memory())
+                   for k, a in reqs]
+        batches = []
+        for t, (k, a), p in zip(tickets, reqs, plain):
+            assert srv.wait(t) == msc.MSC_OK
+            batches.append(srv.result(t)["batch_size"])
+            got = srv.fetch(t)
+            if k == 1:
+                for g, w in zip(got, p):
+                    np.testing.assert_array_equal(g, w)
+            else:
+                np.testing.assert_array_equal(got, p)
+            srv.release(t)
+    assert max(batches) > 1
+    print("[served] oracle on a sample", flush=True)
+    for i, (k, a) in enumerate(reqs[:6]):
+        if k == 1:
+            for g, w in zip(plain[i], O.segment(a)):
+                np.testing.assert_array_equal(g, w)
+        else:
+            np.testing.assert_array_equal(plain[i], O.cc_grid(a)[0])

@@ -276,3 +276,16 @@ def test_fig2_polyline_labels():
     row_ptr = np.array(row_ptr, np.int64)
     lab, k = O.cc_csr(row_ptr, np.array(cols, np.int32))
     assert k == 1 and (lab == 0).all()
+
+
+def test_oracle_is_reentrant():
+    """Concurrent oracle calls (thread pool; the C calls release the GIL)
+    give the serial results: the cell sort keeps no global state."""
+    from concurrent.futures import ThreadPoolExecutor
+    specs = synth.batch_specs(8, seed=5, lo=12, hi=40)
+    fields = [synth.gaussian_field(d, nb, sd) for d, nb, sd in specs]
+    with ThreadPoolExecutor(8) as pool:
+        par = list(pool.map(O.segment, fields))
+    for f, p in zip(fields, par):
+        for x, y in zip(p, O.segment(f)):
+            np.testing.assert_array_equal(x, y)
