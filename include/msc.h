@@ -96,6 +96,23 @@ MSC_API int msc_segment(msc_ctx *ctx, const float *field, const int64_t dims[3],
                 int32_t *asc, int32_t *desc, int32_t *ms, void *stream);
 
 /*
+ * The paper's distributed scheme (Alg. 1 and 2) with `ranks` virtual ranks
+ * on one device, for comparison with the single-domain path: the z-extent
+ * is split into `ranks` slabs of planes [r*Z/ranks, (r+1)*Z/ranks); each
+ * slab is segmented as a field of its own together with one ghost plane on
+ * each side that has a neighbour, the ghost vertices being fixed points
+ * (Alg. 1's ghost rule); the exchange then gives every ghost vertex its
+ * owner's result, compresses that ghost graph and relabels every vertex
+ * whose slab result is a ghost (Alg. 2); cells are paired over the final
+ * labels.  Outputs, layout and errors as msc_segment, and bit-identical to
+ * it; MSC_EINVAL also for ranks < 1 or ranks > Z.  msc_last_stats reports
+ * the final extremum and cell counts.
+ */
+MSC_API int msc_segment_ranks(msc_ctx *ctx, const float *field,
+                              const int64_t dims[3], int ranks, int32_t *asc,
+                              int32_t *desc, int32_t *ms, void *stream);
+
+/*
  * Segmentation of a batch of fields of independent shapes in one set of
  * launches: every pass of msc_segment runs once over the tiles of all
  * fields, so per-call launch and synchronisation costs are paid once per

@@ -136,6 +136,7 @@ void msc_destroy(msc_ctx *ctx) {
   if (ctx->ws.ptr) (void)hipFree(ctx->ws.ptr);
   if (ctx->tab.ptr) (void)hipFree(ctx->tab.ptr);
   if (ctx->xg.ptr) (void)hipFree(ctx->xg.ptr);
+  if (ctx->rk.ptr) (void)hipFree(ctx->rk.ptr);
   if (ctx->dctr) (void)hipFree(ctx->dctr);
   if (ctx->hctr) (void)hipHostFree(ctx->hctr);
   delete ctx;
@@ -146,6 +147,20 @@ int msc_segment(msc_ctx *ctx, const float *field, const int64_t dims[3],
   if (!ctx || !dims) return MSC_EINVAL;
   msc_field f{field, {dims[0], dims[1], dims[2]}, asc, desc, ms};
   return msc_segment_batched(ctx, 1, &f, stream);
+}
+
+int msc_segment_ranks(msc_ctx *ctx, const float *field, const int64_t dims[3],
+                      int ranks, int32_t *asc, int32_t *desc, int32_t *ms,
+                      void *stream) {
+  if (!ctx || !dims || !field || (!asc && !desc && !ms)) return MSC_EINVAL;
+  int64_t n = 0;
+  MSC_TRY(check_dims(dims, &n));
+  if (n > INT32_MAX) return MSC_ERANGE;
+  if (ranks < 1 || ranks > dims[2]) return MSC_EINVAL;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return MSC_EHIP;
+  return msc::segment_ranks_run(ctx, field, dims, ranks, asc, desc, ms,
+                                static_cast<hipStream_t>(stream));
 }
 
 int msc_segment_batched(msc_ctx *ctx, int nfields, const msc_field *fields,

@@ -34,6 +34,8 @@ enum Counter : int {
   kCtrOverflow = 7,  // pair table full (bit 0), broken exit chain (bit 1)
   kCtrRounds = 9,    // longest exit chain walked
   kCtrSteps = 10,    // exit-graph links followed in total
+  kCtrRootsMax = 11, // vertices that are their own ascent label
+  kCtrRootsMin = 12, // vertices that are their own descent label
   kNumCounters = 16
 };
 
@@ -100,6 +102,7 @@ struct msc_ctx {
   // Grow-only device workspaces carved per call: `ws` for per-vertex
   // scratch, `tab` for hash tables and lists sized after a first pass.
   msc::DevBuf ws, tab, xg;  // workspace, pair tables, exit graph
+  msc::DevBuf rk;           // virtual-rank path: slab labels, ghost graph
   // Device counters and a pinned host mirror.
   unsigned long long *dctr = nullptr;
   unsigned long long *hctr = nullptr;
@@ -177,6 +180,9 @@ inline int tile_index(int tx, int ty, int tz) {
 
 // Launchers implemented in the kernel translation units.
 int segment_batch_run(msc_ctx *ctx, int nfields, const msc_field *fields,
+                      hipStream_t s, const uint8_t *ghost = nullptr);
+int segment_ranks_run(msc_ctx *ctx, const float *field, const int64_t dims[3],
+                      int ranks, int32_t *asc, int32_t *desc, int32_t *ms,
                       hipStream_t s);
 int cc_grid_run(msc_ctx *ctx, const uint8_t *mask, int64_t X, int64_t Y,
                 int64_t Z, int64_t *labels, hipStream_t s);

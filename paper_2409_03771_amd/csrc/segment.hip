@@ -90,6 +90,8 @@ struct FieldDev {
   int32_t *vals;
   uint32_t mask;               // table capacity - 1
   uint32_t tile0;              // first global tile of the field
+  uint32_t ghost;              // bit 0 / bit 1: plane z = 0 / z = Z-1 holds
+                               // ghost vertices (fixed points, Alg. 1)
   Geo g;
 };
 
@@ -396,6 +398,13 @@ k_tile_local(const FieldDev *__restrict__ fds,
   // higher-id neighbour wins the max when at least equal and the min when
   // strictly below.  Lower-id neighbours are taken in decreasing id order,
   // higher-id ones in increasing id order.
+  // Ghost planes of a slab (the virtual-rank path); -1 when there are none.
+  // Bit lz is set when plane t.z0 + lz is one (block-uniform).
+  uint32_t gmask = 0;
+  if ((bt.fd.ghost & 1u) && t.z0 == 0) gmask |= 1u;
+  if ((bt.fd.ghost & 2u) && (int)g.Z - 1 - t.z0 < C::TZ)
+    gmask |= 1u << ((int)g.Z - 1 - t.z0);
+  gmask = __builtin_amdgcn_readfirstlane(gmask);
   uint32_t ptr[C::TZ];
   bool any_nan = false;
   float fsum = 0.f;
@@ -437,6 +446,10 @@ k_tile_local(const FieldDev *__restrict__ fds,
     MSC_HI(above.v[6], HXY + HX + 1)
 #undef MSC_LO
 #undef MSC_HI
+    if ((gmask >> lz) & 1u) {  // ghost vertex: a fixed point
+      omax = 0;
+      omin = 0;
+    }
     const bool in = lz < nz;
     any_nan |= in && fv != fv;
     ptr[lz] = in ? (uint32_t)(i + omax) | ((uint32_t)(i + omin) << 16)
@@ -1124,12 +1137,15 @@ __global__ void k_fill_u64(unsigned long long *p, uint32_t n,
   if (i < n) p[i] = value;
 }
 
-uint32_t table_capacity(uint64_t n, uint64_t nmax, uint64_t nmin) {
+// Capacity of a pair table: a power of two at least twice the number of
+// distinct pairs there can be (at most 2^32, so that the mask fits 32 bits).
+uint64_t table_capacity(uint64_t n, uint64_t nmax, uint64_t nmin) {
   uint64_t bound = nmax * nmin;
+  if (nmax != 0 && bound / nmax != nmin) bound = n;  // product overflowed
   if (bound > n) bound = n;
   uint64_t cap = 1024;
-  while (cap < 2 * bound) cap <<= 1;
-  return (uint32_t)cap;
+  while (cap < 2 * bound && cap < (1ull << 32)) cap <<= 1;
+  return cap;
 }
 
 // Grow-only pinned host staging owned by the context.
@@ -1151,7 +1167,7 @@ int stage(msc_ctx *ctx, size_t count, T **out) {
 
 template <class C>
 int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
-                  hipStream_t s) {
+                  const uint8_t *ghost, hipStream_t s) {
   // Geometry, tile ranges and workspace layout of every field.
   std::vector<FieldDev> fd(nfields);
   uint64_t total_tiles = 0, total_n = 0;
@@ -1216,6 +1232,7 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
     fd[i].keys = nullptr;
     fd[i].vals = nullptr;
     fd[i].mask = 0;
+    fd[i].ghost = ghost ? ghost[i] : 0u;
   }
   seg = cv.take<Seg>(nt);
   tkey = cv.take<uint32_t>(nt);
@@ -1311,9 +1328,11 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
       if (!fields[i].ms) continue;
       fd[i].keys = keys + off[i];
       fd[i].vals = vals + off[i];
-      fd[i].mask = table_capacity(fd[i].g.N,
+      fd[i].mask = (uint32_t)(table_capacity(
+                                  fd[i].g.N,
                                   fc[(size_t)i * kFieldCtrs + kFMaxima],
-                                  fc[(size_t)i * kFieldCtrs + kFMinima]) - 1;
+                                  fc[(size_t)i * kFieldCtrs + kFMinima]) -
+                              1);
     }
     char *st = nullptr;
     MSC_TRY(stage(ctx, nfields * sizeof(FieldDev), &st));
@@ -1379,25 +1398,344 @@ using Tile64x8x16 = Cfg<64, 8, 16>;
 }  // namespace
 
 int segment_batch_run(msc_ctx *ctx, int nfields, const msc_field *fields,
-                      hipStream_t s) {
+                      hipStream_t s, const uint8_t *ghost) {
   switch (ctx->tile_choice) {
     case 1:
-      return segment_batch<Tile32x32x16>(ctx, nfields, fields, s);
+      return segment_batch<Tile32x32x16>(ctx, nfields, fields, ghost, s);
     case 2:
-      return segment_batch<Tile32x8x8>(ctx, nfields, fields, s);
+      return segment_batch<Tile32x8x8>(ctx, nfields, fields, ghost, s);
     case 3:
-      return segment_batch<Tile64x16x16>(ctx, nfields, fields, s);
+      return segment_batch<Tile64x16x16>(ctx, nfields, fields, ghost, s);
     case 4:
-      return segment_batch<Tile64x8x8>(ctx, nfields, fields, s);
+      return segment_batch<Tile64x8x8>(ctx, nfields, fields, ghost, s);
     case 5:
-      return segment_batch<Tile32x32x32>(ctx, nfields, fields, s);
+      return segment_batch<Tile32x32x32>(ctx, nfields, fields, ghost, s);
     case 6:
-      return segment_batch<Tile32x8x16>(ctx, nfields, fields, s);
+      return segment_batch<Tile32x8x16>(ctx, nfields, fields, ghost, s);
     case 7:
-      return segment_batch<Tile64x8x16>(ctx, nfields, fields, s);
+      return segment_batch<Tile64x8x16>(ctx, nfields, fields, ghost, s);
     default:
-      return segment_batch<Tile32x16x16>(ctx, nfields, fields, s);
+      return segment_batch<Tile32x16x16>(ctx, nfields, fields, ghost, s);
   }
+}
+
+
+// ---------------------------------------------------------------------------
+// Virtual ranks: the paper's distributed scheme on one device
+// ---------------------------------------------------------------------------
+//
+// Alg. 1 and 2 with z-slabs as ranks.  Slab r owns planes [z0, z1) and is
+// segmented as a field of its own that also holds the plane on each side
+// owned by a neighbour; those ghost vertices are fixed points (every ghost
+// is treated as an extremum).  An owned vertex then ends either at a true
+// extremum of its slab or at a ghost vertex.  The exchange builds the ghost
+// graph -- each ghost vertex gets its owner's result for it, which may be a
+// ghost of the owner in turn -- compresses it, and relabels every vertex
+// whose slab result is a ghost.  Cells are then paired over the final maps.
+
+namespace {
+
+struct SlabDev {
+  uint32_t fs, z0, z1, fe;  // field planes [fs, fe), owned planes [z0, z1)
+  uint64_t off;             // start of the slab's labels in the scratch
+};
+
+struct RankGeo {
+  uint32_t X, XY, Z, R;
+};
+
+// Ghost node of slab r: side 0 = plane z0 - 1, side 1 = plane z1.
+__device__ __forceinline__ uint32_t ghost_node(const RankGeo &g, uint32_t r,
+                                               uint32_t side, uint32_t xy) {
+  return (2u * r + side) * g.XY + xy;
+}
+
+// Node of the ghost vertex x of slab r, or ~0u when x is owned by r.
+__device__ __forceinline__ uint32_t ghost_of(const RankGeo &g,
+                                             const SlabDev &sl, uint32_t r,
+                                             uint32_t x) {
+  const uint32_t z = x / g.XY;
+  if (r > 0 && z == sl.z0 - 1) return ghost_node(g, r, 0, x - z * g.XY);
+  if (r + 1 < g.R && z == sl.z1) return ghost_node(g, r, 1, x - z * g.XY);
+  return ~0u;
+}
+
+// Each ghost vertex takes its owner slab's result for it (as a global id).
+__global__ void __launch_bounds__(kBlock)
+k_rank_ghost_init(RankGeo g, const SlabDev *__restrict__ slabs,
+                  const int32_t *__restrict__ A, const int32_t *__restrict__ D,
+                  uint32_t *__restrict__ GA, uint32_t *__restrict__ GD) {
+  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= 2ull * g.R * g.XY) return;
+  const uint32_t xy = (uint32_t)(i % g.XY), rs = (uint32_t)(i / g.XY);
+  const uint32_t r = rs >> 1, side = rs & 1u;
+  if ((side == 0 && r == 0) || (side == 1 && r + 1 == g.R)) return;
+  const SlabDev me = slabs[r];
+  const uint32_t zg = side ? me.z1 : me.z0 - 1;
+  const SlabDev ow = slabs[side ? r + 1 : r - 1];
+  const uint64_t local = (uint64_t)xy + (uint64_t)g.XY * (zg - ow.fs);
+  const uint32_t base = ow.fs * g.XY;
+  GA[i] = (uint32_t)A[ow.off + local] + base;
+  GD[i] = (uint32_t)D[ow.off + local] + base;
+}
+
+// Ghost graph compression: each node follows its successors (a result that
+// is a ghost of the slab that produced it leads to that ghost's node) to a
+// final extremum.  A path may cross a slab boundary many times, but never
+// visits a node twice (values rise strictly along an ascent, fall along a
+// descent), so the walk ends within the number of nodes.
+__global__ void __launch_bounds__(kBlock)
+k_rank_ghost_resolve(RankGeo g, const SlabDev *__restrict__ slabs,
+                     const uint32_t *__restrict__ G, uint32_t *__restrict__ F) {
+  const uint64_t nodes = 2ull * g.R * g.XY;
+  const uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nodes) return;
+  const uint32_t rs = (uint32_t)(i / g.XY), r = rs >> 1, side = rs & 1u;
+  if ((side == 0 && r == 0) || (side == 1 && r + 1 == g.R)) return;
+  uint32_t s = side ? r + 1 : r - 1;  // the slab that produced G[i]
+  uint32_t x = G[i];
+  for (uint64_t step = 0; step < nodes; ++step) {
+    const uint32_t nd = ghost_of(g, slabs[s], s, x);
+    if (nd == ~0u) break;
+    const uint32_t ns = (nd / g.XY) & 1u ? s + 1 : s - 1;
+    x = G[nd];
+    s = ns;
+  }
+  F[i] = x;
+}
+
+// Final labels: a slab result that is a ghost takes the ghost's resolved
+// value.  Also counts the vertices that are their own labels (extrema).
+__global__ void __launch_bounds__(kBlock)
+k_rank_relabel(RankGeo g, const SlabDev *__restrict__ slabs,
+               const int32_t *__restrict__ A, const int32_t *__restrict__ D,
+               const uint32_t *__restrict__ FA, const uint32_t *__restrict__ FD,
+               int32_t *__restrict__ asc, int32_t *__restrict__ desc,
+               uint32_t *__restrict__ roots) {
+  __shared__ uint32_t s_cnt[2];
+  if (threadIdx.x < 2) s_cnt[threadIdx.x] = 0;
+  __syncthreads();
+  const uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  uint32_t cmax = 0, cmin = 0;
+  if (v < (uint64_t)g.XY * g.Z) {
+    const uint32_t z = (uint32_t)(v / g.XY);
+    uint32_t r = (uint32_t)(((uint64_t)z * g.R) / g.Z);
+    while (r > 0 && slabs[r].z0 > z) --r;
+    while (r + 1 < g.R && slabs[r + 1].z0 <= z) ++r;
+    const SlabDev sl = slabs[r];
+    const uint64_t local = v - (uint64_t)sl.fs * g.XY;
+    const uint32_t base = sl.fs * g.XY;
+    uint32_t a = (uint32_t)A[sl.off + local] + base;
+    uint32_t d = (uint32_t)D[sl.off + local] + base;
+    const uint32_t na = ghost_of(g, sl, r, a), nd = ghost_of(g, sl, r, d);
+    if (na != ~0u) a = FA[na];
+    if (nd != ~0u) d = FD[nd];
+    asc[v] = (int32_t)a;
+    desc[v] = (int32_t)d;
+    cmax = a == (uint32_t)v;
+    cmin = d == (uint32_t)v;
+  }
+  cmax = __popcll(__ballot(cmax));
+  cmin = __popcll(__ballot(cmin));
+  if ((threadIdx.x & 63) == 0) {
+    if (cmax) atomicAdd(&s_cnt[0], cmax);
+    if (cmin) atomicAdd(&s_cnt[1], cmin);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    roots[2 * blockIdx.x] = s_cnt[0];
+    roots[2 * blockIdx.x + 1] = s_cnt[1];
+  }
+}
+
+__global__ void __launch_bounds__(1024)
+k_rank_roots_sum(const uint32_t *__restrict__ roots, uint32_t nb,
+                 unsigned long long *ctr) {
+  __shared__ unsigned long long sa[16], sd[16];
+  unsigned long long a = 0, d = 0;
+  for (uint32_t i = threadIdx.x; i < nb; i += 1024) {
+    a += roots[2 * i];
+    d += roots[2 * i + 1];
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o);
+    d += __shfl_xor(d, o);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    sa[threadIdx.x >> 6] = a;
+    sd[threadIdx.x >> 6] = d;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 16; ++w) {
+      a += sa[w];
+      d += sd[w];
+    }
+    ctr[kCtrRootsMax] = a;
+    ctr[kCtrRootsMin] = d;
+  }
+}
+
+// Cells over final labels: the smallest id of every (asc, desc) pair.  A
+// wave whose lanes all hold lane 0's pair inserts once (lane 0 holds the
+// smallest id); otherwise every lane inserts.
+__global__ void __launch_bounds__(kBlock)
+k_rank_pairs(uint64_t n, const int32_t *__restrict__ asc,
+             const int32_t *__restrict__ desc, unsigned long long *keys,
+             int32_t *vals, uint32_t mask, unsigned long long *ctr) {
+  const uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool in = v < n;
+  const unsigned long long key = in ? pair_key(asc[v], desc[v]) : kEmptyKey;
+  const unsigned long long k0 =
+      ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(key >> 32))
+       << 32) | __builtin_amdgcn_readfirstlane((uint32_t)key);
+  const bool uniform = __ballot(in && key != k0) == 0;
+  unsigned fresh = 0;
+  bool ok = true;
+  if (uniform) {
+    if (in && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)__ballot(in)) - 1))
+      ok = table_insert(keys, vals, mask, key, (int32_t)v, &fresh);
+  } else if (in) {
+    ok = table_insert(keys, vals, mask, key, (int32_t)v, &fresh);
+  }
+  if (!ok) atomicOr(ctr + kCtrOverflow, 1ull);
+}
+
+// Cell ids, and per block the number of vertices that are their own cell
+// id (one per cell).
+__global__ void __launch_bounds__(kBlock)
+k_rank_ms(uint64_t n, const int32_t *__restrict__ asc,
+          const int32_t *__restrict__ desc,
+          const unsigned long long *__restrict__ keys,
+          const int32_t *__restrict__ vals, uint32_t mask, int32_t *ms,
+          uint32_t *__restrict__ counts) {
+  __shared__ uint32_t s_cnt;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  const uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  bool own = false;
+  if (v < n) {
+    const int32_t c = table_lookup(keys, vals, mask, pair_key(asc[v], desc[v]));
+    ms[v] = c;
+    own = (uint64_t)(uint32_t)c == v;
+  }
+  const uint32_t w = __popcll(__ballot(own));
+  if ((threadIdx.x & 63) == 0 && w) atomicAdd(&s_cnt, w);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    counts[2 * blockIdx.x] = s_cnt;
+    counts[2 * blockIdx.x + 1] = 0;
+  }
+}
+
+template <class C>
+int segment_ranks(msc_ctx *ctx, const float *field, const int64_t dims[3],
+                  int ranks, int32_t *asc, int32_t *desc, int32_t *ms,
+                  hipStream_t s) {
+  const uint32_t X = (uint32_t)dims[0], Y = (uint32_t)dims[1],
+                 Z = (uint32_t)dims[2], R = (uint32_t)ranks;
+  const uint64_t XY = (uint64_t)X * Y, N = XY * Z;
+  std::vector<SlabDev> sl(R);
+  std::vector<msc_field> fields(R);
+  std::vector<uint8_t> ghost(R);
+  uint64_t total = 0;
+  for (uint32_t r = 0; r < R; ++r) {
+    SlabDev &q = sl[r];
+    q.z0 = (uint32_t)((uint64_t)r * Z / R);
+    q.z1 = (uint32_t)((uint64_t)(r + 1) * Z / R);
+    q.fs = r > 0 ? q.z0 - 1 : 0;
+    q.fe = r + 1 < R ? q.z1 + 1 : Z;
+    q.off = total;
+    total += XY * (q.fe - q.fs);
+    ghost[r] = (uint8_t)((r > 0 ? 1 : 0) | (r + 1 < R ? 2 : 0));
+  }
+  const uint64_t nodes = 2ull * R * XY;
+  const uint32_t nblk = (uint32_t)((N + kBlock - 1) / kBlock);
+  MSC_TRY(reserve(ctx->rk, 2 * align256(total * 4) + 4 * align256(nodes * 4) +
+                               align256(R * sizeof(SlabDev)) +
+                               2 * align256(N * 4) + align256(nblk * 8ull) +
+                               4096));
+  Carver cv(ctx->rk);
+  int32_t *A = cv.take<int32_t>(total), *D = cv.take<int32_t>(total);
+  uint32_t *GA = cv.take<uint32_t>(nodes), *GD = cv.take<uint32_t>(nodes);
+  uint32_t *FA = cv.take<uint32_t>(nodes), *FD = cv.take<uint32_t>(nodes);
+  SlabDev *dsl = cv.take<SlabDev>(R);
+  uint32_t *roots = cv.take<uint32_t>(2ull * nblk);
+  int32_t *fa = asc ? asc : cv.take<int32_t>(N);
+  int32_t *fd = desc ? desc : cv.take<int32_t>(N);
+  for (uint32_t r = 0; r < R; ++r) {
+    fields[r].field = field + XY * sl[r].fs;
+    fields[r].dims[0] = X;
+    fields[r].dims[1] = Y;
+    fields[r].dims[2] = sl[r].fe - sl[r].fs;
+    fields[r].asc = A + sl[r].off;
+    fields[r].desc = D + sl[r].off;
+    fields[r].ms = nullptr;
+  }
+  // Alg. 1 on every rank, all ranks in one batched call.
+  MSC_TRY(segment_batch<C>(ctx, (int)R, fields.data(), ghost.data(), s));
+
+  char *st = nullptr;
+  MSC_TRY(stage(ctx, R * sizeof(SlabDev), &st));
+  std::memcpy(st, sl.data(), R * sizeof(SlabDev));
+  MSC_HIP_TRY(hipMemcpyAsync(dsl, st, R * sizeof(SlabDev),
+                             hipMemcpyHostToDevice, s));
+  MSC_TRY(clear_counters(ctx, s));
+  const RankGeo rg{X, (uint32_t)XY, Z, R};
+  // Alg. 2: ghost graph, compression, relabelling.
+  MSC_PHASE(ctx, s, "rank_exchange", 24.0 * nodes,
+            (k_rank_ghost_init<<<grid_for(nodes), kBlock, 0, s>>>(
+                 rg, dsl, A, D, GA, GD),
+             k_rank_ghost_resolve<<<grid_for(nodes), kBlock, 0, s>>>(
+                 rg, dsl, GA, FA),
+             k_rank_ghost_resolve<<<grid_for(nodes), kBlock, 0, s>>>(
+                 rg, dsl, GD, FD)));
+  MSC_PHASE(ctx, s, "rank_relabel", 16.0 * N,
+            (k_rank_relabel<<<nblk, kBlock, 0, s>>>(rg, dsl, A, D, FA, FD, fa,
+                                                    fd, roots),
+             k_rank_roots_sum<<<1, 1024, 0, s>>>(roots, nblk, ctx->dctr)));
+  MSC_TRY(read_counters(ctx, s));
+  const uint64_t nmax = ctx->hctr[kCtrRootsMax], nmin = ctx->hctr[kCtrRootsMin];
+  int64_t cells = -1;
+  if (ms) {
+    const uint64_t cap = table_capacity(N, nmax, nmin);
+    MSC_TRY(reserve(ctx->tab, align256(cap * 8) + align256(cap * 4) + 4096));
+    Carver tc(ctx->tab);
+    unsigned long long *keys = tc.take<unsigned long long>(cap);
+    int32_t *vals = tc.take<int32_t>(cap);
+    MSC_PHASE(ctx, s, "rank_pairs", 12.0 * N,
+              (k_table_clear<<<(unsigned)((cap + kBlock - 1) / kBlock), kBlock,
+                               0, s>>>(keys, vals, cap),
+               k_rank_pairs<<<nblk, kBlock, 0, s>>>(N, fa, fd, keys, vals,
+                                                    (uint32_t)(cap - 1),
+                                                    ctx->dctr)));
+    MSC_PHASE(ctx, s, "rank_ms", 12.0 * N,
+              (k_rank_ms<<<nblk, kBlock, 0, s>>>(N, fa, fd, keys, vals,
+                                                 (uint32_t)(cap - 1), ms,
+                                                 roots),
+               k_rank_roots_sum<<<1, 1024, 0, s>>>(roots, nblk, ctx->dctr)));
+    MSC_TRY(read_counters(ctx, s));
+    if (ctx->hctr[kCtrOverflow]) return MSC_ENOMEM;
+    cells = (int64_t)ctx->hctr[kCtrRootsMax];
+  }
+  ctx->stats = msc_stats{};
+  ctx->stats.n_vertices = (int64_t)N;
+  ctx->stats.n_maxima = (int64_t)nmax;
+  ctx->stats.n_minima = (int64_t)nmin;
+  ctx->stats.n_cells = cells;
+  ctx->stats.tile_x = C::TX;
+  ctx->stats.tile_y = C::TY;
+  ctx->stats.tile_z = C::TZ;
+  return MSC_OK;
+}
+
+}  // namespace
+
+int segment_ranks_run(msc_ctx *ctx, const float *field, const int64_t dims[3],
+                      int ranks, int32_t *asc, int32_t *desc, int32_t *ms,
+                      hipStream_t s) {
+  return segment_ranks<Tile32x16x16>(ctx, field, dims, ranks, asc, desc, ms,
+                                     s);
 }
 
 }  // namespace msc

@@ -63,6 +63,8 @@ _SIGS = {
     "msc_segment": ([_P, _P, ctypes.POINTER(_I64), _P, _P, _P, _P], _I32),
     "msc_last_stats": ([_P, ctypes.POINTER(msc_stats)], _I32),
     "msc_segment_batched": ([_P, _I32, ctypes.POINTER(msc_field), _P], _I32),
+    "msc_segment_ranks": ([_P, _P, ctypes.POINTER(_I64), _I32, _P, _P, _P, _P],
+                          _I32),
     "msc_last_field_stats": ([_P, _I32, ctypes.POINTER(msc_stats)], _I32),
     "msc_autotune": ([_P, _I32, ctypes.POINTER(msc_field), _P,
                       ctypes.POINTER(msc_tune)], _I32),
@@ -167,6 +169,23 @@ def segment(field: torch.Tensor, want=("asc", "desc", "ms"), stream=None):
     out = {k: (torch.empty(n, dtype=torch.int32, device=field.device)
                if k in want else None) for k in ("asc", "desc", "ms")}
     segment_into(field, out["asc"], out["desc"], out["ms"], stream=stream)
+    return out["asc"], out["desc"], out["ms"]
+
+
+def segment_ranks(field: torch.Tensor, ranks: int,
+                  want=("asc", "desc", "ms"), stream=None):
+    """The paper's distributed scheme with `ranks` z-slab virtual ranks on
+    one device (see msc_segment_ranks); same outputs as segment()."""
+    n = field.numel()
+    out = {k: (torch.empty(n, dtype=torch.int32, device=field.device)
+               if k in want else None) for k in ("asc", "desc", "ms")}
+    code = _lib.msc_segment_ranks(
+        context(field.device.index), _dev_ptr(field, torch.float32, "field"),
+        _dims_arg(grid_dims(field.shape)), int(ranks),
+        _dev_ptr(out["asc"], torch.int32, "asc"),
+        _dev_ptr(out["desc"], torch.int32, "desc"),
+        _dev_ptr(out["ms"], torch.int32, "ms"), _stream(field, stream))
+    _check(code, "msc_segment_ranks")
     return out["asc"], out["desc"], out["ms"]
 
 
