@@ -63,6 +63,7 @@ struct Cfg {
   static constexpr uint32_t kIdx = kHaloBit ? 0x7fffu : 0xffffu;
   static_assert(H <= 65535, "tile-local pointers are 16-bit");
   static_assert(kThreads % 64 == 0 && kThreads <= 1024, "block shape");
+  static_assert(H % 4 == 0, "flag bytes are read as words");
   static_assert((2 * H + 3) / 4 + 3 * kWords <= H,
                 "exit flags and bitsets alias the pointer array");
   static_assert(kHalo <= (2 * H + 3) / 4, "the exit list fits the flag bytes");
@@ -116,6 +117,10 @@ struct Tile {
   int x0, y0, z0;
 };
 
+// Field values read through a pointer known to be in global memory, so that
+// the loads are global (not flat) ones.
+typedef __attribute__((address_space(1))) float GlobalF;
+
 template <class C>
 __device__ __forceinline__ Tile tile_at(const Geo &g, uint32_t t) {
   uint32_t tx = t % g.ntx, r = t / g.ntx;
@@ -168,6 +173,21 @@ __device__ __forceinline__ uint32_t owned_global(const Geo &g, const Tile &t,
                  lz = code / (C::TX * C::TY);
   return ((uint32_t)t.x0 + lx) + g.X * ((uint32_t)t.y0 + ly) +
          g.XY * ((uint32_t)t.z0 + lz);
+}
+
+// Four flag bytes (each 0 or 1) as a nibble: byte j becomes bit j.
+__device__ __forceinline__ uint32_t flag_nibble(uint32_t v) {
+  const uint32_t t = v | (v >> 7);
+  return (t | (t >> 14)) & 0xfu;
+}
+
+// OR of the values of lanes 8j .. 8j+7, valid in lane 8j+7 (row shifts by
+// 1, 2 and 4 lanes; lanes shifted in from outside a row of 16 read 0).
+__device__ __forceinline__ uint32_t or8(uint32_t x) {
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);
+  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);
+  return x;
 }
 
 __device__ __forceinline__ void wave_count(bool pred, unsigned long long *ctr) {
@@ -359,29 +379,37 @@ k_tile_local(const FieldDev *__restrict__ fds,
   const float *__restrict__ f = bt.fd.f;
   unsigned long long *fc = fctr + (size_t)bt.fi * kFieldCtrs;
   const Tile t = tile_at<C>(g, bt.tile);
-  // Stage the tile and its halo: each thread issues all its loads before
-  // the first LDS store, so the block waits for one memory round trip
-  // (consecutive threads take consecutive indices: coalesced rows).
-  // Positions outside the domain hold NaN, which loses every comparison
-  // below and so is never chosen.
+  // Stage the tile and its halo by z-columns: thread tid takes box columns
+  // tid, tid + T, ... and issues a column's loads before storing any of
+  // them.  Consecutive threads take consecutive columns (coalesced rows);
+  // a column's offset within a plane is computed once, and each plane's
+  // base is uniform over the block.  Positions outside the domain hold NaN,
+  // which loses every comparison below and so is never chosen.
   {
-    constexpr int K = (H + T - 1) / T;
+    constexpr int KC = (HXY + T - 1) / T;
     const uint32_t kNaN = 0x7fc00000u;
-    uint32_t val[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-      const int i = tid + k * T;
-      const int hz = i / HXY, r = i - hz * HXY, hy = r / HX, hx = r - hy * HX;
-      const int gx = t.x0 - 1 + hx, gy = t.y0 - 1 + hy, gz = t.z0 - 1 + hz;
-      const bool in = i < H && gx >= 0 && gx < (int)g.X && gy >= 0 &&
-                      gy < (int)g.Y && gz >= 0 && gz < (int)g.Z;
-      val[k] = in ? __float_as_uint(f[(uint32_t)gx + g.X * (uint32_t)gy +
-                                      g.XY * (uint32_t)gz])
-                  : kNaN;
+    for (int sl = 0; sl < KC; ++sl) {
+      const int col = tid + sl * T;
+      if (col < HXY) {
+        const int hy = col / HX, hx = col - hy * HX;
+        const int gx = t.x0 - 1 + hx, gy = t.y0 - 1 + hy;
+        const bool cin =
+            gx >= 0 && gx < (int)g.X && gy >= 0 && gy < (int)g.Y;
+        const uint32_t off = cin ? (uint32_t)gx + g.X * (uint32_t)gy : 0u;
+        uint32_t val[C::HZ];
+#pragma unroll
+        for (int hz = 0; hz < C::HZ; ++hz) {
+          const int gz = t.z0 - 1 + hz;
+          const bool zin = gz >= 0 && gz < (int)g.Z;
+          const GlobalF *plane = (const GlobalF *)f +
+                                 (size_t)g.XY * (uint32_t)(zin ? gz : 0);
+          val[hz] = cin && zin ? __float_as_uint(plane[off]) : kNaN;
+        }
+#pragma unroll
+        for (int hz = 0; hz < C::HZ; ++hz) lds[col + hz * HXY] = val[hz];
+      }
     }
-#pragma unroll
-    for (int k = 0; k < K; ++k)
-      if (tid + k * T < H) lds[tid + k * T] = val[k];
   }
   __syncthreads();
 
@@ -555,16 +583,27 @@ k_tile_local(const FieldDev *__restrict__ fds,
     }
   }
   __syncthreads();
-  // Flags to bitsets: a wave ballots 64 consecutive indices into two words.
+  // Flags to bitsets: thread q reads the flag bytes of indices 4q .. 4q+3
+  // as one word (all reads issued first) and folds them into a nibble;
+  // eight consecutive lanes OR their shifted nibbles into one bitset word.
   {
-    const int lane = tid & 63;
-    for (int b = tid - lane; b < H; b += T) {
-      const int p = b + lane;
-      const unsigned long long ma = __ballot(p < H && flg[p]);
-      const unsigned long long md = __ballot(p < H && flg[H + p]);
-      if (lane < 2 && (b >> 5) + lane < C::kWords) {
-        xa[(b >> 5) + lane] = (uint32_t)(ma >> (32 * lane));
-        xd[(b >> 5) + lane] = (uint32_t)(md >> (32 * lane));
+    constexpr int Q = H / 4, KQ = (Q + T - 1) / T;
+    const uint32_t sh = 4u * (uint32_t)(tid & 7);
+    uint32_t fa[KQ], fd[KQ];
+#pragma unroll
+    for (int k = 0; k < KQ; ++k) {
+      const int q = tid + k * T;
+      fa[k] = q < Q ? lds[q] : 0u;
+      fd[k] = q < Q ? lds[Q + q] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < KQ; ++k) {
+      const int q = tid + k * T;
+      const uint32_t wa = or8(flag_nibble(fa[k]) << sh);
+      const uint32_t wd = or8(flag_nibble(fd[k]) << sh);
+      if ((tid & 7) == 7 && (q >> 3) < C::kWords) {
+        xa[q >> 3] = wa;
+        xd[q >> 3] = wd;
       }
     }
   }
@@ -612,20 +651,32 @@ k_tile_local(const FieldDev *__restrict__ fds,
 
   // The tile's exits for the exit graph, by their tile-local numbers (the
   // numbers become global with a scan over tiles afterwards).  The list is
-  // built in the flag bytes, no longer read, and copied out in dwords; a
-  // wave takes 64 consecutive halo indices, so its lanes share two words.
+  // built in the flag bytes, no longer read, and copied out in dwords.
+  // Thread q takes indices 4q .. 4q+3 (a nibble of bitset word q / 8) and
+  // reads its words and prefixes before writing any entry.
   {
     uint16_t *sl = reinterpret_cast<uint16_t *>(lds);
-    const int lane = tid & 63;
-    for (int b = tid - lane; b < H; b += T) {
-      const int p = b + lane;
-      if (p >= H) continue;
-      const uint32_t w = (uint32_t)p >> 5, below = (1u << (p & 31)) - 1u;
-      const uint32_t ba = xa[w], bd = xd[w];
-      if ((ba >> (p & 31)) & 1u)
-        sl[(pre[w] & 0xffffu) + __popc(ba & below)] = (uint16_t)p;
-      if ((bd >> (p & 31)) & 1u)
-        sl[na + (pre[w] >> 16) + __popc(bd & below)] = (uint16_t)p;
+    constexpr int Q = H / 4, KQ = (Q + T - 1) / T;
+    const uint32_t sh = 4u * (uint32_t)(tid & 7), below = (1u << sh) - 1u;
+    uint32_t ba[KQ], bd[KQ], bp[KQ];
+#pragma unroll
+    for (int k = 0; k < KQ; ++k) {
+      const int q = tid + k * T;
+      ba[k] = q < Q ? xa[q >> 3] : 0u;
+      bd[k] = q < Q ? xd[q >> 3] : 0u;
+      bp[k] = q < Q ? pre[q >> 3] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < KQ; ++k) {
+      const uint32_t p0 = 4u * (uint32_t)(tid + k * T);
+      uint32_t ra = (bp[k] & 0xffffu) + __popc(ba[k] & below);
+      uint32_t rd = na + (bp[k] >> 16) + __popc(bd[k] & below);
+      const uint32_t ma = ba[k] >> sh, md = bd[k] >> sh;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if ((ma >> j) & 1u) sl[ra++] = (uint16_t)(p0 + j);
+        if ((md >> j) & 1u) sl[rd++] = (uint16_t)(p0 + j);
+      }
     }
     __syncthreads();
     uint32_t *tl = reinterpret_cast<uint32_t *>(xo.tlist +
