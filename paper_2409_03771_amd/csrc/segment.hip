@@ -121,6 +121,15 @@ struct Tile {
 // the loads are global (not flat) ones.
 typedef __attribute__((address_space(1))) float GlobalF;
 
+// Plane z of a per-vertex array as a global-memory pointer: the base is
+// uniform over a block and a column adds a 32-bit offset, so accesses need
+// no per-lane 64-bit address arithmetic.
+template <class T>
+__device__ __forceinline__ __attribute__((address_space(1))) T *plane_ptr(
+    T *p, const Geo &g, int z) {
+  return (__attribute__((address_space(1))) T *)p + (size_t)g.XY * (uint32_t)z;
+}
+
 template <class C>
 __device__ __forceinline__ Tile tile_at(const Geo &g, uint32_t t) {
   uint32_t tx = t % g.ntx, r = t / g.ntx;
@@ -636,16 +645,15 @@ k_tile_local(const FieldDev *__restrict__ fds,
   // The stored local pointer: an owned target by its owned index, an exit
   // by its number (bit 15 set), so that later passes decode it with one
   // lookup in the tile's resolved exits.
-  uint32_t *__restrict__ lp = bt.fd.lp;
+  const uint32_t col = (uint32_t)gx + g.X * (uint32_t)gy;
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz) {
     if (lz < nz) {
-      const uint32_t v = (uint32_t)gx + g.X * (uint32_t)gy +
-                         g.XY * (uint32_t)(t.z0 + lz);
       const uint32_t w = ptr[lz];
       const uint32_t ca = (w & 0xffffu) | (((hmask_a >> lz) & 1u) << 16);
       const uint32_t cd = (w >> 16) | (((hmask_d >> lz) & 1u) << 16);
-      lp[v] = exit_code(ca, xa, pre, 0) | (exit_code(cd, xd, pre, 16) << 16);
+      plane_ptr(bt.fd.lp, g, t.z0 + lz)[col] =
+          exit_code(ca, xa, pre, 0) | (exit_code(cd, xd, pre, 16) << 16);
     }
   }
 
@@ -901,36 +909,49 @@ k_exit_resolve(const uint32_t *__restrict__ order, uint32_t ntiles,
 // pairs and output
 // ---------------------------------------------------------------------------
 
-// A tile's resolved exits, staged in LDS: ascent exits first, then descent.
+// A tile's decode table, staged in LDS: its resolved exits (ascent exits
+// first, then descent) and, after them, the id offset X*ly + X*Y*lz of each
+// row (ly, lz) of the tile, so that either reading of a stored code is one
+// LDS read and an add (no 32-bit multiplies per vertex).
 template <class C>
 struct Decode {
-  int32_t res[2 * C::kHalo];
+  static constexpr int kRows = 2 * C::kHalo;
+  int32_t tab[2 * C::kHalo + C::TY * C::TZ];
   uint32_t na;
+  uint32_t base;  // id of the tile's first vertex
 };
 
 template <class C>
 __device__ __forceinline__ void decode_setup(Decode<C> &s, uint32_t gt,
-                                             const Seg *seg,
-                                             const uint32_t *R) {
+                                             const Seg *seg, const uint32_t *R,
+                                             const Geo &g, const Tile &t) {
   const Seg sg = seg[gt];
   const uint32_t n = (uint32_t)sg.na + sg.nd;
   for (uint32_t k = threadIdx.x; k < n; k += C::kThreads)
-    s.res[k] = (int32_t)(R[sg.base + k] & ~kRoot);
-  if (threadIdx.x == 0) s.na = sg.na;
+    s.tab[k] = (int32_t)(R[sg.base + k] & ~kRoot);
+  for (uint32_t r = threadIdx.x; r < (uint32_t)(C::TY * C::TZ);
+       r += C::kThreads)
+    s.tab[Decode<C>::kRows + r] =
+        (int32_t)(g.X * (r % C::TY) + g.XY * (r / C::TY));
+  if (threadIdx.x == 0) {
+    s.na = sg.na;
+    s.base = (uint32_t)t.x0 + g.X * (uint32_t)t.y0 + g.XY * (uint32_t)t.z0;
+  }
   __syncthreads();
 }
 
 // Final extremum of a stored local pointer code, without branches (this is
-// unrolled over a whole column): both readings are formed, one is kept.
+// unrolled over a whole column): an exit reads its resolved extremum, an
+// owned code its row offset, from the one table.
 template <class C>
 __device__ __forceinline__ int32_t decode_final(const Decode<C> &s,
-                                                const Geo &g, const Tile &t,
                                                 uint32_t code, bool desc) {
+  static_assert((C::TX & (C::TX - 1)) == 0, "power-of-two tile width");
   const bool ex = (code & kExitCode) != 0u;
   const uint32_t low = code & (kExitCode - 1);
-  const int32_t r = s.res[ex ? (desc ? s.na : 0u) + low : 0u];
-  const int32_t o = (int32_t)owned_global<C>(g, t, low);
-  return ex ? r : o;
+  const int32_t v = s.tab[ex ? (desc ? s.na : 0u) + low
+                             : Decode<C>::kRows + low / C::TX];
+  return ex ? v : (int32_t)(s.base + low % C::TX + (uint32_t)v);
 }
 
 __global__ void k_table_clear(unsigned long long *keys, int32_t *vals,
@@ -991,7 +1012,10 @@ constexpr int kPairProbes = 16;
 __device__ __forceinline__ int pair_slot(unsigned long long *skey,
                                          unsigned *fill,
                                          unsigned long long key) {
-  uint32_t h = (uint32_t)mix64(key) & (kPairSlots - 1);
+  // The slot is local to the tile, so a multiply-free hash of the two
+  // labels serves (the global table keeps its 64-bit mix).
+  const uint32_t a = (uint32_t)(key >> 32), d = (uint32_t)key;
+  uint32_t h = (a ^ (a >> 10) ^ (d << 3) ^ (d >> 7)) & (kPairSlots - 1);
 #pragma unroll 1
   for (int probe = 0; probe < kPairProbes; ++probe) {
     unsigned long long cur = skey[h];
@@ -1049,13 +1073,13 @@ k_tile_pairs(const FieldDev *__restrict__ fds,
   const bool col_in = gx < (int)g.X && gy < (int)g.Y;
   int nz = (int)g.Z - t.z0;
   nz = col_in ? (nz < C::TZ ? nz : C::TZ) : 0;
+  // Column offset within a plane; plane bases are uniform over the block.
+  const uint32_t col = (uint32_t)gx + g.X * (uint32_t)gy;
   uint32_t code[C::TZ];
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz)
-    code[lz] = lz < nz ? bt.fd.lp[(uint32_t)gx + g.X * (uint32_t)gy +
-                                  g.XY * (uint32_t)(t.z0 + lz)]
-                       : 0u;
-  decode_setup<C>(s, bt.gt, seg, R);
+    code[lz] = lz < nz ? plane_ptr(bt.fd.lp, g, t.z0 + lz)[col] : 0u;
+  decode_setup<C>(s, bt.gt, seg, R, g, t);
 
   unsigned fresh = 0;
   bool overflow = false;
@@ -1066,12 +1090,11 @@ k_tile_pairs(const FieldDev *__restrict__ fds,
   for (int lz = 0; lz < C::TZ; ++lz) {
     unsigned long long key = kEmptyKey;
     if (lz < nz)
-      key = pair_key(decode_final<C>(s, g, t, code[lz] & 0xffffu, false),
-                     decode_final<C>(s, g, t, code[lz] >> 16, true));
+      key = pair_key(decode_final<C>(s, code[lz] & 0xffffu, false),
+                     decode_final<C>(s, code[lz] >> 16, true));
     if (key != last && key != kEmptyKey) {
       last = key;
-      const int32_t id = (int32_t)((uint32_t)gx + g.X * (uint32_t)gy +
-                                   g.XY * (uint32_t)(t.z0 + lz));
+      const int32_t id = (int32_t)(col + g.XY * (uint32_t)(t.z0 + lz));
       const int slot = pair_slot(skey, &sfill, key);
       if (slot >= 0)
         atomicMin(&sval[slot], id);
@@ -1123,13 +1146,12 @@ k_tile_write(const FieldDev *__restrict__ fds,
   const bool col_in = gx < (int)g.X && gy < (int)g.Y;
   int nz = (int)g.Z - t.z0;
   nz = col_in ? (nz < C::TZ ? nz : C::TZ) : 0;
+  const uint32_t col = (uint32_t)gx + g.X * (uint32_t)gy;
   uint32_t code[C::TZ];
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz)
-    code[lz] = lz < nz ? bt.fd.lp[(uint32_t)gx + g.X * (uint32_t)gy +
-                                  g.XY * (uint32_t)(t.z0 + lz)]
-                       : 0u;
-  decode_setup<C>(s, bt.gt, seg, R);
+    code[lz] = lz < nz ? plane_ptr(bt.fd.lp, g, t.z0 + lz)[col] : 0u;
+  decode_setup<C>(s, bt.gt, seg, R, g, t);
 
   int16_t slot[C::TZ];
   // The slot (or, off the table, the cell) of the column's previous pair.
@@ -1139,14 +1161,12 @@ k_tile_write(const FieldDev *__restrict__ fds,
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz) {
     const bool in = lz < nz;
-    const uint32_t v =
-        (uint32_t)gx + g.X * (uint32_t)gy + g.XY * (uint32_t)(t.z0 + lz);
     int32_t a = 0, d = 0;
     if (in) {
-      a = decode_final<C>(s, g, t, code[lz] & 0xffffu, false);
-      d = decode_final<C>(s, g, t, code[lz] >> 16, true);
-      A[v] = a;
-      D[v] = d;
+      a = decode_final<C>(s, code[lz] & 0xffffu, false);
+      d = decode_final<C>(s, code[lz] >> 16, true);
+      plane_ptr(A, g, t.z0 + lz)[col] = a;
+      plane_ptr(D, g, t.z0 + lz)[col] = d;
     }
     slot[lz] = -1;
     if (ms) {  // uniform over the block: ms belongs to the field
@@ -1159,7 +1179,7 @@ k_tile_write(const FieldDev *__restrict__ fds,
       }
       if (in) {
         slot[lz] = (int16_t)last_slot;
-        if (last_slot < 0) ms[v] = last_cell;
+        if (last_slot < 0) plane_ptr(ms, g, t.z0 + lz)[col] = last_cell;
       }
     }
   }
@@ -1172,8 +1192,7 @@ k_tile_write(const FieldDev *__restrict__ fds,
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz) {
     if (lz < nz && slot[lz] >= 0)
-      ms[(uint32_t)gx + g.X * (uint32_t)gy + g.XY * (uint32_t)(t.z0 + lz)] =
-          scell[slot[lz]];
+      plane_ptr(ms, g, t.z0 + lz)[col] = scell[slot[lz]];
   }
 }
 
