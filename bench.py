@@ -28,7 +28,32 @@ WORKLOAD_TEXT = {
     "gauss1024": "gauss1024: 1024^3 float32, sum of 512 Gaussians "
                  "(sigma U[0.02,0.1]*1024) + U[-1e-4,1e-4] noise, seed 1",
     "gauss64": "gauss64: 64^3 float32, sum of 8 Gaussians + noise, seed 0",
+    "perlin512": "perlin512: 512^3 float32, one layer of Perlin gradient "
+                 "noise, frequency 0.1, amplitude 1, seed 5",
+    "perlin1024": "perlin1024: 1024^3 float32, one layer of Perlin gradient "
+                  "noise, frequency 0.1, amplitude 1, seed 5",
 }
+
+# The paper's one-node times (seconds; 12 cores of an Intel Xeon Gold 6126)
+# on the same synthetic workloads: segmentation at 512^3 and 1024^3 (table
+# "overview") and implicit connected components of the 1024^3 field under
+# the three feature thresholds (table "different_thresholds"; its rows are
+# labelled top 10 / 50 / 90 %).  Another machine's numbers: context only.
+PAPER_1N_SECONDS = {
+    "perlin512": 11.291, "perlin1024": 86.044,
+    "ccperlin_t90": 47.285, "ccperlin_t50": 163.410, "ccperlin_t10": 226.593,
+}
+
+
+def paper_reference(workload, n, value_gvs):
+    """(vs_baseline, reference record) against the paper's one-node time."""
+    sec = PAPER_1N_SECONDS.get(workload)
+    if sec is None:
+        return None, None
+    ref = n / sec / 1e9
+    return round(value_gvs / ref, 1), {
+        "seconds": sec, "gvertices_per_s": round(ref, 5),
+        "hardware": "1 CPU node, 12 cores (Intel Xeon Gold 6126)"}
 
 
 def log(*a):
@@ -115,6 +140,13 @@ CC_TEXT = {
     "cc1024": "cc1024: mask = gauss1024 field (1024^3 float32, 512 Gaussians, "
               "seed 1) above its 70th percentile (k = floor(0.7 N)-th smallest "
               "value), Freudenthal connectivity, int64 labels",
+    "ccperlin_t90": "ccperlin_t90: perlin1024 field normalised to [0,1] by "
+                    "its min and max, mask = value above 0.9, Freudenthal "
+                    "connectivity, int64 labels",
+    "ccperlin_t50": "ccperlin_t50: perlin1024 field normalised to [0,1], "
+                    "mask = value above 0.5, int64 labels",
+    "ccperlin_t10": "ccperlin_t10: perlin1024 field normalised to [0,1], "
+                    "mask = value above 0.1, int64 labels",
     "csr50m": "csr50m: 368^3 = 49.8M-vertex jittered Kuhn tetrahedralisation "
               "as symmetric CSR (int64 row_ptr, int32 col_idx), vertex ids "
               "randomly permuted, seed 2; mask = Gaussian sum (24 bumps) at "
@@ -133,6 +165,17 @@ def bench_cc(args, msc, synth, torch, dev):
         k = int(0.7 * n)
         tau = torch.sort(f.reshape(-1)).values[k]
         mask = (f > tau).to(torch.uint8)
+        del f
+        torch.cuda.empty_cache()
+        labels = torch.empty(n, dtype=torch.int64, device=dev)
+        run = lambda: msc.cc_label_grid_into(mask, labels, stream=stream)
+        fg = int(mask.sum().item())
+    elif args.workload.startswith("ccperlin_t"):
+        level = int(args.workload[-2:]) / 100.0
+        log(f"[bench] generating perlin1024 and its mask above {level}")
+        f = synth.config_field("perlin1024", device=dev)
+        n = f.numel()
+        mask = synth.normalized_mask(f, level)
         del f
         torch.cuda.empty_cache()
         labels = torch.empty(n, dtype=torch.int64, device=dev)
@@ -165,17 +208,20 @@ def bench_cc(args, msc, synth, torch, dev):
     log(f"[bench] {args.steps} steps: {dt * 1e3:.2f} ms/step")
     log_prof(prof)
     ncomp = int((labels == torch.arange(n, device=dev)).sum().item())
+    vs, ref = paper_reference(args.workload, n, n / dt / 1e9)
     out = {
         "metric": "Gvertices/s connected components (" + args.workload + ")",
         "value": round(n / dt / 1e9, 3), "unit": "Gvertices/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+        "scaling": "weak", "vs_baseline": vs, "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": CC_TEXT[args.workload], "vertices": n,
                    "foreground": fg, "components": ncomp},
         "roofline": roofline_of(prof, args.workload),
     }
+    if ref:
+        out["paper_one_node"] = ref
     print(json.dumps(out), flush=True)
 
 
@@ -393,8 +439,8 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="gauss1024",
-                    choices=sorted(WORKLOAD_TEXT) + ["batch256", "serve",
-                                                     "cc1024", "csr50m"])
+                    choices=sorted(WORKLOAD_TEXT) + ["batch256", "serve"]
+                    + sorted(CC_TEXT))
     ap.add_argument("--cpu-depth", type=int, default=100,
                     help="z-planes of the field the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -480,11 +526,12 @@ def main():
     tile = (stats["tile_x"], stats["tile_y"], stats["tile_z"])
     roofline = roofline_of(prof, args.workload, tile)
 
+    vs, ref = paper_reference(args.workload, n, value)
     out = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gvertices/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "scaling": "weak", "vs_baseline": vs, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "vertices": n, "outputs": "int32 asc, desc, ms",
@@ -500,6 +547,8 @@ def main():
             "measured_bytes": path_traffic(args.workload),
             "measured_frac": None},
     }
+    if ref:
+        out["paper_one_node"] = ref
     pr = out["path_roofline"]
     if pr["measured_bytes"]:
         pr["measured_frac"] = round(pr["measured_bytes"] / (ms_per_step * 1e-3)

@@ -161,6 +161,18 @@ MSC_API int msc_autotune(msc_ctx *ctx, int nfields, const msc_field *fields,
 MSC_API int msc_tile_shapes(int *out, int max);
 MSC_API int msc_set_tile(msc_ctx *ctx, int tx, int ty, int tz);
 
+/*
+ * First capacity (slots) of the table of (ascending, descending) label pairs
+ * that gives the MS labels (a tuning knob; results do not depend on it).
+ * 0, the default, sizes it from the extremum counts.  A pass whose pairs do
+ * not fit runs again on a table four times larger, up to a capacity that
+ * always suffices (twice the smaller of the vertex count and the product of
+ * the extremum counts), so a small value costs time, never correctness.
+ * Values are rounded up to a power of two of at least 1024.  MSC_EINVAL for
+ * a NULL context or a value above 2^32.
+ */
+MSC_API int msc_set_table_capacity(msc_ctx *ctx, uint64_t first_capacity);
+
 /* Counters of the last successful msc_segment on this context. */
 typedef struct msc_stats {
   int64_t n_vertices;

@@ -255,6 +255,12 @@ int msc_set_tile(msc_ctx *ctx, int tx, int ty, int tz) {
   return MSC_OK;
 }
 
+int msc_set_table_capacity(msc_ctx *ctx, uint64_t first_capacity) {
+  if (!ctx || first_capacity > (1ull << 32)) return MSC_EINVAL;
+  ctx->table_first = first_capacity;
+  return MSC_OK;
+}
+
 int msc_last_stats(const msc_ctx *ctx, msc_stats *out) {
   if (!ctx || !out) return MSC_EINVAL;
   *out = ctx->stats;

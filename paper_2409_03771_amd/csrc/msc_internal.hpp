@@ -109,6 +109,7 @@ struct msc_ctx {
   msc_stats stats{};
   msc::Profiler prof;
   int tile_choice = 0;         // segmentation tile shape (0 = default)
+  uint64_t table_first = 0;    // first pair-table capacity (0 = automatic)
   void *pinned = nullptr;      // grow-only pinned host staging
   size_t pinned_bytes = 0;
   std::vector<msc_stats> field_stats;  // per field of the last batch

@@ -963,6 +963,12 @@ __global__ void k_table_clear(unsigned long long *keys, int32_t *vals,
   }
 }
 
+// Linear probing gives up after kTableProbes slots: an insert that finds no
+// room reports an overflow (the host then grows the table and runs the pair
+// pass again), and a lookup stops there too, since every key sits within
+// that many slots of its hash.
+constexpr uint32_t kTableProbes = 512;
+
 // Insert (key, id) keeping the smallest id; reads before each atomic so that
 // the common case (key present with a smaller id) stays a plain load.
 __device__ __forceinline__ bool table_insert(unsigned long long *keys,
@@ -971,7 +977,7 @@ __device__ __forceinline__ bool table_insert(unsigned long long *keys,
                                              int32_t id, unsigned *fresh) {
   uint32_t h = (uint32_t)mix64(key) & mask;
 #pragma unroll 1
-  for (uint32_t probe = 0; probe <= mask; ++probe) {
+  for (uint32_t probe = 0; probe <= mask && probe < kTableProbes; ++probe) {
     unsigned long long cur = __atomic_load_n(&keys[h], __ATOMIC_RELAXED);
     if (cur == kEmptyKey) {
       cur = atomicCAS(&keys[h], kEmptyKey, key);
@@ -1038,7 +1044,7 @@ __device__ __forceinline__ int32_t table_lookup(
     const int32_t *__restrict__ vals, uint32_t mask, unsigned long long key) {
   uint32_t h = (uint32_t)mix64(key) & mask;
 #pragma unroll 1
-  for (uint32_t probe = 0; probe <= mask; ++probe) {
+  for (uint32_t probe = 0; probe <= mask && probe < kTableProbes; ++probe) {
     const unsigned long long cur = keys[h];
     if (cur == key) return vals[h];
     if (cur == kEmptyKey) return -1;
@@ -1218,6 +1224,28 @@ uint64_t table_capacity(uint64_t n, uint64_t nmax, uint64_t nmin) {
   return cap;
 }
 
+// First capacity tried: the bound above, or twice an expected cell count of
+// 32 per extremum (plus slack) when that is smaller, or the caller's choice.
+// Cells are pairs of manifolds that meet, far fewer than all pairs of
+// extrema; a field with more makes the pair pass overflow and run again on
+// a larger table.
+uint64_t table_first_capacity(uint64_t n, uint64_t nmax, uint64_t nmin,
+                              uint64_t requested) {
+  const uint64_t full = table_capacity(n, nmax, nmin);
+  uint64_t cap = 1024;
+  const uint64_t want = requested ? (requested + 1) / 2
+                                  : 32 * (nmax + nmin) + 65536;
+  while (cap < 2 * want && cap < full) cap <<= 1;
+  return cap;
+}
+
+// Per-field cell counters back to zero before the pair pass runs again.
+__global__ void k_clear_field_ctr(unsigned long long *fctr, int nfields,
+                                  int which) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < nfields) fctr[(size_t)i * kFieldCtrs + which] = 0;
+}
+
 // Grow-only pinned host staging owned by the context.
 template <class T>
 int stage(msc_ctx *ctx, size_t count, T **out) {
@@ -1378,17 +1406,26 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
     k_steps_reduce<<<kStepsBlocks, 1024, 0, s>>>(rstat, 2 * nt, ctr);
   }
 
-  // Pair tables of the fields that want cells, in one block of `tab`.
-  uint64_t total_cap = 0;
-  std::vector<uint64_t> off(nfields, 0);
+  // Pair tables of the fields that want cells, in one block of `tab`: each
+  // starts at its first capacity and all grow fourfold while the pair pass
+  // overflows (up to the capacity that always suffices).
+  std::vector<uint64_t> cap(nfields, 0);
+  bool any_ms = false;
   for (int i = 0; i < nfields; ++i) {
     if (!fields[i].ms) continue;
-    off[i] = total_cap;
-    total_cap += table_capacity(fd[i].g.N, fc[(size_t)i * kFieldCtrs + kFMaxima],
-                                fc[(size_t)i * kFieldCtrs + kFMinima]);
+    any_ms = true;
+    cap[i] = table_first_capacity(fd[i].g.N,
+                                  fc[(size_t)i * kFieldCtrs + kFMaxima],
+                                  fc[(size_t)i * kFieldCtrs + kFMinima],
+                                  ctx->table_first);
   }
-  bool any_ms = total_cap > 0;
-  if (any_ms) {
+  while (any_ms) {
+    uint64_t total_cap = 0;
+    std::vector<uint64_t> off(nfields, 0);
+    for (int i = 0; i < nfields; ++i) {
+      off[i] = total_cap;
+      total_cap += cap[i];
+    }
     MSC_TRY(reserve(ctx->tab, align256(total_cap * 8) + align256(total_cap * 4) +
                                   4096));
     Carver tc(ctx->tab);
@@ -1398,11 +1435,7 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
       if (!fields[i].ms) continue;
       fd[i].keys = keys + off[i];
       fd[i].vals = vals + off[i];
-      fd[i].mask = (uint32_t)(table_capacity(
-                                  fd[i].g.N,
-                                  fc[(size_t)i * kFieldCtrs + kFMaxima],
-                                  fc[(size_t)i * kFieldCtrs + kFMinima]) -
-                              1);
+      fd[i].mask = (uint32_t)(cap[i] - 1);
     }
     char *st = nullptr;
     MSC_TRY(stage(ctx, nfields * sizeof(FieldDev), &st));
@@ -1417,6 +1450,23 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
                                                           next, ctr, tstat)));
     k_tile_stat_reduce<<<grid_for(nt), kBlock, 0, s>>>(tstat, 2, nt, tfield,
                                                        fctr, kFCells);
+    MSC_TRY(read_counters(ctx, s));
+    if (ctx->hctr[kCtrOverflow] & 2) return MSC_EHIP;
+    if (!(ctx->hctr[kCtrOverflow] & 1)) break;
+    bool grew = false;
+    for (int i = 0; i < nfields; ++i) {
+      if (!fields[i].ms) continue;
+      const uint64_t full = table_capacity(
+          fd[i].g.N, fc[(size_t)i * kFieldCtrs + kFMaxima],
+          fc[(size_t)i * kFieldCtrs + kFMinima]);
+      const uint64_t next_cap = cap[i] * 4 < full ? cap[i] * 4 : full;
+      grew |= next_cap > cap[i];
+      cap[i] = next_cap;
+    }
+    if (!grew) return MSC_ENOMEM;
+    k_clear_field_ctr<<<grid_for(nfields), kBlock, 0, s>>>(fctr, nfields,
+                                                           kFCells);
+    k_fill_u64<<<1, kBlock, 0, s>>>(ctr + kCtrOverflow, 1, 0ull);
   }
   MSC_PHASE(ctx, s, "tile_write", (any_ms ? 16.0 : 12.0) * total_n,
             (k_tile_write<C><<<nt, C::kThreads, 0, s>>>(fds, tfield, seg,

@@ -70,6 +70,7 @@ _SIGS = {
                       ctypes.POINTER(msc_tune)], _I32),
     "msc_tile_shapes": ([ctypes.POINTER(_I32), _I32], _I32),
     "msc_set_tile": ([_P, _I32, _I32, _I32], _I32),
+    "msc_set_table_capacity": ([_P, ctypes.c_uint64], _I32),
     "msc_profile": ([_P, _I32], _I32),
     "msc_profile_read": ([_P, ctypes.POINTER(msc_phase), _I32,
                           ctypes.POINTER(_I32)], _I32),
@@ -269,6 +270,13 @@ def tile_shapes() -> list[tuple[int, int, int]]:
 def set_tile(tx: int, ty: int, tz: int, device: int | None = None):
     """Select the segmentation tile shape of a device's context."""
     _check(_lib.msc_set_tile(context(device), tx, ty, tz), "msc_set_tile")
+
+
+def set_table_capacity(first_capacity: int, device: int | None = None):
+    """First capacity of the cell pair table of a device's context (0 =
+    sized from the extremum counts); an undersized table is grown."""
+    _check(_lib.msc_set_table_capacity(context(device), int(first_capacity)),
+           "msc_set_table_capacity")
 
 
 def profile(enable: bool, device: int | None = None):

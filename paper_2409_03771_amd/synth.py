@@ -77,18 +77,114 @@ def gaussian_field(dims, nbumps: int, seed: int, noise: bool = True,
     return out
 
 
+def perlin_perm(seed: int) -> np.ndarray:
+    """The lattice hash of the noise: a seeded permutation of 0..255,
+    repeated once so that sums of two entries index it directly."""
+    p = np.random.default_rng(seed).permutation(256).astype(np.int64)
+    return np.concatenate([p, p])
+
+
+def perlin_field(dims, seed: int, frequency: float = 0.1,
+                 amplitude: float = 1.0, z_chunk: int = 8, device=None):
+    """float32 field [Z, Y, X] of one layer of Perlin gradient noise,
+    f(x, y, z) = amplitude * noise(frequency * (x, y, z)).
+
+    The noise is Perlin's lattice gradient noise (Perlin 1985) in its
+    improved form (Perlin 2002): the lattice corners of the point's cell
+    each hash, through a seeded permutation, to one of twelve gradient
+    directions (the cube's edge midpoints, two repeated); the dot products
+    of those gradients with the offsets to the point are blended with the
+    quintic fade 6t^5 - 15t^4 + 10t^3 along each axis.  It is zero at lattice
+    points.  Evaluated in float64 with torch (on `device`, default CPU) and
+    rounded once to float32; returns a torch tensor when `device` is given,
+    a numpy array otherwise."""
+    import torch
+    X, Y, Z = (int(d) for d in dims)
+    dev = torch.device("cpu") if device is None else torch.device(device)
+    perm = torch.from_numpy(perlin_perm(seed)).to(dev)
+    out = torch.empty((Z, Y, X), dtype=torch.float32, device=dev)
+    xs = torch.arange(X, dtype=torch.float64, device=dev) * frequency
+    ys = torch.arange(Y, dtype=torch.float64, device=dev) * frequency
+    xi0 = torch.floor(xs)
+    yi0 = torch.floor(ys)
+
+    def fade(t):
+        return t * t * t * (t * (t * 6.0 - 15.0) + 10.0)
+
+    def grad(h, x, y, z):
+        h = h & 15
+        u = torch.where(h < 8, x, y)
+        v = torch.where(h < 4, y, torch.where((h == 12) | (h == 14), x, z))
+        return (torch.where((h & 1) == 0, u, -u) +
+                torch.where((h & 2) == 0, v, -v))
+
+    def lerp(t, a, b):
+        return a + t * (b - a)
+
+    fx = (xs - xi0)[None, None, :]
+    fy = (ys - yi0)[None, :, None]
+    u = fade(fx)
+    v = fade(fy)
+    Xi = (xi0.to(torch.int64) & 255)[None, None, :]
+    Yi = (yi0.to(torch.int64) & 255)[None, :, None]
+    for z0 in range(0, Z, z_chunk):
+        z1 = min(Z, z0 + z_chunk)
+        zs = torch.arange(z0, z1, dtype=torch.float64, device=dev) * frequency
+        zi0 = torch.floor(zs)
+        fz = (zs - zi0)[:, None, None]
+        w = fade(fz)
+        Zi = (zi0.to(torch.int64) & 255)[:, None, None]
+        A = perm[Xi] + Yi
+        B = perm[Xi + 1] + Yi
+        AA, AB = perm[A] + Zi, perm[A + 1] + Zi
+        BA, BB = perm[B] + Zi, perm[B + 1] + Zi
+        n0 = lerp(v, lerp(u, grad(perm[AA], fx, fy, fz),
+                          grad(perm[BA], fx - 1, fy, fz)),
+                  lerp(u, grad(perm[AB], fx, fy - 1, fz),
+                       grad(perm[BB], fx - 1, fy - 1, fz)))
+        n1 = lerp(v, lerp(u, grad(perm[AA + 1], fx, fy, fz - 1),
+                          grad(perm[BA + 1], fx - 1, fy, fz - 1)),
+                  lerp(u, grad(perm[AB + 1], fx, fy - 1, fz - 1),
+                       grad(perm[BB + 1], fx - 1, fy - 1, fz - 1)))
+        out[z0:z1] = (amplitude * lerp(w, n0, n1)).to(torch.float32)
+    return out if device is not None else out.numpy()
+
+
+def normalized_mask(f, level: float):
+    """uint8 feature mask of the threshold study: the field is normalised
+    to [0, 1] by its minimum and maximum, and a vertex is a feature when its
+    normalised value is above `level` (0.9, 0.5 and 0.1 in the study).
+    Works on numpy arrays and torch tensors alike (the comparison is
+    f - min > level * (max - min), in float64)."""
+    try:
+        import torch
+        if isinstance(f, torch.Tensor):
+            lo, hi = f.min().double(), f.max().double()
+            return ((f.double() - lo) > level * (hi - lo)).to(torch.uint8)
+    except ImportError:  # pragma: no cover
+        pass
+    lo, hi = float(f.min()), float(f.max())
+    return ((f.astype(np.float64) - lo) > level * (hi - lo)).astype(np.uint8)
+
+
 WORKLOADS = {
-    # name: (dims, bumps, seed)
-    "gauss64": ((64, 64, 64), 8, 0),
-    "gauss1024": ((1024, 1024, 1024), 512, 1),
+    # name: (kind, dims, bumps, seed); Perlin fields take frequency 0.1 and
+    # amplitude 1 (the paper's synthetic workload).
+    "gauss64": ("gauss", (64, 64, 64), 8, 0),
+    "gauss1024": ("gauss", (1024, 1024, 1024), 512, 1),
+    "perlin512": ("perlin", (512, 512, 512), 0, 5),
+    "perlin1024": ("perlin", (1024, 1024, 1024), 0, 5),
 }
 
 
 def config_field(name: str, device=None):
-    """The named single-field workloads: "gauss64" (64^3, 8 bumps, seed 0)
-    and "gauss1024" (1024^3, 512 bumps, seed 1)."""
+    """The named single-field workloads: "gauss64" (64^3, 8 bumps, seed 0),
+    "gauss1024" (1024^3, 512 bumps, seed 1), and one-layer Perlin noise at
+    frequency 0.1 and amplitude 1, "perlin512" and "perlin1024" (seed 5)."""
     alias = {"c1": "gauss64", "c2": "gauss1024"}
-    dims, nb, seed = WORKLOADS[alias.get(name, name)]
+    kind, dims, nb, seed = WORKLOADS[alias.get(name, name)]
+    if kind == "perlin":
+        return perlin_field(dims, seed, device=device)
     return gaussian_field(dims, nb, seed, device=device)
 
 

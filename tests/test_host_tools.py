@@ -80,3 +80,22 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_perlin_generator_properties():
+    """Perlin noise vanishes at lattice points, stays within the bound of
+    the twelve-gradient noise (|n| <= 1), does not depend on the z chunking,
+    and its normalised masks nest (0.9 within 0.5 within 0.1)."""
+    import numpy as np
+    from paper_2409_03771_amd import synth
+    f = synth.perlin_field((33, 25, 17), seed=5, frequency=0.125)
+    assert np.all(f[::8, ::8, ::8] == 0.0)
+    g = synth.perlin_field((40, 30, 20), seed=5)
+    assert np.abs(g).max() <= 1.0 and g.std() > 0.1
+    h = synth.perlin_field((40, 30, 20), seed=5, z_chunk=3)
+    assert np.array_equal(g, h)
+    assert not np.array_equal(g, synth.perlin_field((40, 30, 20), seed=6))
+    m9, m5, m1 = (synth.normalized_mask(g, t) for t in (0.9, 0.5, 0.1))
+    assert np.all(m9 <= m5) and np.all(m5 <= m1)
+    assert 0 < m9.sum() < m5.sum() < m1.sum() < g.size
+    assert synth.normalized_mask(g, 0.0).sum() == g.size - (g == g.min()).sum()
