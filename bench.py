@@ -119,7 +119,8 @@ def roofline_of(prof, workload=None, tile=None):
     avg_ms = dom["total_ms"] / dom["launches"]
     bpl = dom["bytes"] / dom["launches"]
     achieved = bpl / (avg_ms * 1e-3) / 1e9
-    kname = "k_" + name + ("<%d,%d,%d>" % tile if tile else "")
+    templated = name.startswith(("tile_", "exit_link", "exit_resolve"))
+    kname = "k_" + name + ("<%d,%d,%d>" % tile if tile and templated else "")
     return {"bound": "hbm", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -158,6 +159,14 @@ def bench_cc(args, msc, synth, torch, dev):
     """Connected components: the grid mask at 1024^3 or the 50M-vertex CSR
     mesh, one labelling call per step, inputs resident on the device."""
     stream = torch.cuda.current_stream(dev)
+
+    def cc_grid(mask, labels):
+        if args.ranks > 1:
+            msc.cc_label_grid_ranks_into(mask, args.ranks, labels,
+                                         stream=stream)
+        else:
+            msc.cc_label_grid_into(mask, labels, stream=stream)
+
     if args.workload == "cc1024":
         log("[bench] generating gauss1024 and its 70th-percentile mask")
         f = synth.config_field("gauss1024", device=dev)
@@ -168,7 +177,7 @@ def bench_cc(args, msc, synth, torch, dev):
         del f
         torch.cuda.empty_cache()
         labels = torch.empty(n, dtype=torch.int64, device=dev)
-        run = lambda: msc.cc_label_grid_into(mask, labels, stream=stream)
+        run = lambda: cc_grid(mask, labels)
         fg = int(mask.sum().item())
     elif args.workload.startswith("ccperlin_t"):
         level = int(args.workload[-2:]) / 100.0
@@ -179,7 +188,7 @@ def bench_cc(args, msc, synth, torch, dev):
         del f
         torch.cuda.empty_cache()
         labels = torch.empty(n, dtype=torch.int64, device=dev)
-        run = lambda: msc.cc_label_grid_into(mask, labels, stream=stream)
+        run = lambda: cc_grid(mask, labels)
         fg = int(mask.sum().item())
     else:
         log("[bench] generating the 368^3 Kuhn CSR mesh on the host")
@@ -217,7 +226,8 @@ def bench_cc(args, msc, synth, torch, dev):
         "scaling": "weak", "vs_baseline": vs, "dtype": "int64",
         "data": "synthetic",
         "config": {"workload": CC_TEXT[args.workload], "vertices": n,
-                   "foreground": fg, "components": ncomp},
+                   "foreground": fg, "components": ncomp,
+                   "virtual_ranks": args.ranks},
         "roofline": roofline_of(prof, args.workload),
     }
     if ref:
@@ -451,6 +461,9 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=48)
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the short served leg of the default run")
+    ap.add_argument("--ranks", type=int, default=1,
+                    help="virtual z-slab ranks on the one device (the "
+                         "paper's distributed scheme; 1 = single domain)")
     ap.add_argument("--tile", default=None,
                     help="tile shape of the fused pass, e.g. 32x16x16")
     ap.add_argument("--calibrate-copy", type=float, default=None,
@@ -503,8 +516,15 @@ def main():
     ms = torch.empty_like(asc)
     stream = torch.cuda.current_stream(dev)
 
+    def segment(field, asc, desc, ms):
+        if args.ranks > 1:
+            msc.segment_ranks_into(field, args.ranks, asc, desc, ms,
+                                   stream=stream)
+        else:
+            msc.segment_into(field, asc, desc, ms, stream=stream)
+
     for i in range(args.warmup):
-        msc.segment_into(field, asc, desc, ms, stream=stream)
+        segment(field, asc, desc, ms)
         log(f"[bench] warmup {i + 1}/{args.warmup}")
     torch.cuda.synchronize()
     stats = msc.last_stats()
@@ -514,7 +534,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        msc.segment_into(field, asc, desc, ms, stream=stream)
+        segment(field, asc, desc, ms)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     msc.profile(False)
@@ -536,7 +556,7 @@ def main():
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "vertices": n, "outputs": "int32 asc, desc, ms",
                    "maxima": stats["n_maxima"], "minima": stats["n_minima"],
-                   "cells": stats["n_cells"]},
+                   "cells": stats["n_cells"], "virtual_ranks": args.ranks},
         "roofline": roofline,
         # Whole call: the compulsory 16 B per vertex (read f, write asc, desc,
         # ms) and the rocprofv3-measured HBM bytes of all kernels, per step.

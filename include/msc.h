@@ -233,6 +233,21 @@ MSC_API int cc_label_grid(msc_ctx *ctx, const uint8_t *mask, const int64_t dims[
                   int64_t *labels, void *stream);
 
 /*
+ * cc_label_grid through the paper's distributed scheme with `ranks` virtual
+ * ranks on one device (Alg. 3 followed by the communication phase it
+ * shares with the MS segmentation): the z-extent is split into slabs of
+ * planes [r*Z/ranks, (r+1)*Z/ranks), each slab is labelled as a grid of its
+ * own, and the exchange across every slab boundary joins the labels of the
+ * two ends of each Freudenthal edge that crosses it (both in the mask; the
+ * smaller label wins), after which every vertex takes its merged label.
+ * Outputs, layout and errors as cc_label_grid, and bit-identical to it;
+ * MSC_EINVAL also for ranks < 1 or ranks > Z.
+ */
+MSC_API int cc_label_grid_ranks(msc_ctx *ctx, const uint8_t *mask,
+                                const int64_t dims[3], int ranks,
+                                int64_t *labels, void *stream);
+
+/*
  * Connected components of an explicit graph in CSR form (the paper's
  * "explicit" CC on extracted geometry).
  *

@@ -10,8 +10,14 @@ import importlib
 __all__ = ["msc", "synth"]
 
 
+_SUBMODULES = ("msc", "synth", "build", "profsum")
+
+
 def __getattr__(name):
-    if name in ("msc", "synth"):
+    # Submodules import on their own: `build` in particular must not load
+    # the library it is about to replace (a process keeps the first copy of
+    # a shared object it opened under a given path).
+    if name in _SUBMODULES:
         return importlib.import_module(f"{__name__}.{name}")
     mod = importlib.import_module(f"{__name__}.msc")
     return getattr(mod, name)

@@ -299,6 +299,19 @@ int cc_label_grid(msc_ctx *ctx, const uint8_t *mask, const int64_t dims[3],
                           static_cast<hipStream_t>(stream));
 }
 
+int cc_label_grid_ranks(msc_ctx *ctx, const uint8_t *mask,
+                        const int64_t dims[3], int ranks, int64_t *labels,
+                        void *stream) {
+  if (!ctx || !mask || !labels) return MSC_EINVAL;
+  int64_t n = 0;
+  MSC_TRY(check_dims(dims, &n));
+  if (ranks < 1 || ranks > dims[2]) return MSC_EINVAL;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return MSC_EHIP;
+  return msc::cc_grid_ranks_run(ctx, mask, dims[0], dims[1], dims[2], ranks,
+                                labels, static_cast<hipStream_t>(stream));
+}
+
 int cc_label_csr(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,
                  const int32_t *col_idx, const uint8_t *mask, int64_t *labels,
                  void *stream) {

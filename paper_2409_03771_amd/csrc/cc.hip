@@ -504,7 +504,7 @@ constexpr int kMaxRounds = 96;
 }  // namespace
 
 int cc_grid_run(msc_ctx *ctx, const uint8_t *mask, int64_t X, int64_t Y,
-                int64_t Z, int64_t *labels, hipStream_t s) {
+                int64_t Z, int64_t *labels, hipStream_t s, bool sync) {
   CGeo g{X, Y, Z, X * Y, X * Y * Z, (X + CTX - 1) / CTX, (Y + CTY - 1) / CTY,
          (Z + CTZ - 1) / CTZ};
   const int64_t ntiles = g.ntx * g.nty * g.ntz;
@@ -520,6 +520,7 @@ int cc_grid_run(msc_ctx *ctx, const uint8_t *mask, int64_t X, int64_t Y,
             (k_cc_cross<<<nb, kCThreads, 0, s>>>(g, loc, labels)));
   MSC_PHASE(ctx, s, "cc_final", 10.0 * g.N,
             (k_cc_final<<<nb, kCThreads, 0, s>>>(g, loc, labels)));
+  if (!sync) return MSC_OK;
   MSC_TRY(read_counters(ctx, s));
   ctx->stats = msc_stats{};
   ctx->stats.n_vertices = g.N;
@@ -593,6 +594,107 @@ int jump_run(msc_ctx *ctx, int64_t *d, int64_t n, int rounds, int sync,
   if (src != d)
     MSC_HIP_TRY(hipMemcpyAsync(d, src, n * sizeof(int64_t),
                                hipMemcpyDeviceToDevice, s));
+  return MSC_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Virtual ranks: slab-local labelling, then the exchange across slab
+// boundaries (Alg. 3 with the distributed phase it shares with the MS
+// segmentation).  Slab r holds planes [r*Z/R, (r+1)*Z/R).
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// A slab's labels name vertices by their id within the slab; adding the id
+// of the slab's first vertex makes them global ids.
+__global__ void __launch_bounds__(kBlock)
+k_rank_cc_shift(int64_t *L, int64_t n, int64_t off) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) {
+    const int64_t v = L[i];
+    if (v >= 0) L[i] = v + off;
+  }
+}
+
+// The exchange at the boundary between plane zb (top of one slab) and
+// zb + 1 (bottom of the next): every Freudenthal edge that crosses it,
+// (x, y, zb) -- (x + dx, y + dy, zb + 1) for dx, dy in {0, 1}, joins the
+// two endpoints' trees when both are in the mask.  L is the parent array:
+// every label is a root of its slab's forest, and the smaller root wins.
+__global__ void __launch_bounds__(kBlock)
+k_rank_cc_stitch(const uint8_t *__restrict__ mask, int64_t X, int64_t Y,
+                 int64_t zb, int64_t *L) {
+  const int64_t XY = X * Y;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const bool in = i < XY;
+  const int64_t x = in ? i % X : 0, y = in ? i / X : 0;
+  const int64_t u = i + XY * zb;
+  const bool mu = in && mask[u];
+  // The slab labels of both ends, joined once per distinct pair in a run
+  // of lanes: neighbouring vertices mostly carry the same two labels, and
+  // letting every lane unite them would pile compare-and-swaps onto the
+  // same root.
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int dx = e & 1, dy = e >> 1;
+    int64_t a = -1, b = -1;
+    if (mu && x + dx < X && y + dy < Y) {
+      const int64_t w = u + XY + dx + X * dy;
+      if (mask[w]) {
+        a = L[u];
+        b = L[w];
+      }
+    }
+    const int64_t pa = __shfl_up(a, 1), pb = __shfl_up(b, 1);
+    const bool first = (threadIdx.x & 63) == 0 || pa != a || pb != b;
+    if (a >= 0 && a != b && first) uf_unite<int64_t>(L, a, b);
+  }
+}
+
+// Every masked vertex takes the root of its label (the smallest id of its
+// component); run once no union is in flight.
+__global__ void __launch_bounds__(kBlock)
+k_rank_cc_final(int64_t *L, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) {
+    const int64_t v = L[i];
+    if (v >= 0) L[i] = uf_root<int64_t>(L, v);
+  }
+}
+
+unsigned blocks_for(int64_t n) { return (unsigned)((n + kBlock - 1) / kBlock); }
+
+}  // namespace
+
+int cc_grid_ranks_run(msc_ctx *ctx, const uint8_t *mask, int64_t X,
+                      int64_t Y, int64_t Z, int ranks, int64_t *labels,
+                      hipStream_t s) {
+  const int64_t XY = X * Y, N = XY * Z;
+  const int64_t thickest = (Z + ranks - 1) / ranks;
+  MSC_TRY(reserve(ctx->ws, align256(XY * thickest * sizeof(uint16_t)) + 4096));
+  for (int r = 0; r < ranks; ++r) {
+    const int64_t z0 = r * Z / ranks, z1 = (r + 1) * Z / ranks;
+    // No host round trip per slab: the slabs queue on the stream (the
+    // tile-local workspace is sized for the largest slab up front).
+    MSC_TRY(cc_grid_run(ctx, mask + XY * z0, X, Y, z1 - z0, labels + XY * z0,
+                        s, false));
+    if (z0 > 0)
+      MSC_PHASE(ctx, s, "rank_cc_shift", 16.0 * XY * (z1 - z0),
+                (k_rank_cc_shift<<<blocks_for(XY * (z1 - z0)), kBlock, 0, s>>>(
+                    labels + XY * z0, XY * (z1 - z0), XY * z0)));
+  }
+  for (int r = 1; r < ranks; ++r) {
+    const int64_t zb = r * Z / ranks - 1;
+    MSC_PHASE(ctx, s, "rank_cc_stitch", 2.0 * XY,
+              (k_rank_cc_stitch<<<blocks_for(XY), kBlock, 0, s>>>(mask, X, Y,
+                                                                  zb, labels)));
+  }
+  if (ranks > 1)
+    MSC_PHASE(ctx, s, "rank_cc_final", 16.0 * N,
+              (k_rank_cc_final<<<blocks_for(N), kBlock, 0, s>>>(labels, N)));
+  MSC_TRY(read_counters(ctx, s));
+  ctx->stats = msc_stats{};
+  ctx->stats.n_vertices = N;
   return MSC_OK;
 }
 

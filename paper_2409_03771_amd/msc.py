@@ -75,6 +75,8 @@ _SIGS = {
     "msc_profile_read": ([_P, ctypes.POINTER(msc_phase), _I32,
                           ctypes.POINTER(_I32)], _I32),
     "cc_label_grid": ([_P, _P, ctypes.POINTER(_I64), _P, _P], _I32),
+    "cc_label_grid_ranks": ([_P, _P, ctypes.POINTER(_I64), _I32, _P, _P],
+                            _I32),
     "cc_label_csr": ([_P, _I64, _P, _P, _P, _P, _P], _I32),
     "msc_pointer_jump": ([_P, _P, _I64, _I32, _I32, _P], _I32),
 }
@@ -180,14 +182,19 @@ def segment_ranks(field: torch.Tensor, ranks: int,
     n = field.numel()
     out = {k: (torch.empty(n, dtype=torch.int32, device=field.device)
                if k in want else None) for k in ("asc", "desc", "ms")}
+    segment_ranks_into(field, ranks, out["asc"], out["desc"], out["ms"],
+                       stream)
+    return out["asc"], out["desc"], out["ms"]
+
+
+def segment_ranks_into(field, ranks, asc, desc, ms, stream=None):
+    """segment_ranks into caller-owned int32 outputs (any may be None)."""
     code = _lib.msc_segment_ranks(
         context(field.device.index), _dev_ptr(field, torch.float32, "field"),
         _dims_arg(grid_dims(field.shape)), int(ranks),
-        _dev_ptr(out["asc"], torch.int32, "asc"),
-        _dev_ptr(out["desc"], torch.int32, "desc"),
-        _dev_ptr(out["ms"], torch.int32, "ms"), _stream(field, stream))
+        _dev_ptr(asc, torch.int32, "asc"), _dev_ptr(desc, torch.int32, "desc"),
+        _dev_ptr(ms, torch.int32, "ms"), _stream(field, stream))
     _check(code, "msc_segment_ranks")
-    return out["asc"], out["desc"], out["ms"]
 
 
 def _field_array(fields, outs, dims_list):
@@ -313,6 +320,25 @@ def cc_label_grid(mask: torch.Tensor, stream=None) -> torch.Tensor:
     labels = torch.empty(mask.numel(), dtype=torch.int64, device=mask.device)
     cc_label_grid_into(mask, labels, stream=stream)
     return labels
+
+
+def cc_label_grid_ranks(mask: torch.Tensor, ranks: int, dims=None,
+                        stream=None) -> torch.Tensor:
+    """cc_label_grid through `ranks` virtual z-slab ranks on one device
+    (slab-local labelling, then the exchange across slab boundaries)."""
+    labels = torch.empty(mask.numel(), dtype=torch.int64, device=mask.device)
+    cc_label_grid_ranks_into(mask, ranks, labels, dims, stream)
+    return labels
+
+
+def cc_label_grid_ranks_into(mask, ranks, labels, dims=None, stream=None):
+    if dims is None:
+        dims = grid_dims(mask.shape)
+    code = _lib.cc_label_grid_ranks(
+        context(mask.device.index), _dev_ptr(mask, torch.uint8, "mask"),
+        _dims_arg(dims), int(ranks), _dev_ptr(labels, torch.int64, "labels"),
+        _stream(mask, stream))
+    _check(code, "cc_label_grid_ranks")
 
 
 def cc_label_csr_into(row_ptr, col_idx, labels, mask=None, stream=None):

@@ -72,3 +72,48 @@ def test_ranks_errors(msc):
     with pytest.raises(msc.MscError) as e:
         msc.segment_ranks(g, 3)
     assert e.value.code == msc.MSC_ENAN
+
+
+def _check_cc(msc, mask, ranks_list):
+    t = torch.from_numpy(np.ascontiguousarray(mask)).cuda()
+    want, _ = O.cc_grid(mask)
+    base = msc.cc_label_grid(t)
+    torch.cuda.synchronize()
+    np.testing.assert_array_equal(base.cpu().numpy(), want)
+    for r in ranks_list:
+        got = msc.cc_label_grid_ranks(t, r)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(got.cpu().numpy(), want,
+                                      err_msg=f"{mask.shape} ranks={r}")
+
+
+@pytest.mark.parametrize("dims,density", [
+    ((37, 29, 23), 0.3), ((37, 29, 23), 0.6), ((64, 64, 17), 0.45),
+    ((33, 1, 31), 0.5), ((1, 1, 40), 0.7), ((50, 40, 8), 1.0),
+    ((40, 30, 12), 0.0)])
+def test_cc_ranks_random_masks(msc, dims, density):
+    """Random masks near the percolation threshold of the Freudenthal grid
+    make components that cross many slab boundaries."""
+    X, Y, Z = dims
+    rng = np.random.default_rng(sum(dims))
+    mask = (rng.random((Z, Y, X)) < density).astype(np.uint8)
+    print(f"[cc ranks] dims={dims} density={density}", flush=True)
+    _check_cc(msc, mask, sorted({1, 2, 3, min(5, Z), Z}))
+
+
+@pytest.mark.parametrize("level", [0.9, 0.5, 0.1])
+def test_cc_ranks_perlin_thresholds(msc, level):
+    f = synth.perlin_field((90, 70, 60), seed=8)
+    _check_cc(msc, synth.normalized_mask(f, level), [2, 4, 7, 60])
+
+
+def test_cc_ranks_gaussian_mask(msc):
+    f = synth.gaussian_field((120, 90, 77), 25, seed=4)
+    _check_cc(msc, synth.threshold_mask(f, 0.7), [2, 3, 8, 77])
+
+
+def test_cc_ranks_errors(msc):
+    t = torch.ones((5, 4, 3), dtype=torch.uint8, device="cuda")
+    for bad in (0, 6, -1):
+        with pytest.raises(Exception):
+            msc.cc_label_grid_ranks(t, bad)
