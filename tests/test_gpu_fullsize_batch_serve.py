@@ -79,9 +79,15 @@ def test_served_full_sizes(msc):
         else:
             plain.append(msc.cc_label_grid(t).cpu().numpy())
     torch.cuda.synchronize()
+    # Inputs already in device memory: staging is then a device copy, far
+    # ahead of the worker, so requests queue up and get batched whatever
+    # the speed of the segmentation (host inputs are staged at the PCIe
+    # rate, which may let a fast worker take them one at a time; the
+    # smaller served tests cover host inputs).
+    dev_in = [torch.from_numpy(a).cuda() for _, a in reqs]
+    torch.cuda.synchronize()
     with msc.Server(hbm_budget=64 << 30, max_batch=64) as srv:
-        tickets = [srv.submit(k, torch.from_numpy(a).pin_memory())
-                   for k, a in reqs]
+        tickets = [srv.submit(k, d) for (k, _), d in zip(reqs, dev_in)]
         batches = []
         for t, (k, a), p in zip(tickets, reqs, plain):
             assert srv.wait(t) == msc.MSC_OK
