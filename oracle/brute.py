@@ -104,3 +104,30 @@ def cc_batch(M: np.ndarray, X: int, Y: int, Z: int) -> np.ndarray:
             L[:, u] = np.where(both, m, L[:, u])
             L[:, v] = np.where(both, m, L[:, v])
     return np.where(M, L, -1)
+
+
+def segment_graph(rows, F: np.ndarray):
+    """Segmentation on a general graph for a batch of fields: `rows[v]` lists
+    the neighbours of v (the closed neighbourhood adds v), F is [B, n].  The
+    successor is the candidate no other candidate beats under (f, id) --
+    found by comparing every pair of candidates, not by a running maximum."""
+    F = np.asarray(F, np.float32)
+    B, n = F.shape
+
+    def beats(b, u, w):
+        return (F[b, u] > F[b, w]) or (F[b, u] == F[b, w] and u > w)
+
+    Sp = np.empty((B, n), np.int64)
+    Sm = np.empty((B, n), np.int64)
+    for b in range(B):
+        for v in range(n):
+            cand = sorted(set([v] + [int(u) for u in rows[v]]))
+            top = [u for u in cand if not any(beats(b, w, u) for w in cand
+                                              if w != u)]
+            bot = [u for u in cand if not any(beats(b, u, w) for w in cand
+                                              if w != u)]
+            assert len(top) == 1 and len(bot) == 1
+            Sp[b, v], Sm[b, v] = top[0], bot[0]
+    A = roots_batch(Sp)
+    D = roots_batch(Sm)
+    return A, D, ms_batch(A, D)

@@ -143,6 +143,29 @@ void orc_successors(const float *f, int64_t X, int64_t Y, int64_t Z,
     }
 }
 
+/*
+ * The same successors on a general simplicial complex given by the
+ * adjacency of its vertices in CSR form (the problem statement takes any
+ * complex K; the grid is one case): the neighbourhood of v is row v,
+ * col[row_ptr[v] .. row_ptr[v+1]), closed by v itself.  For the complex's
+ * 1-skeleton the rows are symmetric; the definition does not need them to
+ * be.  Entries equal to v are harmless (v is already a candidate).
+ */
+void orc_successors_csr(const float *f, int64_t n, const int64_t *row_ptr,
+                        const int32_t *col, int32_t *sp, int32_t *sm)
+{
+    for (int64_t v = 0; v < n; ++v) {
+        int64_t hi = v, lo = v;
+        for (int64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            int64_t u = col[e];
+            if (above(f, u, hi)) hi = u;
+            if (above(f, lo, u)) lo = u;
+        }
+        sp[v] = (int32_t)hi;
+        sm[v] = (int32_t)lo;
+    }
+}
+
 /* ------------------------------------------------------------------------ */
 /* Integral lines                                                           */
 /* ------------------------------------------------------------------------ */

@@ -56,6 +56,8 @@ def lib():
         L.orc_stencil.restype = ctypes.c_int
         L.orc_successors.argtypes = [P, I64, I64, I64, P, P]
         L.orc_successors.restype = None
+        L.orc_successors_csr.argtypes = [P, I64, P, P, P, P]
+        L.orc_successors_csr.restype = None
         L.orc_walk_plain.argtypes = [P, I64, P]
         L.orc_walk_plain.restype = None
         L.orc_walk_memo.argtypes = [P, I64, P, P]
@@ -148,6 +150,31 @@ def ms_cells(asc: np.ndarray, desc: np.ndarray):
 def segment(f: np.ndarray, memo: bool | None = None):
     """Full Morse-Smale segmentation: (asc, desc, ms) int32 arrays, flat."""
     sp, sm = successors(f)
+    asc = walk(sp, memo)
+    desc = walk(sm, memo)
+    ms, _ = ms_cells(asc, desc)
+    return asc, desc, ms
+
+
+def successors_csr(row_ptr: np.ndarray, col_idx: np.ndarray, f: np.ndarray):
+    """(S+, S-) over the closed CSR neighbourhoods {v} u row(v)."""
+    row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+    col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+    f = np.ascontiguousarray(f, dtype=np.float32).reshape(-1)
+    n = row_ptr.shape[0] - 1
+    assert f.shape[0] == n
+    sp = np.empty(n, np.int32)
+    sm = np.empty(n, np.int32)
+    lib().orc_successors_csr(_p(f), n, _p(row_ptr), _p(col_idx), _p(sp),
+                             _p(sm))
+    return sp, sm
+
+
+def segment_csr(row_ptr: np.ndarray, col_idx: np.ndarray, f: np.ndarray,
+                memo: bool | None = None):
+    """Morse-Smale segmentation of a field on the vertices of a complex
+    given as CSR adjacency: (asc, desc, ms) int32 arrays."""
+    sp, sm = successors_csr(row_ptr, col_idx, f)
     asc = walk(sp, memo)
     desc = walk(sm, memo)
     ms, _ = ms_cells(asc, desc)

@@ -229,7 +229,8 @@ _KUHN_EDGES = np.array([[1, 0, 0], [0, 1, 0], [0, 0, 1], [1, 1, 0],
 
 
 def kuhn_csr(n_axis: int, seed: int, nbumps: int | None = None,
-             quantile: float = 0.7, jitter: float = 0.25):
+             quantile: float = 0.7, jitter: float = 0.25,
+             permute: bool = True):
     """Mesh input for CSR connected components.
 
     Vertices of an n^3 grid, positions jittered by U[-jitter, jitter] per axis
@@ -239,13 +240,19 @@ def kuhn_csr(n_axis: int, seed: int, nbumps: int | None = None,
     ``row_ptr`` (int64 [n+1]), ``col_idx`` (int32, symmetric, rows sorted),
     ``mask`` (uint8 [n], in permuted ids), ``perm`` (new id of grid vertex
     g) and the explicit-geometry CSR ``fg_row_ptr``/``fg_col_idx`` that
-    keeps only edges whose two endpoints are foreground.
+    keeps only edges whose two endpoints are foreground.  ``field`` holds
+    the float32 field values in grid order (vertex g at grid id g).  With
+    ``permute=False`` the ids are the grid ids (the same draws are made, so
+    the field is the same), which makes the CSR the Freudenthal grid's own
+    adjacency.
     """
     n3 = n_axis ** 3
     if nbumps is None:
         nbumps = max(1, int(round(512 * (n_axis / 1024.0) ** 3)))
     rng = np.random.default_rng(seed)
     perm = rng.permutation(n3).astype(np.int64)             # grid -> new id
+    if not permute:
+        perm = np.arange(n3, dtype=np.int64)
     # Field at jittered positions (per-axis jitter, then the bump sum).
     _, c, a, s = gaussian_params((n_axis,) * 3, nbumps, seed)
     g = np.arange(n3, dtype=np.int64)
