@@ -235,6 +235,67 @@ def bench_cc(args, msc, synth, torch, dev):
     print(json.dumps(out), flush=True)
 
 
+SEGCSR_TEXT = {
+    "segcsr50m": "segcsr50m: MS segmentation of the csr50m mesh (368^3 = "
+                 "49.8M vertices of a jittered Kuhn tetrahedralisation, "
+                 "symmetric CSR, randomly permuted ids, seed 2) with the "
+                 "Gaussian-sum field at its jittered positions; int32 asc, "
+                 "desc, ms",
+}
+
+
+def bench_segcsr(args, msc, synth, torch, dev):
+    """Segmentation over CSR adjacency: the 50M-vertex mesh, one call per
+    step, inputs resident on the device."""
+    stream = torch.cuda.current_stream(dev)
+    log("[bench] generating the 368^3 Kuhn CSR mesh on the host")
+    t0 = time.perf_counter()
+    d = synth.kuhn_csr(368, seed=2)
+    log(f"[bench] mesh ready in {time.perf_counter() - t0:.1f} s")
+    import numpy as np
+    f = np.empty_like(d["field"])
+    f[d["perm"]] = d["field"]
+    rp = torch.from_numpy(d["row_ptr"]).to(dev)
+    ci = torch.from_numpy(d["col_idx"]).to(dev)
+    fd = torch.from_numpy(f).to(dev)
+    nnz = int(d["row_ptr"][-1])
+    del d, f
+    n = rp.numel() - 1
+    asc = torch.empty(n, dtype=torch.int32, device=dev)
+    desc = torch.empty_like(asc)
+    ms = torch.empty_like(asc)
+    run = lambda: msc.segment_csr_into(rp, ci, fd, asc, desc, ms,
+                                       stream=stream)
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    stats = msc.last_stats()
+    msc.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    msc.profile(False)
+    prof = msc.profile_read()
+    log(f"[bench] {args.steps} steps: {dt * 1e3:.2f} ms/step")
+    log_prof(prof)
+    out = {
+        "metric": "Gvertices/s MS segmentation over CSR adjacency "
+                  "(" + args.workload + ")",
+        "value": round(n / dt / 1e9, 3), "unit": "Gvertices/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": SEGCSR_TEXT[args.workload], "vertices": n,
+                   "edges": nnz, "maxima": stats["n_maxima"],
+                   "minima": stats["n_minima"], "cells": stats["n_cells"]},
+        "roofline": roofline_of(prof, args.workload),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def bench_batch(args, msc, synth, torch, dev):
     """256 uneven fields: one batched call per step vs. 256 plain calls."""
     specs = synth.batch_specs(256, seed=3)
@@ -450,7 +511,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="gauss1024",
                     choices=sorted(WORKLOAD_TEXT) + ["batch256", "serve"]
-                    + sorted(CC_TEXT))
+                    + sorted(CC_TEXT) + sorted(SEGCSR_TEXT))
     ap.add_argument("--cpu-depth", type=int, default=100,
                     help="z-planes of the field the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -503,6 +564,8 @@ def main():
         return bench_serve(args, msc, synth, torch, dev)
     if args.workload in CC_TEXT:
         return bench_cc(args, msc, synth, torch, dev)
+    if args.workload in SEGCSR_TEXT:
+        return bench_segcsr(args, msc, synth, torch, dev)
 
     log(f"[bench] generating {args.workload} on {dev}")
     t0 = time.perf_counter()

@@ -108,6 +108,35 @@ MSC_API int msc_segment(msc_ctx *ctx, const float *field, const int64_t dims[3],
  * it; MSC_EINVAL also for ranks < 1 or ranks > Z.  msc_last_stats reports
  * the final extremum and cell counts.
  */
+/*
+ * msc_segment on a general simplicial complex given by the adjacency of its
+ * vertices (the problem statement's K; a grid is one case): steepest
+ * ascent / descent over the closed neighbourhood {v} u row(v) in the
+ * (value, id) order, path compression onto the extrema, cells as for the
+ * grid.
+ *
+ *  n        number of vertices (0 is a no-op, whatever the pointers; at
+ *           most INT32_MAX).
+ *  row_ptr  device, int64[n+1], row_ptr[0] = 0, non-decreasing.
+ *  col_idx  device, int32[row_ptr[n]] (may be NULL when row_ptr[n] is 0;
+ *           rows are only read inside [0, row_ptr[n])): the neighbours of v are
+ *           col_idx[row_ptr[v] .. row_ptr[v+1]).  For the paper's
+ *           semantics the rows are the symmetric 1-skeleton adjacency; the
+ *           call uses each row as given (an edge listed in one row only is
+ *           seen from that vertex only).  Entries equal to v are harmless.
+ *  field    device, float32[n], values in vertex-id order.
+ *  asc, desc, ms  as msc_segment (device int32[n], any may be NULL, not
+ *           all); asc and desc are computed in place of the caller's
+ *           buffers when given, in library scratch otherwise.
+ *  Errors: MSC_EINVAL (NULL arguments, n < 0, a column index outside
+ *          [0, n): outputs undefined), MSC_ERANGE, MSC_ENAN, MSC_ENOMEM,
+ *          MSC_EHIP.  msc_last_stats reports extremum and cell counts.
+ */
+MSC_API int msc_segment_csr(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,
+                            const int32_t *col_idx, const float *field,
+                            int32_t *asc, int32_t *desc, int32_t *ms,
+                            void *stream);
+
 MSC_API int msc_segment_ranks(msc_ctx *ctx, const float *field,
                               const int64_t dims[3], int ranks, int32_t *asc,
                               int32_t *desc, int32_t *ms, void *stream);

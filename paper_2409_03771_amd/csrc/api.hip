@@ -163,6 +163,19 @@ int msc_segment_ranks(msc_ctx *ctx, const float *field, const int64_t dims[3],
                                 static_cast<hipStream_t>(stream));
 }
 
+int msc_segment_csr(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,
+                    const int32_t *col_idx, const float *field, int32_t *asc,
+                    int32_t *desc, int32_t *ms, void *stream) {
+  if (!ctx || n < 0) return MSC_EINVAL;
+  if (n > INT32_MAX) return MSC_ERANGE;
+  if (n > 0 && (!row_ptr || !field || (!asc && !desc && !ms)))
+    return MSC_EINVAL;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return MSC_EHIP;
+  return msc::segment_csr_run(ctx, n, row_ptr, col_idx, field, asc, desc, ms,
+                              static_cast<hipStream_t>(stream));
+}
+
 int msc_segment_batched(msc_ctx *ctx, int nfields, const msc_field *fields,
                         void *stream) {
   if (!ctx || nfields < 0 || (nfields > 0 && !fields)) return MSC_EINVAL;

@@ -36,6 +36,7 @@ enum Counter : int {
   kCtrSteps = 10,    // exit-graph links followed in total
   kCtrRootsMax = 11, // vertices that are their own ascent label
   kCtrRootsMin = 12, // vertices that are their own descent label
+  kCtrNaN = 13,      // a NaN field value seen (CSR segmentation)
   kNumCounters = 16
 };
 
@@ -185,6 +186,9 @@ int segment_batch_run(msc_ctx *ctx, int nfields, const msc_field *fields,
 int segment_ranks_run(msc_ctx *ctx, const float *field, const int64_t dims[3],
                       int ranks, int32_t *asc, int32_t *desc, int32_t *ms,
                       hipStream_t s);
+int segment_csr_run(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,
+                    const int32_t *col_idx, const float *field, int32_t *asc,
+                    int32_t *desc, int32_t *ms, hipStream_t stream);
 // `sync` false skips the closing counter read (the caller synchronises).
 int cc_grid_run(msc_ctx *ctx, const uint8_t *mask, int64_t X, int64_t Y,
                 int64_t Z, int64_t *labels, hipStream_t s, bool sync = true);

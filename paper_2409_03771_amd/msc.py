@@ -75,6 +75,7 @@ _SIGS = {
     "msc_profile_read": ([_P, ctypes.POINTER(msc_phase), _I32,
                           ctypes.POINTER(_I32)], _I32),
     "cc_label_grid": ([_P, _P, ctypes.POINTER(_I64), _P, _P], _I32),
+    "msc_segment_csr": ([_P, _I64, _P, _P, _P, _P, _P, _P, _P], _I32),
     "cc_label_grid_ranks": ([_P, _P, ctypes.POINTER(_I64), _I32, _P, _P],
                             _I32),
     "cc_label_csr": ([_P, _I64, _P, _P, _P, _P, _P], _I32),
@@ -195,6 +196,32 @@ def segment_ranks_into(field, ranks, asc, desc, ms, stream=None):
         _dev_ptr(asc, torch.int32, "asc"), _dev_ptr(desc, torch.int32, "desc"),
         _dev_ptr(ms, torch.int32, "ms"), _stream(field, stream))
     _check(code, "msc_segment_ranks")
+
+
+def segment_csr(row_ptr: torch.Tensor, col_idx: torch.Tensor,
+                field: torch.Tensor, want=("asc", "desc", "ms"), stream=None):
+    """Segmentation of a field on the vertices of a complex given as CSR
+    adjacency (int64 row_ptr [n+1], int32 col_idx, float32 field [n])."""
+    n = row_ptr.numel() - 1
+    out = {k: (torch.empty(n, dtype=torch.int32, device=field.device)
+               if k in want else None) for k in ("asc", "desc", "ms")}
+    segment_csr_into(row_ptr, col_idx, field, out["asc"], out["desc"],
+                     out["ms"], stream)
+    return out["asc"], out["desc"], out["ms"]
+
+
+def segment_csr_into(row_ptr, col_idx, field, asc, desc, ms, stream=None):
+    n = row_ptr.numel() - 1
+    if field.numel() != n:
+        raise ValueError(f"field has {field.numel()} values for {n} vertices")
+    code = _lib.msc_segment_csr(
+        context(field.device.index), int(n),
+        _dev_ptr(row_ptr, torch.int64, "row_ptr"),
+        _dev_ptr(col_idx, torch.int32, "col_idx"),
+        _dev_ptr(field, torch.float32, "field"),
+        _dev_ptr(asc, torch.int32, "asc"), _dev_ptr(desc, torch.int32, "desc"),
+        _dev_ptr(ms, torch.int32, "ms"), _stream(field, stream))
+    _check(code, "msc_segment_csr")
 
 
 def _field_array(fields, outs, dims_list):

@@ -99,12 +99,17 @@ def test_fullsize_cc_grid(full):
     np.testing.assert_array_equal(got, want)
 
 
-def test_fullsize_cc_csr():
+@pytest.fixture(scope="module")
+def kuhn50m():
+    print("[fullsize] generating the 368^3 Kuhn CSR mesh", flush=True)
+    return synth.kuhn_csr(368, seed=2)
+
+
+def test_fullsize_cc_csr(kuhn50m):
     """The 49.8M-vertex permuted Kuhn mesh: masked CSR and the explicit
     foreground graph, every label."""
     from paper_2409_03771_amd import msc
-    print("[fullsize] generating the 368^3 Kuhn CSR mesh", flush=True)
-    d = synth.kuhn_csr(368, seed=2)
+    d = kuhn50m
     cases = [("masked", d["row_ptr"], d["col_idx"], d["mask"]),
              ("explicit", d["fg_row_ptr"], d["fg_col_idx"], None)]
     for name, rp, ci, mask in cases:
@@ -117,3 +122,26 @@ def test_fullsize_cc_csr():
         del lab
         want, _ = O.cc_csr(rp, ci, mask)
         np.testing.assert_array_equal(got, want, err_msg=name)
+
+
+def test_fullsize_segment_csr(kuhn50m):
+    """Segmentation of the mesh's field (values at the jittered positions,
+    in permuted ids) over its CSR adjacency: asc, desc and ms of every vertex
+    equal the oracle's."""
+    from paper_2409_03771_amd import msc
+    d = kuhn50m
+    f = np.empty_like(d["field"])
+    f[d["perm"]] = d["field"]
+    print("[fullsize] csr segmentation on the device", flush=True)
+    got = msc.segment_csr(torch.from_numpy(d["row_ptr"]).cuda(),
+                          torch.from_numpy(d["col_idx"]).cuda(),
+                          torch.from_numpy(f).cuda())
+    torch.cuda.synchronize()
+    got = [x.cpu().numpy() for x in got]
+    st = msc.last_stats()
+    print("[fullsize] csr segmentation on the oracle", flush=True)
+    want = O.segment_csr(d["row_ptr"], d["col_idx"], f)
+    for name, g, w in zip(("asc", "desc", "ms"), got, want):
+        np.testing.assert_array_equal(g, w, err_msg=name)
+    assert st["n_maxima"] == len(np.unique(want[0]))
+    assert st["n_cells"] == len(np.unique(want[2]))
