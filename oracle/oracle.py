@@ -181,6 +181,24 @@ def segment_csr(row_ptr: np.ndarray, col_idx: np.ndarray, f: np.ndarray,
     return asc, desc, ms
 
 
+def csr_from_tets(n: int, tets: np.ndarray):
+    """(row_ptr int64 [n+1], col_idx int32) of the 1-skeleton of a
+    tetrahedral complex: u is a neighbour of v when some tetrahedron holds
+    both and u != v; rows sorted, no duplicates, symmetric.  Written as its
+    definition: every tetrahedron's six vertex pairs in both directions,
+    self pairs dropped, duplicates merged by np.unique."""
+    t = np.asarray(tets, np.int64).reshape(-1, 4)
+    pairs = [(i, j) for i in range(4) for j in range(4) if i != j]
+    a = np.concatenate([t[:, i] for i, _ in pairs])
+    b = np.concatenate([t[:, j] for _, j in pairs])
+    keep = a != b
+    keys = np.unique(a[keep] * np.int64(n) + b[keep])
+    src, dst = keys // n, keys % n
+    row_ptr = np.zeros(n + 1, np.int64)
+    np.cumsum(np.bincount(src, minlength=n), out=row_ptr[1:])
+    return row_ptr, dst.astype(np.int32)
+
+
 def sync_doubling(d: np.ndarray, rounds: int) -> np.ndarray:
     d = np.array(d, dtype=np.int64, copy=True)
     tmp = np.empty_like(d)

@@ -310,6 +310,42 @@ def kuhn_csr(n_axis: int, seed: int, nbumps: int | None = None,
                 fg_col_idx=np.ascontiguousarray(fg_col_idx), field=f32)
 
 
+def kuhn_tets(n_axis: int, perm: np.ndarray | None = None,
+              z_chunk: int = 16) -> np.ndarray:
+    """Tetrahedra of the Kuhn subdivision of an n^3 grid of vertices: each
+    cube with lower corner p splits into the six tetrahedra
+    {p, p+e_a, p+e_a+e_b, p+e_a+e_b+e_c}, (a, b, c) a permutation of the
+    axes.  int32 [6 (n-1)^3, 4] vertex ids (grid ids x + n y + n^2 z, or
+    perm[grid id] when a permutation is given), cubes in id order."""
+    import itertools
+    m = n_axis - 1
+    if m <= 0:
+        return np.zeros((0, 4), np.int32)
+    unit = np.eye(3, dtype=np.int64)
+    corners = []
+    for a, b, c in itertools.permutations(range(3)):
+        o = np.zeros(3, np.int64)
+        path = [o.copy()]
+        for ax in (a, b, c):
+            o = o + unit[ax]
+            path.append(o.copy())
+        corners.append(path)
+    corners = np.array(corners)                      # [6, 4, 3]
+    off = corners[..., 0] + n_axis * corners[..., 1] + \
+        n_axis * n_axis * corners[..., 2]            # [6, 4]
+    out = []
+    for z0 in range(0, m, z_chunk):
+        z = np.arange(z0, min(m, z0 + z_chunk))
+        y = np.arange(m)
+        x = np.arange(m)
+        base = (x[None, None, :] + n_axis * y[None, :, None] +
+                n_axis * n_axis * z[:, None, None]).reshape(-1)
+        t = base[:, None, None] + off[None, :, :]    # [cubes, 6, 4]
+        t = t.reshape(-1, 4)
+        out.append(t if perm is None else perm[t])
+    return np.ascontiguousarray(np.concatenate(out).astype(np.int32))
+
+
 def poisson_trace(rate: float, count: int, seed: int = 4, lo: int = 64,
                   hi: int = 512, ms_frac: float = 0.7):
     """Open-loop request trace: arrival times (s), kind ('ms' or 'cc'),
