@@ -296,6 +296,56 @@ def bench_segcsr(args, msc, synth, torch, dev):
     print(json.dumps(out), flush=True)
 
 
+def bench_tets(args, msc, synth, torch, dev):
+    """CSR adjacency of the 368^3 Kuhn mesh from its 296M tetrahedra (ids
+    randomly permuted, seed 2), one build per step into resident buffers."""
+    stream = torch.cuda.current_stream(dev)
+    import numpy as np
+    na = 368
+    perm = np.random.default_rng(2).permutation(na ** 3).astype(np.int64)
+    log("[bench] generating the tetrahedra")
+    tets = torch.from_numpy(synth.kuhn_tets(na, perm=perm)).to(dev)
+    del perm
+    n = na ** 3
+    rp = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    nnz = msc.csr_from_tets_into(n, tets, rp, None, stream=stream)
+    col = torch.empty(nnz, dtype=torch.int32, device=dev)
+    run = lambda: msc.csr_from_tets_into(n, tets, rp, col, stream=stream)
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    msc.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    msc.profile(False)
+    prof = msc.profile_read()
+    log(f"[bench] {args.steps} steps: {dt * 1e3:.2f} ms/step")
+    log_prof(prof)
+    ntets = tets.numel() // 4
+    out = {
+        "metric": "Gtetrahedra/s CSR adjacency from a tetrahedra list",
+        "value": round(ntets / dt / 1e9, 3), "unit": "Gtetrahedra/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": TETS_TEXT[args.workload], "vertices": n,
+                   "tetrahedra": ntets, "entries": nnz},
+        "roofline": roofline_of(prof, args.workload),
+    }
+    print(json.dumps(out), flush=True)
+
+
+TETS_TEXT = {
+    "tets368": "tets368: the 6*367^3 = 296M Kuhn tetrahedra of a 368^3 grid "
+               "with randomly permuted vertex ids (seed 2) to symmetric CSR "
+               "(int64 row_ptr, int32 col_idx)",
+}
+
+
 def bench_batch(args, msc, synth, torch, dev):
     """256 uneven fields: one batched call per step vs. 256 plain calls."""
     specs = synth.batch_specs(256, seed=3)
@@ -511,7 +561,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="gauss1024",
                     choices=sorted(WORKLOAD_TEXT) + ["batch256", "serve"]
-                    + sorted(CC_TEXT) + sorted(SEGCSR_TEXT))
+                    + sorted(CC_TEXT) + sorted(SEGCSR_TEXT)
+                    + sorted(TETS_TEXT))
     ap.add_argument("--cpu-depth", type=int, default=100,
                     help="z-planes of the field the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -566,6 +617,8 @@ def main():
         return bench_cc(args, msc, synth, torch, dev)
     if args.workload in SEGCSR_TEXT:
         return bench_segcsr(args, msc, synth, torch, dev)
+    if args.workload in TETS_TEXT:
+        return bench_tets(args, msc, synth, torch, dev)
 
     log(f"[bench] generating {args.workload} on {dev}")
     t0 = time.perf_counter()

@@ -272,6 +272,30 @@ MSC_API int cc_label_grid(msc_ctx *ctx, const uint8_t *mask, const int64_t dims[
  * Outputs, layout and errors as cc_label_grid, and bit-identical to it;
  * MSC_EINVAL also for ranks < 1 or ranks > Z.
  */
+/*
+ * CSR adjacency of the 1-skeleton of a tetrahedral complex given by its
+ * tetrahedra (the mesh of the explicit pipeline, where extracted geometry
+ * is triangulated before its components are labelled, and the input of
+ * msc_segment_csr and cc_label_csr): u is a neighbour of v when some
+ * tetrahedron holds both and u != v.
+ *
+ *  n         number of vertices (0 gives row_ptr = {0}).
+ *  ntets     number of tetrahedra (workspace: 48 bytes each).
+ *  tets      device, int32[ntets][4] vertex ids (repeats allowed).
+ *  row_ptr   device, int64[n+1], always written.
+ *  col_idx   device, int32[capacity], or NULL: written (rows in increasing
+ *            order, no duplicates, symmetric) only when capacity >= the
+ *            entry count; otherwise call again with a larger buffer.
+ *  nnz       host, receives the entry count row_ptr[n].
+ *  Synchronises the stream (the entry count is read back).  Errors:
+ *  MSC_EINVAL (NULL arguments, negative sizes, a vertex id outside
+ *  [0, n): outputs undefined), MSC_ERANGE, MSC_ENOMEM, MSC_EHIP.
+ */
+MSC_API int msc_csr_from_tets(msc_ctx *ctx, int64_t n, int64_t ntets,
+                              const int32_t *tets, int64_t *row_ptr,
+                              int32_t *col_idx, int64_t capacity,
+                              int64_t *nnz, void *stream);
+
 MSC_API int cc_label_grid_ranks(msc_ctx *ctx, const uint8_t *mask,
                                 const int64_t dims[3], int ranks,
                                 int64_t *labels, void *stream);

@@ -325,6 +325,19 @@ int cc_label_grid_ranks(msc_ctx *ctx, const uint8_t *mask,
                                 labels, static_cast<hipStream_t>(stream));
 }
 
+int msc_csr_from_tets(msc_ctx *ctx, int64_t n, int64_t ntets,
+                      const int32_t *tets, int64_t *row_ptr, int32_t *col_idx,
+                      int64_t capacity, int64_t *nnz, void *stream) {
+  if (!ctx || n < 0 || ntets < 0 || !row_ptr || !nnz) return MSC_EINVAL;
+  if (n > INT32_MAX || ntets > (INT64_MAX >> 6)) return MSC_ERANGE;
+  if (ntets > 0 && !tets) return MSC_EINVAL;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return MSC_EHIP;
+  return msc::csr_from_tets_run(ctx, n, ntets, tets, row_ptr, col_idx,
+                                capacity, nnz,
+                                static_cast<hipStream_t>(stream));
+}
+
 int cc_label_csr(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,
                  const int32_t *col_idx, const uint8_t *mask, int64_t *labels,
                  void *stream) {

@@ -698,4 +698,260 @@ int cc_grid_ranks_run(msc_ctx *ctx, const uint8_t *mask, int64_t X,
   return MSC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// CSR adjacency of a tetrahedral complex (the mesh of the explicit pipeline
+// and of msc_segment_csr): every tetrahedron's vertices are neighbours of
+// one another.  Per vertex: candidates gathered from its tetrahedra, then
+// the distinct ones written in increasing order.  No global sort: vertex
+// degrees are small, so each row is deduplicated and ranked by comparing
+// its candidates with one another.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+constexpr int kScan = 1024;
+
+// Exclusive prefix of x over the block (1024 threads) and the block total.
+__device__ __forceinline__ uint64_t block_scan64(uint64_t x, uint64_t *tmp,
+                                                 uint64_t *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint64_t inc = x;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint64_t y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) tmp[w] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint64_t run = 0;
+    for (int k = 0; k < kScan / 64; ++k) {
+      const uint64_t t = tmp[k];
+      tmp[k] = run;
+      run += t;
+    }
+    tmp[kScan / 64] = run;
+  }
+  __syncthreads();
+  const uint64_t ex = inc - x + tmp[w];
+  *total = tmp[kScan / 64];
+  __syncthreads();
+  return ex;
+}
+
+__global__ void __launch_bounds__(kScan)
+k_scan64_blocks(const uint32_t *__restrict__ cnt, int64_t n, int64_t *out,
+                uint64_t *bsum) {
+  __shared__ uint64_t tmp[kScan / 64 + 1];
+  const int64_t i = (int64_t)blockIdx.x * kScan + threadIdx.x;
+  uint64_t tot = 0;
+  const uint64_t ex = block_scan64(i < n ? cnt[i] : 0u, tmp, &tot);
+  if (i < n) out[i] = (int64_t)ex;
+  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+}
+
+// Block totals to block offsets in place (one block); the grand total goes
+// to out[n].
+__global__ void __launch_bounds__(kScan)
+k_scan64_sums(uint64_t *bsum, int64_t nb, int64_t *out, int64_t n) {
+  __shared__ uint64_t tmp[kScan / 64 + 1];
+  uint64_t carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += kScan) {
+    const int64_t i = b0 + threadIdx.x;
+    uint64_t tot = 0;
+    const uint64_t ex = block_scan64(i < nb ? bsum[i] : 0u, tmp, &tot);
+    if (i < nb) bsum[i] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) out[n] = (int64_t)carry;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_scan64_add(int64_t *out, int64_t n, const uint64_t *__restrict__ bsum) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) out[i] += (int64_t)bsum[i / kScan];
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_zero32(uint32_t *p, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+// Every valid tetrahedron adds three candidates to each of its vertices; one
+// with a vertex outside [0, n) is skipped and reported.
+__global__ void __launch_bounds__(kBlock)
+k_tet_count(int64_t ntets, const int32_t *__restrict__ tets, int64_t n,
+            uint32_t *cnt, unsigned long long *ctr) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  bool bad = false;
+  if (t < ntets) {
+    int32_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = tets[4 * t + k];
+      bad |= v[k] < 0 || (int64_t)v[k] >= n;
+    }
+    if (!bad)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) atomicAdd(&cnt[v[k]], 3u);
+  }
+  flag_any(bad, ctr + kCtrBadIndex);
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_tet_scatter(int64_t ntets, const int32_t *__restrict__ tets, int64_t n,
+              const int64_t *__restrict__ off, uint32_t *cursor,
+              int32_t *__restrict__ cand) {
+  const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (t >= ntets) return;
+  int32_t v[4];
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    v[k] = tets[4 * t + k];
+    bad |= v[k] < 0 || (int64_t)v[k] >= n;
+  }
+  if (bad) return;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t at = off[v[k]] + atomicAdd(&cursor[v[k]], 3u);
+    int j = 0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+      if (m != k) cand[at + j++] = v[m];
+  }
+}
+
+// A row's candidates are examined eight at a time.  The first pass moves
+// the first occurrence of every neighbour (not the vertex itself) to the
+// front of the row as it goes: a candidate is new when it matches neither
+// that compacted prefix nor an earlier candidate of its batch, and the
+// prefix never reaches past the batch being examined, so every candidate is
+// read before it can be overwritten.  The second pass writes each of the
+// prefix's values at its rank within the prefix.
+constexpr int kRowBatch = 8;
+
+__global__ void __launch_bounds__(kBlock)
+k_row_distinct(int64_t n, const int64_t *__restrict__ off, int32_t *cand,
+               uint32_t *ucnt) {
+  const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (v >= n) return;
+  int32_t *seg = cand + off[v];
+  const int64_t k = off[v + 1] - off[v];
+  uint32_t count = 0;
+  for (int64_t i0 = 0; i0 < k; i0 += kRowBatch) {
+    int32_t c[kRowBatch];
+    bool dup[kRowBatch];
+#pragma unroll
+    for (int t = 0; t < kRowBatch; ++t) {
+      c[t] = i0 + t < k ? seg[i0 + t] : 0;
+      dup[t] = i0 + t >= k || c[t] == (int32_t)v;
+    }
+    for (uint32_t j = 0; j < count; ++j) {
+      const int32_t d = seg[j];
+#pragma unroll
+      for (int t = 0; t < kRowBatch; ++t) dup[t] |= d == c[t];
+    }
+#pragma unroll
+    for (int t = 1; t < kRowBatch; ++t)
+#pragma unroll
+      for (int q = 0; q < t; ++q) dup[t] |= c[q] == c[t];
+#pragma unroll
+    for (int t = 0; t < kRowBatch; ++t)
+      if (!dup[t]) seg[count++] = c[t];
+  }
+  ucnt[v] = count;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_row_fill(int64_t n, const int64_t *__restrict__ off,
+           const int32_t *__restrict__ cand,
+           const int64_t *__restrict__ row_ptr, int32_t *__restrict__ col) {
+  const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (v >= n) return;
+  const int32_t *seg = cand + off[v];
+  const int64_t base = row_ptr[v], u = row_ptr[v + 1] - base;
+  for (int64_t i0 = 0; i0 < u; i0 += kRowBatch) {
+    int32_t c[kRowBatch];
+    uint32_t rank[kRowBatch];
+#pragma unroll
+    for (int t = 0; t < kRowBatch; ++t) {
+      c[t] = i0 + t < u ? seg[i0 + t] : 0;
+      rank[t] = 0;
+    }
+    for (int64_t j = 0; j < u; ++j) {
+      const int32_t d = seg[j];
+#pragma unroll
+      for (int t = 0; t < kRowBatch; ++t) rank[t] += d < c[t];
+    }
+#pragma unroll
+    for (int t = 0; t < kRowBatch; ++t)
+      if (i0 + t < u) col[base + rank[t]] = c[t];
+  }
+}
+
+unsigned grid64(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+int scan64(msc_ctx *ctx, const uint32_t *cnt, int64_t n, int64_t *out,
+           uint64_t *bsum, hipStream_t s) {
+  const int64_t nb = (n + kScan - 1) / kScan;
+  if (n > 0)
+    k_scan64_blocks<<<grid64(n, kScan), kScan, 0, s>>>(cnt, n, out, bsum);
+  k_scan64_sums<<<1, kScan, 0, s>>>(bsum, nb, out, n);  // out[n]: the total
+  if (n > 0) k_scan64_add<<<grid64(n, kBlock), kBlock, 0, s>>>(out, n, bsum);
+  (void)ctx;
+  return MSC_OK;
+}
+
+}  // namespace
+
+int csr_from_tets_run(msc_ctx *ctx, int64_t n, int64_t ntets,
+                      const int32_t *tets, int64_t *row_ptr, int32_t *col_idx,
+                      int64_t capacity, int64_t *nnz, hipStream_t s) {
+  const int64_t nb = (n + kScan - 1) / kScan;
+  const int64_t ncand = 12 * ntets;
+  MSC_TRY(reserve(ctx->ws, align256(n * 4) + align256((n + 1) * 8) +
+                               align256(nb * 8 + 8) + align256(ncand * 4) +
+                               4096));
+  Carver cv(ctx->ws);
+  uint32_t *cnt = cv.take<uint32_t>(n);
+  int64_t *off = cv.take<int64_t>(n + 1);
+  uint64_t *bsum = cv.take<uint64_t>(nb + 1);
+  int32_t *cand = cv.take<int32_t>(ncand);
+  MSC_TRY(clear_counters(ctx, s));
+  if (n > 0) k_zero32<<<grid64(n, kBlock), kBlock, 0, s>>>(cnt, n);
+  if (ntets > 0)
+    MSC_PHASE(ctx, s, "tets_count", 16.0 * ntets,
+              (k_tet_count<<<grid64(ntets, kBlock), kBlock, 0, s>>>(
+                  ntets, tets, n, cnt, ctx->dctr)));
+  MSC_PHASE(ctx, s, "tets_scan", 12.0 * n, (scan64(ctx, cnt, n, off, bsum, s)));
+  if (n > 0) k_zero32<<<grid64(n, kBlock), kBlock, 0, s>>>(cnt, n);
+  if (ntets > 0)
+    MSC_PHASE(ctx, s, "tets_scatter", 16.0 * ntets + 4.0 * ncand,
+              (k_tet_scatter<<<grid64(ntets, kBlock), kBlock, 0, s>>>(
+                  ntets, tets, n, off, cnt, cand)));
+  if (n > 0)
+    MSC_PHASE(ctx, s, "rows_distinct", 4.0 * ncand + 12.0 * n,
+              (k_row_distinct<<<grid64(n, kBlock), kBlock, 0, s>>>(n, off,
+                                                                   cand,
+                                                                   cnt)));
+  MSC_PHASE(ctx, s, "rows_scan", 12.0 * n,
+            (scan64(ctx, cnt, n, row_ptr, bsum, s)));
+  int64_t total = 0;
+  MSC_HIP_TRY(hipMemcpyAsync(&total, row_ptr + n, sizeof(int64_t),
+                             hipMemcpyDeviceToHost, s));
+  MSC_TRY(read_counters(ctx, s));
+  if (ctx->hctr[kCtrBadIndex]) return MSC_EINVAL;
+  *nnz = total;
+  if (col_idx && capacity >= total && total > 0)
+    MSC_PHASE(ctx, s, "rows_fill", 4.0 * ncand + 4.0 * total,
+              (k_row_fill<<<grid64(n, kBlock), kBlock, 0, s>>>(n, off, cand,
+                                                               row_ptr,
+                                                               col_idx)));
+  MSC_TRY(read_counters(ctx, s));
+  ctx->stats = msc_stats{};
+  ctx->stats.n_vertices = n;
+  return MSC_OK;
+}
+
 }  // namespace msc

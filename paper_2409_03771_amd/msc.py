@@ -76,6 +76,8 @@ _SIGS = {
                           ctypes.POINTER(_I32)], _I32),
     "cc_label_grid": ([_P, _P, ctypes.POINTER(_I64), _P, _P], _I32),
     "msc_segment_csr": ([_P, _I64, _P, _P, _P, _P, _P, _P, _P], _I32),
+    "msc_csr_from_tets": ([_P, _I64, _I64, _P, _P, _P, _I64,
+                           ctypes.POINTER(_I64), _P], _I32),
     "cc_label_grid_ranks": ([_P, _P, ctypes.POINTER(_I64), _I32, _P, _P],
                             _I32),
     "cc_label_csr": ([_P, _I64, _P, _P, _P, _P, _P], _I32),
@@ -196,6 +198,39 @@ def segment_ranks_into(field, ranks, asc, desc, ms, stream=None):
         _dev_ptr(asc, torch.int32, "asc"), _dev_ptr(desc, torch.int32, "desc"),
         _dev_ptr(ms, torch.int32, "ms"), _stream(field, stream))
     _check(code, "msc_segment_ranks")
+
+
+def csr_from_tets(n: int, tets: torch.Tensor, stream=None):
+    """(row_ptr int64 [n+1], col_idx int32) of the 1-skeleton of the
+    tetrahedra `tets` (int32 [T, 4] on the device): one call for the entry
+    count, one to fill the rows."""
+    dev = tets.device
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=dev)
+    nnz = _I64(0)
+    args = (context(dev.index), int(n), int(tets.numel() // 4),
+            _dev_ptr(tets, torch.int32, "tets"),
+            _dev_ptr(row_ptr, torch.int64, "row_ptr"))
+    _check(_lib.msc_csr_from_tets(*args, None, 0, ctypes.byref(nnz),
+                                  _stream(tets, stream)), "msc_csr_from_tets")
+    col = torch.empty(max(nnz.value, 1), dtype=torch.int32, device=dev)
+    _check(_lib.msc_csr_from_tets(*args, _dev_ptr(col, torch.int32, "col"),
+                                  nnz.value, ctypes.byref(nnz),
+                                  _stream(tets, stream)), "msc_csr_from_tets")
+    return row_ptr, col[:nnz.value]
+
+
+def csr_from_tets_into(n, tets, row_ptr, col_idx, stream=None) -> int:
+    """One call into caller buffers (col_idx may be None or too small:
+    then only row_ptr is written); returns the entry count."""
+    nnz = _I64(0)
+    cap = 0 if col_idx is None else col_idx.numel()
+    _check(_lib.msc_csr_from_tets(
+        context(tets.device.index), int(n), int(tets.numel() // 4),
+        _dev_ptr(tets, torch.int32, "tets"),
+        _dev_ptr(row_ptr, torch.int64, "row_ptr"),
+        _dev_ptr(col_idx, torch.int32, "col_idx"), int(cap),
+        ctypes.byref(nnz), _stream(tets, stream)), "msc_csr_from_tets")
+    return nnz.value
 
 
 def segment_csr(row_ptr: torch.Tensor, col_idx: torch.Tensor,

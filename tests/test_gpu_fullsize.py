@@ -145,3 +145,21 @@ def test_fullsize_segment_csr(kuhn50m):
         np.testing.assert_array_equal(g, w, err_msg=name)
     assert st["n_maxima"] == len(np.unique(want[0]))
     assert st["n_cells"] == len(np.unique(want[2]))
+
+
+def test_fullsize_csr_from_tets(kuhn50m):
+    """The 368^3 mesh's 296M Kuhn tetrahedra (permuted ids) give, on the
+    device, exactly the adjacency the input module builds from edge
+    vectors."""
+    from paper_2409_03771_amd import msc
+    d = kuhn50m
+    print("[fullsize] generating the 296M tetrahedra", flush=True)
+    tets = synth.kuhn_tets(368, perm=d["perm"])
+    t = torch.from_numpy(tets).cuda()
+    del tets
+    print("[fullsize] building the adjacency on the device", flush=True)
+    rp, ci = msc.csr_from_tets(368 ** 3, t)
+    torch.cuda.synchronize()
+    del t
+    np.testing.assert_array_equal(rp.cpu().numpy(), d["row_ptr"])
+    np.testing.assert_array_equal(ci.cpu().numpy(), d["col_idx"])
