@@ -131,3 +131,40 @@ def segment_graph(rows, F: np.ndarray):
     A = roots_batch(Sp)
     D = roots_batch(Sm)
     return A, D, ms_batch(A, D)
+
+
+def link_components(f: np.ndarray, X: int, Y: int, Z: int):
+    """(lc, uc) per vertex from the lattice characterisation alone: the link
+    of v is the graph on v's neighbours in which two are joined when they
+    are neighbours of each other (the Freudenthal triangulation is a flag
+    complex, so such a pair and v span a triangle)."""
+    f = np.asarray(f, np.float32).reshape(-1)
+    n = X * Y * Z
+    nb = [set() for _ in range(n)]
+    for u, v in edges(X, Y, Z):
+        nb[u].add(v)
+        nb[v].add(u)
+
+    def below(a, b):
+        return f[a] < f[b] or (f[a] == f[b] and a < b)
+
+    def count(v, side):
+        verts = [u for u in nb[v] if (below(v, u) if side > 0 else below(u, v))]
+        seen, comps = set(), 0
+        for s in verts:
+            if s in seen:
+                continue
+            comps += 1
+            stack = [s]
+            seen.add(s)
+            while stack:
+                a = stack.pop()
+                for b in verts:
+                    if b not in seen and b in nb[a]:
+                        seen.add(b)
+                        stack.append(b)
+        return comps
+
+    lc = np.array([count(v, -1) for v in range(n)], np.int64)
+    uc = np.array([count(v, +1) for v in range(n)], np.int64)
+    return lc, uc

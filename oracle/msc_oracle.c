@@ -448,3 +448,233 @@ int64_t orc_check_roots(const float *f, int64_t X, int64_t Y, int64_t Z,
     *first_bad = first;
     return bad;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Critical points and the extremum graph                                   */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * The link of v (background, "Critical Points"): the top simplices of the
+ * grid's triangulation that contain v, without v.  The triangulation's
+ * dimension d is the number of axes longer than one; each unit d-cube over
+ * those axes splits into the d! Kuhn simplices {c, c+e_a1, c+e_a1+e_a2,
+ * ...}.  Writes up to 24 link simplices of d vertices each (unused slots
+ * -1) and returns their number; *dim receives d.
+ */
+static int link_simplices(int64_t X, int64_t Y, int64_t Z, int64_t v,
+                          int64_t out[24][3], int *dim)
+{
+    const int64_t ext[3] = {X, Y, Z}, stride[3] = {1, X, X * Y};
+    const int64_t p[3] = {v % X, (v / X) % Y, v / (X * Y)};
+    int axes[3], d = 0;
+    for (int a = 0; a < 3; ++a)
+        if (ext[a] > 1) axes[d++] = a;
+    *dim = d;
+    if (d == 0) return 0;
+    int perms[6][3], np = 0;
+    /* all orderings of the d active axes */
+    for (int i = 0; i < d; ++i)
+        for (int j = 0; j < d; ++j)
+            for (int k = 0; k < d; ++k) {
+                int o[3] = {i, j, k};
+                int ok = 1;
+                for (int q = 0; q < d; ++q)
+                    for (int r = q + 1; r < d; ++r)
+                        if (o[q] == o[r]) ok = 0;
+                if (!ok) continue;
+                int dup = 0;
+                for (int q = 0; q < np; ++q) {
+                    int same = 1;
+                    for (int r = 0; r < d; ++r)
+                        if (perms[q][r] != axes[o[r]]) same = 0;
+                    if (same) dup = 1;
+                }
+                if (dup) continue;
+                for (int r = 0; r < d; ++r) perms[np][r] = axes[o[r]];
+                ++np;
+            }
+    int n = 0;
+    /* cubes whose lower corner c has c_a in {p_a - 1, p_a} on active axes */
+    for (int mask = 0; mask < (1 << d); ++mask) {
+        int64_t c[3] = {p[0], p[1], p[2]};
+        int inside = 1;
+        for (int r = 0; r < d; ++r) {
+            const int a = axes[r];
+            if (mask & (1 << r)) c[a] -= 1;
+            if (c[a] < 0 || c[a] + 1 >= ext[a]) inside = 0;
+        }
+        if (!inside) continue;
+        for (int q = 0; q < np; ++q) {
+            int64_t corner[3] = {c[0], c[1], c[2]};
+            int64_t ids[4];
+            ids[0] = corner[0] * stride[0] + corner[1] * stride[1] +
+                     corner[2] * stride[2];
+            for (int r = 0; r < d; ++r) {
+                corner[perms[q][r]] += 1;
+                ids[r + 1] = corner[0] * stride[0] + corner[1] * stride[1] +
+                             corner[2] * stride[2];
+            }
+            int has = 0;
+            for (int r = 0; r <= d; ++r)
+                if (ids[r] == v) has = 1;
+            if (!has) continue;
+            int w = 0;
+            for (int r = 0; r < 3; ++r) out[n][r] = -1;
+            for (int r = 0; r <= d; ++r)
+                if (ids[r] != v) out[n][w++] = ids[r];
+            ++n;
+        }
+    }
+    return n;
+}
+
+static int64_t lk_find(int64_t *par, int64_t i)
+{
+    while (par[i] != i) i = par[i];
+    return i;
+}
+
+/*
+ * Lower (side = -1) or upper (side = +1) link of v restricted to the
+ * vertices below / above v in the (f, id) order: its connected components
+ * (through the link's edges) and its Euler characteristic (vertices - edges
+ * + triangles).  comp[k] receives the component (0-based) of lv[k], the
+ * k-th distinct link vertex on that side; returns the component count.
+ */
+static int link_side(const float *f, int64_t X, int64_t Y, int64_t Z,
+                     int64_t v, int side, int64_t *lv, int *nlv, int *comp,
+                     int *chi)
+{
+    int64_t simp[24][3];
+    int d;
+    const int ns = link_simplices(X, Y, Z, v, simp, &d);
+    int nv = 0;
+    for (int s = 0; s < ns; ++s)
+        for (int r = 0; r < d; ++r) {
+            const int64_t u = simp[s][r];
+            const int keep = side > 0 ? above(f, u, v) : above(f, v, u);
+            if (!keep) continue;
+            int seen = 0;
+            for (int q = 0; q < nv; ++q)
+                if (lv[q] == u) seen = 1;
+            if (!seen) lv[nv++] = u;
+        }
+    int64_t par[64];
+    for (int q = 0; q < nv; ++q) par[q] = q;
+    /* distinct edges and triangles whose vertices are all on the side */
+    int64_t edges[72][2];
+    int ne = 0, nt = 0;
+    for (int s = 0; s < ns; ++s) {
+        int all = 1;
+        for (int r = 0; r < d; ++r) {
+            const int64_t u = simp[s][r];
+            if (!(side > 0 ? above(f, u, v) : above(f, v, u))) all = 0;
+        }
+        if (d == 3 && all) ++nt;  /* top link simplices are distinct */
+        for (int a = 0; a < d; ++a)
+            for (int b = a + 1; b < d; ++b) {
+                int64_t u = simp[s][a], w = simp[s][b];
+                const int ua = side > 0 ? above(f, u, v) : above(f, v, u);
+                const int wa = side > 0 ? above(f, w, v) : above(f, v, w);
+                if (!ua || !wa) continue;
+                if (u > w) { int64_t t = u; u = w; w = t; }
+                int seen = 0;
+                for (int q = 0; q < ne; ++q)
+                    if (edges[q][0] == u && edges[q][1] == w) seen = 1;
+                if (seen) continue;
+                edges[ne][0] = u;
+                edges[ne][1] = w;
+                ++ne;
+                int iu = 0, iw = 0;
+                for (int q = 0; q < nv; ++q) {
+                    if (lv[q] == u) iu = q;
+                    if (lv[q] == w) iw = q;
+                }
+                const int64_t ru = lk_find(par, iu), rw = lk_find(par, iw);
+                if (ru != rw) par[ru > rw ? ru : rw] = ru < rw ? ru : rw;
+            }
+    }
+    int nc = 0;
+    int64_t rootid[64];
+    for (int q = 0; q < nv; ++q) {
+        const int64_t r = lk_find(par, q);
+        int found = -1;
+        for (int c = 0; c < nc; ++c)
+            if (rootid[c] == r) found = c;
+        if (found < 0) { rootid[nc] = r; found = nc++; }
+        comp[q] = found;
+    }
+    *nlv = nv;
+    *chi = nv - ne + nt;
+    return nc;
+}
+
+/*
+ * Per vertex: lc = components of the lower link, uc = components of the
+ * upper link (lc = 0: minimum, uc = 0: maximum, lc = uc = 1: regular,
+ * otherwise a saddle), chi = Euler characteristic of the lower link.
+ * Banchoff's critical point theorem makes sum(1 - chi) the Euler
+ * characteristic of the domain.
+ */
+void orc_critical(const float *f, int64_t X, int64_t Y, int64_t Z,
+                  uint8_t *lc, uint8_t *uc, int32_t *chi)
+{
+    const int64_t n = X * Y * Z;
+    int64_t lv[64];
+    int comp[64], nlv, c;
+    for (int64_t v = 0; v < n; ++v) {
+        lc[v] = (uint8_t)link_side(f, X, Y, Z, v, -1, lv, &nlv, comp, &c);
+        chi[v] = c;
+        uc[v] = (uint8_t)link_side(f, X, Y, Z, v, +1, lv, &nlv, comp, &c);
+    }
+}
+
+/*
+ * Extremum graph: for every vertex whose upper link has two or more
+ * components, one edge per component to the maximum that steepest ascent
+ * reaches from the component's highest vertex (asc of it), tagged +1; the
+ * same through the lower link, its lowest vertices and desc, tagged -1.
+ * Edges go to out[3*k .. 3*k+2] = (vertex, extremum, tag) for k < cap, by
+ * increasing vertex, +1 edges first, components by increasing id of that
+ * highest / lowest vertex.  Returns the number of edges.
+ */
+int64_t orc_extremum_edges(const float *f, int64_t X, int64_t Y, int64_t Z,
+                           const int32_t *asc, const int32_t *desc,
+                           int32_t *out, int64_t cap)
+{
+    const int64_t n = X * Y * Z;
+    int64_t count = 0;
+    int64_t lv[64];
+    int comp[64], nlv, chi;
+    for (int64_t v = 0; v < n; ++v) {
+        for (int side = +1; side >= -1; side -= 2) {
+            const int nc = link_side(f, X, Y, Z, v, side, lv, &nlv, comp, &chi);
+            if (nc < 2) continue;
+            int64_t ext[64];
+            for (int c = 0; c < nc; ++c) {
+                int64_t best = -1;
+                for (int q = 0; q < nlv; ++q) {
+                    if (comp[q] != c) continue;
+                    if (best < 0 || (side > 0 ? above(f, lv[q], best)
+                                              : above(f, best, lv[q])))
+                        best = lv[q];
+                }
+                ext[c] = best;
+            }
+            /* components by increasing id of their extreme vertex */
+            for (int a = 1; a < nc; ++a)
+                for (int b = a; b > 0 && ext[b - 1] > ext[b]; --b) {
+                    int64_t t = ext[b]; ext[b] = ext[b - 1]; ext[b - 1] = t;
+                }
+            for (int c = 0; c < nc; ++c) {
+                if (count < cap) {
+                    out[3 * count] = (int32_t)v;
+                    out[3 * count + 1] = side > 0 ? asc[ext[c]] : desc[ext[c]];
+                    out[3 * count + 2] = side;
+                }
+                ++count;
+            }
+        }
+    }
+    return count;
+}

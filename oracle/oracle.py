@@ -58,6 +58,10 @@ def lib():
         L.orc_successors.restype = None
         L.orc_successors_csr.argtypes = [P, I64, P, P, P, P]
         L.orc_successors_csr.restype = None
+        L.orc_critical.argtypes = [P, I64, I64, I64, P, P, P]
+        L.orc_critical.restype = None
+        L.orc_extremum_edges.argtypes = [P, I64, I64, I64, P, P, P, I64]
+        L.orc_extremum_edges.restype = I64
         L.orc_walk_plain.argtypes = [P, I64, P]
         L.orc_walk_plain.restype = None
         L.orc_walk_memo.argtypes = [P, I64, P, P]
@@ -197,6 +201,33 @@ def csr_from_tets(n: int, tets: np.ndarray):
     row_ptr = np.zeros(n + 1, np.int64)
     np.cumsum(np.bincount(src, minlength=n), out=row_ptr[1:])
     return row_ptr, dst.astype(np.int32)
+
+
+def critical(f: np.ndarray):
+    """(lc, uc, chi): components of each vertex's lower and upper link and
+    the Euler characteristic of its lower link (flat arrays)."""
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    X, Y, Z = _dims(f)
+    n = X * Y * Z
+    lc = np.empty(n, np.uint8)
+    uc = np.empty(n, np.uint8)
+    chi = np.empty(n, np.int32)
+    lib().orc_critical(_p(f), X, Y, Z, _p(lc), _p(uc), _p(chi))
+    return lc, uc, chi
+
+
+def extremum_edges(f: np.ndarray, asc: np.ndarray, desc: np.ndarray):
+    """int32 [m, 3] rows (vertex, extremum, +1 / -1) of the extremum
+    graph, by increasing vertex, ascending edges first."""
+    f = np.ascontiguousarray(f, dtype=np.float32)
+    X, Y, Z = _dims(f)
+    asc = np.ascontiguousarray(asc, dtype=np.int32)
+    desc = np.ascontiguousarray(desc, dtype=np.int32)
+    m = lib().orc_extremum_edges(_p(f), X, Y, Z, _p(asc), _p(desc),
+                                 None, 0)
+    out = np.empty((max(m, 1), 3), np.int32)
+    lib().orc_extremum_edges(_p(f), X, Y, Z, _p(asc), _p(desc), _p(out), m)
+    return out[:m]
 
 
 def sync_doubling(d: np.ndarray, rounds: int) -> np.ndarray:
