@@ -339,6 +339,60 @@ def bench_tets(args, msc, synth, torch, dev):
     print(json.dumps(out), flush=True)
 
 
+CRIT_TEXT = {
+    "crit_gauss1024": "crit_gauss1024: link components of every vertex and "
+                      "the extremum graph of the gauss1024 field",
+    "crit_perlin1024": "crit_perlin1024: link components of every vertex and "
+                       "the extremum graph of the perlin1024 field",
+}
+
+
+def bench_crit(args, msc, synth, torch, dev):
+    """Critical points by link components, then the extremum graph from the
+    field's segmentation (computed once, outside the timed region); one of
+    each per step."""
+    stream = torch.cuda.current_stream(dev)
+    name = args.workload.split("_", 1)[1]
+    log(f"[bench] generating {name}")
+    f = synth.config_field(name, device=dev)
+    n = f.numel()
+    code = torch.empty(n, dtype=torch.uint8, device=dev)
+    a, d, _ = msc.segment(f, want=("asc", "desc"))
+    m = msc.extremum_graph(f, a, d).shape[0]
+    edges = torch.empty((m, 3), dtype=torch.int32, device=dev)
+    def run():
+        msc.critical_points_into(f, code, stream=stream)
+        msc.extremum_graph_into(f, a, d, edges, stream=stream)
+
+    for _ in range(args.warmup):
+        run()
+    torch.cuda.synchronize()
+    msc.profile(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        run()
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    msc.profile(False)
+    prof = msc.profile_read()
+    log(f"[bench] {args.steps} steps: {dt * 1e3:.2f} ms/step")
+    log_prof(prof)
+    saddles = int(((code & 15) >= 2).sum() + ((code >> 4) >= 2).sum())
+    out = {
+        "metric": "Gvertices/s critical points + extremum graph "
+                  "(" + args.workload + ")",
+        "value": round(n / dt / 1e9, 3), "unit": "Gvertices/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 3), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": CRIT_TEXT[args.workload], "vertices": n,
+                   "saddle_sides": saddles, "edges": m},
+        "roofline": roofline_of(prof, args.workload),
+    }
+    print(json.dumps(out), flush=True)
+
+
 TETS_TEXT = {
     "tets368": "tets368: the 6*367^3 = 296M Kuhn tetrahedra of a 368^3 grid "
                "with randomly permuted vertex ids (seed 2) to symmetric CSR "
@@ -562,7 +616,7 @@ def main():
     ap.add_argument("--workload", default="gauss1024",
                     choices=sorted(WORKLOAD_TEXT) + ["batch256", "serve"]
                     + sorted(CC_TEXT) + sorted(SEGCSR_TEXT)
-                    + sorted(TETS_TEXT))
+                    + sorted(TETS_TEXT) + sorted(CRIT_TEXT))
     ap.add_argument("--cpu-depth", type=int, default=100,
                     help="z-planes of the field the CPU oracle is timed on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -619,6 +673,8 @@ def main():
         return bench_segcsr(args, msc, synth, torch, dev)
     if args.workload in TETS_TEXT:
         return bench_tets(args, msc, synth, torch, dev)
+    if args.workload in CRIT_TEXT:
+        return bench_crit(args, msc, synth, torch, dev)
 
     log(f"[bench] generating {args.workload} on {dev}")
     t0 = time.perf_counter()

@@ -273,6 +273,44 @@ MSC_API int cc_label_grid(msc_ctx *ctx, const uint8_t *mask, const int64_t dims[
  * MSC_EINVAL also for ranks < 1 or ranks > Z.
  */
 /*
+ * Critical points by the connected components of each vertex's lower and
+ * upper link (background, "Critical Points"): the link of v in the
+ * Freudenthal triangulation restricted to the vertices below / above v in
+ * the (value, id) order.  0 lower components: minimum; 0 upper: maximum;
+ * one of each: regular; more: a saddle (two or more lower components: a
+ * 1-saddle, upper: a 2-saddle; more than two, or both: degenerate).
+ *
+ *  field  device, float32[N] as msc_segment (N <= INT32_MAX).
+ *  code   device, uint8[N]: lower components | upper components << 4.
+ *  Errors: MSC_EINVAL, MSC_ERANGE, MSC_ENAN, MSC_EHIP.
+ */
+MSC_API int msc_critical_points(msc_ctx *ctx, const float *field,
+                                const int64_t dims[3], uint8_t *code,
+                                void *stream);
+
+/*
+ * The extremum graph that the segmentations provide (the paper's outlook:
+ * the input of a merge tree computation): for every vertex whose upper link
+ * has two or more components, one edge per component to the maximum that
+ * steepest ascent reaches from the component's highest vertex; likewise
+ * through the lower link to minima.
+ *
+ *  asc, desc  device, int32[N]: the maps msc_segment wrote for this field.
+ *  edges      device, int32[capacity][3] = (vertex, extremum, +1 for a
+ *             maximum / -1 for a minimum), or NULL; written only when
+ *             capacity >= the edge count, by increasing vertex, a vertex's
+ *             ascending edges first, its components by increasing id of
+ *             their highest / lowest vertex.
+ *  count      host, receives the edge count.
+ *  Synchronises the stream.  Errors: MSC_EINVAL, MSC_ERANGE, MSC_ENAN,
+ *  MSC_ENOMEM, MSC_EHIP.
+ */
+MSC_API int msc_extremum_graph(msc_ctx *ctx, const float *field,
+                               const int64_t dims[3], const int32_t *asc,
+                               const int32_t *desc, int32_t *edges,
+                               int64_t capacity, int64_t *count, void *stream);
+
+/*
  * CSR adjacency of the 1-skeleton of a tetrahedral complex given by its
  * tetrahedra (the mesh of the explicit pipeline, where extracted geometry
  * is triangulated before its components are labelled, and the input of

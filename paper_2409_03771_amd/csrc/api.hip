@@ -325,6 +325,32 @@ int cc_label_grid_ranks(msc_ctx *ctx, const uint8_t *mask,
                                 labels, static_cast<hipStream_t>(stream));
 }
 
+int msc_critical_points(msc_ctx *ctx, const float *field,
+                        const int64_t dims[3], uint8_t *code, void *stream) {
+  if (!ctx || !dims || !field || !code) return MSC_EINVAL;
+  int64_t n = 0;
+  MSC_TRY(check_dims(dims, &n));
+  if (n > INT32_MAX) return MSC_ERANGE;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return MSC_EHIP;
+  return msc::critical_points_run(ctx, field, dims, code,
+                                  static_cast<hipStream_t>(stream));
+}
+
+int msc_extremum_graph(msc_ctx *ctx, const float *field, const int64_t dims[3],
+                       const int32_t *asc, const int32_t *desc, int32_t *edges,
+                       int64_t capacity, int64_t *count, void *stream) {
+  if (!ctx || !dims || !field || !asc || !desc || !count || capacity < 0)
+    return MSC_EINVAL;
+  int64_t n = 0;
+  MSC_TRY(check_dims(dims, &n));
+  if (n > INT32_MAX) return MSC_ERANGE;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return MSC_EHIP;
+  return msc::extremum_graph_run(ctx, field, dims, asc, desc, edges, capacity,
+                                 count, static_cast<hipStream_t>(stream));
+}
+
 int msc_csr_from_tets(msc_ctx *ctx, int64_t n, int64_t ntets,
                       const int32_t *tets, int64_t *row_ptr, int32_t *col_idx,
                       int64_t capacity, int64_t *nnz, void *stream) {

@@ -954,4 +954,265 @@ int csr_from_tets_run(msc_ctx *ctx, int64_t n, int64_t ntets,
   return MSC_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Critical points and the extremum graph (background, "Critical Points";
+// the extremum graph that the segmentations feed): the lower and upper link
+// of every vertex and their connected components, from the 14 Freudenthal
+// neighbours.  The triangulation is a flag complex, so two neighbours of v
+// span a link edge exactly when they are neighbours of each other; a link
+// vertex outside the domain is absent, which gives the link of boundary
+// vertices and of 2-D and 1-D grids.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct NbVec {
+  int dx, dy, dz;
+};
+// The neighbours in increasing (dz, dy, dx), i.e. in increasing vertex id.
+constexpr NbVec kNb[14] = {
+    {-1, -1, -1}, {0, -1, -1}, {-1, 0, -1}, {0, 0, -1}, {-1, -1, 0},
+    {0, -1, 0},   {-1, 0, 0},  {1, 0, 0},   {0, 1, 0},  {1, 1, 0},
+    {0, 0, 1},    {1, 0, 1},   {0, 1, 1},   {1, 1, 1}};
+
+constexpr bool edge_vector(int a, int b, int c) {
+  const bool nonneg = a >= 0 && b >= 0 && c >= 0 && a <= 1 && b <= 1 && c <= 1;
+  const bool nonpos = a <= 0 && b <= 0 && c <= 0 && a >= -1 && b >= -1 &&
+                      c >= -1;
+  return (a | b | c) != 0 && (nonneg || nonpos);
+}
+
+constexpr uint32_t link_adj(int i) {
+  uint32_t m = 0;
+  for (int j = 0; j < 14; ++j)
+    if (j != i && edge_vector(kNb[i].dx - kNb[j].dx, kNb[i].dy - kNb[j].dy,
+                              kNb[i].dz - kNb[j].dz))
+      m |= 1u << j;
+  return m;
+}
+
+struct LinkInfo {
+  uint32_t lower, upper;      // neighbour masks
+  uint32_t lext, uext;        // lowest / highest neighbour of each component
+  int lc, uc;                 // component counts
+  bool nan;
+};
+
+// Components of the neighbours in `mask`, and the (f, id)-extreme member of
+// each (the highest when `high`): neighbour order is id order, so a tie in
+// value goes to the larger index for the highest and the smaller for the
+// lowest.
+__device__ __forceinline__ int link_components(uint32_t mask, const float *fn,
+                                               bool high, uint32_t *ext) {
+  int count = 0;
+  uint32_t rem = mask, ex = 0;
+  while (rem) {
+    uint32_t comp = rem & (0u - rem), prev;
+    do {
+      prev = comp;
+      uint32_t g = comp;
+#pragma unroll
+      for (int i = 0; i < 14; ++i)
+        if ((prev >> i) & 1u) g |= link_adj(i);
+      comp = g & mask;
+    } while (comp != prev);
+    int best = -1;
+    float fb = 0.f;
+#pragma unroll
+    for (int i = 0; i < 14; ++i) {
+      if (!((comp >> i) & 1u)) continue;
+      const bool better = best < 0 || (high ? fn[i] >= fb : fn[i] < fb);
+      if (better) {
+        best = i;
+        fb = fn[i];
+      }
+    }
+    ex |= 1u << best;
+    rem &= ~comp;
+    ++count;
+  }
+  *ext = ex;
+  return count;
+}
+
+__device__ __forceinline__ LinkInfo link_info(const float *__restrict__ f,
+                                              int64_t X, int64_t Y, int64_t Z,
+                                              int64_t v) {
+  const int64_t XY = X * Y;
+  const int64_t x = v % X, y = (v / X) % Y, z = v / XY;
+  const float fv = f[v];
+  float fn[14];
+  uint32_t present = 0;
+#pragma unroll
+  for (int i = 0; i < 14; ++i) {
+    const int64_t a = x + kNb[i].dx, b = y + kNb[i].dy, c = z + kNb[i].dz;
+    const bool in = a >= 0 && a < X && b >= 0 && b < Y && c >= 0 && c < Z;
+    fn[i] = in ? f[v + kNb[i].dx + X * kNb[i].dy + XY * kNb[i].dz] : 0.f;
+    present |= (uint32_t)in << i;
+  }
+  LinkInfo li;
+  li.nan = fv != fv;
+  li.lower = 0;
+#pragma unroll
+  for (int i = 0; i < 14; ++i) {
+    // below v in the (f, id) order; the first 7 neighbours have smaller ids
+    const bool below = fn[i] < fv || (fn[i] == fv && i < 7);
+    li.lower |= (uint32_t)below << i;
+  }
+  li.lower &= present;
+  li.upper = present & ~li.lower;
+  li.lc = link_components(li.lower, fn, false, &li.lext);
+  li.uc = link_components(li.upper, fn, true, &li.uext);
+  return li;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_critical(const float *__restrict__ f, int64_t X, int64_t Y, int64_t Z,
+           uint8_t *__restrict__ code, unsigned long long *ctr) {
+  const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  bool nan = false;
+  if (v < X * Y * Z) {
+    const LinkInfo li = link_info(f, X, Y, Z, v);
+    code[v] = (uint8_t)(li.lc | (li.uc << 4));
+    nan = li.nan;
+  }
+  flag_any(nan, ctr + kCtrNaN);
+}
+
+__device__ __forceinline__ uint32_t edge_count(const LinkInfo &li) {
+  return (li.uc >= 2 ? (uint32_t)li.uc : 0u) + (li.lc >= 2 ? (uint32_t)li.lc : 0u);
+}
+
+// Exclusive prefix over a block of kBlock threads and the block total.
+__device__ __forceinline__ uint32_t block_scan32(uint32_t x, uint32_t *tmp,
+                                                 uint32_t *total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t inc = x;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(inc, o);
+    if (lane >= o) inc += y;
+  }
+  if (lane == 63) tmp[w] = inc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t run = 0;
+    for (int k = 0; k < kBlock / 64; ++k) {
+      const uint32_t t = tmp[k];
+      tmp[k] = run;
+      run += t;
+    }
+    tmp[kBlock / 64] = run;
+  }
+  __syncthreads();
+  const uint32_t ex = inc - x + tmp[w];
+  *total = tmp[kBlock / 64];
+  return ex;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_egraph_count(const float *__restrict__ f, int64_t X, int64_t Y, int64_t Z,
+               uint32_t *bcount, unsigned long long *ctr) {
+  __shared__ uint32_t tmp[kBlock / 64 + 1];
+  const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  uint32_t c = 0;
+  bool nan = false;
+  if (v < X * Y * Z) {
+    const LinkInfo li = link_info(f, X, Y, Z, v);
+    c = edge_count(li);
+    nan = li.nan;
+  }
+  flag_any(nan, ctr + kCtrNaN);
+  uint32_t tot = 0;
+  (void)block_scan32(c, tmp, &tot);
+  if (threadIdx.x == 0) bcount[blockIdx.x] = tot;
+}
+
+// Edges of a vertex: ascending ones first, then descending; within a side,
+// components by increasing id of their extreme vertex (= neighbour order).
+__global__ void __launch_bounds__(kBlock)
+k_egraph_write(const float *__restrict__ f, int64_t X, int64_t Y, int64_t Z,
+               const int32_t *__restrict__ asc,
+               const int32_t *__restrict__ desc,
+               const int64_t *__restrict__ boff, int32_t *__restrict__ out) {
+  __shared__ uint32_t tmp[kBlock / 64 + 1];
+  const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int64_t XY = X * Y;
+  LinkInfo li{};
+  uint32_t c = 0;
+  if (v < X * Y * Z) {
+    li = link_info(f, X, Y, Z, v);
+    c = edge_count(li);
+  }
+  uint32_t tot = 0;
+  const uint32_t ex = block_scan32(c, tmp, &tot);
+  if (!c) return;
+  int64_t at = boff[blockIdx.x] + ex;
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const uint32_t m = side == 0 ? (li.uc >= 2 ? li.uext : 0u)
+                                 : (li.lc >= 2 ? li.lext : 0u);
+#pragma unroll
+    for (int i = 0; i < 14; ++i) {
+      if (!((m >> i) & 1u)) continue;
+      const int64_t u = v + kNb[i].dx + (int64_t)X * kNb[i].dy +
+                        XY * kNb[i].dz;
+      out[3 * at] = (int32_t)v;
+      out[3 * at + 1] = side == 0 ? asc[u] : desc[u];
+      out[3 * at + 2] = side == 0 ? 1 : -1;
+      ++at;
+    }
+  }
+}
+
+}  // namespace
+
+int critical_points_run(msc_ctx *ctx, const float *field, const int64_t *dims,
+                        uint8_t *code, hipStream_t s) {
+  const int64_t X = dims[0], Y = dims[1], Z = dims[2], N = X * Y * Z;
+  MSC_TRY(clear_counters(ctx, s));
+  MSC_PHASE(ctx, s, "critical", 5.0 * N,
+            (k_critical<<<grid64(N, kBlock), kBlock, 0, s>>>(field, X, Y, Z,
+                                                             code,
+                                                             ctx->dctr)));
+  MSC_TRY(read_counters(ctx, s));
+  if (ctx->hctr[kCtrNaN]) return MSC_ENAN;
+  ctx->stats = msc_stats{};
+  ctx->stats.n_vertices = N;
+  return MSC_OK;
+}
+
+int extremum_graph_run(msc_ctx *ctx, const float *field, const int64_t *dims,
+                       const int32_t *asc, const int32_t *desc, int32_t *edges,
+                       int64_t capacity, int64_t *count, hipStream_t s) {
+  const int64_t X = dims[0], Y = dims[1], Z = dims[2], N = X * Y * Z;
+  const int64_t nb = (N + kBlock - 1) / kBlock;
+  const int64_t nsb = (nb + kScan - 1) / kScan;
+  MSC_TRY(reserve(ctx->ws, align256(nb * 4) + align256((nb + 1) * 8) +
+                               align256(nsb * 8 + 8) + 4096));
+  Carver cv(ctx->ws);
+  uint32_t *bcount = cv.take<uint32_t>(nb);
+  int64_t *boff = cv.take<int64_t>(nb + 1);
+  uint64_t *bsum = cv.take<uint64_t>(nsb + 1);
+  MSC_TRY(clear_counters(ctx, s));
+  MSC_PHASE(ctx, s, "egraph_count", 4.0 * N,
+            (k_egraph_count<<<(unsigned)nb, kBlock, 0, s>>>(field, X, Y, Z,
+                                                            bcount,
+                                                            ctx->dctr),
+             scan64(ctx, bcount, nb, boff, bsum, s)));
+  int64_t total = 0;
+  MSC_HIP_TRY(hipMemcpyAsync(&total, boff + nb, sizeof(int64_t),
+                             hipMemcpyDeviceToHost, s));
+  MSC_TRY(read_counters(ctx, s));
+  if (ctx->hctr[kCtrNaN]) return MSC_ENAN;
+  *count = total;
+  if (edges && capacity >= total && total > 0)
+    MSC_PHASE(ctx, s, "egraph_write", 4.0 * N + 12.0 * total,
+              (k_egraph_write<<<(unsigned)nb, kBlock, 0, s>>>(
+                  field, X, Y, Z, asc, desc, boff, edges)));
+  MSC_TRY(read_counters(ctx, s));
+  ctx->stats = msc_stats{};
+  ctx->stats.n_vertices = N;
+  return MSC_OK;
+}
+
 }  // namespace msc

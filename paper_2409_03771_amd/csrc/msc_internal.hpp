@@ -189,6 +189,11 @@ int segment_ranks_run(msc_ctx *ctx, const float *field, const int64_t dims[3],
 int csr_from_tets_run(msc_ctx *ctx, int64_t n, int64_t ntets,
                       const int32_t *tets, int64_t *row_ptr, int32_t *col_idx,
                       int64_t capacity, int64_t *nnz, hipStream_t stream);
+int critical_points_run(msc_ctx *ctx, const float *field, const int64_t *dims,
+                        uint8_t *code, hipStream_t stream);
+int extremum_graph_run(msc_ctx *ctx, const float *field, const int64_t *dims,
+                       const int32_t *asc, const int32_t *desc, int32_t *edges,
+                       int64_t capacity, int64_t *count, hipStream_t stream);
 int segment_csr_run(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,
                     const int32_t *col_idx, const float *field, int32_t *asc,
                     int32_t *desc, int32_t *ms, hipStream_t stream);

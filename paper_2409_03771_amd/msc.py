@@ -76,6 +76,9 @@ _SIGS = {
                           ctypes.POINTER(_I32)], _I32),
     "cc_label_grid": ([_P, _P, ctypes.POINTER(_I64), _P, _P], _I32),
     "msc_segment_csr": ([_P, _I64, _P, _P, _P, _P, _P, _P, _P], _I32),
+    "msc_critical_points": ([_P, _P, ctypes.POINTER(_I64), _P, _P], _I32),
+    "msc_extremum_graph": ([_P, _P, ctypes.POINTER(_I64), _P, _P, _P, _I64,
+                            ctypes.POINTER(_I64), _P], _I32),
     "msc_csr_from_tets": ([_P, _I64, _I64, _P, _P, _P, _I64,
                            ctypes.POINTER(_I64), _P], _I32),
     "cc_label_grid_ranks": ([_P, _P, ctypes.POINTER(_I64), _I32, _P, _P],
@@ -198,6 +201,56 @@ def segment_ranks_into(field, ranks, asc, desc, ms, stream=None):
         _dev_ptr(asc, torch.int32, "asc"), _dev_ptr(desc, torch.int32, "desc"),
         _dev_ptr(ms, torch.int32, "ms"), _stream(field, stream))
     _check(code, "msc_segment_ranks")
+
+
+def critical_points(field: torch.Tensor, stream=None) -> torch.Tensor:
+    """uint8 per vertex: lower-link components | upper-link components << 4."""
+    code = torch.empty(field.numel(), dtype=torch.uint8, device=field.device)
+    critical_points_into(field, code, stream)
+    return code
+
+
+def critical_points_into(field, code, stream=None):
+    _check(_lib.msc_critical_points(
+        context(field.device.index), _dev_ptr(field, torch.float32, "field"),
+        _dims_arg(grid_dims(field.shape)), _dev_ptr(code, torch.uint8, "code"),
+        _stream(field, stream)), "msc_critical_points")
+
+
+def extremum_graph_into(field, asc, desc, edges, stream=None) -> int:
+    """One call into a caller buffer (None or too small: nothing written);
+    returns the edge count."""
+    cnt = _I64(0)
+    cap = 0 if edges is None else edges.numel() // 3
+    _check(_lib.msc_extremum_graph(
+        context(field.device.index), _dev_ptr(field, torch.float32, "field"),
+        _dims_arg(grid_dims(field.shape)), _dev_ptr(asc, torch.int32, "asc"),
+        _dev_ptr(desc, torch.int32, "desc"),
+        _dev_ptr(edges, torch.int32, "edges"), int(cap), ctypes.byref(cnt),
+        _stream(field, stream)), "msc_extremum_graph")
+    return cnt.value
+
+
+def extremum_graph(field: torch.Tensor, asc: torch.Tensor, desc: torch.Tensor,
+                   stream=None) -> torch.Tensor:
+    """int32 [m, 3] rows (vertex, extremum, +1 / -1) of the extremum graph
+    (asc and desc from segment() of the same field)."""
+    cnt = _I64(0)
+    args = (context(field.device.index),
+            _dev_ptr(field, torch.float32, "field"),
+            _dims_arg(grid_dims(field.shape)),
+            _dev_ptr(asc, torch.int32, "asc"),
+            _dev_ptr(desc, torch.int32, "desc"))
+    _check(_lib.msc_extremum_graph(*args, None, 0, ctypes.byref(cnt),
+                                   _stream(field, stream)),
+           "msc_extremum_graph")
+    out = torch.empty((max(cnt.value, 1), 3), dtype=torch.int32,
+                      device=field.device)
+    _check(_lib.msc_extremum_graph(*args, _dev_ptr(out, torch.int32, "edges"),
+                                   cnt.value, ctypes.byref(cnt),
+                                   _stream(field, stream)),
+           "msc_extremum_graph")
+    return out[:cnt.value]
 
 
 def csr_from_tets(n: int, tets: torch.Tensor, stream=None):
