@@ -130,6 +130,13 @@ namespace {
 // buffers: a segmentation's local pointers (4 B/vertex) and exit lists
 // (12 B per exit, at most about a third of the vertices on small tiles); a
 // CC's 16-bit tile labels.
+// A segmentation launch takes at most this many vertices (and at least one
+// request): a batch's requests all complete when the launch does, so an
+// unbounded batch would make its first requests wait for the last ones;
+// 64M vertices keep a launch around a millisecond, long enough to fill the
+// device.
+constexpr int64_t kMaxBatchVertices = 64ll << 20;
+
 size_t workspace_bytes(int kind, int64_t n) {
   if (kind == MSC_REQ_SEGMENT) return (size_t)n * 8 + (1 << 20);
   return (size_t)n * 2 + (1 << 20);
@@ -217,8 +224,11 @@ void worker_loop(msc_queue *q, int kind) {
     }
     std::vector<Request *> batch;
     const int64_t t = now_ns();
-    while (!ready.empty() && (int)batch.size() < cap) {
+    int64_t verts = 0;
+    while (!ready.empty() && (int)batch.size() < cap &&
+           (batch.empty() || verts + ready.front()->n <= kMaxBatchVertices)) {
       Request *r = ready.front();
+      verts += r->n;
       ready.pop_front();
       r->state = kRunning;
       r->t_start = t;
