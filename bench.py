@@ -750,11 +750,12 @@ def main():
         log(f"[bench] timing the CPU oracle on {depth} z-planes")
         out["cpu_baseline"] = cpu_baseline(field, depth)
     if not args.no_serve:
-        # Short served leg: one light and one saturating arrival rate.
+        # Short served leg: a light, a busy and a saturating arrival rate.
         del field, asc, desc, ms
         torch.cuda.empty_cache()
-        text, res, res_dev = served_sweep(msc, synth, torch, dev, [200, 2000],
-                                          50, 300, 24, resident_rates=[2000])
+        text, res, res_dev = served_sweep(msc, synth, torch, dev,
+                                          [200, 1000, 2000], 50, 300, 24,
+                                          resident_rates=[2000])
         out["served"] = {"workload": text, "requests_per_rate": 300,
                          "rates": res,
                          "rates_device_resident_inputs": res_dev}
