@@ -60,14 +60,7 @@ struct Cfg {
   // carries the flag to every pointer that ends in the halo.
   static constexpr bool kHaloBit = H <= 0x8000;
   static constexpr uint32_t kHB = kHaloBit ? 0x8000u : 0u;
-  // When they fit in 14 bits, bit 14 marks the other fixed points (in-tile
-  // extrema, positions outside the domain): then every pointer that has
-  // reached a fixed point carries a flag, and jumping stops in the round
-  // that makes its last change instead of one round later.
-  static constexpr bool kFinalBit = H <= 0x4000;
-  static constexpr uint32_t kFB = kFinalBit ? 0x4000u : 0u;
-  static constexpr uint32_t kIdx =
-      kFinalBit ? 0x3fffu : (kHaloBit ? 0x7fffu : 0xffffu);
+  static constexpr uint32_t kIdx = kHaloBit ? 0x7fffu : 0xffffu;
   static_assert(H <= 65535, "tile-local pointers are 16-bit");
   static_assert(kThreads % 64 == 0 && kThreads <= 1024, "block shape");
   static_assert(H % 4 == 0, "flag bytes are read as words");
@@ -496,10 +489,8 @@ k_tile_local(const FieldDev *__restrict__ fds,
     }
     const bool in = lz < nz;
     any_nan |= in && fv != fv;
-    const uint32_t pa = (uint32_t)(i + omax) | (omax == 0 ? C::kFB : 0u);
-    const uint32_t pd = (uint32_t)(i + omin) | (omin == 0 ? C::kFB : 0u);
-    ptr[lz] = in ? pa | (pd << 16)
-                 : ((uint32_t)i | C::kFB) * 0x10001u;
+    ptr[lz] = in ? (uint32_t)(i + omax) | ((uint32_t)(i + omin) << 16)
+                 : (uint32_t)i | ((uint32_t)i << 16);
     nmax += __popcll(__ballot(in && omax == 0));
     nmin += __popcll(__ballot(in && omin == 0));
     below = cur;
@@ -561,8 +552,6 @@ k_tile_local(const FieldDev *__restrict__ fds,
       q[lz] = (lds[ptr[lz] & C::kIdx] & 0xffffu) |
               (lds[(ptr[lz] >> 16) & C::kIdx] & 0xffff0000u);
     bool changed = false;
-    bool pending = false;  // an entry not yet at a flagged fixed point
-    constexpr uint32_t kFlags = (C::kHB | C::kFB) * 0x10001u;
 #pragma unroll
     for (int lz = 0; lz < C::TZ; ++lz) {
       if (q[lz] != ptr[lz]) {
@@ -570,12 +559,8 @@ k_tile_local(const FieldDev *__restrict__ fds,
         lds[c0 + (lz + 1) * HXY] = q[lz];
         changed = true;
       }
-      if (C::kFinalBit) {
-        const uint32_t fl = ptr[lz] & kFlags;
-        pending |= (fl & 0xffffu) == 0 || (fl >> 16) == 0;
-      }
     }
-    if (!__syncthreads_or(C::kFinalBit ? pending : changed)) break;
+    if (!__syncthreads_or(changed)) break;
   }
   // Every pointer is final in registers: `lds` becomes flags and bitsets.
   for (int w = tid; w < (2 * H + 3) / 4; w += T) lds[w] = 0;
@@ -587,7 +572,7 @@ k_tile_local(const FieldDev *__restrict__ fds,
   // the halo bit only the rare in-tile extremum targets need a decode.
   auto cls = [](uint32_t h) -> uint32_t {
     if (C::kHaloBit && (h & C::kHB)) return 0x10000u | (h & C::kIdx);
-    return classify<C>((int)(h & C::kIdx));
+    return classify<C>((int)h);
   };
   uint32_t hmask_a = 0, hmask_d = 0;
 #pragma unroll
@@ -1104,8 +1089,13 @@ k_tile_pairs(const FieldDev *__restrict__ fds,
 
   unsigned fresh = 0;
   bool overflow = false;
-  // A column's pair seldom changes from one z to the next; a repeated pair
-  // has a larger id than the one already recorded and needs nothing.
+  // Only the smallest id of each pair matters.  A vertex whose pair equals
+  // that of the vertex below it (previous z of the column) or of the lane
+  // before it (a smaller id in the same plane) is not that smallest id and
+  // needs nothing; the smallest one matches neither, so it is never skipped.
+  // In smooth regions this leaves few lanes per plane, and most waves skip
+  // the insert altogether.
+  const bool first_lane = (tid & 63) == 0;
   unsigned long long last = kEmptyKey;
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz) {
@@ -1113,8 +1103,10 @@ k_tile_pairs(const FieldDev *__restrict__ fds,
     if (lz < nz)
       key = pair_key(decode_final<C>(s, code[lz] & 0xffffu, false),
                      decode_final<C>(s, code[lz] >> 16, true));
-    if (key != last && key != kEmptyKey) {
-      last = key;
+    const unsigned long long left = __shfl_up(key, 1);
+    const bool repeat = key == last || (!first_lane && key == left);
+    last = key;
+    if (!repeat && key != kEmptyKey) {
       const int32_t id = (int32_t)(col + g.XY * (uint32_t)(t.z0 + lz));
       const int slot = pair_slot(skey, &sfill, key);
       if (slot >= 0)
