@@ -1633,6 +1633,9 @@ k_rank_ghost_resolve(RankGeo g, const SlabDev *__restrict__ slabs,
 
 // Final labels: a slab result that is a ghost takes the ghost's resolved
 // value.  Also counts the vertices that are their own labels (extrema).
+// Grid: x over the plane's XY vertices, y over planes (strided), so a
+// block's slab is uniform and a slab-local label is recognised as a ghost by
+// its plane alone (first plane or last), without a division.
 __global__ void __launch_bounds__(kBlock)
 k_rank_relabel(RankGeo g, const SlabDev *__restrict__ slabs,
                const int32_t *__restrict__ A, const int32_t *__restrict__ D,
@@ -1642,36 +1645,45 @@ k_rank_relabel(RankGeo g, const SlabDev *__restrict__ slabs,
   __shared__ uint32_t s_cnt[2];
   if (threadIdx.x < 2) s_cnt[threadIdx.x] = 0;
   __syncthreads();
-  const uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint32_t xy = blockIdx.x * kBlock + threadIdx.x;
   uint32_t cmax = 0, cmin = 0;
-  if (v < (uint64_t)g.XY * g.Z) {
-    const uint32_t z = (uint32_t)(v / g.XY);
+  for (uint32_t z = blockIdx.y; z < g.Z; z += gridDim.y) {
     uint32_t r = (uint32_t)(((uint64_t)z * g.R) / g.Z);
     while (r > 0 && slabs[r].z0 > z) --r;
     while (r + 1 < g.R && slabs[r + 1].z0 <= z) ++r;
     const SlabDev sl = slabs[r];
-    const uint64_t local = v - (uint64_t)sl.fs * g.XY;
+    if (xy >= g.XY) continue;
+    const uint64_t v = (uint64_t)z * g.XY + xy;
+    const uint64_t local = (uint64_t)(z - sl.fs) * g.XY + xy;
     const uint32_t base = sl.fs * g.XY;
-    uint32_t a = (uint32_t)A[sl.off + local] + base;
-    uint32_t d = (uint32_t)D[sl.off + local] + base;
-    const uint32_t na = ghost_of(g, sl, r, a), nd = ghost_of(g, sl, r, d);
-    if (na != ~0u) a = FA[na];
-    if (nd != ~0u) d = FD[nd];
+    const uint32_t top = (sl.fe - sl.fs - 1) * g.XY;  // first of the last plane
+    const bool lo = r > 0, hi = r + 1 < g.R;
+    uint32_t a = (uint32_t)A[sl.off + local];
+    uint32_t d = (uint32_t)D[sl.off + local];
+    if (lo && a < g.XY) a = FA[ghost_node(g, r, 0, a)];
+    else if (hi && a >= top) a = FA[ghost_node(g, r, 1, a - top)];
+    else a += base;
+    if (lo && d < g.XY) d = FD[ghost_node(g, r, 0, d)];
+    else if (hi && d >= top) d = FD[ghost_node(g, r, 1, d - top)];
+    else d += base;
     asc[v] = (int32_t)a;
     desc[v] = (int32_t)d;
-    cmax = a == (uint32_t)v;
-    cmin = d == (uint32_t)v;
+    cmax += a == (uint32_t)v;
+    cmin += d == (uint32_t)v;
   }
-  cmax = __popcll(__ballot(cmax));
-  cmin = __popcll(__ballot(cmin));
+  for (int o = 32; o > 0; o >>= 1) {
+    cmax += __shfl_xor(cmax, o);
+    cmin += __shfl_xor(cmin, o);
+  }
   if ((threadIdx.x & 63) == 0) {
     if (cmax) atomicAdd(&s_cnt[0], cmax);
     if (cmin) atomicAdd(&s_cnt[1], cmin);
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    roots[2 * blockIdx.x] = s_cnt[0];
-    roots[2 * blockIdx.x + 1] = s_cnt[1];
+    const uint32_t b = blockIdx.y * gridDim.x + blockIdx.x;
+    roots[2 * b] = s_cnt[0];
+    roots[2 * b + 1] = s_cnt[1];
   }
 }
 
@@ -1704,8 +1716,8 @@ k_rank_roots_sum(const uint32_t *__restrict__ roots, uint32_t nb,
 }
 
 // Cells over final labels: the smallest id of every (asc, desc) pair.  A
-// wave whose lanes all hold lane 0's pair inserts once (lane 0 holds the
-// smallest id); otherwise every lane inserts.
+// lane whose pair equals the previous lane's (one id smaller) is not its
+// pair's smallest id and inserts nothing; a run of equal pairs inserts once.
 __global__ void __launch_bounds__(kBlock)
 k_rank_pairs(uint64_t n, const int32_t *__restrict__ asc,
              const int32_t *__restrict__ desc, unsigned long long *keys,
@@ -1713,18 +1725,11 @@ k_rank_pairs(uint64_t n, const int32_t *__restrict__ asc,
   const uint64_t v = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool in = v < n;
   const unsigned long long key = in ? pair_key(asc[v], desc[v]) : kEmptyKey;
-  const unsigned long long k0 =
-      ((unsigned long long)__builtin_amdgcn_readfirstlane((uint32_t)(key >> 32))
-       << 32) | __builtin_amdgcn_readfirstlane((uint32_t)key);
-  const bool uniform = __ballot(in && key != k0) == 0;
+  const unsigned long long left = __shfl_up(key, 1);
+  const bool start = (threadIdx.x & 63) == 0 || key != left;
   unsigned fresh = 0;
   bool ok = true;
-  if (uniform) {
-    if (in && (threadIdx.x & 63) == (unsigned)(__ffsll((long long)__ballot(in)) - 1))
-      ok = table_insert(keys, vals, mask, key, (int32_t)v, &fresh);
-  } else if (in) {
-    ok = table_insert(keys, vals, mask, key, (int32_t)v, &fresh);
-  }
+  if (in && start) ok = table_insert(keys, vals, mask, key, (int32_t)v, &fresh);
   if (!ok) atomicOr(ctr + kCtrOverflow, 1ull);
 }
 
@@ -1778,16 +1783,20 @@ int segment_ranks(msc_ctx *ctx, const float *field, const int64_t dims[3],
   }
   const uint64_t nodes = 2ull * R * XY;
   const uint32_t nblk = (uint32_t)((N + kBlock - 1) / kBlock);
+  const dim3 rgrid((unsigned)((XY + kBlock - 1) / kBlock),
+                   Z < 65535u ? Z : 65535u);
+  // per-block root counts: for the per-vertex passes and for the relabel grid
+  const uint64_t nroot = std::max<uint64_t>(nblk, (uint64_t)rgrid.x * rgrid.y);
   MSC_TRY(reserve(ctx->rk, 2 * align256(total * 4) + 4 * align256(nodes * 4) +
                                align256(R * sizeof(SlabDev)) +
-                               2 * align256(N * 4) + align256(nblk * 8ull) +
+                               2 * align256(N * 4) + align256(nroot * 8ull) +
                                4096));
   Carver cv(ctx->rk);
   int32_t *A = cv.take<int32_t>(total), *D = cv.take<int32_t>(total);
   uint32_t *GA = cv.take<uint32_t>(nodes), *GD = cv.take<uint32_t>(nodes);
   uint32_t *FA = cv.take<uint32_t>(nodes), *FD = cv.take<uint32_t>(nodes);
   SlabDev *dsl = cv.take<SlabDev>(R);
-  uint32_t *roots = cv.take<uint32_t>(2ull * nblk);
+  uint32_t *roots = cv.take<uint32_t>(2ull * nroot);
   int32_t *fa = asc ? asc : cv.take<int32_t>(N);
   int32_t *fd = desc ? desc : cv.take<int32_t>(N);
   for (uint32_t r = 0; r < R; ++r) {
@@ -1818,9 +1827,10 @@ int segment_ranks(msc_ctx *ctx, const float *field, const int64_t dims[3],
              k_rank_ghost_resolve<<<grid_for(nodes), kBlock, 0, s>>>(
                  rg, dsl, GD, FD)));
   MSC_PHASE(ctx, s, "rank_relabel", 16.0 * N,
-            (k_rank_relabel<<<nblk, kBlock, 0, s>>>(rg, dsl, A, D, FA, FD, fa,
+            (k_rank_relabel<<<rgrid, kBlock, 0, s>>>(rg, dsl, A, D, FA, FD, fa,
                                                     fd, roots),
-             k_rank_roots_sum<<<1, 1024, 0, s>>>(roots, nblk, ctx->dctr)));
+             k_rank_roots_sum<<<1, 1024, 0, s>>>(roots, rgrid.x * rgrid.y,
+                                                 ctx->dctr)));
   MSC_TRY(read_counters(ctx, s));
   const uint64_t nmax = ctx->hctr[kCtrRootsMax], nmin = ctx->hctr[kCtrRootsMin];
   int64_t cells = -1;
