@@ -1100,9 +1100,16 @@ k_tile_pairs(const FieldDev *__restrict__ fds,
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz) {
     unsigned long long key = kEmptyKey;
-    if (lz < nz)
-      key = pair_key(decode_final<C>(s, code[lz] & 0xffffu, false),
-                     decode_final<C>(s, code[lz] >> 16, true));
+    if (lz < nz) {
+      // The final labels are written here, where the pass is bound by its
+      // arithmetic and the stores overlap it; the output pass then writes
+      // only the cell ids.
+      const int32_t a = decode_final<C>(s, code[lz] & 0xffffu, false);
+      const int32_t d = decode_final<C>(s, code[lz] >> 16, true);
+      plane_ptr(bt.fd.A, g, t.z0 + lz)[col] = a;
+      plane_ptr(bt.fd.D, g, t.z0 + lz)[col] = d;
+      key = pair_key(a, d);
+    }
     const unsigned long long left = __shfl_up(key, 1);
     const bool repeat = key == last || (!first_lane && key == left);
     last = key;
@@ -1178,8 +1185,10 @@ k_tile_write(const FieldDev *__restrict__ fds,
     if (in) {
       a = decode_final<C>(s, code[lz] & 0xffffu, false);
       d = decode_final<C>(s, code[lz] >> 16, true);
-      plane_ptr(A, g, t.z0 + lz)[col] = a;
-      plane_ptr(D, g, t.z0 + lz)[col] = d;
+      if (!ms) {  // with cells, the pair pass has written the labels
+        plane_ptr(A, g, t.z0 + lz)[col] = a;
+        plane_ptr(D, g, t.z0 + lz)[col] = d;
+      }
     }
     slot[lz] = -1;
     if (ms) {  // uniform over the block: ms belongs to the field
@@ -1452,7 +1461,7 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
     MSC_PHASE(ctx, s, "table_clear", 12.0 * total_cap,
               (k_table_clear<<<(unsigned)((total_cap + kBlock - 1) / kBlock),
                                kBlock, 0, s>>>(keys, vals, total_cap)));
-    MSC_PHASE(ctx, s, "tile_pairs", 4.0 * total_n,
+    MSC_PHASE(ctx, s, "tile_pairs", 12.0 * total_n,
               (k_tile_pairs<C><<<nt, C::kThreads, 0, s>>>(fds, tfield, seg,
                                                           next, ctr, tstat)));
     k_tile_stat_reduce<<<grid_for(nt), kBlock, 0, s>>>(tstat, 2, nt, tfield,
@@ -1475,7 +1484,7 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
                                                            kFCells);
     k_fill_u64<<<1, kBlock, 0, s>>>(ctr + kCtrOverflow, 1, 0ull);
   }
-  MSC_PHASE(ctx, s, "tile_write", (any_ms ? 16.0 : 12.0) * total_n,
+  MSC_PHASE(ctx, s, "tile_write", (any_ms ? 8.0 : 12.0) * total_n,
             (k_tile_write<C><<<nt, C::kThreads, 0, s>>>(fds, tfield, seg,
                                                         next)));
   MSC_TRY(read_counters(ctx, s));
