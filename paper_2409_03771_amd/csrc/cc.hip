@@ -991,31 +991,110 @@ constexpr uint32_t link_adj(int i) {
   return m;
 }
 
-struct LinkInfo {
-  uint32_t lower, upper;      // neighbour masks
-  uint32_t lext, uext;        // lowest / highest neighbour of each component
-  int lc, uc;                 // component counts
+// Components of the link restricted to a set of neighbours depend on the set
+// alone (the adjacency is fixed and absent neighbours are simply not in the
+// set), so two tables over all 2^14 sets replace the per-vertex growth: the
+// number of components, and the component that holds the set's lowest
+// neighbour.  Removing that component leaves a set whose components are the
+// remaining ones, so repeated lookups enumerate them.
+constexpr int kLinkSets = 1 << 14;
+
+__device__ __forceinline__ uint32_t grow_component(uint32_t seed,
+                                                   uint32_t set) {
+  uint32_t comp = seed, prev;
+  do {
+    prev = comp;
+    uint32_t g = comp;
+#pragma unroll
+    for (int i = 0; i < 14; ++i)
+      if ((prev >> i) & 1u) g |= link_adj(i);
+    comp = g & set;
+  } while (comp != prev);
+  return comp;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_link_tables(uint8_t *__restrict__ ncomp, uint16_t *__restrict__ first) {
+  const uint32_t set = blockIdx.x * kBlock + threadIdx.x;
+  if (set >= (uint32_t)kLinkSets) return;
+  uint32_t rem = set, head = 0;
+  int count = 0;
+  while (rem) {
+    const uint32_t comp = grow_component(rem & (0u - rem), rem);
+    if (!count) head = comp;
+    rem &= ~comp;
+    ++count;
+  }
+  ncomp[set] = (uint8_t)count;
+  first[set] = (uint16_t)head;
+}
+
+struct LinkSets {
+  float fn[14];          // neighbour values (meaningless where absent)
+  uint32_t lower, upper; // neighbours below / above v in the (f, id) order
   bool nan;
 };
 
-// Components of the neighbours in `mask`, and the (f, id)-extreme member of
-// each (the highest when `high`): neighbour order is id order, so a tie in
+// Requires X·Y·Z <= INT32_MAX (checked by the entry points), so ids and id
+// offsets fit 32 bits.
+__device__ __forceinline__ LinkSets link_sets(const float *__restrict__ f,
+                                              int64_t X, int64_t Y, int64_t Z,
+                                              int64_t v) {
+  const uint32_t vv = (uint32_t)v, X32 = (uint32_t)X, Y32 = (uint32_t)Y;
+  const uint32_t row = vv / X32;
+  const uint32_t x = vv - row * X32, y = row % Y32, z = row / Y32;
+  const int32_t sx = 1, sy = (int32_t)X32, sz = (int32_t)(X32 * Y32);
+  // Per axis, whether the step down / up stays in the grid; a step that
+  // would leave it is taken as 0, so every load below stays in bounds and
+  // the neighbour is marked absent.
+  const bool lo[3] = {x > 0, y > 0, z > 0};
+  const bool hi[3] = {x + 1 < X32, y + 1 < Y32, (int64_t)z + 1 < Z};
+  const int32_t step[3] = {sx, sy, sz};
+  const float *p = f + v;
+  const float fv = p[0];
+  LinkSets ls;
+  uint32_t present = 0;
+#pragma unroll
+  for (int i = 0; i < 14; ++i) {
+    const int d[3] = {kNb[i].dx, kNb[i].dy, kNb[i].dz};
+    int32_t off = 0;
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      if (d[a] < 0) {
+        in = in && lo[a];
+        off -= lo[a] ? step[a] : 0;
+      } else if (d[a] > 0) {
+        in = in && hi[a];
+        off += hi[a] ? step[a] : 0;
+      }
+    }
+    ls.fn[i] = p[off];
+    present |= (uint32_t)in << i;
+  }
+  ls.nan = fv != fv;
+  uint32_t lower = 0;
+#pragma unroll
+  for (int i = 0; i < 14; ++i) {
+    // the first 7 neighbours have smaller ids than v
+    const bool below = ls.fn[i] < fv || (ls.fn[i] == fv && i < 7);
+    lower |= (uint32_t)below << i;
+  }
+  ls.lower = lower & present;
+  ls.upper = present & ~lower;
+  return ls;
+}
+
+// The (f, id)-extreme neighbour of each component of `set` (the highest when
+// `high`), as a neighbour mask.  Neighbour order is id order, so a tie in
 // value goes to the larger index for the highest and the smaller for the
 // lowest.
-__device__ __forceinline__ int link_components(uint32_t mask, const float *fn,
-                                               bool high, uint32_t *ext) {
-  int count = 0;
-  uint32_t rem = mask, ex = 0;
+__device__ __forceinline__ uint32_t component_extremes(
+    uint32_t set, const float *fn, bool high,
+    const uint16_t *__restrict__ first) {
+  uint32_t rem = set, ex = 0;
   while (rem) {
-    uint32_t comp = rem & (0u - rem), prev;
-    do {
-      prev = comp;
-      uint32_t g = comp;
-#pragma unroll
-      for (int i = 0; i < 14; ++i)
-        if ((prev >> i) & 1u) g |= link_adj(i);
-      comp = g & mask;
-    } while (comp != prev);
+    const uint32_t comp = first[rem];
     int best = -1;
     float fb = 0.f;
 #pragma unroll
@@ -1029,58 +1108,27 @@ __device__ __forceinline__ int link_components(uint32_t mask, const float *fn,
     }
     ex |= 1u << best;
     rem &= ~comp;
-    ++count;
   }
-  *ext = ex;
-  return count;
-}
-
-__device__ __forceinline__ LinkInfo link_info(const float *__restrict__ f,
-                                              int64_t X, int64_t Y, int64_t Z,
-                                              int64_t v) {
-  const int64_t XY = X * Y;
-  const int64_t x = v % X, y = (v / X) % Y, z = v / XY;
-  const float fv = f[v];
-  float fn[14];
-  uint32_t present = 0;
-#pragma unroll
-  for (int i = 0; i < 14; ++i) {
-    const int64_t a = x + kNb[i].dx, b = y + kNb[i].dy, c = z + kNb[i].dz;
-    const bool in = a >= 0 && a < X && b >= 0 && b < Y && c >= 0 && c < Z;
-    fn[i] = in ? f[v + kNb[i].dx + X * kNb[i].dy + XY * kNb[i].dz] : 0.f;
-    present |= (uint32_t)in << i;
-  }
-  LinkInfo li;
-  li.nan = fv != fv;
-  li.lower = 0;
-#pragma unroll
-  for (int i = 0; i < 14; ++i) {
-    // below v in the (f, id) order; the first 7 neighbours have smaller ids
-    const bool below = fn[i] < fv || (fn[i] == fv && i < 7);
-    li.lower |= (uint32_t)below << i;
-  }
-  li.lower &= present;
-  li.upper = present & ~li.lower;
-  li.lc = link_components(li.lower, fn, false, &li.lext);
-  li.uc = link_components(li.upper, fn, true, &li.uext);
-  return li;
+  return ex;
 }
 
 __global__ void __launch_bounds__(kBlock)
 k_critical(const float *__restrict__ f, int64_t X, int64_t Y, int64_t Z,
-           uint8_t *__restrict__ code, unsigned long long *ctr) {
+           const uint8_t *__restrict__ ncomp, uint8_t *__restrict__ code,
+           unsigned long long *ctr) {
   const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   bool nan = false;
   if (v < X * Y * Z) {
-    const LinkInfo li = link_info(f, X, Y, Z, v);
-    code[v] = (uint8_t)(li.lc | (li.uc << 4));
-    nan = li.nan;
+    const LinkSets ls = link_sets(f, X, Y, Z, v);
+    code[v] = (uint8_t)(ncomp[ls.lower] | (ncomp[ls.upper] << 4));
+    nan = ls.nan;
   }
   flag_any(nan, ctr + kCtrNaN);
 }
 
-__device__ __forceinline__ uint32_t edge_count(const LinkInfo &li) {
-  return (li.uc >= 2 ? (uint32_t)li.uc : 0u) + (li.lc >= 2 ? (uint32_t)li.lc : 0u);
+// Edges of a vertex: one per component of a side that has two or more.
+__device__ __forceinline__ uint32_t edge_count(uint32_t lc, uint32_t uc) {
+  return (uc >= 2 ? uc : 0u) + (lc >= 2 ? lc : 0u);
 }
 
 // Exclusive prefix over a block of kBlock threads and the block total.
@@ -1111,15 +1159,16 @@ __device__ __forceinline__ uint32_t block_scan32(uint32_t x, uint32_t *tmp,
 
 __global__ void __launch_bounds__(kBlock)
 k_egraph_count(const float *__restrict__ f, int64_t X, int64_t Y, int64_t Z,
-               uint32_t *bcount, unsigned long long *ctr) {
+               const uint8_t *__restrict__ ncomp, uint32_t *bcount,
+               unsigned long long *ctr) {
   __shared__ uint32_t tmp[kBlock / 64 + 1];
   const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   uint32_t c = 0;
   bool nan = false;
   if (v < X * Y * Z) {
-    const LinkInfo li = link_info(f, X, Y, Z, v);
-    c = edge_count(li);
-    nan = li.nan;
+    const LinkSets ls = link_sets(f, X, Y, Z, v);
+    c = edge_count(ncomp[ls.lower], ncomp[ls.upper]);
+    nan = ls.nan;
   }
   flag_any(nan, ctr + kCtrNaN);
   uint32_t tot = 0;
@@ -1131,34 +1180,42 @@ k_egraph_count(const float *__restrict__ f, int64_t X, int64_t Y, int64_t Z,
 // components by increasing id of their extreme vertex (= neighbour order).
 __global__ void __launch_bounds__(kBlock)
 k_egraph_write(const float *__restrict__ f, int64_t X, int64_t Y, int64_t Z,
+               const uint8_t *__restrict__ ncomp,
+               const uint16_t *__restrict__ first,
                const int32_t *__restrict__ asc,
                const int32_t *__restrict__ desc,
                const int64_t *__restrict__ boff, int32_t *__restrict__ out) {
   __shared__ uint32_t tmp[kBlock / 64 + 1];
+  // A block without edges has nothing to write (the scan is block-local).
+  if (boff[blockIdx.x + 1] == boff[blockIdx.x]) return;
   const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int64_t XY = X * Y;
-  LinkInfo li{};
-  uint32_t c = 0;
+  LinkSets ls{};
+  uint32_t lc = 0, uc = 0;
   if (v < X * Y * Z) {
-    li = link_info(f, X, Y, Z, v);
-    c = edge_count(li);
+    ls = link_sets(f, X, Y, Z, v);
+    lc = ncomp[ls.lower];
+    uc = ncomp[ls.upper];
   }
+  const uint32_t c = edge_count(lc, uc);
   uint32_t tot = 0;
   const uint32_t ex = block_scan32(c, tmp, &tot);
   if (!c) return;
   int64_t at = boff[blockIdx.x] + ex;
 #pragma unroll
   for (int side = 0; side < 2; ++side) {
-    const uint32_t m = side == 0 ? (li.uc >= 2 ? li.uext : 0u)
-                                 : (li.lc >= 2 ? li.lext : 0u);
+    const bool high = side == 0;
+    const uint32_t set = high ? (uc >= 2 ? ls.upper : 0u)
+                              : (lc >= 2 ? ls.lower : 0u);
+    const uint32_t m = component_extremes(set, ls.fn, high, first);
 #pragma unroll
     for (int i = 0; i < 14; ++i) {
       if (!((m >> i) & 1u)) continue;
       const int64_t u = v + kNb[i].dx + (int64_t)X * kNb[i].dy +
                         XY * kNb[i].dz;
       out[3 * at] = (int32_t)v;
-      out[3 * at + 1] = side == 0 ? asc[u] : desc[u];
-      out[3 * at + 2] = side == 0 ? 1 : -1;
+      out[3 * at + 1] = high ? asc[u] : desc[u];
+      out[3 * at + 2] = high ? 1 : -1;
       ++at;
     }
   }
@@ -1169,11 +1226,17 @@ k_egraph_write(const float *__restrict__ f, int64_t X, int64_t Y, int64_t Z,
 int critical_points_run(msc_ctx *ctx, const float *field, const int64_t *dims,
                         uint8_t *code, hipStream_t s) {
   const int64_t X = dims[0], Y = dims[1], Z = dims[2], N = X * Y * Z;
+  MSC_TRY(reserve(ctx->ws, align256(kLinkSets) + align256(2 * kLinkSets)));
+  Carver cv(ctx->ws);
+  uint8_t *ncomp = cv.take<uint8_t>(kLinkSets);
+  uint16_t *first = cv.take<uint16_t>(kLinkSets);
   MSC_TRY(clear_counters(ctx, s));
+  MSC_PHASE(ctx, s, "link_tables", 3.0 * kLinkSets,
+            (k_link_tables<<<kLinkSets / kBlock, kBlock, 0, s>>>(ncomp,
+                                                                first)));
   MSC_PHASE(ctx, s, "critical", 5.0 * N,
-            (k_critical<<<grid64(N, kBlock), kBlock, 0, s>>>(field, X, Y, Z,
-                                                             code,
-                                                             ctx->dctr)));
+            (k_critical<<<grid64(N, kBlock), kBlock, 0, s>>>(
+                field, X, Y, Z, ncomp, code, ctx->dctr)));
   MSC_TRY(read_counters(ctx, s));
   if (ctx->hctr[kCtrNaN]) return MSC_ENAN;
   ctx->stats = msc_stats{};
@@ -1188,16 +1251,21 @@ int extremum_graph_run(msc_ctx *ctx, const float *field, const int64_t *dims,
   const int64_t nb = (N + kBlock - 1) / kBlock;
   const int64_t nsb = (nb + kScan - 1) / kScan;
   MSC_TRY(reserve(ctx->ws, align256(nb * 4) + align256((nb + 1) * 8) +
-                               align256(nsb * 8 + 8) + 4096));
+                               align256(nsb * 8 + 8) + align256(kLinkSets) +
+                               align256(2 * kLinkSets) + 4096));
   Carver cv(ctx->ws);
   uint32_t *bcount = cv.take<uint32_t>(nb);
   int64_t *boff = cv.take<int64_t>(nb + 1);
   uint64_t *bsum = cv.take<uint64_t>(nsb + 1);
+  uint8_t *ncomp = cv.take<uint8_t>(kLinkSets);
+  uint16_t *first = cv.take<uint16_t>(kLinkSets);
   MSC_TRY(clear_counters(ctx, s));
+  MSC_PHASE(ctx, s, "link_tables", 3.0 * kLinkSets,
+            (k_link_tables<<<kLinkSets / kBlock, kBlock, 0, s>>>(ncomp,
+                                                                first)));
   MSC_PHASE(ctx, s, "egraph_count", 4.0 * N,
-            (k_egraph_count<<<(unsigned)nb, kBlock, 0, s>>>(field, X, Y, Z,
-                                                            bcount,
-                                                            ctx->dctr),
+            (k_egraph_count<<<(unsigned)nb, kBlock, 0, s>>>(
+                 field, X, Y, Z, ncomp, bcount, ctx->dctr),
              scan64(ctx, bcount, nb, boff, bsum, s)));
   int64_t total = 0;
   MSC_HIP_TRY(hipMemcpyAsync(&total, boff + nb, sizeof(int64_t),
@@ -1208,7 +1276,7 @@ int extremum_graph_run(msc_ctx *ctx, const float *field, const int64_t *dims,
   if (edges && capacity >= total && total > 0)
     MSC_PHASE(ctx, s, "egraph_write", 4.0 * N + 12.0 * total,
               (k_egraph_write<<<(unsigned)nb, kBlock, 0, s>>>(
-                  field, X, Y, Z, asc, desc, boff, edges)));
+                  field, X, Y, Z, ncomp, first, asc, desc, boff, edges)));
   MSC_TRY(read_counters(ctx, s));
   ctx->stats = msc_stats{};
   ctx->stats.n_vertices = N;
