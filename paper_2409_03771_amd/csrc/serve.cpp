@@ -137,6 +137,13 @@ namespace {
 // device.
 constexpr int64_t kMaxBatchVertices = 64ll << 20;
 
+// At most this many requests are staged (copy issued) and not yet taken by
+// a worker. Copies issued far ahead of the workers share the link with the
+// ones a worker waits for, so under overload every request's copy finishes
+// late; a short window keeps the link on the requests next in line and
+// still keeps it busy while a launch runs.
+constexpr size_t kMaxStaged = 8;
+
 size_t workspace_bytes(int kind, int64_t n) {
   if (kind == MSC_REQ_SEGMENT) return (size_t)n * 8 + (1 << 20);
   return (size_t)n * 2 + (1 << 20);
@@ -148,6 +155,7 @@ void dispatcher_loop(msc_queue *q) {
   while (!q->stop) {
     bool progress = false;
     while (!q->pending.empty()) {
+      if (q->ready_seg.size() + q->ready_cc.size() >= kMaxStaged) break;
       Request *r = q->pending.front();
       const size_t need = r->in_bytes + r->out_bytes;
       if (q->alloc.used() + round256(need) + q->inflight_ws + r->ws_bytes >
@@ -235,6 +243,7 @@ void worker_loop(msc_queue *q, int kind) {
       batch.push_back(r);
     }
     for (Request *r : batch) r->batch = (int)batch.size();
+    q->cv.notify_all();  // the staging window has room again
     lk.unlock();
     std::vector<int> rc(batch.size(), MSC_OK);
     for (Request *r : batch)
