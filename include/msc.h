@@ -385,12 +385,14 @@ MSC_API int msc_pointer_jump(msc_ctx *ctx, int64_t *d, int64_t n, int rounds,
  * stay within the budget.  That workspace is held by the queue's two
  * library contexts outside the arena; it grows to the largest launch and is
  * kept until msc_queue_destroy.  Admitted inputs are copied to the device
- * on a copy stream; segmentation requests that are staged while a launch is
- * running join the next launch (one msc_segment_batched call of at most
- * `max_batch` fields and, unless a single request is larger, at most 2^26
- * vertices, since a launch's requests all complete together), and mask-CC
- * requests run on their own stream, so the
- * two kinds overlap on the device.  Results stay on the device until
+ * on a copy stream, at most 8 requests ahead of the launches (copies issued
+ * further ahead would share the host link with the ones a launch waits
+ * for); a request beyond that window waits unadmitted.  Segmentation
+ * requests that are staged while a launch is running join the next launch
+ * (one msc_segment_batched call of at most `max_batch` fields and, unless a
+ * single request is larger, at most 2^26 vertices, since a launch's requests
+ * all complete together), and mask-CC requests run on their own stream, so
+ * the two kinds overlap on the device.  Results stay on the device until
  * msc_release; a finished request that is never released keeps its arena
  * space, so the requests behind it wait.  Every call is thread-safe.  A
  * request that fails (e.g. NaN in its field) fails alone: its batch is rerun
