@@ -32,6 +32,10 @@ WORKLOAD_TEXT = {
                  "noise, frequency 0.1, amplitude 1, seed 5",
     "perlin1024": "perlin1024: 1024^3 float32, one layer of Perlin gradient "
                   "noise, frequency 0.1, amplitude 1, seed 5",
+    "perlin2048s": "perlin2048s: 2048x2048x256 float32, z-planes [0, 256) of "
+                   "the 2048^3 one-layer Perlin field (frequency 0.1, "
+                   "amplitude 1, seed 5): one GPU's share of an 8-way z-slab "
+                   "split",
 }
 
 # The paper's one-node times (seconds; 12 cores of an Intel Xeon Gold 6126)

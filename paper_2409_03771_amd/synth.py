@@ -174,13 +174,20 @@ WORKLOADS = {
     "gauss1024": ("gauss", (1024, 1024, 1024), 512, 1),
     "perlin512": ("perlin", (512, 512, 512), 0, 5),
     "perlin1024": ("perlin", (1024, 1024, 1024), 0, 5),
+    # z-planes [0, 256) of the 2048^3 Perlin field: one GPU's share when the
+    # 2048^3 field is split into eight z-slabs (its 2^33 ids do not fit the
+    # int32 labels of a single call).
+    "perlin2048s": ("perlin", (2048, 2048, 256), 0, 5),
 }
 
 
 def config_field(name: str, device=None):
     """The named single-field workloads: "gauss64" (64^3, 8 bumps, seed 0),
     "gauss1024" (1024^3, 512 bumps, seed 1), and one-layer Perlin noise at
-    frequency 0.1 and amplitude 1, "perlin512" and "perlin1024" (seed 5)."""
+    frequency 0.1 and amplitude 1, "perlin512" and "perlin1024" (seed 5),
+    and "perlin2048s", the first of eight 2048x2048x256 z-slabs of the
+    2048^3 field (the noise at a point does not depend on the grid's
+    extent, so the slab is the field generated at its own dims)."""
     alias = {"c1": "gauss64", "c2": "gauss1024"}
     kind, dims, nb, seed = WORKLOADS[alias.get(name, name)]
     if kind == "perlin":

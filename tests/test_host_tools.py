@@ -84,8 +84,9 @@ def test_bench_refuses_more_than_one_gpu():
 
 def test_perlin_generator_properties():
     """Perlin noise vanishes at lattice points, stays within the bound of
-    the twelve-gradient noise (|n| <= 1), does not depend on the z chunking,
-    and its normalised masks nest (0.9 within 0.5 within 0.1)."""
+    the twelve-gradient noise (|n| <= 1), does not depend on the z chunking
+    or on the grid's extent, and its normalised masks nest (0.9 within 0.5
+    within 0.1)."""
     import numpy as np
     from paper_2409_03771_amd import synth
     f = synth.perlin_field((33, 25, 17), seed=5, frequency=0.125)
@@ -95,6 +96,10 @@ def test_perlin_generator_properties():
     h = synth.perlin_field((40, 30, 20), seed=5, z_chunk=3)
     assert np.array_equal(g, h)
     assert not np.array_equal(g, synth.perlin_field((40, 30, 20), seed=6))
+    # The value at a point does not depend on the grid's extent, so a field
+    # generated at a slab's dims is that slab of the larger field.
+    assert np.array_equal(synth.perlin_field((23, 17, 9), seed=5),
+                          g[:9, :17, :23])
     m9, m5, m1 = (synth.normalized_mask(g, t) for t in (0.9, 0.5, 0.1))
     assert np.all(m9 <= m5) and np.all(m5 <= m1)
     assert 0 < m9.sum() < m5.sum() < m1.sum() < g.size
