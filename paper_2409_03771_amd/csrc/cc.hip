@@ -1131,37 +1131,41 @@ __device__ __forceinline__ uint32_t edge_count(uint32_t lc, uint32_t uc) {
   return (uc >= 2 ? uc : 0u) + (lc >= 2 ? lc : 0u);
 }
 
-// Exclusive prefix over a block of kBlock threads and the block total.
-__device__ __forceinline__ uint32_t block_scan32(uint32_t x, uint32_t *tmp,
+// Exclusive prefix over a block of kBlock threads and the block total, for
+// per-thread counts below 16 (a vertex has at most 14 edges: its lower and
+// upper link components together number at most its 14 link vertices).  One
+// ballot per bit: a lane's prefix in its wave is the sum over bits k of 2^k
+// times the number of lower lanes with bit k set.
+__device__ __forceinline__ uint32_t block_scan16(uint32_t x, uint32_t *tmp,
                                                  uint32_t *total) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  uint32_t inc = x;
-  for (int o = 1; o < 64; o <<= 1) {
-    const uint32_t y = __shfl_up(inc, o);
-    if (lane >= o) inc += y;
+  const int w = threadIdx.x >> 6;
+  uint32_t pre = 0, sum = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const unsigned long long b = __ballot((x >> k) & 1u);
+    const uint32_t below = __builtin_amdgcn_mbcnt_hi(
+        (uint32_t)(b >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)b, 0u));
+    pre += below << k;
+    sum += (uint32_t)__popcll(b) << k;
   }
-  if (lane == 63) tmp[w] = inc;
+  if ((threadIdx.x & 63) == 0) tmp[w] = sum;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    uint32_t run = 0;
-    for (int k = 0; k < kBlock / 64; ++k) {
-      const uint32_t t = tmp[k];
-      tmp[k] = run;
-      run += t;
-    }
-    tmp[kBlock / 64] = run;
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (int k = 0; k < kBlock / 64; ++k) {
+    const uint32_t t = tmp[k];
+    before += k < w ? t : 0u;
+    all += t;
   }
-  __syncthreads();
-  const uint32_t ex = inc - x + tmp[w];
-  *total = tmp[kBlock / 64];
-  return ex;
+  *total = all;
+  return before + pre;
 }
 
 __global__ void __launch_bounds__(kBlock)
 k_egraph_count(const float *__restrict__ f, int64_t X, int64_t Y, int64_t Z,
                const uint8_t *__restrict__ ncomp, uint32_t *bcount,
                unsigned long long *ctr) {
-  __shared__ uint32_t tmp[kBlock / 64 + 1];
+  __shared__ uint32_t tmp[kBlock / 64];
   const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   uint32_t c = 0;
   bool nan = false;
@@ -1172,7 +1176,7 @@ k_egraph_count(const float *__restrict__ f, int64_t X, int64_t Y, int64_t Z,
   }
   flag_any(nan, ctr + kCtrNaN);
   uint32_t tot = 0;
-  (void)block_scan32(c, tmp, &tot);
+  (void)block_scan16(c, tmp, &tot);
   if (threadIdx.x == 0) bcount[blockIdx.x] = tot;
 }
 
@@ -1185,7 +1189,7 @@ k_egraph_write(const float *__restrict__ f, int64_t X, int64_t Y, int64_t Z,
                const int32_t *__restrict__ asc,
                const int32_t *__restrict__ desc,
                const int64_t *__restrict__ boff, int32_t *__restrict__ out) {
-  __shared__ uint32_t tmp[kBlock / 64 + 1];
+  __shared__ uint32_t tmp[kBlock / 64];
   // A block without edges has nothing to write (the scan is block-local).
   if (boff[blockIdx.x + 1] == boff[blockIdx.x]) return;
   const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
@@ -1199,7 +1203,7 @@ k_egraph_write(const float *__restrict__ f, int64_t X, int64_t Y, int64_t Z,
   }
   const uint32_t c = edge_count(lc, uc);
   uint32_t tot = 0;
-  const uint32_t ex = block_scan32(c, tmp, &tot);
+  const uint32_t ex = block_scan16(c, tmp, &tot);
   if (!c) return;
   int64_t at = boff[blockIdx.x] + ex;
 #pragma unroll
