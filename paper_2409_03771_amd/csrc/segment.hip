@@ -1769,6 +1769,153 @@ k_rank_ms(uint64_t n, const int32_t *__restrict__ asc,
   }
 }
 
+// Cells over the final labels of a grid, per tile of kRankTX x kRankTY
+// columns of kRankTZ vertices, with the tile passes' dedupe: a vertex whose
+// pair equals that of the previous z of its column or of the lane before it
+// (both smaller ids) is not its pair's smallest id and inserts nothing; the
+// others go through a per-tile table of distinct pairs, so the global insert
+// and the cell lookup run about once per pair and tile.  Requires
+// X*Y*Z <= INT32_MAX.
+constexpr uint32_t kRankTX = 32, kRankTY = kBlock / kRankTX, kRankTZ = 16;
+
+__host__ __device__ inline uint32_t rank_tiles(uint32_t X, uint32_t Y,
+                                               uint32_t Z) {
+  return ((X + kRankTX - 1) / kRankTX) * ((Y + kRankTY - 1) / kRankTY) *
+         ((Z + kRankTZ - 1) / kRankTZ);
+}
+
+struct RankCol {
+  uint32_t col, z0, nz;  // column offset in its plane, first z, its height
+};
+
+__device__ __forceinline__ RankCol rank_col(uint32_t X, uint32_t Y,
+                                            uint32_t Z) {
+  const uint32_t ntx = (X + kRankTX - 1) / kRankTX;
+  const uint32_t nty = (Y + kRankTY - 1) / kRankTY;
+  const uint32_t tx = blockIdx.x % ntx, r = blockIdx.x / ntx;
+  const uint32_t gx = tx * kRankTX + threadIdx.x % kRankTX;
+  const uint32_t gy = (r % nty) * kRankTY + threadIdx.x / kRankTX;
+  RankCol c;
+  c.z0 = (r / nty) * kRankTZ;
+  c.col = gx + X * gy;
+  const uint32_t h = Z - c.z0;
+  c.nz = gx < X && gy < Y ? (h < kRankTZ ? h : kRankTZ) : 0u;
+  return c;
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_rank_tile_pairs(uint32_t X, uint32_t Y, uint32_t Z,
+                  const int32_t *__restrict__ asc,
+                  const int32_t *__restrict__ desc, unsigned long long *keys,
+                  int32_t *vals, uint32_t mask, unsigned long long *ctr) {
+  __shared__ unsigned long long skey[kPairSlots];
+  __shared__ int32_t sval[kPairSlots];
+  __shared__ unsigned sfill;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kPairSlots; i += kBlock) {
+    skey[i] = kEmptyKey;
+    sval[i] = INT32_MAX;
+  }
+  if (tid == 0) sfill = 0;
+  __syncthreads();
+  const RankCol c = rank_col(X, Y, Z);
+  const uint32_t XY = X * Y;
+  unsigned fresh = 0;
+  bool overflow = false;
+  const bool first_lane = (tid & 63) == 0;
+  unsigned long long last = kEmptyKey;
+#pragma unroll
+  for (uint32_t lz = 0; lz < kRankTZ; ++lz) {
+    unsigned long long key = kEmptyKey;
+    const uint32_t v = c.col + XY * (c.z0 + lz);
+    if (lz < c.nz) key = pair_key(asc[v], desc[v]);
+    const unsigned long long left = __shfl_up(key, 1);
+    const bool repeat = key == last || (!first_lane && key == left);
+    last = key;
+    if (!repeat && key != kEmptyKey) {
+      const int slot = pair_slot(skey, &sfill, key);
+      if (slot >= 0)
+        atomicMin(&sval[slot], (int32_t)v);
+      else if (!table_insert(keys, vals, mask, key, (int32_t)v, &fresh))
+        overflow = true;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < kPairSlots; i += kBlock)
+    if (skey[i] != kEmptyKey &&
+        !table_insert(keys, vals, mask, skey[i], sval[i], &fresh))
+      overflow = true;
+  if (overflow) atomicOr(ctr + kCtrOverflow, 1ull);
+}
+
+// Cell ids over the same tiles, and per tile the number of vertices that
+// are their own cell id (one per cell).
+__global__ void __launch_bounds__(kBlock)
+k_rank_tile_ms(uint32_t X, uint32_t Y, uint32_t Z,
+               const int32_t *__restrict__ asc,
+               const int32_t *__restrict__ desc,
+               const unsigned long long *__restrict__ keys,
+               const int32_t *__restrict__ vals, uint32_t mask,
+               int32_t *__restrict__ ms, uint32_t *__restrict__ counts) {
+  __shared__ unsigned long long skey[kPairSlots];
+  __shared__ int32_t scell[kPairSlots];
+  __shared__ unsigned sfill;
+  __shared__ uint32_t s_cnt;
+  const int tid = threadIdx.x;
+  for (int i = tid; i < kPairSlots; i += kBlock) skey[i] = kEmptyKey;
+  if (tid == 0) {
+    sfill = 0;
+    s_cnt = 0;
+  }
+  __syncthreads();
+  const RankCol c = rank_col(X, Y, Z);
+  const uint32_t XY = X * Y;
+  int16_t slot[kRankTZ];
+  unsigned long long last = kEmptyKey;
+  int last_slot = -1;
+  int32_t last_cell = -1;
+  uint32_t own = 0;
+#pragma unroll
+  for (uint32_t lz = 0; lz < kRankTZ; ++lz) {
+    slot[lz] = -1;
+    if (lz < c.nz) {
+      const uint32_t v = c.col + XY * (c.z0 + lz);
+      const unsigned long long key = pair_key(asc[v], desc[v]);
+      if (key != last) {
+        last = key;
+        last_slot = pair_slot(skey, &sfill, key);
+        if (last_slot < 0)  // not in the tile's table: look this pair up alone
+          last_cell = table_lookup(keys, vals, mask, key);
+      }
+      slot[lz] = (int16_t)last_slot;
+      if (last_slot < 0) {
+        ms[v] = last_cell;
+        own += (uint32_t)last_cell == v;
+      }
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < kPairSlots; i += kBlock)
+    if (skey[i] != kEmptyKey) scell[i] = table_lookup(keys, vals, mask, skey[i]);
+  __syncthreads();
+#pragma unroll
+  for (uint32_t lz = 0; lz < kRankTZ; ++lz) {
+    if (lz < c.nz && slot[lz] >= 0) {
+      const uint32_t v = c.col + XY * (c.z0 + lz);
+      const int32_t cell = scell[slot[lz]];
+      ms[v] = cell;
+      own += (uint32_t)cell == v;
+    }
+  }
+  for (int o = 32; o > 0; o >>= 1) own += __shfl_xor(own, o);
+  if ((tid & 63) == 0 && own) atomicAdd(&s_cnt, own);
+  __syncthreads();
+  if (tid == 0) {
+    counts[2 * blockIdx.x] = s_cnt;
+    counts[2 * blockIdx.x + 1] = 0;
+  }
+}
+
 template <class C>
 int segment_ranks(msc_ctx *ctx, const float *field, const int64_t dims[3],
                   int ranks, int32_t *asc, int32_t *desc, int32_t *ms,
@@ -1791,11 +1938,11 @@ int segment_ranks(msc_ctx *ctx, const float *field, const int64_t dims[3],
     ghost[r] = (uint8_t)((r > 0 ? 1 : 0) | (r + 1 < R ? 2 : 0));
   }
   const uint64_t nodes = 2ull * R * XY;
-  const uint32_t nblk = (uint32_t)((N + kBlock - 1) / kBlock);
   const dim3 rgrid((unsigned)((XY + kBlock - 1) / kBlock),
                    Z < 65535u ? Z : 65535u);
-  // per-block root counts: for the per-vertex passes and for the relabel grid
-  const uint64_t nroot = std::max<uint64_t>(nblk, (uint64_t)rgrid.x * rgrid.y);
+  const uint32_t ntile = rank_tiles(X, Y, Z);
+  // per-block root counts: for the cell tiles and for the relabel grid
+  const uint64_t nroot = std::max<uint64_t>(ntile, (uint64_t)rgrid.x * rgrid.y);
   MSC_TRY(reserve(ctx->rk, 2 * align256(total * 4) + 4 * align256(nodes * 4) +
                                align256(R * sizeof(SlabDev)) +
                                2 * align256(N * 4) + align256(nroot * 8ull) +
@@ -1852,14 +1999,14 @@ int segment_ranks(msc_ctx *ctx, const float *field, const int64_t dims[3],
     MSC_PHASE(ctx, s, "rank_pairs", 12.0 * N,
               (k_table_clear<<<(unsigned)((cap + kBlock - 1) / kBlock), kBlock,
                                0, s>>>(keys, vals, cap),
-               k_rank_pairs<<<nblk, kBlock, 0, s>>>(N, fa, fd, keys, vals,
-                                                    (uint32_t)(cap - 1),
-                                                    ctx->dctr)));
+               k_rank_tile_pairs<<<ntile, kBlock, 0, s>>>(
+                   X, Y, Z, fa, fd, keys, vals, (uint32_t)(cap - 1),
+                   ctx->dctr)));
     MSC_PHASE(ctx, s, "rank_ms", 12.0 * N,
-              (k_rank_ms<<<nblk, kBlock, 0, s>>>(N, fa, fd, keys, vals,
-                                                 (uint32_t)(cap - 1), ms,
-                                                 roots),
-               k_rank_roots_sum<<<1, 1024, 0, s>>>(roots, nblk, ctx->dctr)));
+              (k_rank_tile_ms<<<ntile, kBlock, 0, s>>>(
+                   X, Y, Z, fa, fd, keys, vals, (uint32_t)(cap - 1), ms,
+                   roots),
+               k_rank_roots_sum<<<1, 1024, 0, s>>>(roots, ntile, ctx->dctr)));
     MSC_TRY(read_counters(ctx, s));
     if (ctx->hctr[kCtrOverflow]) return MSC_ENOMEM;
     cells = (int64_t)ctx->hctr[kCtrRootsMax];
