@@ -1642,9 +1642,13 @@ k_rank_ghost_resolve(RankGeo g, const SlabDev *__restrict__ slabs,
 
 // Final labels: a slab result that is a ghost takes the ghost's resolved
 // value.  Also counts the vertices that are their own labels (extrema).
-// Grid: x over the plane's XY vertices, y over planes (strided), so a
-// block's slab is uniform and a slab-local label is recognised as a ghost by
-// its plane alone (first plane or last), without a division.
+// Grid: x over the plane's XY vertices, y over planes (strided by at most
+// kRelabelPlanes, so that a block covers several planes and its fixed cost
+// is shared), so a block's slab is uniform at each plane and a slab-local
+// label is recognised as a ghost by its plane alone (first plane or last),
+// without a division.
+constexpr uint32_t kRelabelPlanes = 64;
+
 __global__ void __launch_bounds__(kBlock)
 k_rank_relabel(RankGeo g, const SlabDev *__restrict__ slabs,
                const int32_t *__restrict__ A, const int32_t *__restrict__ D,
@@ -1656,9 +1660,10 @@ k_rank_relabel(RankGeo g, const SlabDev *__restrict__ slabs,
   __syncthreads();
   const uint32_t xy = blockIdx.x * kBlock + threadIdx.x;
   uint32_t cmax = 0, cmin = 0;
+  // The slab of the first plane, then advanced as z grows.
+  uint32_t r = (uint32_t)(((uint64_t)blockIdx.y * g.R) / g.Z);
+  while (r > 0 && slabs[r].z0 > blockIdx.y) --r;
   for (uint32_t z = blockIdx.y; z < g.Z; z += gridDim.y) {
-    uint32_t r = (uint32_t)(((uint64_t)z * g.R) / g.Z);
-    while (r > 0 && slabs[r].z0 > z) --r;
     while (r + 1 < g.R && slabs[r + 1].z0 <= z) ++r;
     const SlabDev sl = slabs[r];
     if (xy >= g.XY) continue;
@@ -1939,7 +1944,7 @@ int segment_ranks(msc_ctx *ctx, const float *field, const int64_t dims[3],
   }
   const uint64_t nodes = 2ull * R * XY;
   const dim3 rgrid((unsigned)((XY + kBlock - 1) / kBlock),
-                   Z < 65535u ? Z : 65535u);
+                   Z < kRelabelPlanes ? Z : kRelabelPlanes);
   const uint32_t ntile = rank_tiles(X, Y, Z);
   // per-block root counts: for the cell tiles and for the relabel grid
   const uint64_t nroot = std::max<uint64_t>(ntile, (uint64_t)rgrid.x * rgrid.y);
