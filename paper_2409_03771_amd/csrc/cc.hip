@@ -621,33 +621,39 @@ k_rank_cc_shift(int64_t *L, int64_t n, int64_t off) {
 // (x, y, zb) -- (x + dx, y + dy, zb + 1) for dx, dy in {0, 1}, joins the
 // two endpoints' trees when both are in the mask.  L is the parent array:
 // every label is a root of its slab's forest, and the smaller root wins.
+// All R - 1 boundaries in one launch (grid y strides over them): unions are
+// safe to run concurrently, and the boundaries' latency-bound root walks
+// overlap.
 __global__ void __launch_bounds__(kBlock)
 k_rank_cc_stitch(const uint8_t *__restrict__ mask, int64_t X, int64_t Y,
-                 int64_t zb, int64_t *L) {
+                 int64_t Z, int64_t R, int64_t *L) {
   const int64_t XY = X * Y;
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const bool in = i < XY;
   const int64_t x = in ? i % X : 0, y = in ? i / X : 0;
-  const int64_t u = i + XY * zb;
-  const bool mu = in && mask[u];
-  // The slab labels of both ends, joined once per distinct pair in a run
-  // of lanes: neighbouring vertices mostly carry the same two labels, and
-  // letting every lane unite them would pile compare-and-swaps onto the
-  // same root.
+  for (int64_t r = 1 + blockIdx.y; r < R; r += gridDim.y) {
+    const int64_t zb = r * Z / R - 1;
+    const int64_t u = i + XY * zb;
+    const bool mu = in && mask[u];
+    // The slab labels of both ends, joined once per distinct pair in a run
+    // of lanes: neighbouring vertices mostly carry the same two labels, and
+    // letting every lane unite them would pile compare-and-swaps onto the
+    // same root.
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const int dx = e & 1, dy = e >> 1;
-    int64_t a = -1, b = -1;
-    if (mu && x + dx < X && y + dy < Y) {
-      const int64_t w = u + XY + dx + X * dy;
-      if (mask[w]) {
-        a = L[u];
-        b = L[w];
+    for (int e = 0; e < 4; ++e) {
+      const int dx = e & 1, dy = e >> 1;
+      int64_t a = -1, b = -1;
+      if (mu && x + dx < X && y + dy < Y) {
+        const int64_t w = u + XY + dx + X * dy;
+        if (mask[w]) {
+          a = L[u];
+          b = L[w];
+        }
       }
+      const int64_t pa = __shfl_up(a, 1), pb = __shfl_up(b, 1);
+      const bool first = (threadIdx.x & 63) == 0 || pa != a || pb != b;
+      if (a >= 0 && a != b && first) uf_unite<int64_t>(L, a, b);
     }
-    const int64_t pa = __shfl_up(a, 1), pb = __shfl_up(b, 1);
-    const bool first = (threadIdx.x & 63) == 0 || pa != a || pb != b;
-    if (a >= 0 && a != b && first) uf_unite<int64_t>(L, a, b);
   }
 }
 
@@ -683,11 +689,11 @@ int cc_grid_ranks_run(msc_ctx *ctx, const uint8_t *mask, int64_t X,
                 (k_rank_cc_shift<<<blocks_for(XY * (z1 - z0)), kBlock, 0, s>>>(
                     labels + XY * z0, XY * (z1 - z0), XY * z0)));
   }
-  for (int r = 1; r < ranks; ++r) {
-    const int64_t zb = r * Z / ranks - 1;
-    MSC_PHASE(ctx, s, "rank_cc_stitch", 2.0 * XY,
-              (k_rank_cc_stitch<<<blocks_for(XY), kBlock, 0, s>>>(mask, X, Y,
-                                                                  zb, labels)));
+  if (ranks > 1) {
+    const unsigned by = ranks - 1 < 65535 ? (unsigned)(ranks - 1) : 65535u;
+    MSC_PHASE(ctx, s, "rank_cc_stitch", 2.0 * XY * (ranks - 1),
+              (k_rank_cc_stitch<<<dim3(blocks_for(XY), by), kBlock, 0, s>>>(
+                  mask, X, Y, Z, ranks, labels)));
   }
   if (ranks > 1)
     MSC_PHASE(ctx, s, "rank_cc_final", 16.0 * N,
