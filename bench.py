@@ -723,8 +723,13 @@ def main():
     roofline = roofline_of(prof, args.workload, tile)
 
     vs, ref = paper_reference(args.workload, n, value)
+    # The headline metric names the 1024^3 shape; other shapes name theirs.
+    dims = tuple(field.shape[::-1])
+    metric = METRIC if dims == (1024, 1024, 1024) else (
+        "Gvertices/s MS segmentation @%dx%dx%d f32 (vs plain); served "
+        "p50/p99 latency" % dims)
     out = {
-        "metric": METRIC, "value": round(value, 3), "unit": "Gvertices/s",
+        "metric": metric, "value": round(value, 3), "unit": "Gvertices/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": vs, "dtype": "f32",
