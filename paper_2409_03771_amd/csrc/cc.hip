@@ -329,8 +329,12 @@ k_cc_cross(CGeo g, const uint16_t *__restrict__ loc, int64_t *L) {
   }
 }
 
+// Every vertex's final label, plus `off` (a slab labelled inside a larger
+// grid writes global ids).  The tile-local roots keep the unshifted root
+// here, since concurrent walks read their entries as indices; k_cc_root_shift
+// adds the offset to them afterwards.
 __global__ void __launch_bounds__(kCThreads)
-k_cc_final(CGeo g, const uint16_t *__restrict__ loc, int64_t *L) {
+k_cc_final(CGeo g, const uint16_t *__restrict__ loc, int64_t *L, int64_t off) {
   const int tid = threadIdx.x;
   const CTile t = ctile_at(g, cc_tile_of_block(blockIdx.x, gridDim.x));
   const int cx = tid % CTX, cy = tid / CTX;
@@ -350,7 +354,26 @@ k_cc_final(CGeo g, const uint16_t *__restrict__ loc, int64_t *L) {
       last = s;
       last_out = uf_root<int64_t>(L, ctile_global(g, t, s));
     }
-    __atomic_store_n(&L[v], s == kOutside ? -1 : last_out, __ATOMIC_RELAXED);
+    const bool root = s == cx + CTX * (cy + CTY * lz);
+    __atomic_store_n(&L[v],
+                     s == kOutside ? -1 : last_out + (root ? 0 : off),
+                     __ATOMIC_RELAXED);
+  }
+}
+
+// The tile-local roots' labels take the offset once no walk is in flight.
+__global__ void __launch_bounds__(kCThreads)
+k_cc_root_shift(CGeo g, const uint16_t *__restrict__ loc, int64_t *L,
+                int64_t off) {
+  const int tid = threadIdx.x;
+  const CTile t = ctile_at(g, cc_tile_of_block(blockIdx.x, gridDim.x));
+  const int cx = tid % CTX, cy = tid / CTX;
+  const int64_t gx = t.x0 + cx, gy = t.y0 + cy;
+  if (gx >= g.X || gy >= g.Y) return;
+  int nz = (int)((g.Z - t.z0) < CTZ ? (g.Z - t.z0) : CTZ);
+  for (int lz = 0; lz < nz; ++lz) {
+    const int64_t v = gx + g.X * gy + g.XY * (t.z0 + lz);
+    if (loc[v] == cx + CTX * (cy + CTY * lz)) L[v] += off;
   }
 }
 
@@ -504,7 +527,8 @@ constexpr int kMaxRounds = 96;
 }  // namespace
 
 int cc_grid_run(msc_ctx *ctx, const uint8_t *mask, int64_t X, int64_t Y,
-                int64_t Z, int64_t *labels, hipStream_t s, bool sync) {
+                int64_t Z, int64_t *labels, hipStream_t s, bool sync,
+                int64_t label_off) {
   CGeo g{X, Y, Z, X * Y, X * Y * Z, (X + CTX - 1) / CTX, (Y + CTY - 1) / CTY,
          (Z + CTZ - 1) / CTZ};
   const int64_t ntiles = g.ntx * g.nty * g.ntz;
@@ -519,7 +543,11 @@ int cc_grid_run(msc_ctx *ctx, const uint8_t *mask, int64_t X, int64_t Y,
   MSC_PHASE(ctx, s, "cc_cross", 0.5 * g.N,
             (k_cc_cross<<<nb, kCThreads, 0, s>>>(g, loc, labels)));
   MSC_PHASE(ctx, s, "cc_final", 10.0 * g.N,
-            (k_cc_final<<<nb, kCThreads, 0, s>>>(g, loc, labels)));
+            (k_cc_final<<<nb, kCThreads, 0, s>>>(g, loc, labels, label_off)));
+  if (label_off)
+    MSC_PHASE(ctx, s, "cc_root_shift", 2.0 * g.N,
+              (k_cc_root_shift<<<nb, kCThreads, 0, s>>>(g, loc, labels,
+                                                        label_off)));
   if (!sync) return MSC_OK;
   MSC_TRY(read_counters(ctx, s));
   ctx->stats = msc_stats{};
@@ -607,15 +635,6 @@ namespace {
 
 // A slab's labels name vertices by their id within the slab; adding the id
 // of the slab's first vertex makes them global ids.
-__global__ void __launch_bounds__(kBlock)
-k_rank_cc_shift(int64_t *L, int64_t n, int64_t off) {
-  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) {
-    const int64_t v = L[i];
-    if (v >= 0) L[i] = v + off;
-  }
-}
-
 // The exchange at the boundary between plane zb (top of one slab) and
 // zb + 1 (bottom of the next): every Freudenthal edge that crosses it,
 // (x, y, zb) -- (x + dx, y + dy, zb + 1) for dx, dy in {0, 1}, joins the
@@ -682,12 +701,10 @@ int cc_grid_ranks_run(msc_ctx *ctx, const uint8_t *mask, int64_t X,
     const int64_t z0 = r * Z / ranks, z1 = (r + 1) * Z / ranks;
     // No host round trip per slab: the slabs queue on the stream (the
     // tile-local workspace is sized for the largest slab up front).
+    // Each slab is labelled in place with global ids (its first id as the
+    // label offset).
     MSC_TRY(cc_grid_run(ctx, mask + XY * z0, X, Y, z1 - z0, labels + XY * z0,
-                        s, false));
-    if (z0 > 0)
-      MSC_PHASE(ctx, s, "rank_cc_shift", 16.0 * XY * (z1 - z0),
-                (k_rank_cc_shift<<<blocks_for(XY * (z1 - z0)), kBlock, 0, s>>>(
-                    labels + XY * z0, XY * (z1 - z0), XY * z0)));
+                        s, false, XY * z0));
   }
   if (ranks > 1) {
     const unsigned by = ranks - 1 < 65535 ? (unsigned)(ranks - 1) : 65535u;

@@ -198,8 +198,11 @@ int segment_csr_run(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,
                     const int32_t *col_idx, const float *field, int32_t *asc,
                     int32_t *desc, int32_t *ms, hipStream_t stream);
 // `sync` false skips the closing counter read (the caller synchronises).
+// label_off is added to every written label (a slab labelled in place
+// inside a larger grid gets global ids).
 int cc_grid_run(msc_ctx *ctx, const uint8_t *mask, int64_t X, int64_t Y,
-                int64_t Z, int64_t *labels, hipStream_t s, bool sync = true);
+                int64_t Z, int64_t *labels, hipStream_t s, bool sync = true,
+                int64_t label_off = 0);
 int cc_grid_ranks_run(msc_ctx *ctx, const uint8_t *mask, int64_t X,
                       int64_t Y, int64_t Z, int ranks, int64_t *labels,
                       hipStream_t stream);
