@@ -108,6 +108,10 @@ MSC_API int msc_segment(msc_ctx *ctx, const float *field, const int64_t dims[3],
  * it; MSC_EINVAL also for ranks < 1 or ranks > Z.  msc_last_stats reports
  * the final extremum and cell counts.
  */
+MSC_API int msc_segment_ranks(msc_ctx *ctx, const float *field,
+                              const int64_t dims[3], int ranks, int32_t *asc,
+                              int32_t *desc, int32_t *ms, void *stream);
+
 /*
  * msc_segment on a general simplicial complex given by the adjacency of its
  * vertices (the problem statement's K; a grid is one case): steepest
@@ -136,10 +140,6 @@ MSC_API int msc_segment_csr(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,
                             const int32_t *col_idx, const float *field,
                             int32_t *asc, int32_t *desc, int32_t *ms,
                             void *stream);
-
-MSC_API int msc_segment_ranks(msc_ctx *ctx, const float *field,
-                              const int64_t dims[3], int ranks, int32_t *asc,
-                              int32_t *desc, int32_t *ms, void *stream);
 
 /*
  * Segmentation of a batch of fields of independent shapes in one set of
@@ -272,6 +272,10 @@ MSC_API int cc_label_grid(msc_ctx *ctx, const uint8_t *mask, const int64_t dims[
  * Outputs, layout and errors as cc_label_grid, and bit-identical to it;
  * MSC_EINVAL also for ranks < 1 or ranks > Z.
  */
+MSC_API int cc_label_grid_ranks(msc_ctx *ctx, const uint8_t *mask,
+                                const int64_t dims[3], int ranks,
+                                int64_t *labels, void *stream);
+
 /*
  * Critical points by the connected components of each vertex's lower and
  * upper link (background, "Critical Points"): the link of v in the
@@ -333,10 +337,6 @@ MSC_API int msc_csr_from_tets(msc_ctx *ctx, int64_t n, int64_t ntets,
                               const int32_t *tets, int64_t *row_ptr,
                               int32_t *col_idx, int64_t capacity,
                               int64_t *nnz, void *stream);
-
-MSC_API int cc_label_grid_ranks(msc_ctx *ctx, const uint8_t *mask,
-                                const int64_t dims[3], int ranks,
-                                int64_t *labels, void *stream);
 
 /*
  * Connected components of an explicit graph in CSR form (the paper's

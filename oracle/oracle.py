@@ -31,11 +31,11 @@ _LIB = os.path.join(_HERE, "liborc.so")
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (plain C, -O2)."""
+    """Compile the oracle with gcc (plain C, -O3)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
         subprocess.check_call(
-            ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
+            ["gcc", "-O3", "-std=c11", "-fPIC", "-shared", "-Wall", "-Wextra",
              "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB

@@ -29,11 +29,21 @@ int reserve(DevBuf &buf, size_t bytes) {
   return MSC_OK;
 }
 
-int clear_counters(msc_ctx *ctx, hipStream_t stream) {
-  MSC_HIP_TRY(hipMemsetAsync(ctx->dctr, 0,
-                             kNumCounters * sizeof(unsigned long long),
-                             stream));
+// Counters are cleared by a kernel, not a memset: a memset node captured
+// into a HIP graph is not safe to replay.
+__global__ void k_zero_u64(unsigned long long *p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0ull;
+}
+
+int zero_u64(unsigned long long *p, int n, hipStream_t stream) {
+  k_zero_u64<<<(n + 63) / 64, 64, 0, stream>>>(p, n);
+  MSC_HIP_TRY(hipGetLastError());
   return MSC_OK;
+}
+
+int clear_counters(msc_ctx *ctx, hipStream_t stream) {
+  return zero_u64(ctx->dctr, kNumCounters, stream);
 }
 
 int read_counters(msc_ctx *ctx, hipStream_t stream) {

@@ -515,9 +515,7 @@ k_check_range(const int64_t *__restrict__ d, int64_t n,
 }
 
 int clear_changed(msc_ctx *ctx, hipStream_t s) {
-  MSC_HIP_TRY(hipMemsetAsync(ctx->dctr + kCtrChanged, 0,
-                             sizeof(unsigned long long), s));
-  return MSC_OK;
+  return zero_u64(ctx->dctr + kCtrChanged, 1, s);
 }
 
 // In-place doubling needs at most about log2(longest path) + 1 rounds; more

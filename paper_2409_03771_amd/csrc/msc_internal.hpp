@@ -140,6 +140,8 @@ inline size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 // Read the counter block back to the host (synchronises `stream`).
 int read_counters(msc_ctx *ctx, hipStream_t stream);
 int clear_counters(msc_ctx *ctx, hipStream_t stream);
+// Zero n counters with a kernel on `stream`.
+int zero_u64(unsigned long long *p, int n, hipStream_t stream);
 
 // Launch `launch` (a statement) bracketed by profiling events when enabled.
 #define MSC_PHASE(ctx, stream, name, bytes, launch)                         \

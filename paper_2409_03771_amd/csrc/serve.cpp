@@ -37,7 +37,9 @@ int64_t now_ns() {
       .count();
 }
 
-enum State { kPending, kStaged, kRunning, kDone, kCanceled };
+// kCopying: taken from `pending`, its input copy being issued with the
+// queue's lock released; from then on it can no longer be cancelled.
+enum State { kPending, kCopying, kStaged, kRunning, kDone, kCanceled };
 
 struct Request {
   uint64_t ticket = 0;
@@ -164,6 +166,7 @@ void dispatcher_loop(msc_queue *q) {
       size_t off = 0;
       if (!q->alloc.alloc(need, &off)) break;
       q->pending.pop_front();
+      r->state = kCopying;  // msc_cancel refuses it from here on
       r->off = off;
       r->dev = q->arena + off;
       q->inflight_ws += r->ws_bytes;
@@ -525,6 +528,7 @@ int msc_queue_info(msc_queue *q, msc_queue_stats *out) {
   for (auto &kv : q->all) {
     switch (kv.second->state) {
       case kPending: ++out->pending; break;
+      case kCopying:
       case kStaged:
       case kRunning: ++out->running; break;
       default: ++out->finished; break;

@@ -106,12 +106,14 @@ def kuhn50m():
 
 
 def test_fullsize_cc_csr(kuhn50m):
-    """The 49.8M-vertex permuted Kuhn mesh: masked CSR and the explicit
-    foreground graph, every label."""
+    """The 49.8M-vertex permuted Kuhn mesh: masked CSR, the explicit
+    foreground graph, and the full mesh with no mask (one component over
+    every vertex: the longest union chains), every label."""
     from paper_2409_03771_amd import msc
     d = kuhn50m
     cases = [("masked", d["row_ptr"], d["col_idx"], d["mask"]),
-             ("explicit", d["fg_row_ptr"], d["fg_col_idx"], None)]
+             ("explicit", d["fg_row_ptr"], d["fg_col_idx"], None),
+             ("full", d["row_ptr"], d["col_idx"], None)]
     for name, rp, ci, mask in cases:
         print(f"[fullsize] csr {name} on the device", flush=True)
         lab = msc.cc_label_csr(
@@ -122,6 +124,8 @@ def test_fullsize_cc_csr(kuhn50m):
         del lab
         want, _ = O.cc_csr(rp, ci, mask)
         np.testing.assert_array_equal(got, want, err_msg=name)
+        if name == "full":  # a connected mesh: every label is vertex 0
+            assert (want == 0).all()
 
 
 def test_fullsize_segment_csr(kuhn50m):
