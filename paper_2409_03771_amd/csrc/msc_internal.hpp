@@ -31,7 +31,8 @@ enum Counter : int {
   kCtrChanged = 0,   // set nonzero by a round that changed something
   kCtrExits = 5,     // exits over all tiles (from the scan)
   kCtrBadIndex = 6,  // out-of-range CSR column seen
-  kCtrOverflow = 7,  // pair table full (bit 0), broken exit chain (bit 1)
+  kCtrOverflow = 7,  // pair table full (bit 0), broken exit chain (bit 1),
+                     // in-tile jumping did not settle (bit 2)
   kCtrRounds = 9,    // longest exit chain walked
   kCtrSteps = 10,    // exit-graph links followed in total
   kCtrRootsMax = 11, // vertices that are their own ascent label
@@ -170,10 +171,9 @@ inline unsigned grid_for(int64_t n, int block = kBlock) {
 
 // Segmentation tile shapes compiled in (index = ctx->tile_choice); the
 // first is the default.
-constexpr int kNumTileShapes = 8;
+constexpr int kNumTileShapes = 5;
 constexpr int kTileShapes[kNumTileShapes][3] = {
-    {32, 16, 16}, {32, 32, 16}, {32, 8, 8}, {64, 16, 16}, {64, 8, 8},
-    {32, 32, 32}, {32, 8, 16}, {64, 8, 16}};
+    {32, 16, 16}, {32, 8, 8}, {64, 8, 8}, {32, 8, 16}, {64, 8, 16}};
 inline int tile_index(int tx, int ty, int tz) {
   for (int i = 0; i < kNumTileShapes; ++i)
     if (kTileShapes[i][0] == tx && kTileShapes[i][1] == ty &&

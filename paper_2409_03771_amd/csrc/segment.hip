@@ -20,8 +20,8 @@
 //                 vertex points to a tile-local extremum or to a halo vertex
 //                 ("exit").  Writes a 16-bit code per vertex and direction
 //                 (an owned extremum, or the tile-local number of an exit)
-//                 and the tile's exit list at the tile's fixed slots.
-//   exit_scan     exclusive scan of the tiles' exit counts: global numbers.
+//                 and the tile's exit list at the tile's fixed slots
+//                 (2 * halo size per tile, so node numbers need no scan).
 //   exit_link     an exit lies on a neighbouring tile's shell; that tile's
 //                 code for it gives the exit's successor: a final extremum or
 //                 another tile's exit.  The exits form a dense graph.
@@ -51,22 +51,15 @@ struct Cfg {
   static constexpr int HX = TX + 2, HY = TY + 2, HZ = TZ + 2;
   static constexpr int HXY = HX * HY;
   static constexpr int H = HXY * HZ;          // tile plus halo
+  static constexpr int TXY = TX * TY;
   static constexpr int kThreads = TX * TY;    // one thread per z-column
   static constexpr int kWords = (H + 31) / 32;
-  static constexpr int kWordsPerThread = (kWords + kThreads - 1) / kThreads;
   static constexpr int kHalo = H - TX * TY * TZ;
-  // When the box indices fit in 15 bits, bit 15 of a 16-bit pointer marks a
-  // halo target: halo vertices start as flagged self-pointers and jumping
-  // carries the flag to every pointer that ends in the halo.
-  static constexpr bool kHaloBit = H <= 0x8000;
-  static constexpr uint32_t kHB = kHaloBit ? 0x8000u : 0u;
-  static constexpr uint32_t kIdx = kHaloBit ? 0x7fffu : 0xffffu;
-  static_assert(H <= 65535, "tile-local pointers are 16-bit");
+  // The in-LDS pointers are 16-bit byte addresses: 4 * (target index) for
+  // ascent, 4 * (target index) + 2 for descent.
+  static_assert(4 * (H - 1) + 2 <= 0xffff, "tile-local pointers are 16-bit");
   static_assert(kThreads % 64 == 0 && kThreads <= 1024, "block shape");
-  static_assert(H % 4 == 0, "flag bytes are read as words");
-  static_assert((2 * H + 3) / 4 + 3 * kWords <= H,
-                "exit flags and bitsets alias the pointer array");
-  static_assert(kHalo <= (2 * H + 3) / 4, "the exit list fits the flag bytes");
+  static_assert(H % 4 == 0, "exit entries are taken four at a time");
   static_assert(TX * TY * TZ <= 0x8000 && kHalo < 0x8000,
                 "local pointer codes are 15-bit");
 };
@@ -75,7 +68,7 @@ constexpr unsigned long long kEmptyKey = ~0ull;
 
 // Per-field counters (kFieldCtrs per field).
 enum FieldCtr : int { kFMaxima = 0, kFMinima = 1, kFCells = 2, kFNaN = 3,
-                      kFieldCtrs = 4 };
+                      kFExits = 4, kFieldCtrs = 5 };
 
 struct Geo {
   uint32_t X, Y, Z, XY, N;
@@ -151,29 +144,6 @@ __device__ __forceinline__ uint32_t halo_global(const Geo &g, const Tile &t,
 // tile's exits of that direction, with bit 15 set.
 constexpr uint32_t kExitCode = 0x8000u;
 
-// Tile-plus-halo index p as the owned code of its vertex, or p itself with
-// bit 16 set when it lies in the halo (one decode per pointer target).
-template <class C>
-__device__ __forceinline__ uint32_t classify(int p) {
-  int hz = p / C::HXY, r = p - hz * C::HXY, hy = r / C::HX, hx = r - hy * C::HX;
-  if (hx >= 1 && hx <= C::TX && hy >= 1 && hy <= C::TY && hz >= 1 &&
-      hz <= C::TZ)
-    return (uint32_t)((hx - 1) + C::TX * ((hy - 1) + C::TY * (hz - 1)));
-  return 0x10000u | (uint32_t)p;
-}
-
-// Stored code of a classified target: owned codes pass through; a halo index
-// becomes its number among the tile's exits of that direction (the word
-// prefixes of that direction sit at bit `shift` of `prefix`).
-__device__ __forceinline__ uint32_t exit_code(uint32_t c, const uint32_t *bits,
-                                              const uint32_t *prefix,
-                                              int shift) {
-  if (!(c & 0x10000u)) return c;
-  const uint32_t p = c & 0xffffu, w = p >> 5;
-  return kExitCode | (((prefix[w] >> shift) & 0xffffu) +
-                      __popc(bits[w] & ((1u << (p & 31)) - 1u)));
-}
-
 // Global id of an owned code.
 template <class C>
 __device__ __forceinline__ uint32_t owned_global(const Geo &g, const Tile &t,
@@ -184,19 +154,15 @@ __device__ __forceinline__ uint32_t owned_global(const Geo &g, const Tile &t,
          g.XY * ((uint32_t)t.z0 + lz);
 }
 
-// Four flag bytes (each 0 or 1) as a nibble: byte j becomes bit j.
-__device__ __forceinline__ uint32_t flag_nibble(uint32_t v) {
-  const uint32_t t = v | (v >> 7);
-  return (t | (t >> 14)) & 0xfu;
-}
+// A halo entry that some vertex's final pointer names.
+constexpr uint32_t kMark = 0xffffu;
 
-// OR of the values of lanes 8j .. 8j+7, valid in lane 8j+7 (row shifts by
-// 1, 2 and 4 lanes; lanes shifted in from outside a row of 16 read 0).
-__device__ __forceinline__ uint32_t or8(uint32_t x) {
-  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xf, 0xf, true);
-  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xf, 0xf, true);
-  x |= (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xf, 0xf, true);
-  return x;
+// 16-bit LDS entries addressed by byte offset from an array base.
+__device__ __forceinline__ uint32_t ld16(const char *base, uint32_t off) {
+  return *reinterpret_cast<const uint16_t *>(base + off);
+}
+__device__ __forceinline__ void st16(char *base, uint32_t off, uint32_t v) {
+  *reinterpret_cast<uint16_t *>(base + off) = (uint16_t)v;
 }
 
 __device__ __forceinline__ void wave_count(bool pred, unsigned long long *ctr) {
@@ -365,19 +331,24 @@ k_steps_reduce(const unsigned long long *__restrict__ rstat, uint32_t nb,
 
 template <class C>
 __global__ void __launch_bounds__(C::kThreads)
+__attribute__((amdgpu_waves_per_eu(6, 6)))
 k_tile_local(const FieldDev *__restrict__ fds,
              const uint32_t *__restrict__ tfield, ExitOut xo,
              unsigned long long *ctr, unsigned long long *fctr) {
   constexpr int HX = C::HX, HXY = C::HXY, H = C::H, T = C::kThreads;
-  // Field bits while the steepest pointers are computed, then the packed
-  // pointers (ascent in the low 16 bits, descent in the high 16 bits).
+  // The field while the steepest pointers are computed.  Then one word per
+  // tile-plus-halo index p: the ascent pointer in its low half, the descent
+  // pointer in its high half.  A pointer is the byte address of the half it
+  // names (4 * target for ascent, 4 * target + 2 for descent), so following
+  // it is a single 16-bit LDS read with no address arithmetic, and the value
+  // read is the next pointer of the same direction.
   __shared__ uint32_t lds[H];
-  // Once the pointers in `lds` are no longer read it holds: one flag byte
-  // per tile-plus-halo index and direction, then the exit bitsets over that
-  // index and their word prefixes (ascent | descent << 16).
-  uint8_t *const flg = reinterpret_cast<uint8_t *>(lds);
-  uint32_t *const xa = lds + (2 * H + 3) / 4, *const xd = xa + C::kWords;
-  uint32_t *const pre = xd + C::kWords;
+  char *const lb = reinterpret_cast<char *>(lds);
+  // Exit bitsets over p (ascent, descent) and their word prefixes
+  // (ascent | descent << 16).
+  // The bitsets are stored 64 bits at a time (padded to an even count).
+  __shared__ __align__(8) uint32_t xa[C::kWords + 1], xd[C::kWords + 1];
+  __shared__ uint32_t pre[C::kWords];
   __shared__ uint32_t scan_tmp[32];
   __shared__ float s_wsum[16];
   __shared__ uint32_t s_wext[16];  // per wave: maxima | minima << 16
@@ -394,6 +365,9 @@ k_tile_local(const FieldDev *__restrict__ fds,
   // a column's offset within a plane is computed once, and each plane's
   // base is uniform over the block.  Positions outside the domain hold NaN,
   // which loses every comparison below and so is never chosen.
+  // A NaN anywhere in the domain is reported (a halo value belongs to a
+  // neighbouring tile, which reports it too).
+  bool any_nan = false;
   {
     constexpr int KC = (HXY + T - 1) / T;
     const uint32_t kNaN = 0x7fc00000u;
@@ -406,6 +380,8 @@ k_tile_local(const FieldDev *__restrict__ fds,
         const bool cin =
             gx >= 0 && gx < (int)g.X && gy >= 0 && gy < (int)g.Y;
         const uint32_t off = cin ? (uint32_t)gx + g.X * (uint32_t)gy : 0u;
+        // Every load is issued before any is used (the addresses are
+        // clamped into the field, so none needs a guard).
         uint32_t val[C::HZ];
 #pragma unroll
         for (int hz = 0; hz < C::HZ; ++hz) {
@@ -413,13 +389,19 @@ k_tile_local(const FieldDev *__restrict__ fds,
           const bool zin = gz >= 0 && gz < (int)g.Z;
           const GlobalF *plane = (const GlobalF *)f +
                                  (size_t)g.XY * (uint32_t)(zin ? gz : 0);
-          val[hz] = cin && zin ? __float_as_uint(plane[off]) : kNaN;
+          val[hz] = __float_as_uint(plane[off]);
         }
 #pragma unroll
-        for (int hz = 0; hz < C::HZ; ++hz) lds[col + hz * HXY] = val[hz];
+        for (int hz = 0; hz < C::HZ; ++hz) {
+          const int gz = t.z0 - 1 + hz;
+          const bool in = cin && gz >= 0 && gz < (int)g.Z;
+          any_nan |= in && (val[hz] & 0x7fffffffu) > 0x7f800000u;
+          lds[col + hz * HXY] = in ? val[hz] : kNaN;
+        }
       }
     }
   }
+  wave_count(any_nan, fc + kFNaN);
   __syncthreads();
 
   const int cx = tid % C::TX, cy = tid / C::TX;
@@ -430,79 +412,143 @@ k_tile_local(const FieldDev *__restrict__ fds,
   const int c0 = (cx + 1) + HX * (cy + 1);  // column index in plane 0
 
   // Steepest ascent / descent over the closed neighbourhood, ordered by
-  // (value, id).  Starting from v itself, a lower-id neighbour must be
-  // strictly above to win the max and at most equal to win the min; a
-  // higher-id neighbour wins the max when at least equal and the min when
-  // strictly below.  Lower-id neighbours are taken in decreasing id order,
-  // higher-id ones in increasing id order.
-  // Ghost planes of a slab (the virtual-rank path); -1 when there are none.
-  // Bit lz is set when plane t.z0 + lz is one (block-uniform).
+  // (value, id).  The 14 Freudenthal neighbours of a vertex at plane P are,
+  // in plane P, the column's (-1,0), (0,-1), (-1,-1) and (+1,0), (0,+1),
+  // (+1,+1) neighbours, and (0,0), (-1,0), (0,-1), (-1,-1) of plane P-1 and
+  // (0,0), (+1,0), (0,+1), (+1,+1) of plane P+1.  So with, per plane,
+  //   LF(P) = best of { c, (-1,0), (0,-1), (-1,-1) }   (c and lower ids)
+  //   UF(P) = best of { c, (+1,0), (0,+1), (+1,+1) }   (c and higher ids)
+  // the vertex at P takes the best of LF(P), UF(P), LF(P-1) and UF(P+1), and
+  // each group is computed once and used by two vertices of the column.
+  // Every id in plane P-1 is below every id in plane P, which is below every
+  // id in plane P+1, so each merge knows which side has the larger id: a
+  // challenger with larger ids wins the max when at least equal and the min
+  // when strictly below; one with smaller ids wins the max when strictly
+  // above and the min when at most equal.  Each chain starts from a vertex
+  // of the domain and takes its challengers in one id order, so a position
+  // outside the domain (NaN) never wins a comparison.
+  // Ghost planes of a slab (the virtual-rank path): bit lz is set when
+  // plane t.z0 + lz holds ghost vertices, which are fixed points
+  // (block-uniform).
   uint32_t gmask = 0;
   if ((bt.fd.ghost & 1u) && t.z0 == 0) gmask |= 1u;
   if ((bt.fd.ghost & 2u) && (int)g.Z - 1 - t.z0 < C::TZ)
     gmask |= 1u << ((int)g.Z - 1 - t.z0);
   gmask = __builtin_amdgcn_readfirstlane(gmask);
-  uint32_t ptr[C::TZ];
-  bool any_nan = false;
+  // Offsets are byte offsets of LDS words (four times the index
+  // difference), relative to the plane's own column: the same seven
+  // constants for every plane.  A vertex outside the domain holds NaN, so
+  // it wins nothing and keeps pointing to itself.
+  struct Best {
+    float v;
+    int o;
+  };
+  struct Groups {
+    Best lmax, lmin, umax, umin;  // LF and UF of one plane, both directions
+  };
+  // The groups of box plane P (P = lz + 1 for the tile's planes); `want_l`
+  // / `want_u` are compile-time after unrolling.
+  auto groups = [&](int P, bool want_l, bool want_u) -> Groups {
+    const int c = c0 + P * HXY;
+    const float fc = __uint_as_float(lds[c]);
+    Groups r;
+    r.lmax = r.lmin = r.umax = r.umin = Best{fc, 0};
+    if (want_l) {
+      const float fxm = __uint_as_float(lds[c - 1]);
+      const float fym = __uint_as_float(lds[c - HX]);
+      const float fxym = __uint_as_float(lds[c - HX - 1]);
+      // Challengers in decreasing id order: strict for the max, at most
+      // equal for the min.
+      if (fxm > r.lmax.v) r.lmax = Best{fxm, -4};
+      if (fxm <= r.lmin.v) r.lmin = Best{fxm, -4};
+      if (fym > r.lmax.v) r.lmax = Best{fym, -4 * HX};
+      if (fym <= r.lmin.v) r.lmin = Best{fym, -4 * HX};
+      if (fxym > r.lmax.v) r.lmax = Best{fxym, -4 * HX - 4};
+      if (fxym <= r.lmin.v) r.lmin = Best{fxym, -4 * HX - 4};
+    }
+    if (want_u) {
+      const float fxp = __uint_as_float(lds[c + 1]);
+      const float fyp = __uint_as_float(lds[c + HX]);
+      const float fxyp = __uint_as_float(lds[c + HX + 1]);
+      // Challengers in increasing id order: at least equal for the max,
+      // strict for the min.
+      if (fxp >= r.umax.v) r.umax = Best{fxp, 4};
+      if (fxp < r.umin.v) r.umin = Best{fxp, 4};
+      if (fyp >= r.umax.v) r.umax = Best{fyp, 4 * HX};
+      if (fyp < r.umin.v) r.umin = Best{fyp, 4 * HX};
+      if (fxyp >= r.umax.v) r.umax = Best{fxyp, 4 * HX + 4};
+      if (fxyp < r.umin.v) r.umin = Best{fxyp, 4 * HX + 4};
+    }
+    return r;
+  };
+  // The column's word at lz = 0; later planes are constant offsets.
+  uint32_t *const own = lds + (c0 + HXY);
+  // The tile's mean value orders the exit resolution (speed only, never a
+  // result), so it is taken over one plane of the tile: the middle one, or
+  // the last one inside the domain (block-uniform).  Read before the pointers
+  // overwrite the field.
   float fsum = 0.f;
+  {
+    const int zs = min(C::TZ / 2, (int)g.Z - 1 - t.z0);
+    if (nz > 0) fsum = __uint_as_float(own[HXY * zs]);
+  }
   unsigned nmax = 0, nmin = 0;
-  Plane below = load_plane<C>(lds, c0);
-  Plane cur = load_plane<C>(lds, c0 + HXY);
+  // Pointers wait in registers in groups of four planes: plane q's values
+  // are last read in iteration q - 2, so once every thread has passed a
+  // barrier after iteration lz, the words of planes up to lz + 2 are free
+  // and the pointers computed so far replace their vertices' values.
+  constexpr int kFlush = 4;
+  static_assert(C::TZ % kFlush == 0, "tile depth");
+  uint32_t ka[kFlush], kd[kFlush];
+  Groups prev = groups(0, true, false);
+  Groups cur = groups(1, true, true);
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz) {
-    const int i = c0 + (lz + 1) * HXY;
-    const Plane above = load_plane<C>(lds, i + HXY);
-    const float fv = cur.v[3];
-    float bmax = fv, bmin = fv;
-    int omax = 0, omin = 0;
-#define MSC_LO(val, off)                        \
-  {                                             \
-    const float fu = (val);                     \
-    if (fu > bmax) { bmax = fu; omax = (off); } \
-    if (fu <= bmin) { bmin = fu; omin = (off); } \
-  }
-#define MSC_HI(val, off)                        \
-  {                                             \
-    const float fu = (val);                     \
-    if (fu >= bmax) { bmax = fu; omax = (off); } \
-    if (fu < bmin) { bmin = fu; omin = (off); }  \
-  }
-    MSC_LO(cur.v[2], -1)
-    MSC_LO(cur.v[1], -HX)
-    MSC_LO(cur.v[0], -HX - 1)
-    MSC_LO(below.v[3], -HXY)
-    MSC_LO(below.v[2], -HXY - 1)
-    MSC_LO(below.v[1], -HXY - HX)
-    MSC_LO(below.v[0], -HXY - HX - 1)
-    MSC_HI(cur.v[4], 1)
-    MSC_HI(cur.v[5], HX)
-    MSC_HI(cur.v[6], HX + 1)
-    MSC_HI(above.v[3], HXY)
-    MSC_HI(above.v[4], HXY + 1)
-    MSC_HI(above.v[5], HXY + HX)
-    MSC_HI(above.v[6], HXY + HX + 1)
-#undef MSC_LO
-#undef MSC_HI
-    if ((gmask >> lz) & 1u) {  // ghost vertex: a fixed point
-      omax = 0;
-      omin = 0;
-    }
+    const int P = lz + 1;
+    const Groups next = groups(P + 1, lz + 1 < C::TZ, true);
+    // In plane P: LF then UF (ids at least as large; the two share only the
+    // column's own vertex).  Then plane P-1 (smaller ids) and plane P+1
+    // (larger), whose offsets move by one plane.
+    Best mx = cur.lmax, mn = cur.lmin;
+    if (cur.umax.v >= mx.v) mx = cur.umax;
+    if (cur.umin.v < mn.v) mn = cur.umin;
+    if (prev.lmax.v > mx.v) mx = Best{prev.lmax.v, prev.lmax.o - 4 * HXY};
+    if (prev.lmin.v <= mn.v) mn = Best{prev.lmin.v, prev.lmin.o - 4 * HXY};
+    if (next.umax.v >= mx.v) mx = Best{next.umax.v, next.umax.o + 4 * HXY};
+    if (next.umin.v < mn.v) mn = Best{next.umin.v, next.umin.o + 4 * HXY};
     const bool in = lz < nz;
-    any_nan |= in && fv != fv;
-    ptr[lz] = in ? (uint32_t)(i + omax) | ((uint32_t)(i + omin) << 16)
-                 : (uint32_t)i | ((uint32_t)i << 16);
-    nmax += __popcll(__ballot(in && omax == 0));
-    nmin += __popcll(__ballot(in && omin == 0));
-    below = cur;
-    cur = above;
-  }
-  wave_count(any_nan, fc + kFNaN);
-  // Extremum counts (wave totals above) of the tile.
-  // The column's sum for the tile mean, in a pass of its own: accumulating
-  // it inside the steepest loop above costs that loop dozens of registers.
+    const uint32_t self = 4u * (uint32_t)(c0 + P * HXY);
+    ka[lz % kFlush] = self + (uint32_t)mx.o;
+    kd[lz % kFlush] = self + (uint32_t)mn.o + 2u;
+    nmax += __popcll(__builtin_amdgcn_ballot_w64(in && mx.o == 0));
+    nmin += __popcll(__builtin_amdgcn_ballot_w64(in && mn.o == 0));
+    prev = cur;
+    cur = next;
+    if (lz % kFlush == kFlush - 1) {
+      __syncthreads();
 #pragma unroll
-  for (int lz = 0; lz < C::TZ; ++lz)
-    if (lz < nz) fsum += __uint_as_float(lds[c0 + (lz + 1) * HXY]);
+      for (int j = 0; j < kFlush; ++j)
+        own[HXY * (lz - kFlush + 1 + j)] = ka[j] | (kd[j] << 16);
+    }
+    // Keep the scheduler from hoisting the next planes' work into this one
+    // (register pressure).
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  if (gmask) {  // ghost vertices are fixed points (block-uniform branch)
+    // The column's vertices inside the domain, as a mask of its own (the
+    // steepest loop's per-plane tests would otherwise stay live until here).
+    const uint32_t inmask = (1u << nz) - 1u;  // nz <= 16
+    for (int lz = 0; lz < C::TZ; ++lz) {
+      if ((gmask >> lz) & 1u) {
+        const uint32_t self = 4u * (uint32_t)(c0 + (lz + 1) * HXY);
+        const uint32_t w = own[HXY * lz];
+        const bool in = (inmask >> lz) & 1u;
+        nmax += __popcll(__ballot(in && (w & 0xffffu) != self));
+        nmin += __popcll(__ballot(in && (w >> 16) != self + 2u));
+        own[HXY * lz] = self | ((self + 2u) << 16);
+      }
+    }
+  }
   for (int o = 32; o > 0; o >>= 1) fsum += __shfl_xor(fsum, o);
   if ((tid & 63) == 0) {
     s_wsum[tid >> 6] = fsum;
@@ -514,12 +560,9 @@ k_tile_local(const FieldDev *__restrict__ fds,
     for (int w = 0; w < T / 64; ++w) c += (s_wext[w] >> (16 * tid)) & 0xffffu;
     xo.tstat[4 * (size_t)bt.gt + tid] = c;
   } else if (tid == 64) {
-    // Mean value of the tile: the order in which exits get resolved.  Taken
-    // here, so that nothing it needs stays live through the later phases.
     float sum = 0.f;
     for (int w = 0; w < T / 64; ++w) sum += s_wsum[w];
-    const int cnt = min(C::TX, (int)g.X - t.x0) * min(C::TY, (int)g.Y - t.y0) *
-                    min(C::TZ, (int)g.Z - t.z0);
+    const int cnt = min(C::TX, (int)g.X - t.x0) * min(C::TY, (int)g.Y - t.y0);
     xo.tkey[bt.gt] = float_key(sum / (float)cnt);
   }
 
@@ -531,141 +574,149 @@ k_tile_local(const FieldDev *__restrict__ fds,
 #pragma unroll
     for (int hz = 0; hz < C::HZ; ++hz) {
       if (edge || hz == 0 || hz == C::HZ - 1) {
-        const uint32_t i = (uint32_t)(col + hz * HXY) | C::kHB;
-        lds[i & C::kIdx] = i | (i << 16);
+        const uint32_t e = 4u * (uint32_t)(col + hz * HXY);
+        lds[col + hz * HXY] = e | ((e + 2u) << 16);
       }
     }
   }
-#pragma unroll
-  for (int lz = 0; lz < C::TZ; ++lz) lds[c0 + (lz + 1) * HXY] = ptr[lz];
   __syncthreads();
+  uint32_t pa[C::TZ], pd[C::TZ];
+#pragma unroll
+  for (int lz = 0; lz < C::TZ; ++lz) {
+    const uint32_t w = own[HXY * lz];
+    pa[lz] = w & 0xffffu;
+    pd[lz] = w >> 16;
+  }
 
   // Pointer jumping inside the tile, in place.  Only the owner writes an
   // entry, so the owner's copy in registers is always current, and any value
-  // read from another entry is an ancestor of it.  Each round gathers the
-  // successors of all the column's entries first (one wait for the lot),
-  // then updates; finished entries gather themselves and stay unchanged.
-  for (;;) {
-    uint32_t q[C::TZ];
+  // read from another entry is an ancestor of it (a concurrent reader sees
+  // the old or the new value, both on the vertex's own path).  Each round
+  // gathers the successors of all the column's entries first (one wait for
+  // the lot), then stores the ones that changed.  Two rounds per iteration,
+  // alternating between two register sets, so that no copies are needed.
+  auto round = [&](const uint32_t (&sa)[C::TZ], const uint32_t (&sd)[C::TZ],
+                   uint32_t (&da)[C::TZ], uint32_t (&dd)[C::TZ]) -> bool {
 #pragma unroll
-    for (int lz = 0; lz < C::TZ; ++lz)
-      q[lz] = (lds[ptr[lz] & C::kIdx] & 0xffffu) |
-              (lds[(ptr[lz] >> 16) & C::kIdx] & 0xffff0000u);
+    for (int lz = 0; lz < C::TZ; ++lz) {
+      da[lz] = ld16(lb, sa[lz]);
+      dd[lz] = ld16(lb, sd[lz]);
+    }
     bool changed = false;
 #pragma unroll
     for (int lz = 0; lz < C::TZ; ++lz) {
-      if (q[lz] != ptr[lz]) {
-        ptr[lz] = q[lz];
-        lds[c0 + (lz + 1) * HXY] = q[lz];
-        changed = true;
-      }
+      // The loaded entry as an opaque 32-bit value: keeps the compiler from
+      // narrowing the pointers to 16 bits and widening them at every use.
+      asm("" : "+v"(da[lz]));
+      asm("" : "+v"(dd[lz]));
+      changed |= (da[lz] != sa[lz]) | (dd[lz] != sd[lz]);
+      own[HXY * lz] = da[lz] | (dd[lz] << 16);
     }
-    if (!__syncthreads_or(changed)) break;
-  }
-  // Every pointer is final in registers: `lds` becomes flags and bitsets.
-  for (int w = tid; w < (2 * H + 3) / 4; w += T) lds[w] = 0;
-  __syncthreads();
-
-  // Halo targets are the tile's exits.  Each target is classified once
-  // (ptr keeps owned code or halo index, hmask_* flags the halo ones) and
-  // flagged with a plain byte store: every writer stores the same 1.  With
-  // the halo bit only the rare in-tile extremum targets need a decode.
-  auto cls = [](uint32_t h) -> uint32_t {
-    if (C::kHaloBit && (h & C::kHB)) return 0x10000u | (h & C::kIdx);
-    return classify<C>((int)h);
+    return __syncthreads_or(changed);
   };
-  uint32_t hmask_a = 0, hmask_d = 0;
+  {
+    // Pointer doubling over a forest of H nodes settles within about
+    // log2(H) + 1 rounds; the bound only turns a broken invariant into an
+    // error (counter bit 2) instead of a hang.
+    constexpr int kMaxPairs = 16;
+    uint32_t qa[C::TZ], qd[C::TZ];
+    int it = 0;
+    for (;; ++it) {
+      if (it == kMaxPairs) {
+        if (tid == 0) atomicOr(ctr + kCtrOverflow, 4ull);
+        break;
+      }
+      if (!round(pa, pd, qa, qd)) {
+#pragma unroll
+        for (int lz = 0; lz < C::TZ; ++lz) {
+          pa[lz] = qa[lz];
+          pd[lz] = qd[lz];
+        }
+        break;
+      }
+      if (!round(qa, qd, pa, pd)) break;
+    }
+  }
+
+  // Every pointer is final: it names an extremum of the tile or a halo
+  // vertex (an exit), both fixed points.  Each vertex marks its two targets'
+  // halves; then every owner overwrites its own word with its stored code in
+  // both halves, so that afterwards exactly the halo halves that are some
+  // vertex's target hold the mark.  Entries that are nobody's target are
+  // never read again.
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz) {
-    if (lz < nz) {
-      const uint32_t ca = cls(ptr[lz] & 0xffffu);
-      const uint32_t cd = cls(ptr[lz] >> 16);
-      if (ca & 0x10000u) {
-        flg[ca & 0xffffu] = 1;
-        hmask_a |= 1u << lz;
-      }
-      if (cd & 0x10000u) {
-        flg[H + (cd & 0xffffu)] = 1;
-        hmask_d |= 1u << lz;
-      }
-      ptr[lz] = (ca & 0xffffu) | (cd << 16);
+    st16(lb, pa[lz], kMark);
+    st16(lb, pd[lz], kMark);
+  }
+  __syncthreads();
+  {
+    const uint32_t code0 = (uint32_t)(cx + C::TX * cy);
+#pragma unroll
+    for (int lz = 0; lz < C::TZ; ++lz) {
+      const uint32_t code = code0 + (uint32_t)(C::TXY * lz);
+      own[HXY * lz] = code | (code << 16);
     }
   }
   __syncthreads();
-  // Flags to bitsets: thread q reads the flag bytes of indices 4q .. 4q+3
-  // as one word (all reads issued first) and folds them into a nibble;
-  // eight consecutive lanes OR their shifted nibbles into one bitset word.
+
+  // Marks to bitsets: the 64 lanes of a wave test 64 consecutive entries,
+  // so one ballot is two bitset words, stored by one lane as a 64-bit word.
+  {
+    constexpr int KB = (H + T - 1) / T;
+    const bool lane0 = (tid & 63) == 0;
+    const uint32_t w0 = (uint32_t)(tid >> 6) * 2u;  // wave-uniform
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int p = tid + k * T;
+      const bool ok = (k + 1) * T <= H || p < H;
+      const uint32_t e = ok ? lds[p] : 0u;
+      const unsigned long long ma = __ballot(ok && (e & 0xffffu) == kMark);
+      const unsigned long long md = __ballot(ok && (e >> 16) == kMark);
+      const uint32_t w = w0 + (uint32_t)(k * (T / 32));
+      if (lane0 && w < (uint32_t)C::kWords) {
+        *reinterpret_cast<unsigned long long *>(xa + w) = ma;
+        *reinterpret_cast<unsigned long long *>(xd + w) = md;
+      }
+    }
+  }
+  __syncthreads();
+
+  // Exits are numbered per direction in increasing index.  Thread tid owns
+  // the consecutive words tid*W .. tid*W+W-1; one scan of packed counts
+  // (ascent | descent << 16, each below 2^16) serves both.
+  constexpr int W = (C::kWords + T - 1) / T;
+  uint32_t tot = 0;
+  {
+    uint32_t wa[W], wd[W];
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const int w = tid * W + j;
+      wa[j] = w < C::kWords ? xa[w] : 0u;
+      wd[j] = w < C::kWords ? xd[w] : 0u;
+      cnt += __popc(wa[j]) | ((uint32_t)__popc(wd[j]) << 16);
+    }
+    uint32_t run = block_exclusive_scan(cnt, scan_tmp, &tot);
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+      const int w = tid * W + j;
+      if (w < C::kWords) pre[w] = run;
+      run += __popc(wa[j]) | ((uint32_t)__popc(wd[j]) << 16);
+    }
+  }
+  const uint32_t na = tot & 0xffffu, nd = tot >> 16;
+  __syncthreads();
+
+  // Each marked entry becomes its exit code (bit 15 and the exit's number
+  // in its direction), and the tile's exit list gets its index (ascent
+  // exits first, then descent).  Thread q takes indices 4q .. 4q+3 (a nibble
+  // of bitset word q / 8) and reads its words and prefixes first.
   {
     constexpr int Q = H / 4, KQ = (Q + T - 1) / T;
     const uint32_t sh = 4u * (uint32_t)(tid & 7);
-    uint32_t fa[KQ], fd[KQ];
-#pragma unroll
-    for (int k = 0; k < KQ; ++k) {
-      const int q = tid + k * T;
-      fa[k] = q < Q ? lds[q] : 0u;
-      fd[k] = q < Q ? lds[Q + q] : 0u;
-    }
-#pragma unroll
-    for (int k = 0; k < KQ; ++k) {
-      const int q = tid + k * T;
-      const uint32_t wa = or8(flag_nibble(fa[k]) << sh);
-      const uint32_t wd = or8(flag_nibble(fd[k]) << sh);
-      if ((tid & 7) == 7 && (q >> 3) < C::kWords) {
-        xa[q >> 3] = wa;
-        xd[q >> 3] = wd;
-      }
-    }
-  }
-  __syncthreads();
-
-  // Exits are numbered ascent then descent, each in increasing halo index.
-  // Thread tid owns the consecutive words tid*W .. tid*W+W-1; one scan of
-  // packed counts (ascent | descent << 16, each below 2^16) serves both.
-  constexpr int W = C::kWordsPerThread;
-  uint32_t wa[W], wd[W];
-  uint32_t cnt = 0;
-#pragma unroll
-  for (int j = 0; j < W; ++j) {
-    const int w = tid * W + j;
-    wa[j] = w < C::kWords ? xa[w] : 0u;
-    wd[j] = w < C::kWords ? xd[w] : 0u;
-    cnt += __popc(wa[j]) | ((uint32_t)__popc(wd[j]) << 16);
-  }
-  uint32_t tot = 0;
-  uint32_t run = block_exclusive_scan(cnt, scan_tmp, &tot);
-  const uint32_t na = tot & 0xffffu, nd = tot >> 16;
-#pragma unroll
-  for (int j = 0; j < W; ++j) {
-    const int w = tid * W + j;
-    if (w < C::kWords) pre[w] = run;
-    run += __popc(wa[j]) | ((uint32_t)__popc(wd[j]) << 16);
-  }
-  __syncthreads();
-
-  // The stored local pointer: an owned target by its owned index, an exit
-  // by its number (bit 15 set), so that later passes decode it with one
-  // lookup in the tile's resolved exits.
-  const uint32_t col = (uint32_t)gx + g.X * (uint32_t)gy;
-#pragma unroll
-  for (int lz = 0; lz < C::TZ; ++lz) {
-    if (lz < nz) {
-      const uint32_t w = ptr[lz];
-      const uint32_t ca = (w & 0xffffu) | (((hmask_a >> lz) & 1u) << 16);
-      const uint32_t cd = (w >> 16) | (((hmask_d >> lz) & 1u) << 16);
-      plane_ptr(bt.fd.lp, g, t.z0 + lz)[col] =
-          exit_code(ca, xa, pre, 0) | (exit_code(cd, xd, pre, 16) << 16);
-    }
-  }
-
-  // The tile's exits for the exit graph, by their tile-local numbers (the
-  // numbers become global with a scan over tiles afterwards).  The list is
-  // built in the flag bytes, no longer read, and copied out in dwords.
-  // Thread q takes indices 4q .. 4q+3 (a nibble of bitset word q / 8) and
-  // reads its words and prefixes before writing any entry.
-  {
-    uint16_t *sl = reinterpret_cast<uint16_t *>(lds);
-    constexpr int Q = H / 4, KQ = (Q + T - 1) / T;
-    const uint32_t sh = 4u * (uint32_t)(tid & 7), below = (1u << sh) - 1u;
+    uint16_t *tl = xo.tlist + (size_t)bt.gt * (2 * C::kHalo);
+    const uint32_t below_mask = (1u << sh) - 1u;
     uint32_t ba[KQ], bd[KQ], bp[KQ];
 #pragma unroll
     for (int k = 0; k < KQ; ++k) {
@@ -677,21 +728,41 @@ k_tile_local(const FieldDev *__restrict__ fds,
 #pragma unroll
     for (int k = 0; k < KQ; ++k) {
       const uint32_t p0 = 4u * (uint32_t)(tid + k * T);
-      uint32_t ra = (bp[k] & 0xffffu) + __popc(ba[k] & below);
-      uint32_t rd = na + (bp[k] >> 16) + __popc(bd[k] & below);
-      const uint32_t ma = ba[k] >> sh, md = bd[k] >> sh;
+      uint32_t ra = (bp[k] & 0xffffu) + __popc(ba[k] & below_mask);
+      uint32_t rd = (bp[k] >> 16) + __popc(bd[k] & below_mask);
+      const uint32_t ma = (ba[k] >> sh) & 0xfu, md = (bd[k] >> sh) & 0xfu;
+      if (ma | md) {
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        if ((ma >> j) & 1u) sl[ra++] = (uint16_t)(p0 + j);
-        if ((md >> j) & 1u) sl[rd++] = (uint16_t)(p0 + j);
+        for (int j = 0; j < 4; ++j) {
+          if ((ma >> j) & 1u) {
+            st16(lb, 4u * (p0 + j), kExitCode | ra);
+            tl[ra++] = (uint16_t)(p0 + j);
+          }
+          if ((md >> j) & 1u) {
+            st16(lb, 4u * (p0 + j) + 2u, kExitCode | rd);
+            tl[na + rd++] = (uint16_t)(p0 + j);
+          }
+        }
       }
     }
-    __syncthreads();
-    uint32_t *tl = reinterpret_cast<uint32_t *>(xo.tlist +
-                                                (size_t)bt.gt * (2 * C::kHalo));
-    for (uint32_t w = tid; w < (na + nd + 1) / 2; w += T) tl[w] = lds[w];
   }
-  if (tid == 0) xo.seg[bt.gt] = Seg{0u, (uint16_t)na, (uint16_t)nd};
+  __syncthreads();
+
+  // The stored local pointer of every vertex is its target's code: an
+  // owned target by its owned index, an exit by its number (bit 15 set), so
+  // that later passes decode it with one lookup in the tile's resolved exits.
+  const uint32_t col = (uint32_t)gx + g.X * (uint32_t)gy;
+#pragma unroll
+  for (int lz = 0; lz < C::TZ; ++lz) {
+    if (lz < nz)
+      plane_ptr(bt.fd.lp, g, t.z0 + lz)[col] =
+          ld16(lb, pa[lz]) | (ld16(lb, pd[lz]) << 16);
+  }
+  if (tid == 0) {
+    xo.seg[bt.gt] =
+        Seg{bt.gt * (uint32_t)(2 * C::kHalo), (uint16_t)na, (uint16_t)nd};
+    xo.tstat[4 * (size_t)bt.gt + 3] = na + nd;
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -712,40 +783,6 @@ __device__ __forceinline__ Tile tile_of_vertex(const Geo &g, uint32_t v,
   uint32_t tx = x / C::TX, ty = y / C::TY, tz = z / C::TZ;
   *tile = tx + g.ntx * (ty + g.nty * tz);
   return Tile{(int)(tx * C::TX), (int)(ty * C::TY), (int)(tz * C::TZ)};
-}
-
-// Exit numbers: an exclusive scan of the tiles' exit counts in tile order,
-// so that the exits of tile t are nodes seg[t].base .. + na + nd - 1.
-__global__ void __launch_bounds__(1024)
-k_seg_scan_blocks(Seg *seg, uint32_t nt, uint32_t *bsum) {
-  __shared__ uint32_t tmp[32];
-  const uint32_t i = blockIdx.x * 1024 + threadIdx.x;
-  const uint32_t c = i < nt ? (uint32_t)seg[i].na + seg[i].nd : 0u;
-  uint32_t tot = 0;
-  const uint32_t ex = block_exclusive_scan(c, tmp, &tot);
-  if (i < nt) seg[i].base = ex;
-  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
-}
-
-__global__ void __launch_bounds__(1024)
-k_seg_scan_sums(uint32_t *bsum, uint32_t nb, unsigned long long *ctr) {
-  __shared__ uint32_t tmp[32];
-  uint32_t carry = 0;
-  for (uint32_t b0 = 0; b0 < nb; b0 += 1024) {
-    const uint32_t i = b0 + threadIdx.x;
-    const uint32_t c = i < nb ? bsum[i] : 0u;
-    uint32_t tot = 0;
-    const uint32_t ex = block_exclusive_scan(c, tmp, &tot);
-    if (i < nb) bsum[i] = carry + ex;
-    carry += tot;
-  }
-  if (threadIdx.x == 0) ctr[kCtrExits] = carry;
-}
-
-__global__ void __launch_bounds__(kBlock)
-k_seg_scan_add(Seg *seg, uint32_t nt, const uint32_t *__restrict__ bsum) {
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < nt) seg[i].base += bsum[i / 1024];
 }
 
 // One block per tile links the tile's exits: exit k is the halo vertex v at
@@ -1308,11 +1345,14 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
     if (!fields[i].desc) need_scratch += align256((size_t)g.N * sizeof(int32_t));
     if (total_tiles > INT32_MAX / 2) return MSC_ERANGE;
   }
+  // Exit-graph nodes: 2 * kHalo fixed slots per tile; node numbers and
+  // final values share 32 bits (bit 31 tags a final value).
+  if (total_tiles * 2 * (uint64_t)C::kHalo >= kRoot) return MSC_ERANGE;
   const uint32_t nt = (uint32_t)total_tiles;
+  const uint32_t nslots = nt * (uint32_t)(2 * C::kHalo);
   unsigned long long *ctr = ctx->dctr;
 
-  uint64_t exits = 0;
-  uint32_t *next = nullptr, *bsum = nullptr;
+  uint32_t *next = nullptr;
   uint16_t *tlist = nullptr;
   uint32_t *tkey = nullptr, *torder = nullptr, *hist = nullptr, *mm = nullptr;
   uint32_t *tfield = nullptr;
@@ -1323,18 +1363,16 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
   std::vector<uint32_t> tf_host(nt);
   for (int i = 0; i < nfields; ++i)
     for (uint32_t k = 0; k < fd[i].g.ntiles; ++k) tf_host[fd[i].tile0 + k] = i;
-  const uint32_t nsb = (nt + 1023) / 1024;  // scan blocks over tiles
-
   const size_t need =
-      need_lp + need_scratch + align256(nt * sizeof(Seg)) +
+      need_lp + need_scratch + align256((size_t)nslots * sizeof(uint32_t)) +
+      align256(nt * sizeof(Seg)) +
       3 * align256(nt * sizeof(uint32_t)) +
       align256((kTileBuckets + 2) * sizeof(uint32_t)) +
       align256(nfields * sizeof(FieldDev)) +
       align256(nfields * kFieldCtrs * sizeof(unsigned long long)) +
       align256(4ull * nt * sizeof(uint32_t)) +
       align256(4ull * nt * sizeof(unsigned long long)) +
-      align256(2ull * C::kHalo * nt * sizeof(uint16_t)) +
-      align256(nsb * sizeof(uint32_t)) + 8192;
+      align256(2ull * C::kHalo * nt * sizeof(uint16_t)) + 8192;
   MSC_TRY(reserve(ctx->ws, need));
   Carver cv(ctx->ws);
   for (int i = 0; i < nfields; ++i) {
@@ -1359,7 +1397,7 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
   tstat = cv.take<uint32_t>(4ull * nt);
   rstat = cv.take<unsigned long long>(4ull * nt);
   tlist = cv.take<uint16_t>(2ull * C::kHalo * nt);
-  bsum = cv.take<uint32_t>(nsb);
+  next = cv.take<uint32_t>(nslots);
 
   // Descriptors and the tile -> field map go up through pinned staging.
   {
@@ -1381,19 +1419,13 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
   k_fill_u32<<<grid_for(4ull * nt), kBlock, 0, s>>>(tstat, 4 * nt, 0u);
   MSC_HIP_TRY(hipGetLastError());
   ExitOut xo{seg, tkey, tstat, tlist};
-  MSC_PHASE(ctx, s, "tile_local", 8.0 * total_n,
+  MSC_PHASE(ctx, s, "tile_local", 12.0 * total_n,
             (k_tile_local<C><<<nt, C::kThreads, 0, s>>>(fds, tfield, xo, ctr,
                                                         fctr)));
-  for (int k = 0; k < 2; ++k)
+  const int kStat[3] = {kFMaxima, kFMinima, kFExits};
+  for (int k = 0; k < 3; ++k)
     k_tile_stat_reduce<<<grid_for(nt), kBlock, 0, s>>>(
-        tstat, k, nt, tfield, fctr, k ? kFMinima : kFMaxima);
-  MSC_PHASE(ctx, s, "exit_scan", 12.0 * nt,
-            (k_seg_scan_blocks<<<nsb, 1024, 0, s>>>(seg, nt, bsum),
-             k_seg_scan_sums<<<1, 1024, 0, s>>>(bsum, nsb, ctr),
-             k_seg_scan_add<<<grid_for(nt), kBlock, 0, s>>>(seg, nt, bsum)));
-  MSC_TRY(read_counters(ctx, s));
-  exits = ctx->hctr[kCtrExits];
-  if (exits >= kRoot) return MSC_ENOMEM;
+        tstat, k == 2 ? 3 : k, nt, tfield, fctr, kStat[k]);
 
   // Per-field counters: NaN check and table sizes.
   std::vector<unsigned long long> fc((size_t)nfields * kFieldCtrs);
@@ -1403,11 +1435,10 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
   for (int i = 0; i < nfields; ++i)
     if (fc[(size_t)i * kFieldCtrs + kFNaN]) return MSC_ENAN;
 
-  if (exits) {
-    const uint32_t ne = (uint32_t)exits;
-    MSC_TRY(reserve(ctx->xg, align256(ne * sizeof(uint32_t))));
-    next = reinterpret_cast<uint32_t *>(ctx->xg.ptr);
-    MSC_PHASE(ctx, s, "exit_link", 18.0 * ne,
+  {
+    // Exit slots are fixed per tile (2 * kHalo from the tile's own base), so
+    // no count has to come back to the host before the graph is built.
+    MSC_PHASE(ctx, s, "exit_link", 18.0 * nt * (double)C::kHalo * 0.5,
               (k_exit_link<C><<<nt, kBlock, 0, s>>>(fds, tfield, seg, tlist,
                                                     next)));
     MSC_PHASE(ctx, s, "tile_order", 12.0 * nt,
@@ -1416,9 +1447,9 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
                k_key_scan<<<1, 1024, 0, s>>>(hist),
                k_key_scatter<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm, hist,
                                                              torder)));
-    MSC_PHASE(ctx, s, "exit_resolve", 12.0 * ne,
+    MSC_PHASE(ctx, s, "exit_resolve", 12.0 * nt * (double)C::kHalo * 0.5,
               (k_exit_resolve<C><<<2 * nt, C::kThreads, 0, s>>>(
-                  torder, nt, seg, ne, next, ctr, rstat)));
+                  torder, nt, seg, nslots, next, ctr, rstat)));
     k_steps_reduce<<<kStepsBlocks, 1024, 0, s>>>(rstat, 2 * nt, ctr);
   }
 
@@ -1467,7 +1498,7 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
     k_tile_stat_reduce<<<grid_for(nt), kBlock, 0, s>>>(tstat, 2, nt, tfield,
                                                        fctr, kFCells);
     MSC_TRY(read_counters(ctx, s));
-    if (ctx->hctr[kCtrOverflow] & 2) return MSC_EHIP;
+    if (ctx->hctr[kCtrOverflow] & 6) return MSC_EHIP;
     if (!(ctx->hctr[kCtrOverflow] & 1)) break;
     bool grew = false;
     for (int i = 0; i < nfields; ++i) {
@@ -1488,7 +1519,7 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
             (k_tile_write<C><<<nt, C::kThreads, 0, s>>>(fds, tfield, seg,
                                                         next)));
   MSC_TRY(read_counters(ctx, s));
-  if (ctx->hctr[kCtrOverflow] & 2) return MSC_EHIP;
+  if (ctx->hctr[kCtrOverflow] & 6) return MSC_EHIP;
   if (ctx->hctr[kCtrOverflow]) return MSC_ENOMEM;
   MSC_HIP_TRY(hipMemcpyAsync(fc.data(), fctr, fc.size() * 8,
                              hipMemcpyDeviceToHost, s));
@@ -1512,7 +1543,10 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
     ctx->stats.n_cells += st.n_cells > 0 ? st.n_cells : 0;
   }
   if (nfields == 1) ctx->stats.n_cells = ctx->field_stats[0].n_cells;
-  ctx->stats.n_exits = (int64_t)exits;
+  for (int i = 0; i < nfields; ++i) {
+    ctx->field_stats[i].n_exits = (int64_t)fc[(size_t)i * kFieldCtrs + kFExits];
+    ctx->stats.n_exits += ctx->field_stats[i].n_exits;
+  }
   ctx->stats.jump_rounds = (int32_t)ctx->hctr[kCtrRounds];
   ctx->stats.exit_steps = (int64_t)ctx->hctr[kCtrSteps];
   ctx->stats.tile_x = C::TX;
@@ -1522,12 +1556,9 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
 }
 
 // Tile shapes compiled in, in the order of kTileShapes.
-using Tile32x32x16 = Cfg<32, 32, 16>;
 using Tile32x16x16 = Cfg<32, 16, 16>;
 using Tile32x8x8 = Cfg<32, 8, 8>;
-using Tile64x16x16 = Cfg<64, 16, 16>;
 using Tile64x8x8 = Cfg<64, 8, 8>;
-using Tile32x32x32 = Cfg<32, 32, 32>;
 using Tile32x8x16 = Cfg<32, 8, 16>;
 using Tile64x8x16 = Cfg<64, 8, 16>;
 
@@ -1537,18 +1568,12 @@ int segment_batch_run(msc_ctx *ctx, int nfields, const msc_field *fields,
                       hipStream_t s, const uint8_t *ghost) {
   switch (ctx->tile_choice) {
     case 1:
-      return segment_batch<Tile32x32x16>(ctx, nfields, fields, ghost, s);
-    case 2:
       return segment_batch<Tile32x8x8>(ctx, nfields, fields, ghost, s);
-    case 3:
-      return segment_batch<Tile64x16x16>(ctx, nfields, fields, ghost, s);
-    case 4:
+    case 2:
       return segment_batch<Tile64x8x8>(ctx, nfields, fields, ghost, s);
-    case 5:
-      return segment_batch<Tile32x32x32>(ctx, nfields, fields, ghost, s);
-    case 6:
+    case 3:
       return segment_batch<Tile32x8x16>(ctx, nfields, fields, ghost, s);
-    case 7:
+    case 4:
       return segment_batch<Tile64x8x16>(ctx, nfields, fields, ghost, s);
     default:
       return segment_batch<Tile32x16x16>(ctx, nfields, fields, ghost, s);
