@@ -64,11 +64,21 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(field_dev, depth: int):
     """The oracle, single-threaded, on the first `depth` z-planes of the
     field taken as a grid of their own."""
-    import numpy as np
-
     from oracle import oracle as O
     slab = field_dev[:depth].cpu().numpy()
     n = slab.size
@@ -76,11 +86,42 @@ def cpu_baseline(field_dev, depth: int):
     O.segment(slab, memo=True)
     dt = time.perf_counter() - t0
     return {"value": n / dt / 1e9, "unit": "Gvertices/s", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "nproc": os.cpu_count(),
+            "cpu_model": cpu_model(), "build": "gcc -O3",
             "sample": f"first {depth} z-planes ({slab.shape[2]}x{slab.shape[1]}"
                       f"x{depth} = {n} vertices) of the same field, "
                       f"{dt:.1f} s, serial C oracle (successors, memoised "
-                      "walks, sort-based cells)"}
+                      "walks, sort-based cells) on one core"}
+
+
+def timed_steps(torch, stream, run, steps):
+    """Time `steps` calls: synchronise, then per call a HIP event pair on the
+    call's stream, synchronise.  Returns (median ms, mean wall ms)."""
+    import statistics
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for a, b in zip(starts, ends):
+        a.record(stream)
+        run()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps * 1e3
+    per = [a.elapsed_time(b) for a, b in zip(starts, ends)]
+    return statistics.median(per), wall
+
+
+def traced_steps(msc, torch, run, steps):
+    """The library's per-kernel event trace over `steps` calls (a pass of
+    its own: the trace adds two event records per launch)."""
+    torch.cuda.synchronize()
+    msc.profile(True)
+    for _ in range(steps):
+        run()
+    torch.cuda.synchronize()
+    msc.profile(False)
+    return msc.profile_read()
 
 
 def traffic_of(workload, kernel, folder=None):
@@ -125,12 +166,21 @@ def roofline_of(prof, workload=None, tile=None):
     achieved = bpl / (avg_ms * 1e-3) / 1e9
     templated = name.startswith(("tile_", "exit_link", "exit_resolve"))
     kname = "k_" + name + ("<%d,%d,%d>" % tile if tile and templated else "")
-    return {"bound": "hbm", "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic_of(workload, kname) if workload else None,
-            "kernel": kname, "avg_ms": round(avg_ms, 4),
-            "bytes_per_launch": bpl}
+    out = {"bound": "hbm", "achieved": round(achieved, 1),
+           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+           "frac": round(achieved / HBM_PEAK_GBS, 4),
+           "traffic": traffic_of(workload, kname) if workload else None,
+           "kernel": kname, "avg_ms": round(avg_ms, 4),
+           "bytes_per_launch": bpl}
+    if name == "tile_local":
+        # The steepest pass's algorithmic bytes as the survey counts them
+        # (f 4 + two int32 pointers 8 = 12 B/vertex); the kernel itself
+        # writes one packed 32-bit code per vertex (f 4 + code 4 = 8 B).
+        n = bpl / 12.0
+        out["bytes_per_vertex"] = 12
+        out["frac_own_bytes_8"] = round(8 * n / (avg_ms * 1e-3) / 1e9 /
+                                        HBM_PEAK_GBS, 4)
+    return out
 
 
 def log_prof(prof):
@@ -404,8 +454,9 @@ TETS_TEXT = {
 }
 
 
-def bench_batch(args, msc, synth, torch, dev):
-    """256 uneven fields: one batched call per step vs. 256 plain calls."""
+def batch_leg(args, msc, synth, torch, dev):
+    """batch256: one batched call vs. 256 plain calls on one stream (both
+    asynchronous, no host synchronisation inside the timed loop)."""
     specs = synth.batch_specs(256, seed=3)
     log("[bench] generating batch256")
     fields = [synth.gaussian_field(d, nb, sd, device=dev) for d, nb, sd in specs]
@@ -416,41 +467,51 @@ def bench_batch(args, msc, synth, torch, dev):
     stream = torch.cuda.current_stream(dev)
     tune = msc.autotune(fields, outs, stream=stream)
     log(f"[bench] autotune {tune}")
-    for _ in range(args.warmup):
-        msc.segment_batched_into(fields, outs, stream=stream)
-    torch.cuda.synchronize()
-    msc.profile(True)
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        msc.segment_batched_into(fields, outs, stream=stream)
-    torch.cuda.synchronize()
-    dt_batch = (time.perf_counter() - t0) / args.steps
-    msc.profile(False)
-    prof = msc.profile_read()
-    # The same fields, one plain call each.
-    for f, (a, d, m) in zip(fields[:8], outs[:8]):
-        msc.segment_into(f, a, d, m, stream=stream)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
+
+    def batched():
+        msc.segment_batched_into(fields, outs, stream=stream, check=False)
+
+    def plain():
         for f, (a, d, m) in zip(fields, outs):
-            msc.segment_into(f, a, d, m, stream=stream)
+            msc.segment_into(f, a, d, m, stream=stream, check=False)
+
+    for _ in range(max(1, args.warmup)):
+        batched()
+        plain()
     torch.cuda.synchronize()
-    dt_plain = (time.perf_counter() - t0) / args.steps
-    log(f"[bench] batched {dt_batch * 1e3:.2f} ms vs plain {dt_plain * 1e3:.2f} ms"
-        f" for {n} vertices")
+    if msc.last_status() != msc.MSC_OK:
+        raise msc.MscError(msc.last_status(), "batch256")
+    steps = max(3, args.steps)
+    b_ms, b_wall = timed_steps(torch, stream, batched, steps)
+    p_ms, p_wall = timed_steps(torch, stream, plain, steps)
+    prof = traced_steps(msc, torch, batched, 2)
+    msc.set_tile(*msc.tile_shapes()[0])
+    log(f"[bench] batch256: batched {b_ms:.2f} ms vs plain {p_ms:.2f} ms "
+        f"for {n} vertices")
+    return {"workload": BATCH_TEXT, "vertices": n, "tile": list(tune["tile"]),
+            "batched_ms": round(b_ms, 3), "plain_ms": round(p_ms, 3),
+            "batched_wall_ms": round(b_wall, 3),
+            "plain_wall_ms": round(p_wall, 3),
+            "batched_gvps": round(n / (b_ms * 1e-3) / 1e9, 3),
+            "plain_gvps": round(n / (p_ms * 1e-3) / 1e9, 3),
+            "speedup_vs_plain": round(p_ms / b_ms, 2),
+            "steps": steps, "roofline": roofline_of(prof)}
+
+
+def bench_batch(args, msc, synth, torch, dev):
+    """256 uneven fields: one batched call per step vs. 256 plain calls."""
+    leg = batch_leg(args, msc, synth, torch, dev)
     out = {
         "metric": "Gvertices/s batched MS segmentation (256 uneven fields)",
-        "value": round(n / dt_batch / 1e9, 3), "unit": "Gvertices/s",
-        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(dt_batch * 1e3, 3), "higher_is_better": True,
+        "value": leg["batched_gvps"], "unit": "Gvertices/s",
+        "n_gpus": 1, "steps": leg["steps"], "warmup": args.warmup,
+        "ms_per_step": leg["batched_ms"], "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": BATCH_TEXT, "vertices": n,
-                   "tile": list(tune["tile"]),
-                   "plain_ms_per_step": round(dt_plain * 1e3, 3),
-                   "speedup_vs_plain": round(dt_plain / dt_batch, 2)},
-        "roofline": roofline_of(prof),
+        "config": {"workload": BATCH_TEXT, "vertices": leg["vertices"],
+                   "tile": leg["tile"], "plain_ms_per_step": leg["plain_ms"],
+                   "speedup_vs_plain": leg["speedup_vs_plain"]},
+        "roofline": leg["roofline"],
     }
     print(json.dumps(out), flush=True)
 
@@ -548,7 +609,7 @@ def run_plain(msc, torch, dev, pool, trace, warm):
             f = fh.to(dev, non_blocking=True)
             a = torch.empty(f.numel(), dtype=torch.int32, device=dev)
             d, m = torch.empty_like(a), torch.empty_like(a)
-            msc.segment_into(f, a, d, m, stream=stream)
+            msc.segment_into(f, a, d, m, stream=stream, check=False)
         else:
             msc.cc_label_grid(mh.to(dev, non_blocking=True), stream=stream)
         torch.cuda.synchronize()
@@ -631,6 +692,8 @@ def main():
     ap.add_argument("--serve-pool", type=int, default=48)
     ap.add_argument("--no-serve", action="store_true",
                     help="skip the short served leg of the default run")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batch256 leg of the default run")
     ap.add_argument("--ranks", type=int, default=1,
                     help="virtual z-slab ranks on the one device (the "
                          "paper's distributed scheme; 1 = single domain)")
@@ -697,7 +760,7 @@ def main():
             msc.segment_ranks_into(field, args.ranks, asc, desc, ms,
                                    stream=stream)
         else:
-            msc.segment_into(field, asc, desc, ms, stream=stream)
+            msc.segment_into(field, asc, desc, ms, stream=stream, check=False)
 
     for i in range(args.warmup):
         segment(field, asc, desc, ms)
@@ -705,19 +768,15 @@ def main():
     torch.cuda.synchronize()
     stats = msc.last_stats()
     log(f"[bench] stats {stats}")
+    if stats["status"] != msc.MSC_OK:
+        raise msc.MscError(stats["status"], "segmentation")
 
-    msc.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        segment(field, asc, desc, ms)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    msc.profile(False)
-    prof = msc.profile_read()
-    ms_per_step = dt / args.steps * 1e3
-    value = n / (dt / args.steps) / 1e9
-    log(f"[bench] {args.steps} steps in {dt:.3f} s: {ms_per_step:.2f} ms/step")
+    run = lambda: segment(field, asc, desc, ms)
+    ms_per_step, wall_ms = timed_steps(torch, stream, run, args.steps)
+    value = n / (ms_per_step * 1e-3) / 1e9
+    log(f"[bench] {args.steps} steps: median {ms_per_step:.3f} ms/step "
+        f"(HIP events), wall {wall_ms:.3f} ms/step")
+    prof = traced_steps(msc, torch, run, args.steps)
     log_prof(prof)
     tile = (stats["tile_x"], stats["tile_y"], stats["tile_z"])
     roofline = roofline_of(prof, args.workload, tile)
@@ -734,10 +793,15 @@ def main():
         "ms_per_step": round(ms_per_step, 3), "higher_is_better": True,
         "scaling": "weak", "vs_baseline": vs, "dtype": "f32",
         "data": "synthetic",
+        "timing": "median of per-step HIP events on the call's stream, "
+                  "trace off; wall_ms_per_step is the synchronised wall "
+                  "clock over the same steps",
+        "wall_ms_per_step": round(wall_ms, 3),
         "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "vertices": n, "outputs": "int32 asc, desc, ms",
                    "maxima": stats["n_maxima"], "minima": stats["n_minima"],
-                   "cells": stats["n_cells"], "virtual_ranks": args.ranks},
+                   "cells": stats["n_cells"], "exits": stats["n_exits"],
+                   "virtual_ranks": args.ranks},
         "roofline": roofline,
         # Whole call: the compulsory 16 B per vertex (read f, write asc, desc,
         # ms) and the rocprofv3-measured HBM bytes of all kernels, per step.
@@ -758,9 +822,12 @@ def main():
         depth = min(args.cpu_depth, field.shape[0])
         log(f"[bench] timing the CPU oracle on {depth} z-planes")
         out["cpu_baseline"] = cpu_baseline(field, depth)
+    if not args.no_batch:
+        del field, asc, desc, ms
+        torch.cuda.empty_cache()
+        out["batched"] = batch_leg(args, msc, synth, torch, dev)
     if not args.no_serve:
         # Short served leg: a light, a busy and a saturating arrival rate.
-        del field, asc, desc, ms
         torch.cuda.empty_cache()
         text, res, res_dev = served_sweep(msc, synth, torch, dev,
                                           [200, 1000, 2000], 50, 300, 24,

@@ -10,9 +10,15 @@
  *  - Buffers named "device" are device pointers on the context's GPU, owned
  *    by the caller; the library never frees or keeps them past the call.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
- *    device work of a call is enqueued on it.  Calls may block the host while
- *    they read small convergence counters back from the device; when a call
- *    returns MSC_OK its outputs are complete once `stream` has completed.
+ *    device work of a call is enqueued on it.  msc_segment,
+ *    msc_segment_batched and cc_label_grid return with their work only
+ *    enqueued (the host waits only when a workspace has to grow); their
+ *    outputs are complete once `stream` has completed, and conditions that
+ *    the device detects (a NaN in a field) are reported afterwards by
+ *    msc_last_status and the stats calls.  Calls documented as synchronising
+ *    read counts back and return when their work is done.  Calls on one
+ *    context are ordered in call order even across streams (a call on
+ *    another stream waits for the previous call's work on the device).
  *  - Outputs must not alias inputs or each other.
  *  - Return value: MSC_OK (0) or one of the MSC_E* codes below; nothing is
  *    thrown across the ABI.  On an error the contents of the outputs are
@@ -89,8 +95,14 @@ MSC_API void msc_destroy(msc_ctx *ctx);
  *         descent (the paper's "ascending manifold").
  *  ms     device, int32[N] or NULL: Morse-Smale cell id = smallest vertex id
  *         u with asc[u] == asc[v] and desc[u] == desc[v].
- *  Errors: MSC_EINVAL (dims < 1, field NULL, all outputs NULL),
- *          MSC_ERANGE (N > INT32_MAX), MSC_ENAN, MSC_ENOMEM, MSC_EHIP.
+ *  Asynchronous on `stream`.  Workspace (device, held by the context):
+ *  about 8 bytes per vertex, plus a cell table of which at most 2 * N slots
+ *  of 12 bytes are reserved and only the part the extremum counts call for
+ *  is used.
+ *  Errors returned: MSC_EINVAL (dims < 1, field NULL, all outputs NULL),
+ *          MSC_ERANGE (N > INT32_MAX), MSC_ENOMEM, MSC_EHIP.
+ *  Reported by msc_last_status after the work has run: MSC_ENAN (outputs
+ *  undefined), MSC_EHIP (a broken internal invariant).
  */
 MSC_API int msc_segment(msc_ctx *ctx, const float *field, const int64_t dims[3],
                 int32_t *asc, int32_t *desc, int32_t *ms, void *stream);
@@ -212,12 +224,25 @@ typedef struct msc_stats {
   int32_t jump_rounds;   /* longest exit-graph chain one exit followed */
   int32_t tile_x, tile_y, tile_z; /* tile of the fused local pass     */
   int64_t exit_steps;    /* exit-graph links followed in total        */
+  int32_t status;        /* outcome on the device (MSC_OK, MSC_ENAN)  */
+  int32_t reserved;
 } msc_stats;
 
+/* Counters of the last segmentation call (they wait for its work). */
 MSC_API int msc_last_stats(const msc_ctx *ctx, msc_stats *out);
 
-/* Counters of field `index` of the last successful segmentation call (a
- * single msc_segment is a batch of one). */
+/*
+ * Outcome of the last asynchronous call on this context, as the device
+ * found it: waits until the call's work has run, then sets *status to
+ * MSC_OK, MSC_ENAN (a field held a NaN; in a batch, the fields whose
+ * msc_last_field_stats status is MSC_ENAN) or MSC_EHIP.  Returns MSC_EINVAL
+ * for NULL arguments or MSC_EHIP if the wait fails.
+ */
+MSC_API int msc_last_status(msc_ctx *ctx, int *status);
+
+/* Counters of field `index` of the last segmentation call (a single
+ * msc_segment is a batch of one); `status` is that field's outcome, so a
+ * NaN in one field of a batch does not invalidate the others. */
 MSC_API int msc_last_field_stats(const msc_ctx *ctx, int index,
                                  msc_stats *out);
 

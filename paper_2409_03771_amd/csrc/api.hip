@@ -9,10 +9,11 @@
 
 namespace msc {
 
-int reserve(DevBuf &buf, size_t bytes) {
+int reserve(msc_ctx *ctx, DevBuf &buf, size_t bytes) {
   if (bytes <= buf.bytes) return MSC_OK;
-  // The old block may still be read by work queued on any stream.
-  MSC_HIP_TRY(hipDeviceSynchronize());
+  // The old block may still be read by this context's queued work.
+  if (ctx->done_valid) MSC_HIP_TRY(hipEventSynchronize(ctx->done));
+  ++ctx->grows;
   if (buf.ptr) {
     MSC_HIP_TRY(hipFree(buf.ptr));
     buf.ptr = nullptr;
@@ -46,6 +47,46 @@ int clear_counters(msc_ctx *ctx, hipStream_t stream) {
   return zero_u64(ctx->dctr, kNumCounters, stream);
 }
 
+int begin_call(msc_ctx *ctx, hipStream_t s) {
+  if (ctx->done_valid && ctx->last_stream != s)
+    MSC_HIP_TRY(hipStreamWaitEvent(s, ctx->done, 0));
+  return MSC_OK;
+}
+
+int end_call(msc_ctx *ctx, hipStream_t s) {
+  MSC_HIP_TRY(hipEventRecord(ctx->done, s));
+  ctx->last_stream = s;
+  ctx->done_valid = true;
+  return MSC_OK;
+}
+
+int pinned_slot(msc_ctx *ctx, size_t bytes, void **out, int *slot) {
+  const int k = ctx->next_slot;
+  ctx->next_slot = (k + 1) % kPinnedSlots;
+  PinnedSlot &ps = ctx->slots[k];
+  // The copy that last read this slot must have executed.
+  if (ps.pending) MSC_HIP_TRY(hipEventSynchronize(ps.copied));
+  ps.pending = false;
+  if (bytes > ps.bytes) {
+    if (ps.ptr) (void)hipHostFree(ps.ptr);
+    ps.ptr = nullptr;
+    ps.bytes = 0;
+    const size_t want = bytes + bytes / 4 + 4096;
+    if (hipHostMalloc(&ps.ptr, want, hipHostMallocDefault) != hipSuccess)
+      return MSC_ENOMEM;
+    ps.bytes = want;
+  }
+  *out = ps.ptr;
+  *slot = k;
+  return MSC_OK;
+}
+
+int slot_copied(msc_ctx *ctx, int slot, hipStream_t s) {
+  MSC_HIP_TRY(hipEventRecord(ctx->slots[slot].copied, s));
+  ctx->slots[slot].pending = true;
+  return MSC_OK;
+}
+
 int read_counters(msc_ctx *ctx, hipStream_t stream) {
   MSC_HIP_TRY(hipMemcpyAsync(ctx->hctr, ctx->dctr,
                              kNumCounters * sizeof(unsigned long long),
@@ -70,6 +111,14 @@ struct DeviceGuard {
     if (prev >= 0) (void)hipSetDevice(prev);
   }
 };
+
+// Entry of a call that synchronises: the pending counters of an earlier
+// asynchronous call are folded first (this call replaces the stats), and
+// the call's work is ordered after that call's.
+int enter_sync(msc_ctx *ctx, hipStream_t s) {
+  MSC_TRY(msc::finish_last(ctx));
+  return msc::begin_call(ctx, s);
+}
 
 int check_dims(const int64_t dims[3], int64_t *n) {
   if (!dims) return MSC_EINVAL;
@@ -126,6 +175,15 @@ int msc_create(msc_ctx **out, int device) {
     return MSC_ENOMEM;
   }
   std::memset(c->hctr, 0, msc::kNumCounters * sizeof(unsigned long long));
+  bool ev_ok = hipEventCreateWithFlags(&c->done, hipEventDisableTiming) ==
+               hipSuccess;
+  for (int k = 0; ev_ok && k < msc::kPinnedSlots; ++k)
+    ev_ok = hipEventCreateWithFlags(&c->slots[k].copied,
+                                    hipEventDisableTiming) == hipSuccess;
+  if (!ev_ok) {
+    msc_destroy(c);
+    return MSC_EHIP;
+  }
   // Tile shape override for tuning runs, e.g. MSC_TILE=32x16x16.
   if (const char *t = std::getenv("MSC_TILE")) {
     int tx = 0, ty = 0, tz = 0;
@@ -149,6 +207,12 @@ void msc_destroy(msc_ctx *ctx) {
   if (ctx->rk.ptr) (void)hipFree(ctx->rk.ptr);
   if (ctx->dctr) (void)hipFree(ctx->dctr);
   if (ctx->hctr) (void)hipHostFree(ctx->hctr);
+  if (ctx->hfctr) (void)hipHostFree(ctx->hfctr);
+  for (msc::PinnedSlot &ps : ctx->slots) {
+    if (ps.ptr) (void)hipHostFree(ps.ptr);
+    if (ps.copied) (void)hipEventDestroy(ps.copied);
+  }
+  if (ctx->done) (void)hipEventDestroy(ctx->done);
   delete ctx;
 }
 
@@ -169,6 +233,7 @@ int msc_segment_ranks(msc_ctx *ctx, const float *field, const int64_t dims[3],
   if (ranks < 1 || ranks > dims[2]) return MSC_EINVAL;
   DeviceGuard g(ctx->device);
   if (!g.ok) return MSC_EHIP;
+  MSC_TRY(enter_sync(ctx, static_cast<hipStream_t>(stream)));
   return msc::segment_ranks_run(ctx, field, dims, ranks, asc, desc, ms,
                                 static_cast<hipStream_t>(stream));
 }
@@ -182,6 +247,7 @@ int msc_segment_csr(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,
     return MSC_EINVAL;
   DeviceGuard g(ctx->device);
   if (!g.ok) return MSC_EHIP;
+  MSC_TRY(enter_sync(ctx, static_cast<hipStream_t>(stream)));
   return msc::segment_csr_run(ctx, n, row_ptr, col_idx, field, asc, desc, ms,
                               static_cast<hipStream_t>(stream));
 }
@@ -204,9 +270,20 @@ int msc_segment_batched(msc_ctx *ctx, int nfields, const msc_field *fields,
 }
 
 int msc_last_field_stats(const msc_ctx *ctx, int index, msc_stats *out) {
-  if (!ctx || !out || index < 0 || index >= (int)ctx->field_stats.size())
-    return MSC_EINVAL;
+  if (!ctx || !out) return MSC_EINVAL;
+  msc_ctx *c = const_cast<msc_ctx *>(ctx);
+  DeviceGuard g(c->device);
+  MSC_TRY(msc::finish_last(c));
+  if (index < 0 || index >= (int)ctx->field_stats.size()) return MSC_EINVAL;
   *out = ctx->field_stats[index];
+  return MSC_OK;
+}
+
+int msc_last_status(msc_ctx *ctx, int *status) {
+  if (!ctx || !status) return MSC_EINVAL;
+  DeviceGuard g(ctx->device);
+  MSC_TRY(msc::finish_last(ctx));
+  *status = ctx->last.status;
   return MSC_OK;
 }
 
@@ -286,6 +363,9 @@ int msc_set_table_capacity(msc_ctx *ctx, uint64_t first_capacity) {
 
 int msc_last_stats(const msc_ctx *ctx, msc_stats *out) {
   if (!ctx || !out) return MSC_EINVAL;
+  msc_ctx *c = const_cast<msc_ctx *>(ctx);
+  DeviceGuard g(c->device);
+  MSC_TRY(msc::finish_last(c));
   *out = ctx->stats;
   return MSC_OK;
 }
@@ -305,6 +385,13 @@ int msc_profile(msc_ctx *ctx, int enable) {
 
 int msc_profile_read(const msc_ctx *ctx, msc_phase *out, int max, int *count) {
   if (!ctx || !count || max < 0 || (max > 0 && !out)) return MSC_EINVAL;
+  // Fold the recorded launches (their events must have completed).
+  msc_ctx *c = const_cast<msc_ctx *>(ctx);
+  if (!c->prof.pending.empty()) {
+    DeviceGuard g(c->device);
+    MSC_HIP_TRY(hipEventSynchronize(c->prof.pending.back().b));
+    c->prof.flush();
+  }
   int n = (int)ctx->prof.totals.size();
   *count = n;
   for (int i = 0; i < n && i < max; ++i) out[i] = ctx->prof.totals[i];
@@ -318,8 +405,11 @@ int cc_label_grid(msc_ctx *ctx, const uint8_t *mask, const int64_t dims[3],
   MSC_TRY(check_dims(dims, &n));
   DeviceGuard g(ctx->device);
   if (!g.ok) return MSC_EHIP;
-  return msc::cc_grid_run(ctx, mask, dims[0], dims[1], dims[2], labels,
-                          static_cast<hipStream_t>(stream));
+  ctx->last.pending = false;  // this call replaces the stats
+  MSC_TRY(msc::begin_call(ctx, static_cast<hipStream_t>(stream)));
+  MSC_TRY(msc::cc_grid_run(ctx, mask, dims[0], dims[1], dims[2], labels,
+                           static_cast<hipStream_t>(stream)));
+  return msc::end_call(ctx, static_cast<hipStream_t>(stream));
 }
 
 int cc_label_grid_ranks(msc_ctx *ctx, const uint8_t *mask,
@@ -331,6 +421,7 @@ int cc_label_grid_ranks(msc_ctx *ctx, const uint8_t *mask,
   if (ranks < 1 || ranks > dims[2]) return MSC_EINVAL;
   DeviceGuard g(ctx->device);
   if (!g.ok) return MSC_EHIP;
+  MSC_TRY(enter_sync(ctx, static_cast<hipStream_t>(stream)));
   return msc::cc_grid_ranks_run(ctx, mask, dims[0], dims[1], dims[2], ranks,
                                 labels, static_cast<hipStream_t>(stream));
 }
@@ -343,6 +434,7 @@ int msc_critical_points(msc_ctx *ctx, const float *field,
   if (n > INT32_MAX) return MSC_ERANGE;
   DeviceGuard g(ctx->device);
   if (!g.ok) return MSC_EHIP;
+  MSC_TRY(enter_sync(ctx, static_cast<hipStream_t>(stream)));
   return msc::critical_points_run(ctx, field, dims, code,
                                   static_cast<hipStream_t>(stream));
 }
@@ -357,6 +449,7 @@ int msc_extremum_graph(msc_ctx *ctx, const float *field, const int64_t dims[3],
   if (n > INT32_MAX) return MSC_ERANGE;
   DeviceGuard g(ctx->device);
   if (!g.ok) return MSC_EHIP;
+  MSC_TRY(enter_sync(ctx, static_cast<hipStream_t>(stream)));
   return msc::extremum_graph_run(ctx, field, dims, asc, desc, edges, capacity,
                                  count, static_cast<hipStream_t>(stream));
 }
@@ -369,6 +462,7 @@ int msc_csr_from_tets(msc_ctx *ctx, int64_t n, int64_t ntets,
   if (ntets > 0 && !tets) return MSC_EINVAL;
   DeviceGuard g(ctx->device);
   if (!g.ok) return MSC_EHIP;
+  MSC_TRY(enter_sync(ctx, static_cast<hipStream_t>(stream)));
   return msc::csr_from_tets_run(ctx, n, ntets, tets, row_ptr, col_idx,
                                 capacity, nnz,
                                 static_cast<hipStream_t>(stream));
@@ -383,6 +477,7 @@ int cc_label_csr(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,
   if (!row_ptr || !labels) return MSC_EINVAL;
   DeviceGuard g(ctx->device);
   if (!g.ok) return MSC_EHIP;
+  MSC_TRY(enter_sync(ctx, static_cast<hipStream_t>(stream)));
   return msc::cc_csr_run(ctx, n, row_ptr, col_idx, mask, labels,
                          static_cast<hipStream_t>(stream));
 }
@@ -394,6 +489,7 @@ int msc_pointer_jump(msc_ctx *ctx, int64_t *d, int64_t n, int rounds,
   if (!d) return MSC_EINVAL;
   DeviceGuard g(ctx->device);
   if (!g.ok) return MSC_EHIP;
+  MSC_TRY(enter_sync(ctx, static_cast<hipStream_t>(stream)));
   return msc::jump_run(ctx, d, n, rounds, synchronous,
                        static_cast<hipStream_t>(stream));
 }

@@ -531,7 +531,7 @@ int cc_grid_run(msc_ctx *ctx, const uint8_t *mask, int64_t X, int64_t Y,
          (Z + CTZ - 1) / CTZ};
   const int64_t ntiles = g.ntx * g.nty * g.ntz;
   if (ntiles > INT32_MAX) return MSC_ERANGE;
-  MSC_TRY(reserve(ctx->ws, align256(g.N * sizeof(uint16_t)) + 4096));
+  MSC_TRY(reserve(ctx, ctx->ws, align256(g.N * sizeof(uint16_t)) + 4096));
   Carver cv(ctx->ws);
   uint16_t *loc = cv.take<uint16_t>(g.N);
   MSC_TRY(clear_counters(ctx, s));
@@ -547,7 +547,7 @@ int cc_grid_run(msc_ctx *ctx, const uint8_t *mask, int64_t X, int64_t Y,
               (k_cc_root_shift<<<nb, kCThreads, 0, s>>>(g, loc, labels,
                                                         label_off)));
   if (!sync) return MSC_OK;
-  MSC_TRY(read_counters(ctx, s));
+  // Nothing to read back: the labels are the whole result.
   ctx->stats = msc_stats{};
   ctx->stats.n_vertices = g.N;
   ctx->stats.tile_x = CTX;
@@ -599,7 +599,7 @@ int jump_run(msc_ctx *ctx, int64_t *d, int64_t n, int rounds, int sync,
     }
     return MSC_OK;
   }
-  MSC_TRY(reserve(ctx->ws, align256(n * sizeof(int64_t)) + 4096));
+  MSC_TRY(reserve(ctx, ctx->ws, align256(n * sizeof(int64_t)) + 4096));
   Carver cv(ctx->ws);
   int64_t *tmp = cv.take<int64_t>(n);
   int64_t *src = d, *dst = tmp;
@@ -694,7 +694,7 @@ int cc_grid_ranks_run(msc_ctx *ctx, const uint8_t *mask, int64_t X,
                       hipStream_t s) {
   const int64_t XY = X * Y, N = XY * Z;
   const int64_t thickest = (Z + ranks - 1) / ranks;
-  MSC_TRY(reserve(ctx->ws, align256(XY * thickest * sizeof(uint16_t)) + 4096));
+  MSC_TRY(reserve(ctx, ctx->ws, align256(XY * thickest * sizeof(uint16_t)) + 4096));
   for (int r = 0; r < ranks; ++r) {
     const int64_t z0 = r * Z / ranks, z1 = (r + 1) * Z / ranks;
     // No host round trip per slab: the slabs queue on the stream (the
@@ -931,7 +931,7 @@ int csr_from_tets_run(msc_ctx *ctx, int64_t n, int64_t ntets,
                       int64_t capacity, int64_t *nnz, hipStream_t s) {
   const int64_t nb = (n + kScan - 1) / kScan;
   const int64_t ncand = 12 * ntets;
-  MSC_TRY(reserve(ctx->ws, align256(n * 4) + align256((n + 1) * 8) +
+  MSC_TRY(reserve(ctx, ctx->ws, align256(n * 4) + align256((n + 1) * 8) +
                                align256(nb * 8 + 8) + align256(ncand * 4) +
                                4096));
   Carver cv(ctx->ws);
@@ -1251,7 +1251,7 @@ k_egraph_write(const float *__restrict__ f, int64_t X, int64_t Y, int64_t Z,
 int critical_points_run(msc_ctx *ctx, const float *field, const int64_t *dims,
                         uint8_t *code, hipStream_t s) {
   const int64_t X = dims[0], Y = dims[1], Z = dims[2], N = X * Y * Z;
-  MSC_TRY(reserve(ctx->ws, align256(kLinkSets) + align256(2 * kLinkSets)));
+  MSC_TRY(reserve(ctx, ctx->ws, align256(kLinkSets) + align256(2 * kLinkSets)));
   Carver cv(ctx->ws);
   uint8_t *ncomp = cv.take<uint8_t>(kLinkSets);
   uint16_t *first = cv.take<uint16_t>(kLinkSets);
@@ -1275,7 +1275,7 @@ int extremum_graph_run(msc_ctx *ctx, const float *field, const int64_t *dims,
   const int64_t X = dims[0], Y = dims[1], Z = dims[2], N = X * Y * Z;
   const int64_t nb = (N + kBlock - 1) / kBlock;
   const int64_t nsb = (nb + kScan - 1) / kScan;
-  MSC_TRY(reserve(ctx->ws, align256(nb * 4) + align256((nb + 1) * 8) +
+  MSC_TRY(reserve(ctx, ctx->ws, align256(nb * 4) + align256((nb + 1) * 8) +
                                align256(nsb * 8 + 8) + align256(kLinkSets) +
                                align256(2 * kLinkSets) + 4096));
   Carver cv(ctx->ws);

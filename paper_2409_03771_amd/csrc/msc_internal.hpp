@@ -99,6 +99,29 @@ struct Profiler {
 };
 }  // namespace msc
 
+namespace msc {
+// Pinned host slot for a call's small host-to-device copies; reused once the
+// copy that last read it has executed (its event has completed).
+struct PinnedSlot {
+  void *ptr = nullptr;
+  size_t bytes = 0;
+  hipEvent_t copied = nullptr;
+  bool pending = false;
+};
+constexpr int kPinnedSlots = 8;
+
+// What the stats calls need of the last segmentation call; its counters
+// arrive in pinned memory when the call's work completes.
+struct LastCall {
+  bool pending = false;          // counters not folded into the stats yet
+  int nfields = 0;
+  std::vector<int64_t> n;        // vertices per field
+  std::vector<char> has_ms;      // cells requested per field
+  int tile[3] = {0, 0, 0};
+  int status = MSC_OK;           // device-detected outcome of the call
+};
+}  // namespace msc
+
 struct msc_ctx {
   int device = 0;
   // Grow-only device workspaces carved per call: `ws` for per-vertex
@@ -115,13 +138,41 @@ struct msc_ctx {
   void *pinned = nullptr;      // grow-only pinned host staging
   size_t pinned_bytes = 0;
   std::vector<msc_stats> field_stats;  // per field of the last batch
+  // Calls return with their work enqueued.  `done` is recorded on the
+  // call's stream after its last work; a call on another stream first
+  // waits for it (the workspaces are shared), and the stats calls wait for
+  // it before reading the counters.
+  hipEvent_t done = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool done_valid = false;
+  msc::PinnedSlot slots[msc::kPinnedSlots];
+  int next_slot = 0;
+  unsigned long long *hfctr = nullptr;  // pinned per-field counters
+  size_t hfctr_cap = 0;                 // entries
+  msc::LastCall last;
+  // Workspace growths (each one waits for the context's earlier work).
+  int64_t grows = 0;
 };
 
 namespace msc {
 
-// Make sure `buf` holds at least `bytes`.  Growing synchronises the device
-// (the old block may still be in use) and discards the old contents.
-int reserve(DevBuf &buf, size_t bytes);
+// Make sure `buf` holds at least `bytes`.  Growing waits for the context's
+// earlier work (the old block may still be in use) and discards the old
+// contents.
+int reserve(msc_ctx *ctx, DevBuf &buf, size_t bytes);
+
+// Order a call on stream `s` after the context's previous call (which may
+// have run on another stream), and mark the end of a call's work.
+int begin_call(msc_ctx *ctx, hipStream_t s);
+int end_call(msc_ctx *ctx, hipStream_t s);
+
+// A pinned host buffer of at least `bytes` for one host-to-device copy on
+// `s`; call slot_copied after issuing the copy.
+int pinned_slot(msc_ctx *ctx, size_t bytes, void **out, int *slot);
+int slot_copied(msc_ctx *ctx, int slot, hipStream_t s);
+
+// Wait for the last segmentation call and fold its counters into the stats.
+int finish_last(msc_ctx *ctx);
 
 // Bump allocator over a DevBuf for the duration of one call.
 struct Carver {
@@ -199,7 +250,7 @@ int extremum_graph_run(msc_ctx *ctx, const float *field, const int64_t *dims,
 int segment_csr_run(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,
                     const int32_t *col_idx, const float *field, int32_t *asc,
                     int32_t *desc, int32_t *ms, hipStream_t stream);
-// `sync` false skips the closing counter read (the caller synchronises).
+// `sync` false marks a slab of a larger call (no stats of its own).
 // label_off is added to every written label (a slab labelled in place
 // inside a larger grid gets global ids).
 int cc_grid_run(msc_ctx *ctx, const uint8_t *mask, int64_t X, int64_t Y,

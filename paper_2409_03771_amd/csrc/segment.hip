@@ -224,6 +224,17 @@ struct BlockTile {
   FieldDev fd;
 };
 
+__device__ __forceinline__ BlockTile block_tile_at(const FieldDev *fds,
+                                                   const uint32_t *tfield,
+                                                   uint32_t blk, uint32_t nb) {
+  BlockTile b;
+  b.gt = tile_of_block(blk, nb);
+  b.fi = tfield[b.gt];
+  b.fd = fds[b.fi];
+  b.tile = b.gt - b.fd.tile0;
+  return b;
+}
+
 __device__ __forceinline__ BlockTile block_tile(const FieldDev *fds,
                                                 const uint32_t *tfield) {
   BlockTile b;
@@ -1095,88 +1106,94 @@ __global__ void __launch_bounds__(C::kThreads)
 k_tile_pairs(const FieldDev *__restrict__ fds,
              const uint32_t *__restrict__ tfield, const Seg *__restrict__ seg,
              const uint32_t *__restrict__ R, unsigned long long *ctr,
-             uint32_t *tstat) {
+             uint32_t *tstat, uint32_t ntiles, const uint32_t *run) {
   __shared__ Decode<C> s;
   __shared__ uint32_t s_fresh[C::kThreads / 64];
   __shared__ unsigned long long skey[kPairSlots];
   __shared__ int32_t sval[kPairSlots];
   __shared__ unsigned sfill;
   const int tid = threadIdx.x;
-  const BlockTile bt = block_tile(fds, tfield);
-  if (!bt.fd.ms) return;
-  const Geo &g = bt.fd.g;
-  const Tile t = tile_at<C>(g, bt.tile);
-  for (int i = tid; i < kPairSlots; i += C::kThreads) {
-    skey[i] = kEmptyKey;
-    sval[i] = INT32_MAX;
-  }
-  if (tid == 0) sfill = 0;
-  const int cx = tid % C::TX, cy = tid / C::TX;
-  const int gx = t.x0 + cx, gy = t.y0 + cy;
-  const bool col_in = gx < (int)g.X && gy < (int)g.Y;
-  int nz = (int)g.Z - t.z0;
-  nz = col_in ? (nz < C::TZ ? nz : C::TZ) : 0;
-  // Column offset within a plane; plane bases are uniform over the block.
-  const uint32_t col = (uint32_t)gx + g.X * (uint32_t)gy;
-  uint32_t code[C::TZ];
-#pragma unroll
-  for (int lz = 0; lz < C::TZ; ++lz)
-    code[lz] = lz < nz ? plane_ptr(bt.fd.lp, g, t.z0 + lz)[col] : 0u;
-  decode_setup<C>(s, bt.gt, seg, R, g, t);
-
-  unsigned fresh = 0;
-  bool overflow = false;
-  // Only the smallest id of each pair matters.  A vertex whose pair equals
-  // that of the vertex below it (previous z of the column) or of the lane
-  // before it (a smaller id in the same plane) is not that smallest id and
-  // needs nothing; the smallest one matches neither, so it is never skipped.
-  // In smooth regions this leaves few lanes per plane, and most waves skip
-  // the insert altogether.
-  const bool first_lane = (tid & 63) == 0;
-  unsigned long long last = kEmptyKey;
-#pragma unroll
-  for (int lz = 0; lz < C::TZ; ++lz) {
-    unsigned long long key = kEmptyKey;
-    if (lz < nz) {
-      // The final labels are written here, where the pass is bound by its
-      // arithmetic and the stores overlap it; the output pass then writes
-      // only the cell ids.
-      const int32_t a = decode_final<C>(s, code[lz] & 0xffffu, false);
-      const int32_t d = decode_final<C>(s, code[lz] >> 16, true);
-      plane_ptr(bt.fd.A, g, t.z0 + lz)[col] = a;
-      plane_ptr(bt.fd.D, g, t.z0 + lz)[col] = d;
-      key = pair_key(a, d);
+  // The second pass (after an overflow) runs only when *run is set, over a
+  // smaller grid that strides through the tiles.
+  if (run && !*run) return;
+  for (uint32_t blk = blockIdx.x; blk < ntiles; blk += gridDim.x) {
+    const BlockTile bt = block_tile_at(fds, tfield, blk, ntiles);
+    if (!bt.fd.ms) continue;  // uniform over the block
+    const Geo &g = bt.fd.g;
+    const Tile t = tile_at<C>(g, bt.tile);
+    for (int i = tid; i < kPairSlots; i += C::kThreads) {
+      skey[i] = kEmptyKey;
+      sval[i] = INT32_MAX;
     }
-    const unsigned long long left = __shfl_up(key, 1);
-    const bool repeat = key == last || (!first_lane && key == left);
-    last = key;
-    if (!repeat && key != kEmptyKey) {
-      const int32_t id = (int32_t)(col + g.XY * (uint32_t)(t.z0 + lz));
-      const int slot = pair_slot(skey, &sfill, key);
-      if (slot >= 0)
-        atomicMin(&sval[slot], id);
-      else if (!table_insert(bt.fd.keys, bt.fd.vals, bt.fd.mask, key, id,
-                             &fresh))
+    if (tid == 0) sfill = 0;
+    const int cx = tid % C::TX, cy = tid / C::TX;
+    const int gx = t.x0 + cx, gy = t.y0 + cy;
+    const bool col_in = gx < (int)g.X && gy < (int)g.Y;
+    int nz = (int)g.Z - t.z0;
+    nz = col_in ? (nz < C::TZ ? nz : C::TZ) : 0;
+    // Column offset within a plane; plane bases are uniform over the block.
+    const uint32_t col = (uint32_t)gx + g.X * (uint32_t)gy;
+    uint32_t code[C::TZ];
+  #pragma unroll
+    for (int lz = 0; lz < C::TZ; ++lz)
+      code[lz] = lz < nz ? plane_ptr(bt.fd.lp, g, t.z0 + lz)[col] : 0u;
+    decode_setup<C>(s, bt.gt, seg, R, g, t);
+
+    unsigned fresh = 0;
+    bool overflow = false;
+    // Only the smallest id of each pair matters.  A vertex whose pair equals
+    // that of the vertex below it (previous z of the column) or of the lane
+    // before it (a smaller id in the same plane) is not that smallest id and
+    // needs nothing; the smallest one matches neither, so it is never skipped.
+    // In smooth regions this leaves few lanes per plane, and most waves skip
+    // the insert altogether.
+    const bool first_lane = (tid & 63) == 0;
+    unsigned long long last = kEmptyKey;
+  #pragma unroll
+    for (int lz = 0; lz < C::TZ; ++lz) {
+      unsigned long long key = kEmptyKey;
+      if (lz < nz) {
+        // The final labels are written here, where the pass is bound by its
+        // arithmetic and the stores overlap it; the output pass then writes
+        // only the cell ids.
+        const int32_t a = decode_final<C>(s, code[lz] & 0xffffu, false);
+        const int32_t d = decode_final<C>(s, code[lz] >> 16, true);
+        plane_ptr(bt.fd.A, g, t.z0 + lz)[col] = a;
+        plane_ptr(bt.fd.D, g, t.z0 + lz)[col] = d;
+        key = pair_key(a, d);
+      }
+      const unsigned long long left = __shfl_up(key, 1);
+      const bool repeat = key == last || (!first_lane && key == left);
+      last = key;
+      if (!repeat && key != kEmptyKey) {
+        const int32_t id = (int32_t)(col + g.XY * (uint32_t)(t.z0 + lz));
+        const int slot = pair_slot(skey, &sfill, key);
+        if (slot >= 0)
+          atomicMin(&sval[slot], id);
+        else if (!table_insert(bt.fd.keys, bt.fd.vals, bt.fd.mask, key, id,
+                               &fresh))
+          overflow = true;
+      }
+    }
+    __syncthreads();
+    for (int i = tid; i < kPairSlots; i += C::kThreads) {
+      if (skey[i] != kEmptyKey &&
+          !table_insert(bt.fd.keys, bt.fd.vals, bt.fd.mask, skey[i], sval[i],
+                        &fresh))
         overflow = true;
     }
+    // New pairs this tile inserted: summed per tile, folded per field later.
+    for (int o = 32; o > 0; o >>= 1) fresh += __shfl_xor(fresh, o);
+    if ((tid & 63) == 0) s_fresh[tid >> 6] = fresh;
+    __syncthreads();
+    if (tid == 0) {
+      uint32_t c = 0;
+      for (int w = 0; w < C::kThreads / 64; ++w) c += s_fresh[w];
+      tstat[4 * (size_t)bt.gt + 2] = c;
+    }
+    if (overflow) atomicOr(ctr + kCtrOverflow, 1ull);
+    __syncthreads();  // the LDS tables are cleared for the next tile
   }
-  __syncthreads();
-  for (int i = tid; i < kPairSlots; i += C::kThreads) {
-    if (skey[i] != kEmptyKey &&
-        !table_insert(bt.fd.keys, bt.fd.vals, bt.fd.mask, skey[i], sval[i],
-                      &fresh))
-      overflow = true;
-  }
-  // New pairs this tile inserted: summed per tile, folded per field later.
-  for (int o = 32; o > 0; o >>= 1) fresh += __shfl_xor(fresh, o);
-  if ((tid & 63) == 0) s_fresh[tid >> 6] = fresh;
-  __syncthreads();
-  if (tid == 0) {
-    uint32_t c = 0;
-    for (int w = 0; w < C::kThreads / 64; ++w) c += s_fresh[w];
-    tstat[4 * (size_t)bt.gt + 2] = c;
-  }
-  if (overflow) atomicOr(ctr + kCtrOverflow, 1ull);
 }
 
 template <class C>
@@ -1268,7 +1285,8 @@ __global__ void k_fill_u64(unsigned long long *p, uint32_t n,
 
 // Capacity of a pair table: a power of two at least twice the number of
 // distinct pairs there can be (at most 2^32, so that the mask fits 32 bits).
-uint64_t table_capacity(uint64_t n, uint64_t nmax, uint64_t nmin) {
+__host__ __device__ inline uint64_t table_capacity(uint64_t n, uint64_t nmax,
+                                                   uint64_t nmin) {
   uint64_t bound = nmax * nmin;
   if (nmax != 0 && bound / nmax != nmin) bound = n;  // product overflowed
   if (bound > n) bound = n;
@@ -1281,9 +1299,11 @@ uint64_t table_capacity(uint64_t n, uint64_t nmax, uint64_t nmin) {
 // 32 per extremum (plus slack) when that is smaller, or the caller's choice.
 // Cells are pairs of manifolds that meet, far fewer than all pairs of
 // extrema; a field with more makes the pair pass overflow and run again on
-// a larger table.
-uint64_t table_first_capacity(uint64_t n, uint64_t nmax, uint64_t nmin,
-                              uint64_t requested) {
+// the table of the full capacity.
+__host__ __device__ inline uint64_t table_first_capacity(uint64_t n,
+                                                         uint64_t nmax,
+                                                         uint64_t nmin,
+                                                         uint64_t requested) {
   const uint64_t full = table_capacity(n, nmax, nmin);
   uint64_t cap = 1024;
   const uint64_t want = requested ? (requested + 1) / 2
@@ -1292,14 +1312,121 @@ uint64_t table_first_capacity(uint64_t n, uint64_t nmax, uint64_t nmin,
   return cap;
 }
 
-// Per-field cell counters back to zero before the pair pass runs again.
-__global__ void k_clear_field_ctr(unsigned long long *fctr, int nfields,
-                                  int which) {
-  const int i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < nfields) fctr[(size_t)i * kFieldCtrs + which] = 0;
+// The tile -> field map, from the fields' first tiles (increasing).
+__global__ void __launch_bounds__(kBlock)
+k_fill_tfield(const FieldDev *__restrict__ fds, int nfields, uint32_t *tfield,
+              uint32_t nt) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nt) return;
+  int lo = 0, hi = nfields - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (fds[mid].tile0 <= i) lo = mid;
+    else hi = mid - 1;
+  }
+  tfield[i] = (uint32_t)lo;
 }
 
-// Grow-only pinned host staging owned by the context.
+// Table capacity of every field that wants cells, chosen on the device from
+// its extremum counts: the first capacity (`regrow` == 0), or, when the pair
+// pass overflowed (`regrow` != 0), the capacity that always suffices, with
+// the field's cell counter cleared for the second pass.  *run tells the
+// passes that follow whether they have work.  The host reserved each
+// field's region for the largest capacity its vertex count allows.
+__global__ void __launch_bounds__(kBlock)
+k_table_plan(FieldDev *fds, int nfields, unsigned long long *fctr,
+             unsigned long long *ctr, uint64_t requested, int regrow,
+             uint32_t *run) {
+  const bool again = regrow && (ctr[kCtrOverflow] & 1ull);
+  for (int i = threadIdx.x; i < nfields; i += kBlock) {
+    if (!fds[i].ms) continue;
+    const uint64_t n = fds[i].g.N;
+    const unsigned long long *fc = fctr + (size_t)i * kFieldCtrs;
+    if (!regrow) {
+      fds[i].mask = (uint32_t)(
+          table_first_capacity(n, fc[kFMaxima], fc[kFMinima], requested) - 1);
+    } else if (again) {
+      fds[i].mask = (uint32_t)(table_capacity(n, fc[kFMaxima], fc[kFMinima]) - 1);
+      fctr[(size_t)i * kFieldCtrs + kFCells] = 0;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    *run = regrow ? (again ? 1u : 0u) : 1u;
+    if (again) ctr[kCtrOverflow] &= ~1ull;
+  }
+}
+
+// Clear the tables of the fields that want cells (capacities from the
+// plan), over a fixed grid; nothing to do when *run is 0.
+constexpr unsigned kClearBlocks = 2048;
+
+__global__ void __launch_bounds__(kBlock)
+k_table_clear_all(const FieldDev *__restrict__ fds, int nfields,
+                  const uint32_t *__restrict__ run) {
+  if (!*run) return;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (int i = 0; i < nfields; ++i) {
+    const FieldDev fd = fds[i];
+    if (!fd.ms) continue;
+    const uint64_t cap = (uint64_t)fd.mask + 1;
+    for (uint64_t k = (uint64_t)blockIdx.x * kBlock + threadIdx.x; k < cap;
+         k += stride) {
+      fd.keys[k] = kEmptyKey;
+      fd.vals[k] = INT32_MAX;
+    }
+  }
+}
+
+}  // namespace
+
+// Fold the counters of the last segmentation call into the stats; waits for
+// the call's work.
+int finish_last(msc_ctx *ctx) {
+  LastCall &L = ctx->last;
+  if (!L.pending) return MSC_OK;
+  MSC_HIP_TRY(hipEventSynchronize(ctx->done));
+  L.pending = false;
+  const unsigned long long *fc = ctx->hfctr;
+  const unsigned long long ovf = ctx->hctr[kCtrOverflow];
+  int status = MSC_OK;
+  if (ovf & 6) status = MSC_EHIP;        // broken invariant (never expected)
+  else if (ovf & 1) status = MSC_ENOMEM;  // table full at the full capacity
+  ctx->stats = msc_stats{};
+  ctx->field_stats.assign(L.nfields, msc_stats{});
+  for (int i = 0; i < L.nfields; ++i) {
+    msc_stats &st = ctx->field_stats[i];
+    const unsigned long long *f = fc + (size_t)i * kFieldCtrs;
+    st.n_vertices = L.n[i];
+    st.n_maxima = (int64_t)f[kFMaxima];
+    st.n_minima = (int64_t)f[kFMinima];
+    st.n_cells = L.has_ms[i] ? (int64_t)f[kFCells] : -1;
+    st.n_exits = (int64_t)f[kFExits];
+    st.tile_x = L.tile[0];
+    st.tile_y = L.tile[1];
+    st.tile_z = L.tile[2];
+    st.status = status != MSC_OK ? status : (f[kFNaN] ? MSC_ENAN : MSC_OK);
+    if (st.status != MSC_OK && L.status == MSC_OK) L.status = st.status;
+    ctx->stats.n_vertices += st.n_vertices;
+    ctx->stats.n_maxima += st.n_maxima;
+    ctx->stats.n_minima += st.n_minima;
+    ctx->stats.n_cells += st.n_cells > 0 ? st.n_cells : 0;
+    ctx->stats.n_exits += st.n_exits;
+  }
+  if (L.nfields == 1) ctx->stats.n_cells = ctx->field_stats[0].n_cells;
+  ctx->stats.jump_rounds = (int32_t)ctx->hctr[kCtrRounds];
+  ctx->stats.exit_steps = (int64_t)ctx->hctr[kCtrSteps];
+  ctx->stats.tile_x = L.tile[0];
+  ctx->stats.tile_y = L.tile[1];
+  ctx->stats.tile_z = L.tile[2];
+  ctx->stats.status = L.status;
+  return MSC_OK;
+}
+
+namespace {
+
+// Grow-only pinned host staging owned by the context (the synchronous
+// virtual-rank path).
 template <class T>
 int stage(msc_ctx *ctx, size_t count, T **out) {
   const size_t bytes = count * sizeof(T);
@@ -1316,13 +1443,23 @@ int stage(msc_ctx *ctx, size_t count, T **out) {
   return MSC_OK;
 }
 
+// One segmentation call over a batch of fields.  Everything is enqueued on
+// `s`; the host never waits for the device (only a workspace growth or a
+// reused pinned slot can make it wait for earlier work).  Conditions the
+// device detects (NaN, a broken invariant) are reported by the stats calls
+// and msc_last_status once the work has run.
 template <class C>
 int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
                   const uint8_t *ghost, hipStream_t s) {
+  MSC_TRY(finish_last(ctx));  // stats of the previous call, if any
+  MSC_TRY(begin_call(ctx, s));
   // Geometry, tile ranges and workspace layout of every field.
   std::vector<FieldDev> fd(nfields);
   uint64_t total_tiles = 0, total_n = 0;
   size_t need_lp = 0, need_scratch = 0;
+  uint64_t tab_slots = 0;
+  std::vector<uint64_t> tab_off(nfields, 0);
+  bool any_ms = false;
   for (int i = 0; i < nfields; ++i) {
     const int64_t X = fields[i].dims[0], Y = fields[i].dims[1],
                   Z = fields[i].dims[2];
@@ -1344,6 +1481,13 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
     if (!fields[i].asc) need_scratch += align256((size_t)g.N * sizeof(int32_t));
     if (!fields[i].desc) need_scratch += align256((size_t)g.N * sizeof(int32_t));
     if (total_tiles > INT32_MAX / 2) return MSC_ERANGE;
+    if (fields[i].ms) {
+      // Room for the largest table the field can need; the device uses
+      // (and clears) only what its extremum counts call for.
+      any_ms = true;
+      tab_off[i] = tab_slots;
+      tab_slots += table_capacity(g.N, g.N, g.N);
+    }
   }
   // Exit-graph nodes: 2 * kHalo fixed slots per tile; node numbers and
   // final values share 32 bits (bit 31 tags a final value).
@@ -1352,65 +1496,66 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
   const uint32_t nslots = nt * (uint32_t)(2 * C::kHalo);
   unsigned long long *ctr = ctx->dctr;
 
-  uint32_t *next = nullptr;
-  uint16_t *tlist = nullptr;
-  uint32_t *tkey = nullptr, *torder = nullptr, *hist = nullptr, *mm = nullptr;
-  uint32_t *tfield = nullptr;
-  unsigned long long *fctr = nullptr, *rstat = nullptr;
-  uint32_t *tstat = nullptr;
-  FieldDev *fds = nullptr;
-  Seg *seg = nullptr;
-  std::vector<uint32_t> tf_host(nt);
-  for (int i = 0; i < nfields; ++i)
-    for (uint32_t k = 0; k < fd[i].g.ntiles; ++k) tf_host[fd[i].tile0 + k] = i;
   const size_t need =
       need_lp + need_scratch + align256((size_t)nslots * sizeof(uint32_t)) +
-      align256(nt * sizeof(Seg)) +
-      3 * align256(nt * sizeof(uint32_t)) +
+      align256(nt * sizeof(Seg)) + 3 * align256(nt * sizeof(uint32_t)) +
       align256((kTileBuckets + 2) * sizeof(uint32_t)) +
       align256(nfields * sizeof(FieldDev)) +
       align256(nfields * kFieldCtrs * sizeof(unsigned long long)) +
       align256(4ull * nt * sizeof(uint32_t)) +
       align256(4ull * nt * sizeof(unsigned long long)) +
       align256(2ull * C::kHalo * nt * sizeof(uint16_t)) + 8192;
-  MSC_TRY(reserve(ctx->ws, need));
+  MSC_TRY(reserve(ctx, ctx->ws, need));
+  if (any_ms)
+    MSC_TRY(reserve(ctx, ctx->tab,
+                    align256(tab_slots * 8) + align256(tab_slots * 4) + 4096));
   Carver cv(ctx->ws);
+  unsigned long long *keys = nullptr;
+  int32_t *vals = nullptr;
+  if (any_ms) {
+    Carver tc(ctx->tab);
+    keys = tc.take<unsigned long long>(tab_slots);
+    vals = tc.take<int32_t>(tab_slots);
+  }
   for (int i = 0; i < nfields; ++i) {
     fd[i].f = fields[i].field;
     fd[i].lp = cv.take<uint32_t>(fd[i].g.N);
     fd[i].A = fields[i].asc ? fields[i].asc : cv.take<int32_t>(fd[i].g.N);
     fd[i].D = fields[i].desc ? fields[i].desc : cv.take<int32_t>(fd[i].g.N);
     fd[i].ms = fields[i].ms;
-    fd[i].keys = nullptr;
-    fd[i].vals = nullptr;
-    fd[i].mask = 0;
+    fd[i].keys = fields[i].ms ? keys + tab_off[i] : nullptr;
+    fd[i].vals = fields[i].ms ? vals + tab_off[i] : nullptr;
+    fd[i].mask = 0;  // set on the device
     fd[i].ghost = ghost ? ghost[i] : 0u;
   }
-  seg = cv.take<Seg>(nt);
-  tkey = cv.take<uint32_t>(nt);
-  torder = cv.take<uint32_t>(nt);
-  tfield = cv.take<uint32_t>(nt);
-  hist = cv.take<uint32_t>(kTileBuckets + 2);
-  mm = hist + kTileBuckets;
-  fds = cv.take<FieldDev>(nfields);
-  fctr = cv.take<unsigned long long>((size_t)nfields * kFieldCtrs);
-  tstat = cv.take<uint32_t>(4ull * nt);
-  rstat = cv.take<unsigned long long>(4ull * nt);
-  tlist = cv.take<uint16_t>(2ull * C::kHalo * nt);
-  next = cv.take<uint32_t>(nslots);
+  uint32_t *next = cv.take<uint32_t>(nslots);
+  Seg *seg = cv.take<Seg>(nt);
+  uint32_t *tkey = cv.take<uint32_t>(nt);
+  uint32_t *torder = cv.take<uint32_t>(nt);
+  uint32_t *tfield = cv.take<uint32_t>(nt);
+  uint32_t *hist = cv.take<uint32_t>(kTileBuckets + 2);
+  uint32_t *mm = hist + kTileBuckets;
+  FieldDev *fds = cv.take<FieldDev>(nfields);
+  unsigned long long *fctr =
+      cv.take<unsigned long long>((size_t)nfields * kFieldCtrs);
+  uint32_t *tstat = cv.take<uint32_t>(4ull * nt);
+  unsigned long long *rstat = cv.take<unsigned long long>(4ull * nt);
+  uint16_t *tlist = cv.take<uint16_t>(2ull * C::kHalo * nt);
+  uint32_t *run = cv.take<uint32_t>(1);
 
-  // Descriptors and the tile -> field map go up through pinned staging.
+  // The descriptors go up through a pinned slot; the tile -> field map is
+  // built on the device.
   {
-    char *st = nullptr;
-    const size_t fbytes = nfields * sizeof(FieldDev), tbytes = nt * 4ull;
-    MSC_TRY(stage(ctx, fbytes + tbytes, &st));
+    void *st = nullptr;
+    int slot = 0;
+    const size_t fbytes = nfields * sizeof(FieldDev);
+    MSC_TRY(pinned_slot(ctx, fbytes, &st, &slot));
     std::memcpy(st, fd.data(), fbytes);
-    std::memcpy(st + fbytes, tf_host.data(), tbytes);
     MSC_HIP_TRY(hipMemcpyAsync(fds, st, fbytes, hipMemcpyHostToDevice, s));
-    MSC_HIP_TRY(hipMemcpyAsync(tfield, st + fbytes, tbytes,
-                               hipMemcpyHostToDevice, s));
+    MSC_TRY(slot_copied(ctx, slot, s));
   }
   MSC_TRY(clear_counters(ctx, s));
+  k_fill_tfield<<<grid_for(nt), kBlock, 0, s>>>(fds, nfields, tfield, nt);
   k_fill_u64<<<grid_for((uint64_t)nfields * kFieldCtrs), kBlock, 0, s>>>(
       fctr, (uint32_t)(nfields * kFieldCtrs), 0ull);
   k_fill_u32<<<grid_for(kTileBuckets + 2), kBlock, 0, s>>>(
@@ -1426,132 +1571,77 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
   for (int k = 0; k < 3; ++k)
     k_tile_stat_reduce<<<grid_for(nt), kBlock, 0, s>>>(
         tstat, k == 2 ? 3 : k, nt, tfield, fctr, kStat[k]);
+  // Exit slots are fixed per tile (2 * kHalo from the tile's own base), so
+  // no count has to come back to the host before the graph is built.
+  MSC_PHASE(ctx, s, "exit_link", 18.0 * nt * (double)C::kHalo * 0.5,
+            (k_exit_link<C><<<nt, kBlock, 0, s>>>(fds, tfield, seg, tlist,
+                                                  next)));
+  MSC_PHASE(ctx, s, "tile_order", 12.0 * nt,
+            (k_key_minmax<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm),
+             k_key_hist<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm, hist),
+             k_key_scan<<<1, 1024, 0, s>>>(hist),
+             k_key_scatter<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm, hist,
+                                                           torder)));
+  MSC_PHASE(ctx, s, "exit_resolve", 12.0 * nt * (double)C::kHalo * 0.5,
+            (k_exit_resolve<C><<<2 * nt, C::kThreads, 0, s>>>(
+                torder, nt, seg, nslots, next, ctr, rstat)));
+  k_steps_reduce<<<kStepsBlocks, 1024, 0, s>>>(rstat, 2 * nt, ctr);
 
-  // Per-field counters: NaN check and table sizes.
-  std::vector<unsigned long long> fc((size_t)nfields * kFieldCtrs);
-  MSC_HIP_TRY(hipMemcpyAsync(fc.data(), fctr, fc.size() * 8,
-                             hipMemcpyDeviceToHost, s));
-  MSC_HIP_TRY(hipStreamSynchronize(s));
-  for (int i = 0; i < nfields; ++i)
-    if (fc[(size_t)i * kFieldCtrs + kFNaN]) return MSC_ENAN;
-
-  {
-    // Exit slots are fixed per tile (2 * kHalo from the tile's own base), so
-    // no count has to come back to the host before the graph is built.
-    MSC_PHASE(ctx, s, "exit_link", 18.0 * nt * (double)C::kHalo * 0.5,
-              (k_exit_link<C><<<nt, kBlock, 0, s>>>(fds, tfield, seg, tlist,
-                                                    next)));
-    MSC_PHASE(ctx, s, "tile_order", 12.0 * nt,
-              (k_key_minmax<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm),
-               k_key_hist<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm, hist),
-               k_key_scan<<<1, 1024, 0, s>>>(hist),
-               k_key_scatter<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm, hist,
-                                                             torder)));
-    MSC_PHASE(ctx, s, "exit_resolve", 12.0 * nt * (double)C::kHalo * 0.5,
-              (k_exit_resolve<C><<<2 * nt, C::kThreads, 0, s>>>(
-                  torder, nt, seg, nslots, next, ctr, rstat)));
-    k_steps_reduce<<<kStepsBlocks, 1024, 0, s>>>(rstat, 2 * nt, ctr);
-  }
-
-  // Pair tables of the fields that want cells, in one block of `tab`: each
-  // starts at its first capacity and all grow fourfold while the pair pass
-  // overflows (up to the capacity that always suffices).
-  std::vector<uint64_t> cap(nfields, 0);
-  bool any_ms = false;
-  for (int i = 0; i < nfields; ++i) {
-    if (!fields[i].ms) continue;
-    any_ms = true;
-    cap[i] = table_first_capacity(fd[i].g.N,
-                                  fc[(size_t)i * kFieldCtrs + kFMaxima],
-                                  fc[(size_t)i * kFieldCtrs + kFMinima],
-                                  ctx->table_first);
-  }
-  while (any_ms) {
-    uint64_t total_cap = 0;
-    std::vector<uint64_t> off(nfields, 0);
-    for (int i = 0; i < nfields; ++i) {
-      off[i] = total_cap;
-      total_cap += cap[i];
-    }
-    MSC_TRY(reserve(ctx->tab, align256(total_cap * 8) + align256(total_cap * 4) +
-                                  4096));
-    Carver tc(ctx->tab);
-    unsigned long long *keys = tc.take<unsigned long long>(total_cap);
-    int32_t *vals = tc.take<int32_t>(total_cap);
-    for (int i = 0; i < nfields; ++i) {
-      if (!fields[i].ms) continue;
-      fd[i].keys = keys + off[i];
-      fd[i].vals = vals + off[i];
-      fd[i].mask = (uint32_t)(cap[i] - 1);
-    }
-    char *st = nullptr;
-    MSC_TRY(stage(ctx, nfields * sizeof(FieldDev), &st));
-    std::memcpy(st, fd.data(), nfields * sizeof(FieldDev));
-    MSC_HIP_TRY(hipMemcpyAsync(fds, st, nfields * sizeof(FieldDev),
-                               hipMemcpyHostToDevice, s));
-    MSC_PHASE(ctx, s, "table_clear", 12.0 * total_cap,
-              (k_table_clear<<<(unsigned)((total_cap + kBlock - 1) / kBlock),
-                               kBlock, 0, s>>>(keys, vals, total_cap)));
+  if (any_ms) {
+    // Pair tables sized on the device; a pass that overflows its first
+    // table runs once more on the capacity that always suffices (the second
+    // pass and its clear return at once when nothing overflowed).
+    const unsigned cb = (unsigned)std::min<uint64_t>(
+        kClearBlocks, (tab_slots + kBlock - 1) / kBlock);
+    k_table_plan<<<1, kBlock, 0, s>>>(fds, nfields, fctr, ctr,
+                                      ctx->table_first, 0, run);
+    MSC_PHASE(ctx, s, "table_clear", 12.0 * total_n,
+              (k_table_clear_all<<<cb, kBlock, 0, s>>>(fds, nfields, run)));
     MSC_PHASE(ctx, s, "tile_pairs", 12.0 * total_n,
-              (k_tile_pairs<C><<<nt, C::kThreads, 0, s>>>(fds, tfield, seg,
-                                                          next, ctr, tstat)));
+              (k_tile_pairs<C><<<nt, C::kThreads, 0, s>>>(
+                  fds, tfield, seg, next, ctr, tstat, nt, nullptr)));
+    k_table_plan<<<1, kBlock, 0, s>>>(fds, nfields, fctr, ctr,
+                                      ctx->table_first, 1, run);
+    k_table_clear_all<<<cb, kBlock, 0, s>>>(fds, nfields, run);
+    const unsigned rb = nt < 4096u ? nt : 4096u;
+    k_tile_pairs<C><<<rb, C::kThreads, 0, s>>>(fds, tfield, seg, next, ctr,
+                                               tstat, nt, run);
+    MSC_HIP_TRY(hipGetLastError());
     k_tile_stat_reduce<<<grid_for(nt), kBlock, 0, s>>>(tstat, 2, nt, tfield,
                                                        fctr, kFCells);
-    MSC_TRY(read_counters(ctx, s));
-    if (ctx->hctr[kCtrOverflow] & 6) return MSC_EHIP;
-    if (!(ctx->hctr[kCtrOverflow] & 1)) break;
-    bool grew = false;
-    for (int i = 0; i < nfields; ++i) {
-      if (!fields[i].ms) continue;
-      const uint64_t full = table_capacity(
-          fd[i].g.N, fc[(size_t)i * kFieldCtrs + kFMaxima],
-          fc[(size_t)i * kFieldCtrs + kFMinima]);
-      const uint64_t next_cap = cap[i] * 4 < full ? cap[i] * 4 : full;
-      grew |= next_cap > cap[i];
-      cap[i] = next_cap;
-    }
-    if (!grew) return MSC_ENOMEM;
-    k_clear_field_ctr<<<grid_for(nfields), kBlock, 0, s>>>(fctr, nfields,
-                                                           kFCells);
-    k_fill_u64<<<1, kBlock, 0, s>>>(ctr + kCtrOverflow, 1, 0ull);
   }
   MSC_PHASE(ctx, s, "tile_write", (any_ms ? 8.0 : 12.0) * total_n,
             (k_tile_write<C><<<nt, C::kThreads, 0, s>>>(fds, tfield, seg,
                                                         next)));
-  MSC_TRY(read_counters(ctx, s));
-  if (ctx->hctr[kCtrOverflow] & 6) return MSC_EHIP;
-  if (ctx->hctr[kCtrOverflow]) return MSC_ENOMEM;
-  MSC_HIP_TRY(hipMemcpyAsync(fc.data(), fctr, fc.size() * 8,
+  // Counters back to pinned host memory, for the stats calls.
+  if ((size_t)nfields * kFieldCtrs > ctx->hfctr_cap) {
+    if (ctx->hfctr) (void)hipHostFree(ctx->hfctr);
+    ctx->hfctr = nullptr;
+    ctx->hfctr_cap = 0;
+    const size_t cap = (size_t)nfields * kFieldCtrs * 2 + 64;
+    if (hipHostMalloc(&ctx->hfctr, cap * 8, hipHostMallocDefault) != hipSuccess)
+      return MSC_ENOMEM;
+    ctx->hfctr_cap = cap;
+  }
+  MSC_HIP_TRY(hipMemcpyAsync(ctx->hfctr, fctr,
+                             (size_t)nfields * kFieldCtrs * 8,
                              hipMemcpyDeviceToHost, s));
-  MSC_HIP_TRY(hipStreamSynchronize(s));
-
-  ctx->stats = msc_stats{};
-  ctx->field_stats.assign(nfields, msc_stats{});
+  MSC_HIP_TRY(hipMemcpyAsync(ctx->hctr, ctr, kNumCounters * 8,
+                             hipMemcpyDeviceToHost, s));
+  MSC_TRY(end_call(ctx, s));
+  LastCall &L = ctx->last;
+  L.pending = true;
+  L.nfields = nfields;
+  L.status = MSC_OK;
+  L.n.resize(nfields);
+  L.has_ms.resize(nfields);
   for (int i = 0; i < nfields; ++i) {
-    msc_stats &st = ctx->field_stats[i];
-    st.n_vertices = fd[i].g.N;
-    st.n_maxima = (int64_t)fc[(size_t)i * kFieldCtrs + kFMaxima];
-    st.n_minima = (int64_t)fc[(size_t)i * kFieldCtrs + kFMinima];
-    st.n_cells =
-        fields[i].ms ? (int64_t)fc[(size_t)i * kFieldCtrs + kFCells] : -1;
-    st.tile_x = C::TX;
-    st.tile_y = C::TY;
-    st.tile_z = C::TZ;
-    ctx->stats.n_vertices += st.n_vertices;
-    ctx->stats.n_maxima += st.n_maxima;
-    ctx->stats.n_minima += st.n_minima;
-    ctx->stats.n_cells += st.n_cells > 0 ? st.n_cells : 0;
+    L.n[i] = fd[i].g.N;
+    L.has_ms[i] = fields[i].ms != nullptr;
   }
-  if (nfields == 1) ctx->stats.n_cells = ctx->field_stats[0].n_cells;
-  for (int i = 0; i < nfields; ++i) {
-    ctx->field_stats[i].n_exits = (int64_t)fc[(size_t)i * kFieldCtrs + kFExits];
-    ctx->stats.n_exits += ctx->field_stats[i].n_exits;
-  }
-  ctx->stats.jump_rounds = (int32_t)ctx->hctr[kCtrRounds];
-  ctx->stats.exit_steps = (int64_t)ctx->hctr[kCtrSteps];
-  ctx->stats.tile_x = C::TX;
-  ctx->stats.tile_y = C::TY;
-  ctx->stats.tile_z = C::TZ;
+  L.tile[0] = C::TX;
+  L.tile[1] = C::TY;
+  L.tile[2] = C::TZ;
   return MSC_OK;
 }
 
@@ -1973,7 +2063,7 @@ int segment_ranks(msc_ctx *ctx, const float *field, const int64_t dims[3],
   const uint32_t ntile = rank_tiles(X, Y, Z);
   // per-block root counts: for the cell tiles and for the relabel grid
   const uint64_t nroot = std::max<uint64_t>(ntile, (uint64_t)rgrid.x * rgrid.y);
-  MSC_TRY(reserve(ctx->rk, 2 * align256(total * 4) + 4 * align256(nodes * 4) +
+  MSC_TRY(reserve(ctx, ctx->rk, 2 * align256(total * 4) + 4 * align256(nodes * 4) +
                                align256(R * sizeof(SlabDev)) +
                                2 * align256(N * 4) + align256(nroot * 8ull) +
                                4096));
@@ -1996,6 +2086,9 @@ int segment_ranks(msc_ctx *ctx, const float *field, const int64_t dims[3],
   }
   // Alg. 1 on every rank, all ranks in one batched call.
   MSC_TRY(segment_batch<C>(ctx, (int)R, fields.data(), ghost.data(), s));
+  // This path reads counts back anyway: take the slabs' outcome now.
+  MSC_TRY(finish_last(ctx));
+  if (ctx->last.status != MSC_OK) return ctx->last.status;
 
   char *st = nullptr;
   MSC_TRY(stage(ctx, R * sizeof(SlabDev), &st));
@@ -2022,7 +2115,7 @@ int segment_ranks(msc_ctx *ctx, const float *field, const int64_t dims[3],
   int64_t cells = -1;
   if (ms) {
     const uint64_t cap = table_capacity(N, nmax, nmin);
-    MSC_TRY(reserve(ctx->tab, align256(cap * 8) + align256(cap * 4) + 4096));
+    MSC_TRY(reserve(ctx, ctx->tab, align256(cap * 8) + align256(cap * 4) + 4096));
     Carver tc(ctx->tab);
     unsigned long long *keys = tc.take<unsigned long long>(cap);
     int32_t *vals = tc.take<int32_t>(cap);
@@ -2208,7 +2301,7 @@ int segment_csr_run(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,
                              hipMemcpyDeviceToHost, s));
   MSC_HIP_TRY(hipStreamSynchronize(s));
   if (nnz < 0 || (nnz > 0 && !col_idx)) return MSC_EINVAL;
-  MSC_TRY(reserve(ctx->rk, 2 * align256((uint64_t)n * 4) +
+  MSC_TRY(reserve(ctx, ctx->rk, 2 * align256((uint64_t)n * 4) +
                                align256(nblk * 8ull) + 4096));
   Carver cv(ctx->rk);
   uint32_t *roots = cv.take<uint32_t>(2ull * nblk);
@@ -2235,7 +2328,7 @@ int segment_csr_run(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,
                                         ctx->table_first);
     const uint64_t full = table_capacity((uint64_t)n, nmax, nmin);
     for (;;) {
-      MSC_TRY(reserve(ctx->tab, align256(cap * 8) + align256(cap * 4) + 4096));
+      MSC_TRY(reserve(ctx, ctx->tab, align256(cap * 8) + align256(cap * 4) + 4096));
       Carver tc(ctx->tab);
       unsigned long long *keys = tc.take<unsigned long long>(cap);
       int32_t *vals = tc.take<int32_t>(cap);

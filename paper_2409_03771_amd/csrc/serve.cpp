@@ -259,12 +259,15 @@ void worker_loop(msc_queue *q, int kind) {
                     ? msc_segment_batched(ctx, (int)fields.size(),
                                           fields.data(), s)
                     : rc[0];
-      if (all == MSC_OK || batch.size() == 1) {
-        for (int &x : rc) x = all;
-      } else {
-        // One bad request (e.g. NaN) must not fail the others: rerun alone.
-        for (size_t i = 0; i < batch.size(); ++i)
-          rc[i] = msc_segment_batched(ctx, 1, &fields[i], s);
+      if (all == MSC_OK && hipStreamSynchronize(s) != hipSuccess)
+        all = MSC_EHIP;
+      for (size_t i = 0; i < batch.size(); ++i) {
+        // Each field's own outcome: a NaN in one request fails it alone.
+        msc_stats st{};
+        rc[i] = all;
+        if (all == MSC_OK)
+          rc[i] = msc_last_field_stats(ctx, (int)i, &st) == MSC_OK ? st.status
+                                                                  : MSC_EHIP;
       }
     } else {
       Request *r = batch[0];

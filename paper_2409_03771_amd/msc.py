@@ -38,7 +38,7 @@ class msc_stats(ctypes.Structure):
     _fields_ = [("n_vertices", _I64), ("n_maxima", _I64), ("n_minima", _I64),
                 ("n_cells", _I64), ("n_exits", _I64), ("jump_rounds", _I32),
                 ("tile_x", _I32), ("tile_y", _I32), ("tile_z", _I32),
-                ("exit_steps", _I64)]
+                ("exit_steps", _I64), ("status", _I32), ("reserved", _I32)]
 
 
 class msc_phase(ctypes.Structure):
@@ -62,6 +62,7 @@ _SIGS = {
     "msc_destroy": ([_P], None),
     "msc_segment": ([_P, _P, ctypes.POINTER(_I64), _P, _P, _P, _P], _I32),
     "msc_last_stats": ([_P, ctypes.POINTER(msc_stats)], _I32),
+    "msc_last_status": ([_P, ctypes.POINTER(_I32)], _I32),
     "msc_segment_batched": ([_P, _I32, ctypes.POINTER(msc_field), _P], _I32),
     "msc_segment_ranks": ([_P, _P, ctypes.POINTER(_I64), _I32, _P, _P, _P, _P],
                           _I32),
@@ -158,9 +159,27 @@ def _dims_arg(dims):
     return (_I64 * 3)(*[int(d) for d in dims])
 
 
-def segment_into(field, asc=None, desc=None, ms=None, dims=None, stream=None):
+def last_status(device: int | None = None) -> int:
+    """Outcome of the last asynchronous call of a device's context, as the
+    device found it (waits for that call's work): MSC_OK, MSC_ENAN, ..."""
+    st = _I32(0)
+    _check(_lib.msc_last_status(context(device), ctypes.byref(st)),
+           "msc_last_status")
+    return st.value
+
+
+def _check_async(device, where):
+    code = last_status(device)
+    if code != MSC_OK:
+        raise MscError(code, where)
+
+
+def segment_into(field, asc=None, desc=None, ms=None, dims=None, stream=None,
+                 check=True):
     """Write ascent roots, descent roots and Morse-Smale cell ids into the
-    given int32 tensors (any may be None)."""
+    given int32 tensors (any may be None).  The call returns with the work
+    enqueued on the stream; with `check` it then waits for the work and
+    raises if the device found the field invalid (NaN)."""
     if dims is None:
         dims = grid_dims(field.shape)
     code = _lib.msc_segment(
@@ -169,15 +188,19 @@ def segment_into(field, asc=None, desc=None, ms=None, dims=None, stream=None):
         _dev_ptr(desc, torch.int32, "desc"), _dev_ptr(ms, torch.int32, "ms"),
         _stream(field, stream))
     _check(code, "msc_segment")
+    if check:
+        _check_async(field.device.index, "msc_segment")
 
 
-def segment(field: torch.Tensor, want=("asc", "desc", "ms"), stream=None):
+def segment(field: torch.Tensor, want=("asc", "desc", "ms"), stream=None,
+            check=True):
     """Morse-Smale segmentation of a float32 field on the GPU.  Returns a
     tuple (asc, desc, ms) of flat int32 tensors (None where not wanted)."""
     n = field.numel()
     out = {k: (torch.empty(n, dtype=torch.int32, device=field.device)
                if k in want else None) for k in ("asc", "desc", "ms")}
-    segment_into(field, out["asc"], out["desc"], out["ms"], stream=stream)
+    segment_into(field, out["asc"], out["desc"], out["ms"], stream=stream,
+                 check=check)
     return out["asc"], out["desc"], out["ms"]
 
 
@@ -330,9 +353,11 @@ def _batch_outputs(fields, want):
             for f in fields]
 
 
-def segment_batched_into(fields, outs, dims=None, stream=None):
+def segment_batched_into(fields, outs, dims=None, stream=None, check=True):
     """Segment several fields in one set of launches; `outs` holds an
-    (asc, desc, ms) tuple of int32 tensors (or None) per field."""
+    (asc, desc, ms) tuple of int32 tensors (or None) per field.  With
+    `check`, waits for the work and raises if any field was invalid (each
+    field's own outcome: last_field_stats(i)["status"])."""
     if not fields:
         return
     dims = dims or [grid_dims(f.shape) for f in fields]
@@ -341,13 +366,16 @@ def segment_batched_into(fields, outs, dims=None, stream=None):
                                     len(fields), arr,
                                     _stream(fields[0], stream))
     _check(code, "msc_segment_batched")
+    if check:
+        _check_async(fields[0].device.index, "msc_segment_batched")
 
 
-def segment_batched(fields, want=("asc", "desc", "ms"), stream=None):
+def segment_batched(fields, want=("asc", "desc", "ms"), stream=None,
+                    check=True):
     """Batched segmentation of a list of float32 fields (any shapes).
     Returns one (asc, desc, ms) tuple per field."""
     outs = _batch_outputs(fields, want)
-    segment_batched_into(fields, outs, stream=stream)
+    segment_batched_into(fields, outs, stream=stream, check=check)
     return outs
 
 

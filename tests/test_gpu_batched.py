@@ -86,6 +86,18 @@ def test_batch_error_reports_and_context_survives(msc):
     with pytest.raises(msc.MscError) as e:
         msc.segment_batched(dev)
     assert e.value.code == msc.MSC_ENAN
+    # The NaN is reported for its own field only; the others are valid.
+    outs = msc.segment_batched(dev, check=False)
+    torch.cuda.synchronize()
+    assert msc.last_status() == msc.MSC_ENAN
+    for i in range(len(dev)):
+        st = msc.last_field_stats(i)["status"]
+        assert st == (msc.MSC_ENAN if i == 2 else msc.MSC_OK), i
+        if i != 2:
+            for name, g, w in zip(("asc", "desc", "ms"), outs[i],
+                                  O.segment(fields[i])):
+                np.testing.assert_array_equal(g.cpu().numpy(), w,
+                                              err_msg=f"field {i} {name}")
     dev[2] = torch.from_numpy(fields[2]).cuda()
     outs = msc.segment_batched(dev)
     torch.cuda.synchronize()

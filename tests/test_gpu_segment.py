@@ -183,3 +183,54 @@ def test_side_stream_and_determinism(msc):
     s.synchronize()
     torch.cuda.synchronize()
     assert torch.equal(a0, a1) and torch.equal(d0, d1) and torch.equal(m0, m1)
+
+
+def test_calls_queue_without_host_sync(msc):
+    """msc_segment returns with its work only enqueued: calls queued back to
+    back on one stream, with no host synchronisation between them (and the
+    stream still busy when the last one returns), reuse the context's
+    workspace in stream order and each equal the oracle."""
+    small = [synth.gaussian_field(d, 12, sd) for d, sd in
+             (((96, 80, 64), 1), ((64, 70, 50), 2), ((33, 17, 90), 3))]
+    big = synth.gaussian_field((512, 512, 256), 64, 4)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        dev = [torch.from_numpy(f).cuda() for f in small + [big] + small]
+        outs = [tuple(torch.empty(t.numel(), dtype=torch.int32, device="cuda")
+                      for _ in range(3)) for t in dev]
+    s.synchronize()
+    for t, (a, d, m) in zip(dev, outs):
+        msc.segment_into(t, a, d, m, stream=s, check=False)
+    busy = not s.query()
+    s.synchronize()
+    assert busy, "the calls waited for the device"
+    assert msc.last_status() == msc.MSC_OK
+    wants = {}
+    for i, f in enumerate(small + [big] + small):
+        key = id(f)
+        if key not in wants:
+            wants[key] = O.segment(f)
+        for name, g, w in zip(("asc", "desc", "ms"), outs[i], wants[key]):
+            np.testing.assert_array_equal(g.cpu().numpy(), w,
+                                          err_msg=f"call {i} {name}")
+
+
+def test_calls_on_two_streams_are_ordered(msc):
+    """Consecutive calls on one context from two streams: the second waits
+    for the first's work on the device (shared workspace)."""
+    f1 = synth.gaussian_field((200, 150, 120), 30, 11)
+    f2 = synth.gaussian_field((120, 200, 150), 30, 12)
+    s1, s2 = torch.cuda.Stream(), torch.cuda.Stream()
+    t1, t2 = torch.from_numpy(f1).cuda(), torch.from_numpy(f2).cuda()
+    o1 = tuple(torch.empty(t1.numel(), dtype=torch.int32, device="cuda")
+               for _ in range(3))
+    o2 = tuple(torch.empty(t2.numel(), dtype=torch.int32, device="cuda")
+               for _ in range(3))
+    torch.cuda.synchronize()
+    msc.segment_into(t1, *o1, stream=s1, check=False)
+    msc.segment_into(t2, *o2, stream=s2, check=False)
+    s2.synchronize()
+    s1.synchronize()
+    for f, o in ((f1, o1), (f2, o2)):
+        for name, g, w in zip(("asc", "desc", "ms"), o, O.segment(f)):
+            np.testing.assert_array_equal(g.cpu().numpy(), w, err_msg=name)
