@@ -297,6 +297,25 @@ MSC_API int cc_label_grid(msc_ctx *ctx, const uint8_t *mask, const int64_t dims[
  * Outputs, layout and errors as cc_label_grid, and bit-identical to it;
  * MSC_EINVAL also for ranks < 1 or ranks > Z.
  */
+/*
+ * cc_label_grid for callers that cannot allocate (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * labels, with no context and no allocation of any kind.  The tile-local
+ * roots live in a static device array of 2^27 16-bit entries (256 MiB on
+ * each GPU the library runs on, held until the process ends), taken on the
+ * call's first use on a device.
+ *
+ *  Runs on the current HIP device; mask, dims, labels and stream as
+ *  cc_label_grid.  At most 2^27 vertices (512^3).
+ *  Every call on one GPU shares that GPU's array: calls whose work overlaps
+ *  on the device (two streams, or two host threads) race; calls on one
+ *  stream are ordered and safe.
+ *  Errors: MSC_EINVAL (NULL pointers, dims < 1), MSC_ERANGE (more than 2^27
+ *  vertices), MSC_EHIP.
+ */
+MSC_API int cc_label_grid_noalloc(const uint8_t *mask, const int64_t dims[3],
+                                  int64_t *labels, void *stream);
+
 MSC_API int cc_label_grid_ranks(msc_ctx *ctx, const uint8_t *mask,
                                 const int64_t dims[3], int ranks,
                                 int64_t *labels, void *stream);

@@ -23,6 +23,7 @@
 // CSR graphs have no locality to exploit: init to the smallest masked
 // neighbour, one union per listed edge, then a final find per vertex.
 #include <climits>
+#include <mutex>
 
 #include "msc_internal.hpp"
 
@@ -622,6 +623,75 @@ int jump_run(msc_ctx *ctx, int64_t *d, int64_t n, int rounds, int sync,
                                hipMemcpyDeviceToDevice, s));
   return MSC_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Grid CC with no allocation (for callers that cannot allocate: code under
+// graph capture, tight serving loops).  The tile-local roots live in one
+// static device array per GPU, taken once per device by symbol address.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+// 16-bit tile-local root per vertex: 2^27 entries (256 MiB per GPU the
+// library runs on, held until the process ends) bound a call at 2^27
+// vertices (512^3).
+constexpr int64_t kNoAllocMaxVertices = INT64_C(1) << 27;
+static __device__ __align__(256) uint16_t scratch[kNoAllocMaxVertices];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+uint16_t *g_scratch_ptr[kMaxDevices] = {};
+
+// The array's device address on `dev`, the current device (the host-side
+// name `scratch` is only a stand-in, never a device address).
+int scratch_of(int dev, uint16_t **out) {
+  if (dev < 0 || dev >= kMaxDevices) return MSC_EINVAL;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return MSC_EHIP;
+    }
+    g_scratch_ptr[dev] = static_cast<uint16_t *>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return MSC_OK;
+}
+
+}  // namespace
+}  // namespace msc
+
+extern "C" int cc_label_grid_noalloc(const uint8_t *mask,
+                                     const int64_t dims[3], int64_t *labels,
+                                     void *stream) {
+  using namespace msc;
+  if (!mask || !labels || !dims) return MSC_EINVAL;
+  for (int k = 0; k < 3; ++k)
+    if (dims[k] < 1) return MSC_EINVAL;
+  if (dims[0] > kNoAllocMaxVertices || dims[1] > kNoAllocMaxVertices ||
+      dims[2] > kNoAllocMaxVertices ||
+      dims[0] * dims[1] > kNoAllocMaxVertices ||
+      dims[0] * dims[1] * dims[2] > kNoAllocMaxVertices)
+    return MSC_ERANGE;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return MSC_EHIP;
+  uint16_t *loc = nullptr;
+  MSC_TRY(scratch_of(dev, &loc));
+  const int64_t X = dims[0], Y = dims[1], Z = dims[2];
+  CGeo g{X, Y, Z, X * Y, X * Y * Z, (X + CTX - 1) / CTX, (Y + CTY - 1) / CTY,
+         (Z + CTZ - 1) / CTZ};
+  const unsigned nb = (unsigned)(g.ntx * g.nty * g.ntz);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // Every entry of `loc` the kernels read is written first (k_cc_tile
+  // writes each vertex's root or kOutside), so nothing is cleared.
+  k_cc_tile<<<nb, kCThreads, 0, s>>>(mask, g, loc, labels);
+  k_cc_cross<<<nb, kCThreads, 0, s>>>(g, loc, labels);
+  k_cc_final<<<nb, kCThreads, 0, s>>>(g, loc, labels, 0);
+  return hipGetLastError() == hipSuccess ? MSC_OK : MSC_EHIP;
+}
+
+namespace msc {
 
 // ---------------------------------------------------------------------------
 // Virtual ranks: slab-local labelling, then the exchange across slab

@@ -85,6 +85,7 @@ _SIGS = {
     "cc_label_grid_ranks": ([_P, _P, ctypes.POINTER(_I64), _I32, _P, _P],
                             _I32),
     "cc_label_csr": ([_P, _I64, _P, _P, _P, _P, _P], _I32),
+    "cc_label_grid_noalloc": ([_P, ctypes.POINTER(_I64), _P, _P], _I32),
     "msc_pointer_jump": ([_P, _P, _I64, _I32, _I32, _P], _I32),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -463,6 +464,17 @@ def cc_label_grid(mask: torch.Tensor, stream=None) -> torch.Tensor:
     labels = torch.empty(mask.numel(), dtype=torch.int64, device=mask.device)
     cc_label_grid_into(mask, labels, stream=stream)
     return labels
+
+
+def cc_label_grid_noalloc_into(mask, labels, dims=None, stream=None):
+    """cc_label_grid into a caller tensor through the entry point that
+    allocates nothing (current device; at most 2^27 vertices)."""
+    if dims is None:
+        dims = grid_dims(mask.shape)
+    code = _lib.cc_label_grid_noalloc(
+        _dev_ptr(mask, torch.uint8, "mask"), _dims_arg(dims),
+        _dev_ptr(labels, torch.int64, "labels"), _stream(mask, stream))
+    _check(code, "cc_label_grid_noalloc")
 
 
 def cc_label_grid_ranks(mask: torch.Tensor, ranks: int, dims=None,
