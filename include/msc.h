@@ -11,8 +11,10 @@
  *    by the caller; the library never frees or keeps them past the call.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
  *    device work of a call is enqueued on it.  msc_segment,
- *    msc_segment_batched and cc_label_grid return with their work only
- *    enqueued (the host waits only when a workspace has to grow); their
+ *    msc_segment_batched, cc_label_grid and cc_label_grid_batched return
+ *    with their work only enqueued (the host waits only when a workspace has
+ *    to grow, or when more than four segmentation calls of one context are
+ *    still running: the oldest is waited for); their
  *    outputs are complete once `stream` has completed, and conditions that
  *    the device detects (a NaN in a field) are reported afterwards by
  *    msc_last_status and the stats calls.  Calls documented as synchronising
@@ -60,6 +62,9 @@ enum {
   MSC_EBUSY = 8    /* ticket not finished (msc_poll)                      */
 };
 
+/* Kinds of work: segmentation of a float32 field, CC of a grid mask. */
+enum { MSC_REQ_SEGMENT = 1, MSC_REQ_CC_GRID = 2 };
+
 typedef struct msc_ctx msc_ctx;
 
 /* Static string for an error code (never NULL). */
@@ -72,6 +77,32 @@ MSC_API int msc_create(msc_ctx **out, int device);
 /* Release the context and its workspace.  Synchronises the device first.
  * NULL is ignored. */
 MSC_API void msc_destroy(msc_ctx *ctx);
+
+/*
+ * Caller-owned workspace.  msc_set_workspace makes the context carve every
+ * call's per-call scratch from `ptr` (device memory of the context's GPU,
+ * 256-byte aligned, `bytes` long) instead of memory it allocates: a call
+ * whose scratch does not fit returns MSC_ENOMEM and allocates nothing for
+ * it.  msc_segment, msc_segment_batched, cc_label_grid and
+ * cc_label_grid_batched need nothing else; the virtual-rank calls and
+ * msc_segment_csr also keep buffers of their own that the library
+ * allocates.  ptr == NULL returns to a library-owned workspace.  Waits for the context's earlier work (the old
+ * workspace may still be in use); the memory must stay valid, and unused by
+ * anything else while the context's work runs, until it is replaced or the
+ * context is destroyed.
+ *  Errors: MSC_EINVAL (ctx NULL, ptr misaligned, bytes < 4096 with ptr set),
+ *  MSC_EHIP.
+ *
+ * msc_workspace_size: the scratch bytes one call needs, with the context's
+ * current tile shape: kind MSC_REQ_SEGMENT for msc_segment_batched over
+ * `n` msc_field descriptors, MSC_REQ_CC_GRID for cc_label_grid_batched over
+ * `n` msc_mask descriptors (n = 1: msc_segment / cc_label_grid).  Only the
+ * descriptors' dims and which outputs are NULL are read.
+ *  Errors: MSC_EINVAL, MSC_ERANGE (the call itself would fail with it).
+ */
+MSC_API int msc_set_workspace(msc_ctx *ctx, void *ptr, size_t bytes);
+MSC_API int msc_workspace_size(const msc_ctx *ctx, int kind, int n,
+                               const void *descs, size_t *bytes);
 
 /*
  * Morse-Smale segmentation of a float32 scalar field on a grid.
@@ -287,6 +318,26 @@ MSC_API int cc_label_grid(msc_ctx *ctx, const uint8_t *mask, const int64_t dims[
                   int64_t *labels, void *stream);
 
 /*
+ * cc_label_grid over several masks of independent shapes in shared
+ * launches (up to 32 masks per launch): each mask is labelled on its own,
+ * with ids local to it, bit-identical to a cc_label_grid call per mask.
+ * Asynchronous like cc_label_grid; the masks' outputs must not overlap.
+ *
+ *  masks   host array of `nmasks` descriptors (read during the call only);
+ *          each holds a device mask, its dims and its device labels.
+ *  Errors: MSC_EINVAL (NULL pointers, dims < 1, nmasks < 0), MSC_ERANGE,
+ *  MSC_ENOMEM, MSC_EHIP.  nmasks == 0 does nothing.
+ */
+typedef struct msc_mask {
+  const uint8_t *mask;  /* device, uint8[N]                */
+  int64_t dims[3];      /* X, Y, Z                         */
+  int64_t *labels;      /* device, int64[N]                */
+} msc_mask;
+
+MSC_API int cc_label_grid_batched(msc_ctx *ctx, int nmasks,
+                                  const msc_mask *masks, void *stream);
+
+/*
  * cc_label_grid through the paper's distributed scheme with `ranks` virtual
  * ranks on one device (Alg. 3 followed by the communication phase it
  * shares with the MS segmentation): the z-extent is split into slabs of
@@ -297,6 +348,10 @@ MSC_API int cc_label_grid(msc_ctx *ctx, const uint8_t *mask, const int64_t dims[
  * Outputs, layout and errors as cc_label_grid, and bit-identical to it;
  * MSC_EINVAL also for ranks < 1 or ranks > Z.
  */
+MSC_API int cc_label_grid_ranks(msc_ctx *ctx, const uint8_t *mask,
+                                const int64_t dims[3], int ranks,
+                                int64_t *labels, void *stream);
+
 /*
  * cc_label_grid for callers that cannot allocate (code under HIP graph
  * capture, tight serving loops, harnesses that forbid allocation): the same
@@ -315,10 +370,6 @@ MSC_API int cc_label_grid(msc_ctx *ctx, const uint8_t *mask, const int64_t dims[
  */
 MSC_API int cc_label_grid_noalloc(const uint8_t *mask, const int64_t dims[3],
                                   int64_t *labels, void *stream);
-
-MSC_API int cc_label_grid_ranks(msc_ctx *ctx, const uint8_t *mask,
-                                const int64_t dims[3], int ranks,
-                                int64_t *labels, void *stream);
 
 /*
  * Critical points by the connected components of each vertex's lower and
@@ -421,38 +472,41 @@ MSC_API int msc_pointer_jump(msc_ctx *ctx, int64_t *d, int64_t n, int rounds,
 /*
  * Serving: a request queue with continuous batching.
  *
- * A queue reserves `hbm_budget` bytes of device memory as an arena for
- * request-resident buffers (each request's input and outputs) and admits
- * requests in arrival order while the arena holds their buffers and the
- * resident bytes plus an estimate of the workspace of every admitted,
- * unfinished request (8 bytes per vertex for a segmentation, 2 for a CC)
- * stay within the budget.  That workspace is held by the queue's two
- * library contexts outside the arena; it grows to the largest launch and is
- * kept until msc_queue_destroy.  Admitted inputs are copied to the device
- * on a copy stream, at most 8 requests ahead of the launches (copies issued
- * further ahead would share the host link with the ones a launch waits
- * for); a request beyond that window waits unadmitted.  Segmentation
- * requests that are staged while a launch is running join the next launch
- * (one msc_segment_batched call of at most `max_batch` fields and, unless a
- * single request is larger, at most 2^26 vertices, since a launch's requests
- * all complete together), and mask-CC requests run on their own stream, so
- * the two kinds overlap on the device.  Results stay on the device until
- * msc_release; a finished request that is never released keeps its arena
- * space, so the requests behind it wait.  Every call is thread-safe.  A
- * request that fails (e.g. NaN in its field) fails alone: its batch is rerun
- * field by field.
+ * A queue takes `hbm_budget` bytes of device memory at creation and splits
+ * it: a workspace for segmentation launches (a quarter of the budget, at
+ * most 8 GiB), one for mask-CC launches (a sixteenth, at most 1 GiB), and an
+ * arena for request-resident buffers (each request's input and outputs).
+ * Requests are admitted in arrival order within their kind while the arena
+ * holds their buffers and their kind has fewer than 8 requests staged ahead
+ * of its launches (copies issued further ahead would share the host link
+ * with the ones a launch waits for); a request of one kind never waits for
+ * the other kind's window.  Admitted inputs are copied to the device on a
+ * copy stream.  Each kind has its own stream: staged requests that arrive
+ * while launches run join the next launch of their kind (one batched call of
+ * at most `max_batch` requests and, unless a single request is larger, at
+ * most 2^26 vertices, since a launch's requests all complete together), at
+ * most two launches per kind are in flight, and the two kinds overlap on the
+ * device.  The workspaces are never reallocated while the queue serves.
+ * Results stay on the device until msc_release; a finished request that is
+ * never released keeps its arena space, so the requests behind it wait.
+ * Every call is thread-safe.  A request that fails (e.g. NaN in its field)
+ * fails alone: the other requests of its launch keep their results.
  *
  *  msc_queue_create: `device` is the HIP device index, `hbm_budget` at least
- *  1 MiB, `max_batch` >= 1 (1 = one field per launch).  MSC_EINVAL,
- *  MSC_ENOMEM (arena allocation failed), MSC_EHIP.  Starts three host
- *  threads; msc_queue_destroy joins them after the running launches end and
- *  frees everything, including unreleased results.
+ *  1 MiB, `max_batch` >= 1 (1 = one request per launch).  MSC_EINVAL,
+ *  MSC_ENOMEM (allocation failed), MSC_EHIP.  Starts five host threads;
+ *  msc_queue_destroy joins them after the running launches end and frees
+ *  everything, including unreleased results.
  *  msc_request.host_input: the input, read until the request is staged:
  *  host memory (page-locked memory makes the copy asynchronous) or device
  *  memory of the queue's device; float32[N] for MSC_REQ_SEGMENT, uint8
- *  mask[N] for MSC_REQ_CC_GRID.  It is copied into the queue's arena.
- *  msc_submit: MSC_EBUDGET if the request alone exceeds the budget,
- *  MSC_EINVAL / MSC_ERANGE as msc_segment.  *ticket names the request.
+ *  mask[N] for MSC_REQ_CC_GRID.  It is copied into the queue's arena on the
+ *  queue's own streams, which are not ordered after any stream of the
+ *  caller: an input in device memory must be complete (its producer
+ *  synchronised) before msc_submit.
+ *  msc_submit: MSC_EBUDGET if the request's buffers exceed the arena or its
+ *  launch scratch exceeds its kind's workspace, MSC_EINVAL / MSC_ERANGE as
+ *  msc_segment.  *ticket names the request.
  *  msc_poll: *status = MSC_EBUSY while queued or running, MSC_ECANCELED, or
  *  the request's own result code.
  *  msc_wait: blocks until the request is finished; returns its result code.
@@ -461,9 +515,12 @@ MSC_API int msc_pointer_jump(msc_ctx *ctx, int64_t *d, int64_t n, int rounds,
  *  msc_cancel: removes a request that is still waiting for admission
  *  (MSC_EBUSY once admitted).
  *  msc_release: frees a finished or cancelled request's device memory.
+ *  msc_queue_info: budget; arena_size and arena_used (request buffers);
+ *  workspace_reserved (the two workspaces); request counts by state;
+ *  launches issued; workspace_grows (0 while serving: the workspaces are
+ *  fixed) and host_waits (times a worker's host thread waited for the device
+ *  before enqueuing a launch).
  */
-enum { MSC_REQ_SEGMENT = 1, MSC_REQ_CC_GRID = 2 };
-
 typedef struct msc_queue msc_queue;
 
 typedef struct msc_request {
@@ -485,6 +542,8 @@ typedef struct msc_result {
 typedef struct msc_queue_stats {
   size_t budget, arena_used, workspace_reserved;
   int64_t pending, running, finished;
+  size_t arena_size;
+  int64_t launches, workspace_grows, host_waits;
 } msc_queue_stats;
 
 MSC_API int msc_queue_create(int device, size_t hbm_budget, int max_batch,

@@ -9,10 +9,20 @@
 
 namespace msc {
 
+int host_wait(msc_ctx *ctx, hipEvent_t e) {
+  const hipError_t q = hipEventQuery(e);
+  if (q == hipSuccess) return MSC_OK;
+  if (q != hipErrorNotReady) return MSC_EHIP;
+  ++ctx->host_waits;
+  MSC_HIP_TRY(hipEventSynchronize(e));
+  return MSC_OK;
+}
+
 int reserve(msc_ctx *ctx, DevBuf &buf, size_t bytes) {
   if (bytes <= buf.bytes) return MSC_OK;
+  if (buf.external) return MSC_ENOMEM;
   // The old block may still be read by this context's queued work.
-  if (ctx->done_valid) MSC_HIP_TRY(hipEventSynchronize(ctx->done));
+  if (ctx->done_valid) MSC_TRY(host_wait(ctx, ctx->done));
   ++ctx->grows;
   if (buf.ptr) {
     MSC_HIP_TRY(hipFree(buf.ptr));
@@ -65,7 +75,7 @@ int pinned_slot(msc_ctx *ctx, size_t bytes, void **out, int *slot) {
   ctx->next_slot = (k + 1) % kPinnedSlots;
   PinnedSlot &ps = ctx->slots[k];
   // The copy that last read this slot must have executed.
-  if (ps.pending) MSC_HIP_TRY(hipEventSynchronize(ps.copied));
+  if (ps.pending) MSC_TRY(host_wait(ctx, ps.copied));
   ps.pending = false;
   if (bytes > ps.bytes) {
     if (ps.ptr) (void)hipHostFree(ps.ptr);
@@ -117,6 +127,7 @@ struct DeviceGuard {
 // the call's work is ordered after that call's.
 int enter_sync(msc_ctx *ctx, hipStream_t s) {
   MSC_TRY(msc::finish_last(ctx));
+  msc::stats_replaced(ctx);
   return msc::begin_call(ctx, s);
 }
 
@@ -180,6 +191,9 @@ int msc_create(msc_ctx **out, int device) {
   for (int k = 0; ev_ok && k < msc::kPinnedSlots; ++k)
     ev_ok = hipEventCreateWithFlags(&c->slots[k].copied,
                                     hipEventDisableTiming) == hipSuccess;
+  for (int k = 0; ev_ok && k < msc::kCallRing; ++k)
+    ev_ok = hipEventCreateWithFlags(&c->calls[k].done,
+                                    hipEventDisableTiming) == hipSuccess;
   if (!ev_ok) {
     msc_destroy(c);
     return MSC_EHIP;
@@ -201,19 +215,66 @@ void msc_destroy(msc_ctx *ctx) {
   DeviceGuard g(ctx->device);
   (void)hipDeviceSynchronize();
   if (ctx->pinned) (void)hipHostFree(ctx->pinned);
-  if (ctx->ws.ptr) (void)hipFree(ctx->ws.ptr);
+  if (ctx->ws.ptr && !ctx->ws.external) (void)hipFree(ctx->ws.ptr);
   if (ctx->tab.ptr) (void)hipFree(ctx->tab.ptr);
   if (ctx->xg.ptr) (void)hipFree(ctx->xg.ptr);
   if (ctx->rk.ptr) (void)hipFree(ctx->rk.ptr);
   if (ctx->dctr) (void)hipFree(ctx->dctr);
   if (ctx->hctr) (void)hipHostFree(ctx->hctr);
-  if (ctx->hfctr) (void)hipHostFree(ctx->hfctr);
+  for (msc::CallRec &r : ctx->calls) {
+    if (r.hctr) (void)hipHostFree(r.hctr);
+    if (r.hfctr) (void)hipHostFree(r.hfctr);
+    if (r.done) (void)hipEventDestroy(r.done);
+  }
   for (msc::PinnedSlot &ps : ctx->slots) {
     if (ps.ptr) (void)hipHostFree(ps.ptr);
     if (ps.copied) (void)hipEventDestroy(ps.copied);
   }
   if (ctx->done) (void)hipEventDestroy(ctx->done);
   delete ctx;
+}
+
+int msc_set_workspace(msc_ctx *ctx, void *ptr, size_t bytes) {
+  if (!ctx) return MSC_EINVAL;
+  if (ptr && ((reinterpret_cast<uintptr_t>(ptr) & 255) || bytes < 4096))
+    return MSC_EINVAL;
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return MSC_EHIP;
+  // The current workspace may still be read by queued work.
+  if (ctx->done_valid) MSC_HIP_TRY(hipEventSynchronize(ctx->done));
+  if (ctx->ws.ptr && !ctx->ws.external) MSC_HIP_TRY(hipFree(ctx->ws.ptr));
+  ctx->ws = msc::DevBuf{};
+  if (ptr) {
+    ctx->ws.ptr = static_cast<char *>(ptr);
+    ctx->ws.bytes = bytes;
+    ctx->ws.external = true;
+  }
+  return MSC_OK;
+}
+
+int msc_workspace_size(const msc_ctx *ctx, int kind, int n, const void *descs,
+                       size_t *bytes) {
+  if (!ctx || !bytes || n < 0 || (n > 0 && !descs)) return MSC_EINVAL;
+  *bytes = 0;
+  if (kind == MSC_REQ_SEGMENT) {
+    const msc_field *f = static_cast<const msc_field *>(descs);
+    for (int i = 0; i < n; ++i) {
+      int64_t v = 0;
+      MSC_TRY(check_dims(f[i].dims, &v));
+      if (v > INT32_MAX) return MSC_ERANGE;
+    }
+    return n ? msc::segment_workspace(ctx, n, f, bytes) : MSC_OK;
+  }
+  if (kind == MSC_REQ_CC_GRID) {
+    const msc_mask *m = static_cast<const msc_mask *>(descs);
+    for (int i = 0; i < n; ++i) {
+      int64_t v = 0;
+      MSC_TRY(check_dims(m[i].dims, &v));
+    }
+    *bytes = msc::cc_grid_workspace(n, m);
+    return MSC_OK;
+  }
+  return MSC_EINVAL;
 }
 
 int msc_segment(msc_ctx *ctx, const float *field, const int64_t dims[3],
@@ -283,7 +344,7 @@ int msc_last_status(msc_ctx *ctx, int *status) {
   if (!ctx || !status) return MSC_EINVAL;
   DeviceGuard g(ctx->device);
   MSC_TRY(msc::finish_last(ctx));
-  *status = ctx->last.status;
+  *status = ctx->last_status;
   return MSC_OK;
 }
 
@@ -405,11 +466,29 @@ int cc_label_grid(msc_ctx *ctx, const uint8_t *mask, const int64_t dims[3],
   MSC_TRY(check_dims(dims, &n));
   DeviceGuard g(ctx->device);
   if (!g.ok) return MSC_EHIP;
-  ctx->last.pending = false;  // this call replaces the stats
+  msc::stats_replaced(ctx);  // this call replaces the stats
   MSC_TRY(msc::begin_call(ctx, static_cast<hipStream_t>(stream)));
   MSC_TRY(msc::cc_grid_run(ctx, mask, dims[0], dims[1], dims[2], labels,
                            static_cast<hipStream_t>(stream)));
   return msc::end_call(ctx, static_cast<hipStream_t>(stream));
+}
+
+int cc_label_grid_batched(msc_ctx *ctx, int nmasks, const msc_mask *masks,
+                          void *stream) {
+  if (!ctx || nmasks < 0 || (nmasks > 0 && !masks)) return MSC_EINVAL;
+  if (nmasks == 0) return MSC_OK;
+  for (int i = 0; i < nmasks; ++i) {
+    if (!masks[i].mask || !masks[i].labels) return MSC_EINVAL;
+    int64_t n = 0;
+    MSC_TRY(check_dims(masks[i].dims, &n));
+  }
+  DeviceGuard g(ctx->device);
+  if (!g.ok) return MSC_EHIP;
+  msc::stats_replaced(ctx);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  MSC_TRY(msc::begin_call(ctx, s));
+  MSC_TRY(msc::cc_grid_batch_run(ctx, nmasks, masks, s));
+  return msc::end_call(ctx, s);
 }
 
 int cc_label_grid_ranks(msc_ctx *ctx, const uint8_t *mask,

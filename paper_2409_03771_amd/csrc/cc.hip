@@ -129,19 +129,64 @@ __device__ __forceinline__ int64_t ctile_global(const CGeo &g, const CTile &t,
   return (t.x0 + lx) + g.X * (t.y0 + ly) + g.XY * (t.z0 + lz);
 }
 
+// One mask of a launch: its buffers, shape and first tile.  A launch covers
+// the tiles of up to B masks (B = 1 for a single mask), passed by value.
+struct CGrid {
+  const uint8_t *mask;
+  int64_t *L;      // labels, also the union-find parent array
+  uint16_t *loc;   // tile-local roots (workspace)
+  int64_t off;     // added to every label (a slab inside a larger grid)
+  int64_t X, Y, Z;
+  uint32_t tile0;  // first tile of this mask in the launch
+};
+
+template <int B>
+struct CBatch {
+  int n;
+  CGrid g[B];
+};
+
+// The mask and geometry of launch tile `tt`, and the tile's index within it.
+template <int B>
+__device__ __forceinline__ const CGrid &cgrid_of(const CBatch<B> &b,
+                                                 uint32_t tt, CGeo *g,
+                                                 int64_t *t) {
+  int lo = 0;
+  if (B > 1) {
+    int hi = b.n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (b.g[mid].tile0 <= tt) lo = mid;
+      else hi = mid - 1;
+    }
+  }
+  const CGrid &d = b.g[lo];
+  const int64_t X = d.X, Y = d.Y, Z = d.Z;
+  *g = CGeo{X, Y, Z, X * Y, X * Y * Z, (X + CTX - 1) / CTX,
+            (Y + CTY - 1) / CTY, (Z + CTZ - 1) / CTZ};
+  *t = (int64_t)(tt - d.tile0);
+  return d;
+}
+
 // First z of the run of consecutive set bits of `bits` that contains bit z.
 __device__ __forceinline__ int run_start(uint32_t bits, int z) {
   const uint32_t zeros = ~bits & ((1u << z) - 1u);
   return zeros ? 32 - __clz(zeros) : 0;
 }
 
-__global__ void __launch_bounds__(kCThreads)
-k_cc_tile(const uint8_t *__restrict__ mask, CGeo g, uint16_t *__restrict__ loc,
-          int64_t *__restrict__ L) {
+template <int B>
+__global__ void __launch_bounds__(kCThreads) k_cc_tile(CBatch<B> b) {
   __shared__ int32_t par[kCOwned];
   __shared__ uint32_t cols[kCThreads];  // mask bits of every column
   const int tid = threadIdx.x;
-  const CTile t = ctile_at(g, cc_tile_of_block(blockIdx.x, gridDim.x));
+  CGeo g;
+  int64_t ti;
+  const CGrid &d = cgrid_of(b, cc_tile_of_block(blockIdx.x, gridDim.x), &g,
+                            &ti);
+  const uint8_t *__restrict__ mask = d.mask;
+  uint16_t *__restrict__ loc = d.loc;
+  int64_t *__restrict__ L = d.L;
+  const CTile t = ctile_at(g, ti);
   const int cx = tid % CTX, cy = tid / CTX;
   const int64_t gx = t.x0 + cx, gy = t.y0 + cy;
   const bool col_in = gx < g.X && gy < g.Y;
@@ -261,8 +306,8 @@ __device__ __forceinline__ void cross_unite(const CGeo &g, const CTile &t,
                     ctile_global(g, tu, (int)lu));
 }
 
-__global__ void __launch_bounds__(kCThreads)
-k_cc_cross(CGeo g, const uint16_t *__restrict__ loc, int64_t *L) {
+template <int B>
+__global__ void __launch_bounds__(kCThreads) k_cc_cross(CBatch<B> b) {
   static_assert(kCOwned <= (1 << 13), "13-bit local roots in the keys");
   // The tile grown by one vertex on its upper sides; only the two upper
   // layers of each side are read: the tile's upper faces and the vertices
@@ -274,7 +319,13 @@ k_cc_cross(CGeo g, const uint16_t *__restrict__ loc, int64_t *L) {
   __shared__ uint32_t set[kCrossSlots];
   const int tid = threadIdx.x;
   for (int i = tid; i < kCrossSlots; i += kCThreads) set[i] = kNoKey;
-  const CTile t = ctile_at(g, cc_tile_of_block(blockIdx.x, gridDim.x));
+  CGeo g;
+  int64_t ti;
+  const CGrid &d = cgrid_of(b, cc_tile_of_block(blockIdx.x, gridDim.x), &g,
+                            &ti);
+  const uint16_t *__restrict__ loc = d.loc;
+  int64_t *L = d.L;
+  const CTile t = ctile_at(g, ti);
   {
     uint16_t val[K];
 #pragma unroll
@@ -334,10 +385,17 @@ k_cc_cross(CGeo g, const uint16_t *__restrict__ loc, int64_t *L) {
 // grid writes global ids).  The tile-local roots keep the unshifted root
 // here, since concurrent walks read their entries as indices; k_cc_root_shift
 // adds the offset to them afterwards.
-__global__ void __launch_bounds__(kCThreads)
-k_cc_final(CGeo g, const uint16_t *__restrict__ loc, int64_t *L, int64_t off) {
+template <int B>
+__global__ void __launch_bounds__(kCThreads) k_cc_final(CBatch<B> b) {
   const int tid = threadIdx.x;
-  const CTile t = ctile_at(g, cc_tile_of_block(blockIdx.x, gridDim.x));
+  CGeo g;
+  int64_t ti;
+  const CGrid &d = cgrid_of(b, cc_tile_of_block(blockIdx.x, gridDim.x), &g,
+                            &ti);
+  const uint16_t *__restrict__ loc = d.loc;
+  int64_t *L = d.L;
+  const int64_t off = d.off;
+  const CTile t = ctile_at(g, ti);
   const int cx = tid % CTX, cy = tid / CTX;
   const int64_t gx = t.x0 + cx, gy = t.y0 + cy;
   if (gx >= g.X || gy >= g.Y) return;
@@ -363,11 +421,17 @@ k_cc_final(CGeo g, const uint16_t *__restrict__ loc, int64_t *L, int64_t off) {
 }
 
 // The tile-local roots' labels take the offset once no walk is in flight.
-__global__ void __launch_bounds__(kCThreads)
-k_cc_root_shift(CGeo g, const uint16_t *__restrict__ loc, int64_t *L,
-                int64_t off) {
+template <int B>
+__global__ void __launch_bounds__(kCThreads) k_cc_root_shift(CBatch<B> b) {
   const int tid = threadIdx.x;
-  const CTile t = ctile_at(g, cc_tile_of_block(blockIdx.x, gridDim.x));
+  CGeo g;
+  int64_t ti;
+  const CGrid &d = cgrid_of(b, cc_tile_of_block(blockIdx.x, gridDim.x), &g,
+                            &ti);
+  const uint16_t *__restrict__ loc = d.loc;
+  int64_t *L = d.L;
+  const int64_t off = d.off;
+  const CTile t = ctile_at(g, ti);
   const int cx = tid % CTX, cy = tid / CTX;
   const int64_t gx = t.x0 + cx, gy = t.y0 + cy;
   if (gx >= g.X || gy >= g.Y) return;
@@ -525,32 +589,96 @@ constexpr int kMaxRounds = 96;
 
 }  // namespace
 
+namespace {
+
+// Masks per launch of a batched call: their descriptors travel as kernel
+// arguments (64 bytes each).
+constexpr int kCCBatch = 32;
+
+// The grid-CC kernels over `nb` tiles of the masks in `b`.
+template <int B>
+int cc_launch(msc_ctx *ctx, const CBatch<B> &b, uint32_t nb, int64_t nverts,
+              bool shift, hipStream_t s) {
+  MSC_PHASE(ctx, s, "cc_tile", 3.0 * nverts,
+            (k_cc_tile<B><<<nb, kCThreads, 0, s>>>(b)));
+  MSC_PHASE(ctx, s, "cc_cross", 0.5 * nverts,
+            (k_cc_cross<B><<<nb, kCThreads, 0, s>>>(b)));
+  MSC_PHASE(ctx, s, "cc_final", 10.0 * nverts,
+            (k_cc_final<B><<<nb, kCThreads, 0, s>>>(b)));
+  if (shift)
+    MSC_PHASE(ctx, s, "cc_root_shift", 2.0 * nverts,
+              (k_cc_root_shift<B><<<nb, kCThreads, 0, s>>>(b)));
+  return MSC_OK;
+}
+
+int64_t cc_tiles(int64_t X, int64_t Y, int64_t Z) {
+  return ((X + CTX - 1) / CTX) * ((Y + CTY - 1) / CTY) * ((Z + CTZ - 1) / CTZ);
+}
+
+}  // namespace
+
+size_t cc_grid_workspace(int n, const msc_mask *masks) {
+  size_t need = 4096;
+  for (int i = 0; i < n; ++i)
+    need += align256((size_t)(masks[i].dims[0] * masks[i].dims[1] *
+                              masks[i].dims[2]) * sizeof(uint16_t));
+  return need;
+}
+
 int cc_grid_run(msc_ctx *ctx, const uint8_t *mask, int64_t X, int64_t Y,
                 int64_t Z, int64_t *labels, hipStream_t s, bool sync,
                 int64_t label_off) {
-  CGeo g{X, Y, Z, X * Y, X * Y * Z, (X + CTX - 1) / CTX, (Y + CTY - 1) / CTY,
-         (Z + CTZ - 1) / CTZ};
-  const int64_t ntiles = g.ntx * g.nty * g.ntz;
+  const int64_t N = X * Y * Z;
+  const int64_t ntiles = cc_tiles(X, Y, Z);
   if (ntiles > INT32_MAX) return MSC_ERANGE;
-  MSC_TRY(reserve(ctx, ctx->ws, align256(g.N * sizeof(uint16_t)) + 4096));
+  MSC_TRY(reserve(ctx, ctx->ws, align256(N * sizeof(uint16_t)) + 4096));
   Carver cv(ctx->ws);
-  uint16_t *loc = cv.take<uint16_t>(g.N);
-  MSC_TRY(clear_counters(ctx, s));
-  const unsigned nb = (unsigned)ntiles;
-  MSC_PHASE(ctx, s, "cc_tile", 3.0 * g.N,
-            (k_cc_tile<<<nb, kCThreads, 0, s>>>(mask, g, loc, labels)));
-  MSC_PHASE(ctx, s, "cc_cross", 0.5 * g.N,
-            (k_cc_cross<<<nb, kCThreads, 0, s>>>(g, loc, labels)));
-  MSC_PHASE(ctx, s, "cc_final", 10.0 * g.N,
-            (k_cc_final<<<nb, kCThreads, 0, s>>>(g, loc, labels, label_off)));
-  if (label_off)
-    MSC_PHASE(ctx, s, "cc_root_shift", 2.0 * g.N,
-              (k_cc_root_shift<<<nb, kCThreads, 0, s>>>(g, loc, labels,
-                                                        label_off)));
+  uint16_t *loc = cv.take<uint16_t>(N);
+  CBatch<1> b{1, {CGrid{mask, labels, loc, label_off, X, Y, Z, 0u}}};
+  MSC_TRY(cc_launch(ctx, b, (uint32_t)ntiles, N, label_off != 0, s));
   if (!sync) return MSC_OK;
   // Nothing to read back: the labels are the whole result.
   ctx->stats = msc_stats{};
-  ctx->stats.n_vertices = g.N;
+  ctx->stats.n_vertices = N;
+  ctx->stats.tile_x = CTX;
+  ctx->stats.tile_y = CTY;
+  ctx->stats.tile_z = CTZ;
+  return MSC_OK;
+}
+
+int cc_grid_batch_run(msc_ctx *ctx, int n, const msc_mask *masks,
+                      hipStream_t s) {
+  int64_t total = 0;
+  for (int i = 0; i < n; ++i) {
+    const int64_t *d = masks[i].dims;
+    if (cc_tiles(d[0], d[1], d[2]) > INT32_MAX) return MSC_ERANGE;
+    total += d[0] * d[1] * d[2];
+  }
+  MSC_TRY(reserve(ctx, ctx->ws, cc_grid_workspace(n, masks)));
+  Carver cv(ctx->ws);
+  CBatch<kCCBatch> b{};
+  uint64_t tiles = 0;
+  int64_t verts = 0;
+  for (int i = 0; i <= n; ++i) {
+    const int64_t *d = i < n ? masks[i].dims : nullptr;
+    const int64_t nt = d ? cc_tiles(d[0], d[1], d[2]) : 0;
+    // Launch what is collected when the batch is full, would pass 2^31 - 1
+    // tiles, or the masks are exhausted.
+    if (b.n > 0 && (i == n || b.n == kCCBatch || tiles + nt > INT32_MAX)) {
+      MSC_TRY(cc_launch(ctx, b, (uint32_t)tiles, verts, false, s));
+      b.n = 0;
+      tiles = 0;
+      verts = 0;
+    }
+    if (i == n) break;
+    const int64_t N = d[0] * d[1] * d[2];
+    b.g[b.n++] = CGrid{masks[i].mask, masks[i].labels, cv.take<uint16_t>(N), 0,
+                       d[0], d[1], d[2], (uint32_t)tiles};
+    tiles += (uint64_t)nt;
+    verts += N;
+  }
+  ctx->stats = msc_stats{};
+  ctx->stats.n_vertices = total;
   ctx->stats.tile_x = CTX;
   ctx->stats.tile_y = CTY;
   ctx->stats.tile_z = CTZ;
@@ -679,15 +807,15 @@ extern "C" int cc_label_grid_noalloc(const uint8_t *mask,
   uint16_t *loc = nullptr;
   MSC_TRY(scratch_of(dev, &loc));
   const int64_t X = dims[0], Y = dims[1], Z = dims[2];
-  CGeo g{X, Y, Z, X * Y, X * Y * Z, (X + CTX - 1) / CTX, (Y + CTY - 1) / CTY,
-         (Z + CTZ - 1) / CTZ};
-  const unsigned nb = (unsigned)(g.ntx * g.nty * g.ntz);
+  const unsigned nb = (unsigned)(((X + CTX - 1) / CTX) * ((Y + CTY - 1) / CTY) *
+                                 ((Z + CTZ - 1) / CTZ));
+  const CBatch<1> b{1, {CGrid{mask, labels, loc, 0, X, Y, Z, 0u}}};
   hipStream_t s = static_cast<hipStream_t>(stream);
   // Every entry of `loc` the kernels read is written first (k_cc_tile
   // writes each vertex's root or kOutside), so nothing is cleared.
-  k_cc_tile<<<nb, kCThreads, 0, s>>>(mask, g, loc, labels);
-  k_cc_cross<<<nb, kCThreads, 0, s>>>(g, loc, labels);
-  k_cc_final<<<nb, kCThreads, 0, s>>>(g, loc, labels, 0);
+  k_cc_tile<1><<<nb, kCThreads, 0, s>>>(b);
+  k_cc_cross<1><<<nb, kCThreads, 0, s>>>(b);
+  k_cc_final<1><<<nb, kCThreads, 0, s>>>(b);
   return hipGetLastError() == hipSuccess ? MSC_OK : MSC_EHIP;
 }
 

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstddef>
 #include <cstdint>
 #include <cstring>
@@ -48,6 +49,7 @@ namespace msc {
 struct DevBuf {
   char *ptr = nullptr;
   size_t bytes = 0;
+  bool external = false;  // caller-owned: never freed or grown
 };
 
 // Event-bracketed per-kernel timing; see msc_profile in msc.h.
@@ -110,16 +112,24 @@ struct PinnedSlot {
 };
 constexpr int kPinnedSlots = 8;
 
-// What the stats calls need of the last segmentation call; its counters
-// arrive in pinned memory when the call's work completes.
-struct LastCall {
-  bool pending = false;          // counters not folded into the stats yet
+// One asynchronous segmentation call: what the stats calls need of it.  Its
+// counters arrive in the record's pinned buffers once its work completes
+// (event `done`).  Records are reused round-robin; a record is taken again
+// only after its call's event has completed.
+struct CallRec {
+  hipEvent_t done = nullptr;
+  bool pending = false;                 // issued; its event not yet waited on
+  unsigned long long *hctr = nullptr;   // pinned copy of the counter block
+  unsigned long long *hfctr = nullptr;  // pinned per-field counters
+  size_t hfctr_cap = 0;                 // entries
   int nfields = 0;
-  std::vector<int64_t> n;        // vertices per field
-  std::vector<char> has_ms;      // cells requested per field
+  std::vector<int64_t> n;               // vertices per field
+  std::vector<char> has_ms;             // cells requested per field
   int tile[3] = {0, 0, 0};
-  int status = MSC_OK;           // device-detected outcome of the call
 };
+// Asynchronous calls that may be in flight on one context before a new one
+// waits for the oldest.
+constexpr int kCallRing = 4;
 }  // namespace msc
 
 struct msc_ctx {
@@ -147,19 +157,29 @@ struct msc_ctx {
   bool done_valid = false;
   msc::PinnedSlot slots[msc::kPinnedSlots];
   int next_slot = 0;
-  unsigned long long *hfctr = nullptr;  // pinned per-field counters
-  size_t hfctr_cap = 0;                 // entries
-  msc::LastCall last;
-  // Workspace growths (each one waits for the context's earlier work).
-  int64_t grows = 0;
+  // Records of the asynchronous segmentation calls; `last_call` is the
+  // record whose stats the stats calls report (-1: the stats are those of a
+  // call that set them itself).
+  msc::CallRec calls[msc::kCallRing];
+  int next_call = 0;
+  int last_call = -1;
+  bool last_folded = true;     // last_call's counters are in `stats`
+  int last_status = MSC_OK;    // device-detected outcome of the last call
+  // Workspace growths (each one waits for the context's earlier work), and
+  // every time the host waited for the device before enqueuing work.
+  std::atomic<int64_t> grows{0};
+  std::atomic<int64_t> host_waits{0};
 };
 
 namespace msc {
 
 // Make sure `buf` holds at least `bytes`.  Growing waits for the context's
 // earlier work (the old block may still be in use) and discards the old
-// contents.
+// contents; a caller-owned buffer is never grown (MSC_ENOMEM).
 int reserve(msc_ctx *ctx, DevBuf &buf, size_t bytes);
+
+// Wait for `e` on the host, counting the wait when it was not complete.
+int host_wait(msc_ctx *ctx, hipEvent_t e);
 
 // Order a call on stream `s` after the context's previous call (which may
 // have run on another stream), and mark the end of a call's work.
@@ -173,6 +193,21 @@ int slot_copied(msc_ctx *ctx, int slot, hipStream_t s);
 
 // Wait for the last segmentation call and fold its counters into the stats.
 int finish_last(msc_ctx *ctx);
+
+// Mark the stats as set by a call that is not a recorded asynchronous one.
+inline void stats_replaced(msc_ctx *ctx) {
+  ctx->last_call = -1;
+  ctx->last_folded = true;
+  ctx->last_status = MSC_OK;
+  ctx->field_stats.clear();
+}
+
+// A record for a new asynchronous call whose counters need `nfields`
+// per-field entries; waits for the record's previous call if still pending.
+int take_call(msc_ctx *ctx, int nfields, int *index);
+
+// Outcome of field `i` of a recorded call, once its event has completed.
+int call_field_status(const msc_ctx *ctx, int index, int i);
 
 // Bump allocator over a DevBuf for the duration of one call.
 struct Carver {
@@ -234,8 +269,14 @@ inline int tile_index(int tx, int ty, int tz) {
 }
 
 // Launchers implemented in the kernel translation units.
+// Workspace bytes segment_batch_run carves for this batch (the context's
+// tile shape).
+int segment_workspace(const msc_ctx *ctx, int nfields, const msc_field *fields,
+                      size_t *bytes);
+// `rec` receives the index of the call's record (see take_call).
 int segment_batch_run(msc_ctx *ctx, int nfields, const msc_field *fields,
-                      hipStream_t s, const uint8_t *ghost = nullptr);
+                      hipStream_t s, const uint8_t *ghost = nullptr,
+                      int *rec = nullptr);
 int segment_ranks_run(msc_ctx *ctx, const float *field, const int64_t dims[3],
                       int ranks, int32_t *asc, int32_t *desc, int32_t *ms,
                       hipStream_t s);
@@ -256,6 +297,11 @@ int segment_csr_run(msc_ctx *ctx, int64_t n, const int64_t *row_ptr,
 int cc_grid_run(msc_ctx *ctx, const uint8_t *mask, int64_t X, int64_t Y,
                 int64_t Z, int64_t *labels, hipStream_t s, bool sync = true,
                 int64_t label_off = 0);
+// Several masks, each labelled on its own, in launches of up to 32 masks.
+int cc_grid_batch_run(msc_ctx *ctx, int n, const msc_mask *masks,
+                      hipStream_t s);
+// Workspace bytes cc_grid_batch_run carves for these masks.
+size_t cc_grid_workspace(int n, const msc_mask *masks);
 int cc_grid_ranks_run(msc_ctx *ctx, const uint8_t *mask, int64_t X,
                       int64_t Y, int64_t Z, int ranks, int64_t *labels,
                       hipStream_t stream);

@@ -1382,44 +1382,98 @@ k_table_clear_all(const FieldDev *__restrict__ fds, int nfields,
 
 // Fold the counters of the last segmentation call into the stats; waits for
 // the call's work.
+namespace {
+// Outcome of a whole recorded call from its counter block.
+int call_status(const CallRec &R) {
+  const unsigned long long ovf = R.hctr[kCtrOverflow];
+  if (ovf & 6) return MSC_EHIP;        // broken invariant (never expected)
+  if (ovf & 1) return MSC_ENOMEM;      // table full at the full capacity
+  return MSC_OK;
+}
+}  // namespace
+
+int take_call(msc_ctx *ctx, int nfields, int *index) {
+  const int k = ctx->next_call;
+  CallRec &R = ctx->calls[k];
+  if (R.pending) {
+    MSC_TRY(host_wait(ctx, R.done));
+    R.pending = false;
+  }
+  if (ctx->last_call == k) {
+    // Its stats are replaced by the new call's.
+    ctx->last_call = -1;
+    ctx->last_folded = true;
+  }
+  if (!R.hctr &&
+      hipHostMalloc(&R.hctr, kNumCounters * 8, hipHostMallocDefault) !=
+          hipSuccess) {
+    R.hctr = nullptr;
+    return MSC_ENOMEM;
+  }
+  const size_t want = (size_t)nfields * kFieldCtrs;
+  if (want > R.hfctr_cap) {
+    if (R.hfctr) (void)hipHostFree(R.hfctr);
+    R.hfctr = nullptr;
+    R.hfctr_cap = 0;
+    const size_t cap = want * 2 + 64;
+    if (hipHostMalloc(&R.hfctr, cap * 8, hipHostMallocDefault) != hipSuccess) {
+      R.hfctr = nullptr;
+      return MSC_ENOMEM;
+    }
+    R.hfctr_cap = cap;
+  }
+  ctx->next_call = (k + 1) % kCallRing;
+  *index = k;
+  return MSC_OK;
+}
+
+int call_field_status(const msc_ctx *ctx, int index, int i) {
+  const CallRec &R = ctx->calls[index];
+  const int all = call_status(R);
+  if (all != MSC_OK) return all;
+  return R.hfctr[(size_t)i * kFieldCtrs + kFNaN] ? MSC_ENAN : MSC_OK;
+}
+
 int finish_last(msc_ctx *ctx) {
-  LastCall &L = ctx->last;
-  if (!L.pending) return MSC_OK;
-  MSC_HIP_TRY(hipEventSynchronize(ctx->done));
-  L.pending = false;
-  const unsigned long long *fc = ctx->hfctr;
-  const unsigned long long ovf = ctx->hctr[kCtrOverflow];
-  int status = MSC_OK;
-  if (ovf & 6) status = MSC_EHIP;        // broken invariant (never expected)
-  else if (ovf & 1) status = MSC_ENOMEM;  // table full at the full capacity
+  if (ctx->last_call < 0 || ctx->last_folded) return MSC_OK;
+  CallRec &R = ctx->calls[ctx->last_call];
+  if (R.pending) {
+    MSC_HIP_TRY(hipEventSynchronize(R.done));
+    R.pending = false;
+  }
+  ctx->last_folded = true;
+  const unsigned long long *fc = R.hfctr;
+  const int status = call_status(R);
+  int last = MSC_OK;
   ctx->stats = msc_stats{};
-  ctx->field_stats.assign(L.nfields, msc_stats{});
-  for (int i = 0; i < L.nfields; ++i) {
+  ctx->field_stats.assign(R.nfields, msc_stats{});
+  for (int i = 0; i < R.nfields; ++i) {
     msc_stats &st = ctx->field_stats[i];
     const unsigned long long *f = fc + (size_t)i * kFieldCtrs;
-    st.n_vertices = L.n[i];
+    st.n_vertices = R.n[i];
     st.n_maxima = (int64_t)f[kFMaxima];
     st.n_minima = (int64_t)f[kFMinima];
-    st.n_cells = L.has_ms[i] ? (int64_t)f[kFCells] : -1;
+    st.n_cells = R.has_ms[i] ? (int64_t)f[kFCells] : -1;
     st.n_exits = (int64_t)f[kFExits];
-    st.tile_x = L.tile[0];
-    st.tile_y = L.tile[1];
-    st.tile_z = L.tile[2];
+    st.tile_x = R.tile[0];
+    st.tile_y = R.tile[1];
+    st.tile_z = R.tile[2];
     st.status = status != MSC_OK ? status : (f[kFNaN] ? MSC_ENAN : MSC_OK);
-    if (st.status != MSC_OK && L.status == MSC_OK) L.status = st.status;
+    if (st.status != MSC_OK && last == MSC_OK) last = st.status;
     ctx->stats.n_vertices += st.n_vertices;
     ctx->stats.n_maxima += st.n_maxima;
     ctx->stats.n_minima += st.n_minima;
     ctx->stats.n_cells += st.n_cells > 0 ? st.n_cells : 0;
     ctx->stats.n_exits += st.n_exits;
   }
-  if (L.nfields == 1) ctx->stats.n_cells = ctx->field_stats[0].n_cells;
-  ctx->stats.jump_rounds = (int32_t)ctx->hctr[kCtrRounds];
-  ctx->stats.exit_steps = (int64_t)ctx->hctr[kCtrSteps];
-  ctx->stats.tile_x = L.tile[0];
-  ctx->stats.tile_y = L.tile[1];
-  ctx->stats.tile_z = L.tile[2];
-  ctx->stats.status = L.status;
+  if (R.nfields == 1) ctx->stats.n_cells = ctx->field_stats[0].n_cells;
+  ctx->stats.jump_rounds = (int32_t)R.hctr[kCtrRounds];
+  ctx->stats.exit_steps = (int64_t)R.hctr[kCtrSteps];
+  ctx->stats.tile_x = R.tile[0];
+  ctx->stats.tile_y = R.tile[1];
+  ctx->stats.tile_z = R.tile[2];
+  ctx->stats.status = last;
+  ctx->last_status = last;
   return MSC_OK;
 }
 
@@ -1443,27 +1497,26 @@ int stage(msc_ctx *ctx, size_t count, T **out) {
   return MSC_OK;
 }
 
-// One segmentation call over a batch of fields.  Everything is enqueued on
-// `s`; the host never waits for the device (only a workspace growth or a
-// reused pinned slot can make it wait for earlier work).  Conditions the
-// device detects (NaN, a broken invariant) are reported by the stats calls
-// and msc_last_status once the work has run.
-template <class C>
-int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
-                  const uint8_t *ghost, hipStream_t s) {
-  MSC_TRY(finish_last(ctx));  // stats of the previous call, if any
-  MSC_TRY(begin_call(ctx, s));
-  // Geometry, tile ranges and workspace layout of every field.
-  std::vector<FieldDev> fd(nfields);
-  uint64_t total_tiles = 0, total_n = 0;
-  size_t need_lp = 0, need_scratch = 0;
-  uint64_t tab_slots = 0;
-  std::vector<uint64_t> tab_off(nfields, 0);
+// Geometry, tile ranges and workspace size of a batch.
+struct BatchPlan {
+  std::vector<FieldDev> fd;
+  std::vector<uint64_t> tab_off;  // first slot of each field's pair table
+  uint64_t total_n = 0, tab_slots = 0;
+  uint32_t nt = 0, nslots = 0;
   bool any_ms = false;
+  size_t need = 0;                // workspace bytes the call carves
+};
+
+template <class C>
+int plan_batch(int nfields, const msc_field *fields, BatchPlan &p) {
+  p.fd.assign(nfields, FieldDev{});
+  p.tab_off.assign(nfields, 0);
+  uint64_t total_tiles = 0;
+  size_t need_lp = 0, need_scratch = 0;
   for (int i = 0; i < nfields; ++i) {
     const int64_t X = fields[i].dims[0], Y = fields[i].dims[1],
                   Z = fields[i].dims[2];
-    Geo &g = fd[i].g;
+    Geo &g = p.fd[i].g;
     g.X = (uint32_t)X;
     g.Y = (uint32_t)Y;
     g.Z = (uint32_t)Z;
@@ -1474,9 +1527,9 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
     g.ntz = (uint32_t)((Z + C::TZ - 1) / C::TZ);
     const uint64_t nt = (uint64_t)g.ntx * g.nty * g.ntz;
     g.ntiles = (uint32_t)nt;
-    fd[i].tile0 = (uint32_t)total_tiles;
+    p.fd[i].tile0 = (uint32_t)total_tiles;
     total_tiles += nt;
-    total_n += g.N;
+    p.total_n += g.N;
     need_lp += align256((size_t)g.N * sizeof(uint32_t));
     if (!fields[i].asc) need_scratch += align256((size_t)g.N * sizeof(int32_t));
     if (!fields[i].desc) need_scratch += align256((size_t)g.N * sizeof(int32_t));
@@ -1484,38 +1537,57 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
     if (fields[i].ms) {
       // Room for the largest table the field can need; the device uses
       // (and clears) only what its extremum counts call for.
-      any_ms = true;
-      tab_off[i] = tab_slots;
-      tab_slots += table_capacity(g.N, g.N, g.N);
+      p.any_ms = true;
+      p.tab_off[i] = p.tab_slots;
+      p.tab_slots += table_capacity(g.N, g.N, g.N);
     }
   }
   // Exit-graph nodes: 2 * kHalo fixed slots per tile; node numbers and
   // final values share 32 bits (bit 31 tags a final value).
   if (total_tiles * 2 * (uint64_t)C::kHalo >= kRoot) return MSC_ERANGE;
   const uint32_t nt = (uint32_t)total_tiles;
-  const uint32_t nslots = nt * (uint32_t)(2 * C::kHalo);
-  unsigned long long *ctr = ctx->dctr;
-
-  const size_t need =
-      need_lp + need_scratch + align256((size_t)nslots * sizeof(uint32_t)) +
+  p.nt = nt;
+  p.nslots = nt * (uint32_t)(2 * C::kHalo);
+  p.need =
+      need_lp + need_scratch + align256((size_t)p.nslots * sizeof(uint32_t)) +
       align256(nt * sizeof(Seg)) + 3 * align256(nt * sizeof(uint32_t)) +
       align256((kTileBuckets + 2) * sizeof(uint32_t)) +
       align256(nfields * sizeof(FieldDev)) +
       align256(nfields * kFieldCtrs * sizeof(unsigned long long)) +
       align256(4ull * nt * sizeof(uint32_t)) +
       align256(4ull * nt * sizeof(unsigned long long)) +
-      align256(2ull * C::kHalo * nt * sizeof(uint16_t)) + 8192;
+      align256(2ull * C::kHalo * nt * sizeof(uint16_t)) + 8192 +
+      (p.any_ms ? align256(p.tab_slots * 8) + align256(p.tab_slots * 4) : 0);
+  return MSC_OK;
+}
+
+// One segmentation call over a batch of fields.  Everything is enqueued on
+// `s`; the host never waits for the device (only a workspace growth or a
+// record or pinned slot still in use by an earlier call can make it wait).
+// Conditions the device detects (NaN, a broken invariant) are reported by
+// the stats calls and msc_last_status once the work has run.
+template <class C>
+int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
+                  const uint8_t *ghost, hipStream_t s, int *rec_out = nullptr) {
+  BatchPlan plan;
+  MSC_TRY(plan_batch<C>(nfields, fields, plan));
+  std::vector<FieldDev> &fd = plan.fd;
+  const std::vector<uint64_t> &tab_off = plan.tab_off;
+  const uint64_t total_n = plan.total_n, tab_slots = plan.tab_slots;
+  const uint32_t nt = plan.nt, nslots = plan.nslots;
+  const bool any_ms = plan.any_ms;
+  const size_t need = plan.need;
+  unsigned long long *ctr = ctx->dctr;
+  int rec = 0;
+  MSC_TRY(take_call(ctx, nfields, &rec));
+  MSC_TRY(begin_call(ctx, s));
   MSC_TRY(reserve(ctx, ctx->ws, need));
-  if (any_ms)
-    MSC_TRY(reserve(ctx, ctx->tab,
-                    align256(tab_slots * 8) + align256(tab_slots * 4) + 4096));
   Carver cv(ctx->ws);
   unsigned long long *keys = nullptr;
   int32_t *vals = nullptr;
   if (any_ms) {
-    Carver tc(ctx->tab);
-    keys = tc.take<unsigned long long>(tab_slots);
-    vals = tc.take<int32_t>(tab_slots);
+    keys = cv.take<unsigned long long>(tab_slots);
+    vals = cv.take<int32_t>(tab_slots);
   }
   for (int i = 0; i < nfields; ++i) {
     fd[i].f = fields[i].field;
@@ -1613,35 +1685,28 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
   MSC_PHASE(ctx, s, "tile_write", (any_ms ? 8.0 : 12.0) * total_n,
             (k_tile_write<C><<<nt, C::kThreads, 0, s>>>(fds, tfield, seg,
                                                         next)));
-  // Counters back to pinned host memory, for the stats calls.
-  if ((size_t)nfields * kFieldCtrs > ctx->hfctr_cap) {
-    if (ctx->hfctr) (void)hipHostFree(ctx->hfctr);
-    ctx->hfctr = nullptr;
-    ctx->hfctr_cap = 0;
-    const size_t cap = (size_t)nfields * kFieldCtrs * 2 + 64;
-    if (hipHostMalloc(&ctx->hfctr, cap * 8, hipHostMallocDefault) != hipSuccess)
-      return MSC_ENOMEM;
-    ctx->hfctr_cap = cap;
-  }
-  MSC_HIP_TRY(hipMemcpyAsync(ctx->hfctr, fctr,
-                             (size_t)nfields * kFieldCtrs * 8,
+  // Counters back to the record's pinned memory, for the stats calls.
+  CallRec &R = ctx->calls[rec];
+  MSC_HIP_TRY(hipMemcpyAsync(R.hfctr, fctr, (size_t)nfields * kFieldCtrs * 8,
                              hipMemcpyDeviceToHost, s));
-  MSC_HIP_TRY(hipMemcpyAsync(ctx->hctr, ctr, kNumCounters * 8,
+  MSC_HIP_TRY(hipMemcpyAsync(R.hctr, ctr, kNumCounters * 8,
                              hipMemcpyDeviceToHost, s));
+  MSC_HIP_TRY(hipEventRecord(R.done, s));
   MSC_TRY(end_call(ctx, s));
-  LastCall &L = ctx->last;
-  L.pending = true;
-  L.nfields = nfields;
-  L.status = MSC_OK;
-  L.n.resize(nfields);
-  L.has_ms.resize(nfields);
+  R.pending = true;
+  R.nfields = nfields;
+  R.n.resize(nfields);
+  R.has_ms.resize(nfields);
   for (int i = 0; i < nfields; ++i) {
-    L.n[i] = fd[i].g.N;
-    L.has_ms[i] = fields[i].ms != nullptr;
+    R.n[i] = fd[i].g.N;
+    R.has_ms[i] = fields[i].ms != nullptr;
   }
-  L.tile[0] = C::TX;
-  L.tile[1] = C::TY;
-  L.tile[2] = C::TZ;
+  R.tile[0] = C::TX;
+  R.tile[1] = C::TY;
+  R.tile[2] = C::TZ;
+  ctx->last_call = rec;
+  ctx->last_folded = false;
+  if (rec_out) *rec_out = rec;
   return MSC_OK;
 }
 
@@ -1654,19 +1719,34 @@ using Tile64x8x16 = Cfg<64, 8, 16>;
 
 }  // namespace
 
+int segment_workspace(const msc_ctx *ctx, int nfields, const msc_field *fields,
+                      size_t *bytes) {
+  BatchPlan p;
+  int rc = MSC_OK;
+  switch (ctx->tile_choice) {
+    case 1: rc = plan_batch<Tile32x8x8>(nfields, fields, p); break;
+    case 2: rc = plan_batch<Tile64x8x8>(nfields, fields, p); break;
+    case 3: rc = plan_batch<Tile32x8x16>(nfields, fields, p); break;
+    case 4: rc = plan_batch<Tile64x8x16>(nfields, fields, p); break;
+    default: rc = plan_batch<Tile32x16x16>(nfields, fields, p); break;
+  }
+  *bytes = p.need;
+  return rc;
+}
+
 int segment_batch_run(msc_ctx *ctx, int nfields, const msc_field *fields,
-                      hipStream_t s, const uint8_t *ghost) {
+                      hipStream_t s, const uint8_t *ghost, int *rec) {
   switch (ctx->tile_choice) {
     case 1:
-      return segment_batch<Tile32x8x8>(ctx, nfields, fields, ghost, s);
+      return segment_batch<Tile32x8x8>(ctx, nfields, fields, ghost, s, rec);
     case 2:
-      return segment_batch<Tile64x8x8>(ctx, nfields, fields, ghost, s);
+      return segment_batch<Tile64x8x8>(ctx, nfields, fields, ghost, s, rec);
     case 3:
-      return segment_batch<Tile32x8x16>(ctx, nfields, fields, ghost, s);
+      return segment_batch<Tile32x8x16>(ctx, nfields, fields, ghost, s, rec);
     case 4:
-      return segment_batch<Tile64x8x16>(ctx, nfields, fields, ghost, s);
+      return segment_batch<Tile64x8x16>(ctx, nfields, fields, ghost, s, rec);
     default:
-      return segment_batch<Tile32x16x16>(ctx, nfields, fields, ghost, s);
+      return segment_batch<Tile32x16x16>(ctx, nfields, fields, ghost, s, rec);
   }
 }
 
@@ -2088,7 +2168,7 @@ int segment_ranks(msc_ctx *ctx, const float *field, const int64_t dims[3],
   MSC_TRY(segment_batch<C>(ctx, (int)R, fields.data(), ghost.data(), s));
   // This path reads counts back anyway: take the slabs' outcome now.
   MSC_TRY(finish_last(ctx));
-  if (ctx->last.status != MSC_OK) return ctx->last.status;
+  if (ctx->last_status != MSC_OK) return ctx->last_status;
 
   char *st = nullptr;
   MSC_TRY(stage(ctx, R * sizeof(SlabDev), &st));

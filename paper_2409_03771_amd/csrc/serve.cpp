@@ -1,22 +1,27 @@
 // Request queue with continuous batching (host runtime of libmsc.so).
 //
-// A queue owns an HBM arena of `budget` bytes for request-resident buffers
-// (inputs and outputs) and two library contexts, one per kind of work, each
-// with its own stream.  Three host threads drive it:
+// A queue takes `budget` bytes of device memory in one block and splits it:
+// a workspace for each kind of work (the scratch of the library context that
+// runs that kind, attached as a caller-owned workspace so that it is never
+// reallocated while serving) and an arena for request-resident buffers
+// (inputs and outputs).  Each kind has its own context and stream.  Five
+// host threads drive it:
 //
-//   dispatcher   admits pending requests in arrival order while their
-//                footprint (resident buffers plus the workspace their launch
-//                needs) fits the budget, places their buffers in the arena and
-//                copies their inputs to the device, round-robin over a few
-//                copy streams so that several DMA engines share the link;
-//   seg worker   takes every admitted segmentation request whose launch slot
-//                is free -- requests that arrived while the previous launch
-//                ran join the next one -- and segments them in one batched
-//                call after waiting for their input copies;
-//   cc worker    the same for mask connected components, one request at a
-//                time on its own stream, overlapping with segmentation.
+//   dispatcher   admits pending requests in arrival order (within a kind)
+//                while the arena holds their buffers and their kind has room
+//                in its staging window, and copies their inputs to the
+//                device, round-robin over a few copy streams so that several
+//                DMA engines share the link;
+//   two workers  one per kind: take every staged request of the kind, up to
+//                the launch limits -- requests that arrived while earlier
+//                launches ran join the next one -- and enqueue one batched
+//                call after their input copies, without waiting for the
+//                device; at most two launches per kind are in flight;
+//   two completers  one per kind: wait for each launch's completion event
+//                and finish its requests (each with its own outcome).
 //
 // Results stay on the device until the client releases the request.
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -106,49 +111,79 @@ size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
 
 }  // namespace
 
+struct Launch {
+  std::vector<Request *> reqs;
+  hipEvent_t done = nullptr;
+  int rec = -1;       // call record of a segmentation launch
+  int rc = MSC_OK;    // outcome of enqueuing it
+};
+
 struct msc_queue {
   int device = 0;
   size_t budget = 0;
   int max_batch = 1;
-  char *arena = nullptr;
+  char *mem = nullptr;           // the whole budget
+  char *arena = nullptr;         // request-resident part of it
+  size_t arena_size = 0;
+  size_t ws_size[2] = {0, 0};    // workspace of each kind (seg, cc)
   Arena alloc;
-  size_t inflight_ws = 0;
-  msc_ctx *ctx_seg = nullptr, *ctx_cc = nullptr;
+  msc_ctx *ctx[2] = {nullptr, nullptr};
   static constexpr int kCopyStreams = 4;  // copies spread over DMA engines
-  hipStream_t s_copy[kCopyStreams] = {}, s_seg = nullptr, s_cc = nullptr;
+  hipStream_t s_copy[kCopyStreams] = {}, s_run[2] = {nullptr, nullptr};
   int next_copy = 0;
   std::mutex mu;
   std::condition_variable cv;
-  std::deque<Request *> pending, ready_seg, ready_cc;
+  std::deque<Request *> pending, ready[2];
+  std::deque<Launch *> inflight[2];
+  std::vector<Launch *> spare[2];  // finished launches, their events reused
   std::map<uint64_t, Request *> all;
   uint64_t next_ticket = 1;
-  bool stop = false;
-  std::thread dispatcher, worker_seg, worker_cc;
+  int64_t launches = 0;
+  bool stop = false;   // dispatcher and workers end
+  bool drain = false;  // completers end once nothing is in flight
+  std::thread dispatcher, worker[2], completer[2];
 };
 
 namespace {
 
-// Estimated device bytes a launch of this request needs beyond its resident
-// buffers: a segmentation's local pointers (4 B/vertex) and exit lists
-// (12 B per exit, at most about a third of the vertices on small tiles); a
-// CC's 16-bit tile labels.
-// A segmentation launch takes at most this many vertices (and at least one
-// request): a batch's requests all complete when the launch does, so an
-// unbounded batch would make its first requests wait for the last ones;
-// 64M vertices keep a launch around a millisecond, long enough to fill the
-// device.
+int kind_index(int kind) { return kind == MSC_REQ_SEGMENT ? 0 : 1; }
+
+// A launch takes at most this many vertices (and at least one request): a
+// launch's requests all complete when it does, so an unbounded batch would
+// make its first requests wait for the last ones; 64M vertices keep a
+// launch around a millisecond, long enough to fill the device.
 constexpr int64_t kMaxBatchVertices = 64ll << 20;
 
-// At most this many requests are staged (copy issued) and not yet taken by
-// a worker. Copies issued far ahead of the workers share the link with the
-// ones a worker waits for, so under overload every request's copy finishes
-// late; a short window keeps the link on the requests next in line and
-// still keeps it busy while a launch runs.
+// At most this many requests of a kind are staged (copy issued) and not yet
+// taken by its worker.  Copies issued far ahead of the workers share the
+// link with the ones a worker waits for, so under overload every request's
+// copy finishes late; a short window keeps the link on the requests next in
+// line and still keeps it busy while a launch runs.
 constexpr size_t kMaxStaged = 8;
 
-size_t workspace_bytes(int kind, int64_t n) {
-  if (kind == MSC_REQ_SEGMENT) return (size_t)n * 8 + (1 << 20);
-  return (size_t)n * 2 + (1 << 20);
+// Launches of one kind enqueued and not yet completed.  Two keep the device
+// fed while the host prepares the next one; the call records of a context
+// (four) outlast them.
+constexpr size_t kMaxInflight = 2;
+
+// Share of the budget given to each kind's workspace, and its cap.
+constexpr size_t kSegWsDiv = 4, kCcWsDiv = 16;
+constexpr size_t kSegWsCap = 8ull << 30, kCcWsCap = 1ull << 30;
+
+// Workspace one request adds to a launch of its kind (an upper bound: the
+// launch's own need is at most the sum over its requests).
+int request_workspace(const msc_queue *q, const Request *r, size_t *bytes) {
+  if (r->kind == MSC_REQ_SEGMENT) {
+    static float dummy_f;
+    static int32_t dummy_i;
+    msc_field f{&dummy_f, {r->dims[0], r->dims[1], r->dims[2]}, &dummy_i,
+                &dummy_i, &dummy_i};
+    return msc_workspace_size(q->ctx[0], MSC_REQ_SEGMENT, 1, &f, bytes);
+  }
+  static uint8_t dummy_m;
+  static int64_t dummy_l;
+  msc_mask m{&dummy_m, {r->dims[0], r->dims[1], r->dims[2]}, &dummy_l};
+  return msc_workspace_size(q->ctx[1], MSC_REQ_CC_GRID, 1, &m, bytes);
 }
 
 void dispatcher_loop(msc_queue *q) {
@@ -156,20 +191,22 @@ void dispatcher_loop(msc_queue *q) {
   std::unique_lock<std::mutex> lk(q->mu);
   while (!q->stop) {
     bool progress = false;
-    while (!q->pending.empty()) {
-      if (q->ready_seg.size() + q->ready_cc.size() >= kMaxStaged) break;
-      Request *r = q->pending.front();
+    for (;;) {
+      // The oldest pending request whose kind has room in its window; a
+      // request of a kind whose window is full does not hold up the other.
+      auto it = q->pending.begin();
+      while (it != q->pending.end() &&
+             q->ready[kind_index((*it)->kind)].size() >= kMaxStaged)
+        ++it;
+      if (it == q->pending.end()) break;
+      Request *r = *it;
       const size_t need = r->in_bytes + r->out_bytes;
-      if (q->alloc.used() + round256(need) + q->inflight_ws + r->ws_bytes >
-          q->budget)
-        break;  // the head waits: arrival order is kept
       size_t off = 0;
-      if (!q->alloc.alloc(need, &off)) break;
-      q->pending.pop_front();
+      if (!q->alloc.alloc(need, &off)) break;  // it waits: order is kept
+      q->pending.erase(it);
       r->state = kCopying;  // msc_cancel refuses it from here on
       r->off = off;
       r->dev = q->arena + off;
-      q->inflight_ws += r->ws_bytes;
       hipStream_t cs = q->s_copy[q->next_copy];
       q->next_copy = (q->next_copy + 1) % msc_queue::kCopyStreams;
       lk.unlock();
@@ -184,10 +221,9 @@ void dispatcher_loop(msc_queue *q) {
         r->rc = rc;
         r->state = kDone;
         r->t_done = now_ns();
-        q->inflight_ws -= r->ws_bytes;
       } else {
         r->state = kStaged;
-        (r->kind == MSC_REQ_SEGMENT ? q->ready_seg : q->ready_cc).push_back(r);
+        q->ready[kind_index(r->kind)].push_back(r);
       }
       progress = true;
       q->cv.notify_all();
@@ -207,79 +243,123 @@ msc_field seg_field(const Request *r) {
   return f;
 }
 
-void finish(msc_queue *q, std::vector<Request *> &batch,
-            const std::vector<int> &rc) {
-  const int64_t t = now_ns();
-  std::lock_guard<std::mutex> lk(q->mu);
-  for (size_t i = 0; i < batch.size(); ++i) {
-    batch[i]->rc = rc[i];
-    batch[i]->t_done = t;
-    batch[i]->state = kDone;
-    q->inflight_ws -= batch[i]->ws_bytes;
-  }
-  q->cv.notify_all();
+msc_mask cc_mask(const Request *r) {
+  msc_mask m{};
+  m.mask = reinterpret_cast<const uint8_t *>(r->dev);
+  for (int k = 0; k < 3; ++k) m.dims[k] = r->dims[k];
+  m.labels = reinterpret_cast<int64_t *>(r->dev + round256(r->in_bytes));
+  return m;
 }
 
-void worker_loop(msc_queue *q, int kind) {
+// Enqueue one launch on the kind's stream; never waits for the device.
+int issue(msc_queue *q, int k, Launch *L) {
+  hipStream_t s = q->s_run[k];
+  msc_ctx *ctx = q->ctx[k];
+  for (Request *r : L->reqs)
+    if (hipStreamWaitEvent(s, r->copied, 0) != hipSuccess) return MSC_EHIP;
+  if (k == 0) {
+    std::vector<msc_field> fields;
+    fields.reserve(L->reqs.size());
+    for (Request *r : L->reqs) fields.push_back(seg_field(r));
+    MSC_TRY(msc::segment_batch_run(ctx, (int)fields.size(), fields.data(), s,
+                                   nullptr, &L->rec));
+  } else {
+    std::vector<msc_mask> masks;
+    masks.reserve(L->reqs.size());
+    for (Request *r : L->reqs) masks.push_back(cc_mask(r));
+    msc::stats_replaced(ctx);
+    MSC_TRY(msc::begin_call(ctx, s));
+    MSC_TRY(msc::cc_grid_batch_run(ctx, (int)masks.size(), masks.data(), s));
+    MSC_TRY(msc::end_call(ctx, s));
+  }
+  if (hipEventRecord(L->done, s) != hipSuccess) return MSC_EHIP;
+  return MSC_OK;
+}
+
+void worker_loop(msc_queue *q, int k) {
   (void)hipSetDevice(q->device);
-  std::deque<Request *> &ready = kind == MSC_REQ_SEGMENT ? q->ready_seg
-                                                          : q->ready_cc;
-  hipStream_t s = kind == MSC_REQ_SEGMENT ? q->s_seg : q->s_cc;
-  msc_ctx *ctx = kind == MSC_REQ_SEGMENT ? q->ctx_seg : q->ctx_cc;
-  const int cap = kind == MSC_REQ_SEGMENT ? q->max_batch : 1;
+  std::deque<Request *> &ready = q->ready[k];
   std::unique_lock<std::mutex> lk(q->mu);
   while (!q->stop) {
-    if (ready.empty()) {
+    if (ready.empty() || q->inflight[k].size() >= kMaxInflight) {
       q->cv.wait(lk);
       continue;
     }
-    std::vector<Request *> batch;
+    Launch *L = nullptr;
+    if (!q->spare[k].empty()) {
+      L = q->spare[k].back();
+      q->spare[k].pop_back();
+    } else {
+      L = new (std::nothrow) Launch();
+      if (L && hipEventCreateWithFlags(&L->done, hipEventDisableTiming) !=
+                   hipSuccess) {
+        delete L;
+        L = nullptr;
+      }
+      if (!L) {  // retried once a launch finishes and frees its record
+        q->cv.wait(lk);
+        continue;
+      }
+    }
+    L->reqs.clear();
+    L->rec = -1;
     const int64_t t = now_ns();
     int64_t verts = 0;
-    while (!ready.empty() && (int)batch.size() < cap &&
-           (batch.empty() || verts + ready.front()->n <= kMaxBatchVertices)) {
+    size_t ws = 0;
+    while (!ready.empty() && (int)L->reqs.size() < q->max_batch) {
       Request *r = ready.front();
+      if (!L->reqs.empty() && (verts + r->n > kMaxBatchVertices ||
+                               ws + r->ws_bytes > q->ws_size[k]))
+        break;
       verts += r->n;
+      ws += r->ws_bytes;
       ready.pop_front();
       r->state = kRunning;
       r->t_start = t;
-      batch.push_back(r);
+      L->reqs.push_back(r);
     }
-    for (Request *r : batch) r->batch = (int)batch.size();
+    for (Request *r : L->reqs) r->batch = (int)L->reqs.size();
     q->cv.notify_all();  // the staging window has room again
     lk.unlock();
-    std::vector<int> rc(batch.size(), MSC_OK);
-    for (Request *r : batch)
-      if (hipStreamWaitEvent(s, r->copied, 0) != hipSuccess)
-        for (int &x : rc) x = MSC_EHIP;
-    if (kind == MSC_REQ_SEGMENT) {
-      std::vector<msc_field> fields;
-      for (Request *r : batch) fields.push_back(seg_field(r));
-      int all = rc[0] == MSC_OK
-                    ? msc_segment_batched(ctx, (int)fields.size(),
-                                          fields.data(), s)
-                    : rc[0];
-      if (all == MSC_OK && hipStreamSynchronize(s) != hipSuccess)
-        all = MSC_EHIP;
-      for (size_t i = 0; i < batch.size(); ++i) {
-        // Each field's own outcome: a NaN in one request fails it alone.
-        msc_stats st{};
-        rc[i] = all;
-        if (all == MSC_OK)
-          rc[i] = msc_last_field_stats(ctx, (int)i, &st) == MSC_OK ? st.status
-                                                                  : MSC_EHIP;
-      }
-    } else {
-      Request *r = batch[0];
-      if (rc[0] == MSC_OK)
-        rc[0] = cc_label_grid(
-            ctx, reinterpret_cast<const uint8_t *>(r->dev), r->dims,
-            reinterpret_cast<int64_t *>(r->dev + round256(r->in_bytes)), s);
-      if (rc[0] == MSC_OK && hipStreamSynchronize(s) != hipSuccess)
-        rc[0] = MSC_EHIP;
-    }
-    finish(q, batch, rc);
+    L->rc = issue(q, k, L);
     lk.lock();
+    q->inflight[k].push_back(L);
+    ++q->launches;
+    q->cv.notify_all();
+  }
+}
+
+void completer_loop(msc_queue *q, int k) {
+  (void)hipSetDevice(q->device);
+  std::unique_lock<std::mutex> lk(q->mu);
+  for (;;) {
+    if (q->inflight[k].empty()) {
+      if (q->drain) break;  // set once the worker has ended
+      q->cv.wait(lk);
+      continue;
+    }
+    Launch *L = q->inflight[k].front();
+    lk.unlock();
+    std::vector<int> rc(L->reqs.size(), L->rc);
+    if (L->rc == MSC_OK) {
+      const bool ok = hipEventSynchronize(L->done) == hipSuccess;
+      for (size_t i = 0; i < L->reqs.size(); ++i)
+        rc[i] = !ok ? MSC_EHIP
+                : k == 0 ? msc::call_field_status(q->ctx[0], L->rec, (int)i)
+                         : MSC_OK;
+    }
+    const int64_t t = now_ns();
+    lk.lock();
+    for (size_t i = 0; i < L->reqs.size(); ++i) {
+      Request *r = L->reqs[i];
+      r->rc = rc[i];
+      r->t_done = t;
+      r->state = kDone;
+    }
+    L->reqs.clear();
+    q->inflight[k].pop_front();
+    q->spare[k].push_back(L);
+    q->cv.notify_all();
   }
 }
 
@@ -301,8 +381,11 @@ int msc_queue_create(int device, size_t hbm_budget, int max_batch,
   q->device = device;
   q->budget = hbm_budget;
   q->max_batch = max_batch;
-  int rc = msc_create(&q->ctx_seg, device);
-  if (rc == MSC_OK) rc = msc_create(&q->ctx_cc, device);
+  q->ws_size[0] = std::min(hbm_budget / kSegWsDiv, kSegWsCap) & ~size_t(255);
+  q->ws_size[1] = std::min(hbm_budget / kCcWsDiv, kCcWsCap) & ~size_t(255);
+  q->arena_size = hbm_budget - q->ws_size[0] - q->ws_size[1];
+  int rc = msc_create(&q->ctx[0], device);
+  if (rc == MSC_OK) rc = msc_create(&q->ctx[1], device);
   if (rc == MSC_OK) {
     int prev = -1;
     (void)hipGetDevice(&prev);
@@ -310,24 +393,31 @@ int msc_queue_create(int device, size_t hbm_budget, int max_batch,
     for (int k = 0; ok && k < msc_queue::kCopyStreams; ++k)
       ok = hipStreamCreateWithFlags(&q->s_copy[k], hipStreamNonBlocking) ==
            hipSuccess;
-    ok = ok &&
-         hipStreamCreateWithFlags(&q->s_seg, hipStreamNonBlocking) ==
-             hipSuccess &&
-         hipStreamCreateWithFlags(&q->s_cc, hipStreamNonBlocking) == hipSuccess;
+    for (int k = 0; ok && k < 2; ++k)
+      ok = hipStreamCreateWithFlags(&q->s_run[k], hipStreamNonBlocking) ==
+           hipSuccess;
     if (!ok)
       rc = MSC_EHIP;
-    else if (hipMalloc(&q->arena, hbm_budget) != hipSuccess)
+    else if (hipMalloc(&q->mem, hbm_budget) != hipSuccess)
       rc = MSC_ENOMEM;
     if (prev >= 0) (void)hipSetDevice(prev);
   }
+  // The workspaces lead the block; each context carves every launch's
+  // scratch from its own and never allocates while serving.
+  if (rc == MSC_OK) rc = msc_set_workspace(q->ctx[0], q->mem, q->ws_size[0]);
+  if (rc == MSC_OK)
+    rc = msc_set_workspace(q->ctx[1], q->mem + q->ws_size[0], q->ws_size[1]);
   if (rc != MSC_OK) {
     msc_queue_destroy(q);
     return rc;
   }
-  q->alloc.reset(hbm_budget);
+  q->arena = q->mem + q->ws_size[0] + q->ws_size[1];
+  q->alloc.reset(q->arena_size);
   q->dispatcher = std::thread(dispatcher_loop, q);
-  q->worker_seg = std::thread(worker_loop, q, MSC_REQ_SEGMENT);
-  q->worker_cc = std::thread(worker_loop, q, MSC_REQ_CC_GRID);
+  for (int k = 0; k < 2; ++k) {
+    q->worker[k] = std::thread(worker_loop, q, k);
+    q->completer[k] = std::thread(completer_loop, q, k);
+  }
   *out = q;
   return MSC_OK;
 }
@@ -340,8 +430,15 @@ void msc_queue_destroy(msc_queue *q) {
   }
   q->cv.notify_all();
   if (q->dispatcher.joinable()) q->dispatcher.join();
-  if (q->worker_seg.joinable()) q->worker_seg.join();
-  if (q->worker_cc.joinable()) q->worker_cc.join();
+  for (int k = 0; k < 2; ++k)
+    if (q->worker[k].joinable()) q->worker[k].join();
+  {
+    std::lock_guard<std::mutex> lk(q->mu);
+    q->drain = true;
+  }
+  q->cv.notify_all();
+  for (int k = 0; k < 2; ++k)
+    if (q->completer[k].joinable()) q->completer[k].join();
   int prev = -1;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(q->device);
@@ -350,14 +447,21 @@ void msc_queue_destroy(msc_queue *q) {
     if (kv.second->copied) (void)hipEventDestroy(kv.second->copied);
     delete kv.second;
   }
-  if (q->arena) (void)hipFree(q->arena);
+  for (int k = 0; k < 2; ++k)
+    for (Launch *L : q->spare[k]) {
+      if (L->done) (void)hipEventDestroy(L->done);
+      delete L;
+    }
+  // The contexts go first: their workspaces live in the block.
+  msc_destroy(q->ctx[0]);
+  msc_destroy(q->ctx[1]);
+  (void)hipSetDevice(q->device);
+  if (q->mem) (void)hipFree(q->mem);
   for (hipStream_t cs : q->s_copy)
     if (cs) (void)hipStreamDestroy(cs);
-  if (q->s_seg) (void)hipStreamDestroy(q->s_seg);
-  if (q->s_cc) (void)hipStreamDestroy(q->s_cc);
+  for (hipStream_t rs : q->s_run)
+    if (rs) (void)hipStreamDestroy(rs);
   if (prev >= 0) (void)hipSetDevice(prev);
-  msc_destroy(q->ctx_seg);
-  msc_destroy(q->ctx_cc);
   delete q;
 }
 
@@ -384,8 +488,13 @@ int msc_submit(msc_queue *q, const msc_request *req, uint64_t *ticket) {
     r->out_bytes = (size_t)n * 8;
   }
   r->out_bytes += 256;  // outputs start on a 256-byte boundary
-  r->ws_bytes = workspace_bytes(r->kind, n);
-  if (round256(r->in_bytes + r->out_bytes) + r->ws_bytes > q->budget) {
+  const int wrc = request_workspace(q, r, &r->ws_bytes);
+  if (wrc != MSC_OK) {
+    delete r;
+    return wrc;
+  }
+  if (round256(r->in_bytes + r->out_bytes) > q->arena_size ||
+      r->ws_bytes > q->ws_size[kind_index(r->kind)]) {
     delete r;
     return MSC_EBUDGET;
   }
@@ -527,7 +636,13 @@ int msc_queue_info(msc_queue *q, msc_queue_stats *out) {
   *out = msc_queue_stats{};
   out->budget = q->budget;
   out->arena_used = q->alloc.used();
-  out->workspace_reserved = q->inflight_ws;
+  out->workspace_reserved = q->ws_size[0] + q->ws_size[1];
+  out->arena_size = q->arena_size;
+  out->launches = q->launches;
+  for (msc_ctx *c : q->ctx) {
+    out->workspace_grows += c->grows.load(std::memory_order_relaxed);
+    out->host_waits += c->host_waits.load(std::memory_order_relaxed);
+  }
   for (auto &kv : q->all) {
     switch (kv.second->state) {
       case kPending: ++out->pending; break;

@@ -51,6 +51,10 @@ class msc_field(ctypes.Structure):
                 ("ms", _P)]
 
 
+class msc_mask(ctypes.Structure):
+    _fields_ = [("mask", _P), ("dims", _I64 * 3), ("labels", _P)]
+
+
 class msc_tune(ctypes.Structure):
     _fields_ = [("best", _I32), ("tile", _I32 * 3), ("n_shapes", _I32),
                 ("ms", ctypes.c_float * 8)]
@@ -86,6 +90,10 @@ _SIGS = {
                             _I32),
     "cc_label_csr": ([_P, _I64, _P, _P, _P, _P, _P], _I32),
     "cc_label_grid_noalloc": ([_P, ctypes.POINTER(_I64), _P, _P], _I32),
+    "cc_label_grid_batched": ([_P, _I32, ctypes.POINTER(msc_mask), _P], _I32),
+    "msc_set_workspace": ([_P, _P, ctypes.c_size_t], _I32),
+    "msc_workspace_size": ([_P, _I32, _I32, _P, ctypes.POINTER(ctypes.c_size_t)],
+                           _I32),
     "msc_pointer_jump": ([_P, _P, _I64, _I32, _I32, _P], _I32),
 }
 for _name, (_args, _res) in _SIGS.items():
@@ -466,6 +474,71 @@ def cc_label_grid(mask: torch.Tensor, stream=None) -> torch.Tensor:
     return labels
 
 
+def cc_label_grid_batched_into(masks, labels, dims=None, stream=None):
+    """Label several uint8 masks (any shapes) in shared launches; `labels`
+    holds one int64 tensor per mask."""
+    if not masks:
+        return
+    dims = dims or [grid_dims(m.shape) for m in masks]
+    if len(labels) != len(masks):
+        raise ValueError("one label tensor per mask")
+    arr = (msc_mask * len(masks))()
+    for i, (m, lab, d) in enumerate(zip(masks, labels, dims)):
+        if lab.numel() < m.numel():
+            raise ValueError(f"labels {i} shorter than its mask")
+        arr[i].mask = _dev_ptr(m, torch.uint8, "mask")
+        for k in range(3):
+            arr[i].dims[k] = int(d[k])
+        arr[i].labels = _dev_ptr(lab, torch.int64, "labels")
+    code = _lib.cc_label_grid_batched(context(masks[0].device.index),
+                                      len(masks), arr,
+                                      _stream(masks[0], stream))
+    _check(code, "cc_label_grid_batched")
+
+
+def cc_label_grid_batched(masks, stream=None):
+    """Batched cc_label_grid; one flat int64 label tensor per mask."""
+    labels = [torch.empty(m.numel(), dtype=torch.int64, device=m.device)
+              for m in masks]
+    cc_label_grid_batched_into(masks, labels, stream=stream)
+    return labels
+
+
+def workspace_size(kind: int, dims_list, device: int | None = None) -> int:
+    """Scratch bytes one call needs: kind REQ_SEGMENT (asc, desc and ms
+    wanted) or REQ_CC_GRID, over fields / masks of the given dims."""
+    n = len(dims_list)
+    if kind == REQ_SEGMENT:
+        arr = (msc_field * n)()
+        for i, d in enumerate(dims_list):
+            for k in range(3):
+                arr[i].dims[k] = int(d[k])
+            arr[i].field = arr[i].asc = arr[i].desc = arr[i].ms = 1
+    else:
+        arr = (msc_mask * n)()
+        for i, d in enumerate(dims_list):
+            for k in range(3):
+                arr[i].dims[k] = int(d[k])
+            arr[i].mask = arr[i].labels = 1
+    out = ctypes.c_size_t(0)
+    _check(_lib.msc_workspace_size(context(device), int(kind), n,
+                                   ctypes.cast(arr, _P), ctypes.byref(out)),
+           "msc_workspace_size")
+    return out.value
+
+
+def set_workspace(buf, device: int | None = None):
+    """Make the device's context carve its scratch from `buf` (a uint8 CUDA
+    tensor kept alive by the caller, 256-byte aligned), or from memory the
+    library owns again when `buf` is None."""
+    if buf is None:
+        code = _lib.msc_set_workspace(context(device), None, 0)
+    else:
+        code = _lib.msc_set_workspace(context(buf.device.index),
+                                      buf.data_ptr(), buf.numel())
+    _check(code, "msc_set_workspace")
+
+
 def cc_label_grid_noalloc_into(mask, labels, dims=None, stream=None):
     """cc_label_grid into a caller tensor through the entry point that
     allocates nothing (current device; at most 2^27 vertices)."""
@@ -546,7 +619,9 @@ class msc_result(ctypes.Structure):
 class msc_queue_stats(ctypes.Structure):
     _fields_ = [("budget", ctypes.c_size_t), ("arena_used", ctypes.c_size_t),
                 ("workspace_reserved", ctypes.c_size_t), ("pending", _I64),
-                ("running", _I64), ("finished", _I64)]
+                ("running", _I64), ("finished", _I64),
+                ("arena_size", ctypes.c_size_t), ("launches", _I64),
+                ("workspace_grows", _I64), ("host_waits", _I64)]
 
 
 _U64 = ctypes.c_uint64

@@ -179,3 +179,50 @@ def test_pointer_jump_random_forest(msc):
         d = torch.from_numpy(parent).cuda()
         msc.pointer_jump(d, synchronous=sync)
         np.testing.assert_array_equal(d.cpu().numpy(), want)
+
+
+def test_batched_masks_equal_oracle(msc):
+    """70 masks of uneven shapes (more than one launch's worth, with edge
+    shapes and empty and full masks) in one batched call: every mask's
+    labels equal the oracle's, ids local to the mask."""
+    rng = np.random.default_rng(31)
+    masks = []
+    shapes = [(1, 1, 1), (33, 17, 17), (64, 1, 1), (1, 40, 3), (32, 16, 16)]
+    for k in range(70):
+        dims = shapes[k] if k < len(shapes) else tuple(
+            int(x) for x in rng.integers(1, 70, size=3))
+        X, Y, Z = dims
+        if k == 5:
+            m = np.zeros((Z, Y, X), np.uint8)
+        elif k == 6:
+            m = np.ones((Z, Y, X), np.uint8)
+        elif k % 3 == 0:
+            f = synth.gaussian_field(dims, 6, 300 + k)
+            m = synth.threshold_mask(f, 0.6)
+        else:
+            m = (rng.uniform(size=(Z, Y, X)) < rng.uniform(0.1, 0.9)).astype(
+                np.uint8)
+        masks.append(m)
+    dev = [torch.from_numpy(m).cuda() for m in masks]
+    labels = [torch.full((m.size,), -7, dtype=torch.int64, device="cuda")
+              for m in masks]
+    msc.cc_label_grid_batched_into(dev, labels)
+    torch.cuda.synchronize()
+    for k, (m, lab) in enumerate(zip(masks, labels)):
+        want, _ = O.cc_grid(m)
+        np.testing.assert_array_equal(lab.cpu().numpy(), want,
+                                      err_msg=f"mask {k} {m.shape}")
+
+
+def test_batched_masks_edge_cases(msc):
+    assert msc.cc_label_grid_batched([]) == []
+    m = torch.ones((5, 4, 3), dtype=torch.uint8, device="cuda")
+    with pytest.raises(TypeError):
+        msc.cc_label_grid_batched_into([m], [torch.empty(60, dtype=torch.int32,
+                                                         device="cuda")])
+    with pytest.raises(ValueError):
+        msc.cc_label_grid_batched_into([m], [torch.empty(59, dtype=torch.int64,
+                                                         device="cuda")])
+    (lab,) = msc.cc_label_grid_batched([m])
+    torch.cuda.synchronize()
+    assert (lab == 0).all()

@@ -107,7 +107,7 @@ def _serve_and_check(msc, reqs, inputs, tag):
                     got, want, err_msg=f"{tag} request {i} cc")
             srv.release(t)
         info = srv.info()
-    assert info["arena_used"] == 0 and info["workspace_reserved"] == 0
+    assert info["arena_used"] == 0 and info["workspace_grows"] == 0
     return batches
 
 

@@ -57,8 +57,12 @@ def test_mix_matches_oracle_alone_and_plain(msc):
             _check(k, a, srv.fetch(t), f"ticket {t} {a.shape}")
             srv.release(t)
         info = srv.info()
-        assert info["arena_used"] == 0 and info["workspace_reserved"] == 0
+        assert info["arena_used"] == 0
         assert info["pending"] == info["running"] == info["finished"] == 0
+        # The workspaces were fixed at creation and never reallocated.
+        assert info["workspace_grows"] == 0
+        assert info["arena_size"] + info["workspace_reserved"] == 1 << 30
+        assert 1 <= info["launches"] < len(reqs)
     # Requests submitted together were packed into shared launches.
     assert max(batches) > 1
     # The same requests alone, each in a fresh queue, and as plain calls.
@@ -80,38 +84,46 @@ def test_mix_matches_oracle_alone_and_plain(msc):
             srv.release(t)
 
 
+def _resident(kind, n):
+    """Arena bytes a request holds: input, outputs, alignment."""
+    b = (4 * n if kind == 1 else n) + (12 * n if kind == 1 else 8 * n) + 256
+    return (b + 255) // 256 * 256
+
+
 def test_budget_backpressure(msc):
-    """A budget that holds about three requests: later ones wait for
+    """A budget whose arena holds a handful of requests: later ones wait for
     releases, arrival order is kept and every result is still exact."""
     dims = (40, 36, 32)
     n = dims[0] * dims[1] * dims[2]
-    per = 16 * n + 256 + 8 * n + (1 << 20)      # resident + workspace estimate
-    budget = 3 * per + per // 2
-    fields = [synth.gaussian_field(dims, 6, 100 + i) for i in range(10)]
+    # The segmentation workspace (a quarter of the budget) holds one launch
+    # of one request; the arena then holds about seven results.
+    budget = 4 * msc.workspace_size(msc.REQ_SEGMENT, [dims]) + (64 << 10)
+    fields = [synth.gaussian_field(dims, 6, 100 + i) for i in range(20)]
     with msc.Server(hbm_budget=budget, max_batch=8) as srv:
+        arena = srv.info()["arena_size"]
+        assert 3 * _resident(1, n) < arena < len(fields) * _resident(1, n)
         tickets = [srv.submit(1, f) for f in fields]
         starts = []
         for t, f in zip(tickets, fields):
-            info = srv.info()
-            assert info["arena_used"] + info["workspace_reserved"] <= budget
+            assert srv.info()["arena_used"] <= arena
             assert srv.wait(t) == msc.MSC_OK
             starts.append(srv.result(t)["t_start_ns"])
             _check(1, f, srv.fetch(t), f"ticket {t}")
             srv.release(t)
         assert starts == sorted(starts)
-        assert srv.info()["arena_used"] == 0
+        info = srv.info()
+        assert info["arena_used"] == 0 and info["workspace_grows"] == 0
 
 
 def test_rejects_and_cancel(msc):
-    big = np.zeros((128, 128, 128), np.float32)
     fa = synth.gaussian_field((60, 50, 40), 6, 5)       # 120000 vertices
     fb = synth.gaussian_field((50, 40, 30), 4, 6)       # 60000 vertices
-    # Room for fa alone (resident 16 B/vertex + 8 B/vertex workspace + 1 MiB),
-    # but not for fb beside fa's unreleased result.
-    budget = 24 * 120000 + (1 << 20) + (64 << 10)
+    budget = 8 * msc.workspace_size(msc.REQ_SEGMENT, [(60, 50, 40)])
     with msc.Server(hbm_budget=budget, max_batch=4) as srv:
+        arena = srv.info()["arena_size"]
+        big = np.zeros(arena // 16 + 1, np.float32)
         with pytest.raises(msc.MscError) as e:
-            srv.submit(1, big)                      # alone exceeds the budget
+            srv.submit(1, big)                      # alone exceeds the arena
         assert e.value.code == msc.MSC_EBUDGET
         with pytest.raises(TypeError):
             srv.submit(1, fa.astype(np.float64))
@@ -119,7 +131,12 @@ def test_rejects_and_cancel(msc):
             srv.poll(987654)                        # unknown ticket
         ta = srv.submit(1, fa)
         assert srv.wait(ta) == msc.MSC_OK
-        tb = srv.submit(1, fb)                      # waits for fa's release
+        # Fill the arena with held results until fb no longer fits.
+        held = []
+        while arena - srv.info()["arena_used"] >= _resident(1, fb.size):
+            held.append(srv.submit(1, fb))
+            assert srv.wait(held[-1]) == msc.MSC_OK
+        tb = srv.submit(1, fb)                      # waits for a release
         assert srv.poll(tb) == msc.MSC_EBUSY
         assert srv.info()["pending"] == 1
         srv.cancel(tb)
@@ -139,6 +156,9 @@ def test_rejects_and_cancel(msc):
         with pytest.raises(msc.MscError):
             srv.cancel(tc)                          # already finished
         srv.release(tc)
+        _check(1, fb, srv.fetch(held[0]), "held filler")
+        for t in held:
+            srv.release(t)
         t = srv.submit(2, synth.threshold_mask(fb, 0.5))
         assert srv.wait(t) == msc.MSC_OK
         with pytest.raises(msc.MscError):           # outputs of a CC
