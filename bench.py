@@ -42,10 +42,14 @@ WORKLOAD_TEXT = {
 # on the same synthetic workloads: segmentation at 512^3 and 1024^3 (table
 # "overview") and implicit connected components of the 1024^3 field under
 # the three feature thresholds (table "different_thresholds"; its rows are
-# labelled top 10 / 50 / 90 %).  Another machine's numbers: context only.
+# labelled top 10 / 50 / 90 %), and implicit connected components of the
+# 512^3 and 1024^3 fields with the top 10 % of vertices masked (table
+# "overview", the CC scaling figure).  Another machine's numbers: context
+# only.
 PAPER_1N_SECONDS = {
     "perlin512": 11.291, "perlin1024": 86.044,
     "ccperlin_t90": 47.285, "ccperlin_t50": 163.410, "ccperlin_t10": 226.593,
+    "ccperlin512_top10": 5.973, "ccperlin1024_top10": 44.7504,
 }
 
 
@@ -202,6 +206,15 @@ CC_TEXT = {
                     "mask = value above 0.5, int64 labels",
     "ccperlin_t10": "ccperlin_t10: perlin1024 field normalised to [0,1], "
                     "mask = value above 0.1, int64 labels",
+    "ccperlin512_top10": "ccperlin512_top10: perlin512 field (512^3 float32, "
+                         "one layer of Perlin noise, frequency 0.1, seed 5), "
+                         "mask = the top 10 % of vertices (above the "
+                         "floor(0.9 N)-th smallest value), Freudenthal "
+                         "connectivity, int64 labels",
+    "ccperlin1024_top10": "ccperlin1024_top10: perlin1024 field, mask = the "
+                          "top 10 % of vertices (above the floor(0.9 N)-th "
+                          "smallest value), Freudenthal connectivity, int64 "
+                          "labels",
     "csr50m": "csr50m: 368^3 = 49.8M-vertex jittered Kuhn tetrahedralisation "
               "as symmetric CSR (int64 row_ptr, int32 col_idx), vertex ids "
               "randomly permuted, seed 2; mask = Gaussian sum (24 bumps) at "
@@ -228,6 +241,17 @@ def bench_cc(args, msc, synth, torch, dev):
         k = int(0.7 * n)
         tau = torch.sort(f.reshape(-1)).values[k]
         mask = (f > tau).to(torch.uint8)
+        del f
+        torch.cuda.empty_cache()
+        labels = torch.empty(n, dtype=torch.int64, device=dev)
+        run = lambda: cc_grid(mask, labels)
+        fg = int(mask.sum().item())
+    elif args.workload.endswith("_top10"):
+        name = args.workload[2:-len("_top10")]
+        log(f"[bench] generating {name} and its top-10 % mask")
+        f = synth.config_field(name, device=dev)
+        n = f.numel()
+        mask = synth.threshold_mask(f, 0.9)
         del f
         torch.cuda.empty_cache()
         labels = torch.empty(n, dtype=torch.int64, device=dev)

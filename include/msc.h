@@ -65,6 +65,19 @@ enum {
 /* Kinds of work: segmentation of a float32 field, CC of a grid mask. */
 enum { MSC_REQ_SEGMENT = 1, MSC_REQ_CC_GRID = 2 };
 
+/*
+ * Host-side fault injection, for tests of the error paths (failure
+ * detection): after `after` more checks of the given kind succeed, the next
+ * one fails, once.  MSC_INJECT_ENOMEM fails a device or pinned host
+ * allocation of the library (nothing is allocated; the call reports
+ * MSC_ENOMEM); MSC_INJECT_EHIP makes a checked HIP runtime call report
+ * failure after it has run (the call reports MSC_EHIP; work it already
+ * enqueued runs normally).  after < 0 disarms.  Process-wide, thread-safe;
+ * no device is touched.  Errors: MSC_EINVAL (unknown kind).
+ */
+enum { MSC_INJECT_ENOMEM = 1, MSC_INJECT_EHIP = 2 };
+MSC_API int msc_debug_inject(int what, int after);
+
 typedef struct msc_ctx msc_ctx;
 
 /* Static string for an error code (never NULL). */

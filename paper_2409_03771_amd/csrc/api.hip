@@ -9,6 +9,20 @@
 
 namespace msc {
 
+namespace {
+std::atomic<int> g_inject[3] = {{-1}, {-1}, {-1}};
+}  // namespace
+
+bool inject_fault(int what) {
+  std::atomic<int> &c = g_inject[what];
+  int v = c.load(std::memory_order_relaxed);
+  while (v >= 0) {
+    if (c.compare_exchange_weak(v, v - 1, std::memory_order_relaxed))
+      return v == 0;
+  }
+  return false;
+}
+
 int host_wait(msc_ctx *ctx, hipEvent_t e) {
   const hipError_t q = hipEventQuery(e);
   if (q == hipSuccess) return MSC_OK;
@@ -31,7 +45,7 @@ int reserve(msc_ctx *ctx, DevBuf &buf, size_t bytes) {
   }
   size_t want = bytes + bytes / 8 + (1 << 20);
   void *p = nullptr;
-  if (hipMalloc(&p, want) != hipSuccess) {
+  if (dev_malloc(&p, want) != hipSuccess) {
     (void)hipGetLastError();
     return MSC_ENOMEM;
   }
@@ -82,7 +96,7 @@ int pinned_slot(msc_ctx *ctx, size_t bytes, void **out, int *slot) {
     ps.ptr = nullptr;
     ps.bytes = 0;
     const size_t want = bytes + bytes / 4 + 4096;
-    if (hipHostMalloc(&ps.ptr, want, hipHostMallocDefault) != hipSuccess)
+    if (host_malloc(&ps.ptr, want) != hipSuccess)
       return MSC_ENOMEM;
     ps.bytes = want;
   }
@@ -174,13 +188,15 @@ int msc_create(msc_ctx **out, int device) {
   msc_ctx *c = new (std::nothrow) msc_ctx();
   if (!c) return MSC_ENOMEM;
   c->device = device;
-  if (hipMalloc(&c->dctr, msc::kNumCounters * sizeof(unsigned long long)) !=
+  if (msc::dev_malloc(reinterpret_cast<void **>(&c->dctr),
+                      msc::kNumCounters * sizeof(unsigned long long)) !=
       hipSuccess) {
     delete c;
     return MSC_ENOMEM;
   }
-  if (hipHostMalloc(&c->hctr, msc::kNumCounters * sizeof(unsigned long long),
-                    hipHostMallocDefault) != hipSuccess) {
+  if (msc::host_malloc(reinterpret_cast<void **>(&c->hctr),
+                       msc::kNumCounters * sizeof(unsigned long long)) !=
+      hipSuccess) {
     (void)hipFree(c->dctr);
     delete c;
     return MSC_ENOMEM;
@@ -232,6 +248,12 @@ void msc_destroy(msc_ctx *ctx) {
   }
   if (ctx->done) (void)hipEventDestroy(ctx->done);
   delete ctx;
+}
+
+int msc_debug_inject(int what, int after) {
+  if (what != MSC_INJECT_ENOMEM && what != MSC_INJECT_EHIP) return MSC_EINVAL;
+  msc::g_inject[what].store(after < 0 ? -1 : after, std::memory_order_relaxed);
+  return MSC_OK;
 }
 
 int msc_set_workspace(msc_ctx *ctx, void *ptr, size_t bytes) {

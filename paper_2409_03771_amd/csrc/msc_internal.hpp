@@ -11,10 +11,29 @@
 
 #include "../../include/msc.h"
 
+namespace msc {
+// Host-side fault injection (msc_debug_inject): the check that takes a
+// kind's countdown to zero reports a failure.
+bool inject_fault(int what);
+// A runtime call's result, failed by an armed MSC_INJECT_EHIP countdown.
+inline bool hip_ok(hipError_t e) {
+  return e == hipSuccess && !inject_fault(MSC_INJECT_EHIP);
+}
+// Device and pinned host allocations, failed by an armed MSC_INJECT_ENOMEM
+// countdown (nothing is allocated then).
+inline hipError_t dev_malloc(void **p, size_t bytes) {
+  if (inject_fault(MSC_INJECT_ENOMEM)) return hipErrorOutOfMemory;
+  return hipMalloc(p, bytes);
+}
+inline hipError_t host_malloc(void **p, size_t bytes) {
+  if (inject_fault(MSC_INJECT_ENOMEM)) return hipErrorOutOfMemory;
+  return hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
+}  // namespace msc
+
 #define MSC_HIP_TRY(expr)                                                   \
   do {                                                                      \
-    hipError_t e_ = (expr);                                                 \
-    if (e_ != hipSuccess) return MSC_EHIP;                                  \
+    if (!msc::hip_ok(expr)) return MSC_EHIP;                                \
   } while (0)
 
 #define MSC_TRY(expr)                                                       \

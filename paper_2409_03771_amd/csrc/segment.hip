@@ -1296,10 +1296,12 @@ __host__ __device__ inline uint64_t table_capacity(uint64_t n, uint64_t nmax,
 }
 
 // First capacity tried: the bound above, or twice an expected cell count of
-// 32 per extremum (plus slack) when that is smaller, or the caller's choice.
+// 8 per extremum (plus slack) when that is smaller, or the caller's choice.
 // Cells are pairs of manifolds that meet, far fewer than all pairs of
-// extrema; a field with more makes the pair pass overflow and run again on
-// the table of the full capacity.
+// extrema: smooth, Perlin and pure-noise fields alike have 2 to 4 per
+// extremum, so the table stays at most a quarter full and short to clear; a
+// field with more makes the pair pass overflow and run again on the table of
+// the full capacity.
 __host__ __device__ inline uint64_t table_first_capacity(uint64_t n,
                                                          uint64_t nmax,
                                                          uint64_t nmin,
@@ -1307,7 +1309,7 @@ __host__ __device__ inline uint64_t table_first_capacity(uint64_t n,
   const uint64_t full = table_capacity(n, nmax, nmin);
   uint64_t cap = 1024;
   const uint64_t want = requested ? (requested + 1) / 2
-                                  : 32 * (nmax + nmin) + 65536;
+                                  : 8 * (nmax + nmin) + 4096;
   while (cap < 2 * want && cap < full) cap <<= 1;
   return cap;
 }
@@ -1405,7 +1407,7 @@ int take_call(msc_ctx *ctx, int nfields, int *index) {
     ctx->last_folded = true;
   }
   if (!R.hctr &&
-      hipHostMalloc(&R.hctr, kNumCounters * 8, hipHostMallocDefault) !=
+      host_malloc(reinterpret_cast<void **>(&R.hctr), kNumCounters * 8) !=
           hipSuccess) {
     R.hctr = nullptr;
     return MSC_ENOMEM;
@@ -1416,7 +1418,8 @@ int take_call(msc_ctx *ctx, int nfields, int *index) {
     R.hfctr = nullptr;
     R.hfctr_cap = 0;
     const size_t cap = want * 2 + 64;
-    if (hipHostMalloc(&R.hfctr, cap * 8, hipHostMallocDefault) != hipSuccess) {
+    if (host_malloc(reinterpret_cast<void **>(&R.hfctr), cap * 8) !=
+        hipSuccess) {
       R.hfctr = nullptr;
       return MSC_ENOMEM;
     }
@@ -1489,7 +1492,7 @@ int stage(msc_ctx *ctx, size_t count, T **out) {
     ctx->pinned = nullptr;
     ctx->pinned_bytes = 0;
     const size_t want = bytes + bytes / 4 + 4096;
-    if (hipHostMalloc(&ctx->pinned, want, hipHostMallocDefault) != hipSuccess)
+    if (host_malloc(&ctx->pinned, want) != hipSuccess)
       return MSC_ENOMEM;
     ctx->pinned_bytes = want;
   }

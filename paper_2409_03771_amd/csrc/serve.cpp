@@ -114,8 +114,9 @@ size_t round256(size_t b) { return (b + 255) & ~size_t(255); }
 struct Launch {
   std::vector<Request *> reqs;
   hipEvent_t done = nullptr;
-  int rec = -1;       // call record of a segmentation launch
-  int rc = MSC_OK;    // outcome of enqueuing it
+  int rec = -1;           // call record of a segmentation launch
+  int rc = MSC_OK;        // outcome of enqueuing it
+  bool recorded = false;  // `done` marks the end of what it enqueued
 };
 
 struct msc_queue {
@@ -212,10 +213,14 @@ void dispatcher_loop(msc_queue *q) {
       lk.unlock();
       int rc = MSC_OK;
       // The input may be host or device memory (unified addressing).
-      if (hipMemcpyAsync(r->dev, r->host_in, r->in_bytes, hipMemcpyDefault,
-                         cs) != hipSuccess ||
-          hipEventRecord(r->copied, cs) != hipSuccess)
+      if (!msc::hip_ok(hipMemcpyAsync(r->dev, r->host_in, r->in_bytes,
+                                      hipMemcpyDefault, cs)) ||
+          !msc::hip_ok(hipEventRecord(r->copied, cs))) {
         rc = MSC_EHIP;
+        // A copy may still be in flight into the request's arena space,
+        // which the client frees once the request is finished.
+        (void)hipStreamSynchronize(cs);
+      }
       lk.lock();
       if (rc != MSC_OK) {
         r->rc = rc;
@@ -256,7 +261,7 @@ int issue(msc_queue *q, int k, Launch *L) {
   hipStream_t s = q->s_run[k];
   msc_ctx *ctx = q->ctx[k];
   for (Request *r : L->reqs)
-    if (hipStreamWaitEvent(s, r->copied, 0) != hipSuccess) return MSC_EHIP;
+    if (!msc::hip_ok(hipStreamWaitEvent(s, r->copied, 0))) return MSC_EHIP;
   if (k == 0) {
     std::vector<msc_field> fields;
     fields.reserve(L->reqs.size());
@@ -272,7 +277,6 @@ int issue(msc_queue *q, int k, Launch *L) {
     MSC_TRY(msc::cc_grid_batch_run(ctx, (int)masks.size(), masks.data(), s));
     MSC_TRY(msc::end_call(ctx, s));
   }
-  if (hipEventRecord(L->done, s) != hipSuccess) return MSC_EHIP;
   return MSC_OK;
 }
 
@@ -322,6 +326,12 @@ void worker_loop(msc_queue *q, int k) {
     q->cv.notify_all();  // the staging window has room again
     lk.unlock();
     L->rc = issue(q, k, L);
+    // Recorded even after a failure: the completer waits for whatever the
+    // launch did enqueue before its requests' memory can be released.
+    L->recorded = hipEventRecord(L->done, q->s_run[k]) == hipSuccess;
+    if (L->rc == MSC_OK && !msc::hip_ok(L->recorded ? hipSuccess
+                                                    : hipErrorUnknown))
+      L->rc = MSC_EHIP;
     lk.lock();
     q->inflight[k].push_back(L);
     ++q->launches;
@@ -341,12 +351,14 @@ void completer_loop(msc_queue *q, int k) {
     Launch *L = q->inflight[k].front();
     lk.unlock();
     std::vector<int> rc(L->reqs.size(), L->rc);
-    if (L->rc == MSC_OK) {
-      const bool ok = hipEventSynchronize(L->done) == hipSuccess;
-      for (size_t i = 0; i < L->reqs.size(); ++i)
-        rc[i] = !ok ? MSC_EHIP
-                : k == 0 ? msc::call_field_status(q->ctx[0], L->rec, (int)i)
-                         : MSC_OK;
+    const bool ok = L->recorded
+                        ? hipEventSynchronize(L->done) == hipSuccess
+                        : hipStreamSynchronize(q->s_run[k]) == hipSuccess;
+    for (size_t i = 0; i < L->reqs.size(); ++i) {
+      if (rc[i] != MSC_OK) continue;
+      rc[i] = !ok ? MSC_EHIP
+              : k == 0 ? msc::call_field_status(q->ctx[0], L->rec, (int)i)
+                       : MSC_OK;
     }
     const int64_t t = now_ns();
     lk.lock();
@@ -398,7 +410,8 @@ int msc_queue_create(int device, size_t hbm_budget, int max_batch,
            hipSuccess;
     if (!ok)
       rc = MSC_EHIP;
-    else if (hipMalloc(&q->mem, hbm_budget) != hipSuccess)
+    else if (msc::dev_malloc(reinterpret_cast<void **>(&q->mem),
+                             hbm_budget) != hipSuccess)
       rc = MSC_ENOMEM;
     if (prev >= 0) (void)hipSetDevice(prev);
   }
@@ -593,9 +606,9 @@ int msc_copy_result(msc_queue *q, uint64_t ticket, int which, void *dst) {
   int prev = -1;
   (void)hipGetDevice(&prev);
   (void)hipSetDevice(q->device);
-  const hipError_t e = hipMemcpy(dst, src, bytes, hipMemcpyDefault);
+  const bool ok = msc::hip_ok(hipMemcpy(dst, src, bytes, hipMemcpyDefault));
   if (prev >= 0) (void)hipSetDevice(prev);
-  return e == hipSuccess ? MSC_OK : MSC_EHIP;
+  return ok ? MSC_OK : MSC_EHIP;
 }
 
 int msc_release(msc_queue *q, uint64_t ticket) {

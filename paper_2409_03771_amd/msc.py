@@ -92,6 +92,7 @@ _SIGS = {
     "cc_label_grid_noalloc": ([_P, ctypes.POINTER(_I64), _P, _P], _I32),
     "cc_label_grid_batched": ([_P, _I32, ctypes.POINTER(msc_mask), _P], _I32),
     "msc_set_workspace": ([_P, _P, ctypes.c_size_t], _I32),
+    "msc_debug_inject": ([_I32, _I32], _I32),
     "msc_workspace_size": ([_P, _I32, _I32, _P, ctypes.POINTER(ctypes.c_size_t)],
                            _I32),
     "msc_pointer_jump": ([_P, _P, _I64, _I32, _I32, _P], _I32),
@@ -537,6 +538,16 @@ def set_workspace(buf, device: int | None = None):
         code = _lib.msc_set_workspace(context(buf.device.index),
                                       buf.data_ptr(), buf.numel())
     _check(code, "msc_set_workspace")
+
+
+INJECT_ENOMEM, INJECT_EHIP = 1, 2
+
+
+def debug_inject(what: int, after: int = 0):
+    """Arm host-side fault injection: after `after` more successful checks
+    of the kind (INJECT_ENOMEM: allocations, INJECT_EHIP: HIP runtime
+    calls), the next one fails once; after < 0 disarms."""
+    _check(_lib.msc_debug_inject(int(what), int(after)), "msc_debug_inject")
 
 
 def cc_label_grid_noalloc_into(mask, labels, dims=None, stream=None):

@@ -195,9 +195,20 @@ def config_field(name: str, device=None):
     return gaussian_field(dims, nb, seed, device=device)
 
 
-def threshold_mask(f: np.ndarray, quantile: float = 0.7) -> np.ndarray:
+def threshold_mask(f, quantile: float = 0.7):
     """uint8 mask f > tau, tau the k-th smallest value, k = floor(q*N)
-    (0-based): about (1-q) of the vertices are foreground."""
+    (0-based): about (1-q) of the vertices are foreground.  A torch tensor
+    gives a tensor on its device (tau from a sort there)."""
+    try:
+        import torch
+        if isinstance(f, torch.Tensor):
+            flat = f.reshape(-1)
+            k = min(max(int(math.floor(quantile * flat.numel())), 0),
+                    flat.numel() - 1)
+            tau = torch.sort(flat).values[k]
+            return (f > tau).to(torch.uint8)
+    except ImportError:  # pragma: no cover
+        pass
     flat = f.reshape(-1)
     k = int(math.floor(quantile * flat.size))
     k = min(max(k, 0), flat.size - 1)

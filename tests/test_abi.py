@@ -53,3 +53,16 @@ def test_null_arguments_rejected_before_any_device_call():
                                  None) == msc.MSC_EINVAL
     assert msc._lib.msc_pointer_jump(None, None, 3, 0, 0, None) == msc.MSC_EINVAL
     assert msc._lib.msc_create(None, 0) == msc.MSC_EINVAL
+    assert msc._lib.cc_label_grid_batched(None, 1, None, None) == msc.MSC_EINVAL
+    assert msc._lib.msc_set_workspace(None, None, 0) == msc.MSC_EINVAL
+    assert msc._lib.msc_workspace_size(None, 1, 0, None, None) == msc.MSC_EINVAL
+
+
+def test_fault_injection_hook_without_gpu():
+    """Arming and disarming touch no device; unknown kinds are rejected."""
+    from paper_2409_03771_amd import msc
+    assert msc._lib.msc_debug_inject(msc.INJECT_ENOMEM, 3) == msc.MSC_OK
+    assert msc._lib.msc_debug_inject(msc.INJECT_EHIP, 0) == msc.MSC_OK
+    assert msc._lib.msc_debug_inject(7, 0) == msc.MSC_EINVAL
+    assert msc._lib.msc_debug_inject(msc.INJECT_ENOMEM, -1) == msc.MSC_OK
+    assert msc._lib.msc_debug_inject(msc.INJECT_EHIP, -1) == msc.MSC_OK
