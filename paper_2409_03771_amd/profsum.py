@@ -1,6 +1,6 @@
 """Summaries of rocprofv3 output for the profiles folder.
 
-    python -m paper_2409_03771_amd.profsum stats KERNEL_STATS_CSV \\
+    python -m paper_2409_03771_amd.profsum stats KERNEL_TRACE_CSV \\
         --cmd "<the rocprofv3 command>" --out profiles/NAME.md
     python -m paper_2409_03771_amd.profsum traffic \\
         --fetch FETCH_CSV --write WRITE_CSV \\
@@ -10,12 +10,13 @@
     python -m paper_2409_03771_amd.profsum counters COUNTER_CSV \\
         --cmd "<the rocprofv3 command>" --out profiles/NAME.md
 
-`stats` turns a --kernel-trace --stats summary into a table of the library's
-kernels.  `traffic` turns two --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB per
-dispatch) into HBM bytes per launch, each scaled by what the same counter
-reads for a device copy of known size, and records the hash of the kernel
-sources it was measured on: the benchmark reports these bytes only while the
-sources are unchanged.  `counters` tabulates any other --pmc run.
+`stats` turns a --kernel-trace run (its per-dispatch trace) into a table of
+the library's kernels, one row per kernel and grid size.  `traffic` turns
+two --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB per dispatch) into HBM bytes per
+launch, each scaled by what the same counter reads for a device copy of
+known size, and records the hash of the kernel sources it was measured on:
+the benchmark reports these bytes only while the sources are unchanged.
+`counters` tabulates any other --pmc run.
 """
 from __future__ import annotations
 
@@ -56,31 +57,57 @@ def _ours(name: str) -> bool:
     return short_name(name).startswith("k_")
 
 
+def _keyed(rows, name_col, grid_col):
+    """(kernel, grid) -> rows; a kernel launched with several grid sizes
+    (e.g. a pass and its rerun) is listed once per grid size."""
+    by = collections.defaultdict(list)
+    for r in rows:
+        if _ours(r[name_col]):
+            by[(short_name(r[name_col]), int(float(r[grid_col])))].append(r)
+    grids = collections.Counter(k for k, _ in by)
+    return {(f"{k} [grid {g}]" if grids[k] > 1 else k): v
+            for (k, g), v in by.items()}
+
+
 def cmd_stats(args):
+    """Per-kernel durations from a --kernel-trace CSV (one row a dispatch)."""
     rows = list(csv.DictReader(open(args.csv)))
-    total = sum(float(r["TotalDurationNs"]) for r in rows if _ours(r["Name"]))
+    by = _keyed(rows, "Kernel_Name", "Grid_Size_X")
+    dur = {k: [(float(r["End_Timestamp"]) - float(r["Start_Timestamp"]))
+               for r in v] for k, v in by.items()}
+    total = sum(sum(d) for d in dur.values())
     lines = [f"# Kernel trace: {args.title}", "", "Command:", "",
              "```", args.cmd, "```", "",
              "| kernel | calls | avg ms | min ms | max ms | share of library time |",
              "|---|---:|---:|---:|---:|---:|"]
-    for r in rows:
-        if not _ours(r["Name"]):
-            continue
+    ranked = sorted(dur.items(), key=lambda kv: -sum(kv[1]))
+    shown = ranked[:args.top] if args.top else ranked
+    for k, d in shown:
         lines.append(
-            f"| {short_name(r['Name'])} | {r['Calls']} | "
-            f"{float(r['AverageNs']) / 1e6:.3f} | {float(r['MinNs']) / 1e6:.3f}"
-            f" | {float(r['MaxNs']) / 1e6:.3f} | "
-            f"{100 * float(r['TotalDurationNs']) / total:.1f}% |")
+            f"| {k} | {len(d)} | {sum(d) / len(d) / 1e6:.3f} | "
+            f"{min(d) / 1e6:.3f} | {max(d) / 1e6:.3f} | "
+            f"{100 * sum(d) / total:.1f}% |")
+    if len(shown) < len(ranked):
+        rest = ranked[len(shown):]
+        lines.append(f"| ({len(rest)} more rows) | "
+                     f"{sum(len(d) for _, d in rest)} | | | | "
+                     f"{100 * sum(sum(d) for _, d in rest) / total:.1f}% |")
     lines += ["", f"Sum over all launches of the library's kernels in the traced "
-              f"run: {total / 1e6:.3f} ms."]
+              f"run: {total / 1e6:.3f} ms.", "",
+              f"Kernel sources sha256: `{source_hash()}`"]
     _write(args.out, lines)
 
 
 def _per_kernel(path, counter):
-    acc = collections.defaultdict(list)
-    for r in csv.DictReader(open(path)):
-        if r["Counter_Name"] == counter:
-            acc[short_name(r["Kernel_Name"])].append(float(r["Counter_Value"]))
+    rows = [r for r in csv.DictReader(open(path))
+            if r["Counter_Name"] == counter]
+    acc = {k: [float(r["Counter_Value"]) for r in v]
+           for k, v in _keyed(rows, "Kernel_Name", "Grid_Size").items()}
+    # The copy kernel of the calibration run is not one of the library's.
+    for r in rows:
+        if not _ours(r["Kernel_Name"]):
+            acc.setdefault(short_name(r["Kernel_Name"]), []).append(
+                float(r["Counter_Value"]))
     return acc
 
 
@@ -125,10 +152,10 @@ def cmd_traffic(args):
 
 def cmd_counters(args):
     acc = collections.defaultdict(lambda: collections.defaultdict(list))
-    for r in csv.DictReader(open(args.csv)):
-        if _ours(r["Kernel_Name"]):
-            acc[short_name(r["Kernel_Name"])][r["Counter_Name"]].append(
-                float(r["Counter_Value"]))
+    rows = list(csv.DictReader(open(args.csv)))
+    for k, v in _keyed(rows, "Kernel_Name", "Grid_Size").items():
+        for r in v:
+            acc[k][r["Counter_Name"]].append(float(r["Counter_Value"]))
     names = sorted({c for d in acc.values() for c in d})
     lines = [f"# Counters: {args.title}", "", "Command:", "", "```", args.cmd,
              "```", "", "Mean per dispatch.", "",
@@ -151,6 +178,8 @@ def main():
     sub = ap.add_subparsers(dest="what", required=True)
     a = sub.add_parser("stats")
     a.add_argument("csv")
+    a.add_argument("--top", type=int, default=0,
+                   help="only the N rows with the most time")
     for p in (a,):
         p.add_argument("--cmd", required=True)
         p.add_argument("--out", required=True)

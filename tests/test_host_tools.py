@@ -27,11 +27,39 @@ def test_short_names():
 
 def _counter_csv(path, rows):
     with open(path, "w", newline="") as fh:
-        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Counter_Name",
-                                           "Counter_Value"])
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Grid_Size",
+                                           "Counter_Name", "Counter_Value"])
         w.writeheader()
         for r in rows:
-            w.writerow(r)
+            w.writerow({"Grid_Size": 4096, **r})
+
+
+def test_stats_one_row_per_kernel_and_grid(tmp_path):
+    """A kernel launched with two grid sizes (a pass and its rerun) gets a
+    row per grid size; the shares add up to the whole."""
+    k = ("void msc::(anonymous namespace)::k_tile_pairs<msc::(anonymous "
+         "namespace)::Cfg<32, 16, 16> >(int)")
+    rows = [(k, 1024, 0, 3000), (k, 1024, 5000, 9000), (k, 64, 9000, 9010),
+            ("void msc::(anonymous namespace)::k_key_hist(int)", 256,
+             10000, 10990)]
+    path = tmp_path / "trace.csv"
+    with open(path, "w", newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=["Kernel_Name", "Grid_Size_X",
+                                           "Start_Timestamp",
+                                           "End_Timestamp"])
+        w.writeheader()
+        for name, grid, a, b in rows:
+            w.writerow({"Kernel_Name": name, "Grid_Size_X": grid,
+                        "Start_Timestamp": a, "End_Timestamp": b})
+    out = tmp_path / "s.md"
+    subprocess.run([sys.executable, "-m", "paper_2409_03771_amd.profsum",
+                    "stats", str(path), "--cmd", "demo", "--out", str(out)],
+                   check=True, cwd=ROOT)
+    text = out.read_text()
+    assert "| k_tile_pairs<32,16,16> [grid 1024] | 2 | 0.004 |" in text
+    assert "| k_tile_pairs<32,16,16> [grid 64] | 1 | 0.000 |" in text
+    assert "| k_key_hist | 1 | 0.001 |" in text
+    assert "8.000 ms" not in text and "0.008 ms." in text
 
 
 def test_traffic_scaling_and_source_guard(tmp_path):
