@@ -504,12 +504,6 @@ k_tile_local(const FieldDev *__restrict__ fds,
     if (nz > 0) fsum = __uint_as_float(own[HXY * zs]);
   }
   unsigned nmax = 0, nmin = 0;
-  // Planes of the tile inside the domain (block-uniform), and the wave's
-  // columns inside it: a vertex is counted as an extremum when its pointer
-  // stays home, with the predicate's ballot masked by the columns, so the
-  // count costs one compare per direction.
-  const int nzt = min((int)g.Z - t.z0, C::TZ);
-  const unsigned long long colmask = __builtin_amdgcn_ballot_w64(col_in);
   // Pointers wait in registers in groups of four planes: plane q's values
   // are last read in iteration q - 2, so once every thread has passed a
   // barrier after iteration lz, the words of planes up to lz + 2 are free
@@ -533,12 +527,12 @@ k_tile_local(const FieldDev *__restrict__ fds,
     if (prev.lmin.v <= mn.v) mn = Best{prev.lmin.v, prev.lmin.o - 4 * HXY};
     if (next.umax.v >= mx.v) mx = Best{next.umax.v, next.umax.o + 4 * HXY};
     if (next.umin.v < mn.v) mn = Best{next.umin.v, next.umin.o + 4 * HXY};
+    const bool in = lz < nz;
     const uint32_t self = 4u * (uint32_t)(c0 + P * HXY);
     ka[lz % kFlush] = self + (uint32_t)mx.o;
     kd[lz % kFlush] = self + (uint32_t)mn.o + 2u;
-    const unsigned long long cm = lz < nzt ? colmask : 0ull;
-    nmax += __popcll(__builtin_amdgcn_ballot_w64(mx.o == 0) & cm);
-    nmin += __popcll(__builtin_amdgcn_ballot_w64(mn.o == 0) & cm);
+    nmax += __popcll(__builtin_amdgcn_ballot_w64(in && mx.o == 0));
+    nmin += __popcll(__builtin_amdgcn_ballot_w64(in && mn.o == 0));
     prev = cur;
     cur = next;
     if (lz % kFlush == kFlush - 1) {
