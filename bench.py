@@ -509,11 +509,20 @@ def batch_leg(args, msc, synth, torch, dev):
     b_ms, b_wall = timed_steps(torch, stream, batched, steps)
     p_ms, p_wall = timed_steps(torch, stream, plain, steps)
     prof = traced_steps(msc, torch, batched, 2)
+    # The same batch captured into a HIP graph and replayed.
+    graph = msc.Graph(fields, outs, stream=stream)
+    for _ in range(max(1, args.warmup)):
+        graph.launch(stream=stream)
+    torch.cuda.synchronize()
+    g_ms, _ = timed_steps(torch, stream, lambda: graph.launch(stream=stream),
+                          steps)
+    graph.close()
     msc.set_tile(*msc.tile_shapes()[0])
-    log(f"[bench] batch256: batched {b_ms:.2f} ms vs plain {p_ms:.2f} ms "
-        f"for {n} vertices")
+    log(f"[bench] batch256: batched {b_ms:.2f} ms (graph replay {g_ms:.2f} "
+        f"ms) vs plain {p_ms:.2f} ms for {n} vertices")
     return {"workload": BATCH_TEXT, "vertices": n, "tile": list(tune["tile"]),
             "batched_ms": round(b_ms, 3), "plain_ms": round(p_ms, 3),
+            "graph_replay_ms": round(g_ms, 3),
             "batched_wall_ms": round(b_wall, 3),
             "plain_wall_ms": round(p_wall, 3),
             "batched_gvps": round(n / (b_ms * 1e-3) / 1e9, 3),

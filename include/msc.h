@@ -291,6 +291,32 @@ MSC_API int msc_last_field_stats(const msc_ctx *ctx, int index,
                                  msc_stats *out);
 
 /*
+ * Graph-captured batched segmentation, for fields segmented again and again
+ * with the same buffers and shapes (a time series, a serving loop with
+ * fixed slots).  msc_graph_create runs one msc_segment_batched call over
+ * `fields`, ordered after the work already on `stream`, and returns when it
+ * has run (the outputs hold its result), having captured the same call
+ * into a HIP graph; msc_graph_launch replays
+ * it on `stream` with one launch call, reading the fields' current
+ * contents and rewriting the same outputs.  The graph owns its workspace,
+ * counters and copy of the descriptors, so replays share no memory with
+ * `ctx` or with other graphs; `ctx` only gives the device and tile shape.
+ * Replays of one graph must not overlap (issue them on one stream, or
+ * order them).  The fields and outputs must stay allocated until
+ * msc_graph_destroy; the descriptor array is read during msc_graph_create
+ * only.
+ *  msc_graph_field_stats: waits for the last replay and reports field
+ *  `index`'s counts and status (MSC_ENAN for a NaN in that field).
+ *  Errors: as msc_segment_batched; MSC_EINVAL for a replay-less stats call.
+ */
+typedef struct msc_graph msc_graph;
+MSC_API int msc_graph_create(msc_ctx *ctx, int nfields, const msc_field *fields,
+                             void *stream, msc_graph **out);
+MSC_API int msc_graph_launch(msc_graph *g, void *stream);
+MSC_API int msc_graph_field_stats(msc_graph *g, int index, msc_stats *out);
+MSC_API void msc_graph_destroy(msc_graph *g);
+
+/*
  * Per-kernel timing (the library's own trace).  While enabled, every kernel
  * launch of the calls on this context is bracketed by HIP events recorded on
  * the call's stream, and its elapsed time is added to a per-kernel record

@@ -352,6 +352,113 @@ int msc_segment_batched(msc_ctx *ctx, int nfields, const msc_field *fields,
                                 static_cast<hipStream_t>(stream));
 }
 
+}  // extern "C"
+
+struct msc_graph {
+  msc_ctx *ctx = nullptr;  // the graph's own workspace, counters and records
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  hipEvent_t done = nullptr;  // recorded after each replay
+  int rec = -1;               // call record the captured call writes
+  bool launched = false;
+};
+
+extern "C" {
+
+int msc_graph_create(msc_ctx *ctx, int nfields, const msc_field *fields,
+                     void *stream, msc_graph **out) {
+  if (!ctx || !out || nfields < 1 || !fields) return MSC_EINVAL;
+  *out = nullptr;
+  for (int i = 0; i < nfields; ++i) {
+    const msc_field &f = fields[i];
+    if (!f.field || (!f.asc && !f.desc && !f.ms)) return MSC_EINVAL;
+    int64_t n = 0;
+    MSC_TRY(check_dims(f.dims, &n));
+    if (n > INT32_MAX) return MSC_ERANGE;
+  }
+  DeviceGuard dg(ctx->device);
+  if (!dg.ok) return MSC_EHIP;
+  msc_graph *g = new (std::nothrow) msc_graph();
+  if (!g) return MSC_ENOMEM;
+  auto fail = [&](int rc) {
+    msc_graph_destroy(g);
+    return rc;
+  };
+  int rc = msc_create(&g->ctx, ctx->device);
+  if (rc != MSC_OK) return fail(rc);
+  g->ctx->tile_choice = ctx->tile_choice;
+  g->ctx->table_first = ctx->table_first;
+  if (!msc::hip_ok(hipStreamCreateWithFlags(&g->cap, hipStreamNonBlocking)) ||
+      !msc::hip_ok(hipEventCreateWithFlags(&g->done, hipEventDisableTiming)))
+    return fail(MSC_EHIP);
+  // The fields may still be produced by work on the caller's stream.
+  if (!msc::hip_ok(hipEventRecord(g->done, static_cast<hipStream_t>(stream))) ||
+      !msc::hip_ok(hipStreamWaitEvent(g->cap, g->done, 0)))
+    return fail(MSC_EHIP);
+  // One ordinary call first: it sizes the workspace and allocates the call
+  // record and the pinned descriptor slot, so that the captured call
+  // allocates nothing and waits for nothing (and it leaves the outputs
+  // computed).  The captured call then reuses that record and slot.
+  rc = msc::segment_batch_run(g->ctx, nfields, fields, g->cap);
+  if (rc != MSC_OK) return fail(rc);
+  if (!msc::hip_ok(hipStreamSynchronize(g->cap))) return fail(MSC_EHIP);
+  rc = msc::finish_last(g->ctx);
+  if (rc != MSC_OK) return fail(rc);
+  g->ctx->next_call = 0;
+  g->ctx->calls[0].pending = false;
+  g->ctx->next_slot = 0;
+  g->ctx->slots[0].pending = false;
+  if (!msc::hip_ok(
+          hipStreamBeginCapture(g->cap, hipStreamCaptureModeThreadLocal)))
+    return fail(MSC_EHIP);
+  rc = msc::segment_batch_run(g->ctx, nfields, fields, g->cap, nullptr,
+                              &g->rec);
+  hipGraph_t graph = nullptr;
+  const hipError_t ec = hipStreamEndCapture(g->cap, &graph);
+  g->graph = graph;
+  if (rc != MSC_OK) return fail(rc);
+  if (!msc::hip_ok(ec) || !graph) return fail(MSC_EHIP);
+  if (!msc::hip_ok(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)))
+    return fail(MSC_EHIP);
+  *out = g;
+  return MSC_OK;
+}
+
+int msc_graph_launch(msc_graph *g, void *stream) {
+  if (!g || !g->exec) return MSC_EINVAL;
+  DeviceGuard dg(g->ctx->device);
+  if (!dg.ok) return MSC_EHIP;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  MSC_HIP_TRY(hipGraphLaunch(g->exec, s));
+  MSC_HIP_TRY(hipEventRecord(g->done, s));
+  g->launched = true;
+  return MSC_OK;
+}
+
+int msc_graph_field_stats(msc_graph *g, int index, msc_stats *out) {
+  if (!g || !out || !g->launched) return MSC_EINVAL;
+  DeviceGuard dg(g->ctx->device);
+  if (!dg.ok) return MSC_EHIP;
+  MSC_HIP_TRY(hipEventSynchronize(g->done));
+  return msc::call_field_stats(g->ctx, g->rec, index, out);
+}
+
+void msc_graph_destroy(msc_graph *g) {
+  if (!g) return;
+  if (g->ctx) {
+    DeviceGuard dg(g->ctx->device);
+    if (g->cap) (void)hipStreamSynchronize(g->cap);
+    if (g->launched && g->done) (void)hipEventSynchronize(g->done);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->done) (void)hipEventDestroy(g->done);
+    if (g->cap) (void)hipStreamDestroy(g->cap);
+    msc_destroy(g->ctx);
+  }
+  delete g;
+}
+
 int msc_last_field_stats(const msc_ctx *ctx, int index, msc_stats *out) {
   if (!ctx || !out) return MSC_EINVAL;
   msc_ctx *c = const_cast<msc_ctx *>(ctx);

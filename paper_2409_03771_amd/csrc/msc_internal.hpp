@@ -225,8 +225,10 @@ inline void stats_replaced(msc_ctx *ctx) {
 // per-field entries; waits for the record's previous call if still pending.
 int take_call(msc_ctx *ctx, int nfields, int *index);
 
-// Outcome of field `i` of a recorded call, once its event has completed.
+// Outcome of field `i` of a recorded call, once its event has completed,
+// and its counts.
 int call_field_status(const msc_ctx *ctx, int index, int i);
+int call_field_stats(const msc_ctx *ctx, int index, int i, msc_stats *st);
 
 // Bump allocator over a DevBuf for the duration of one call.
 struct Carver {

@@ -1437,6 +1437,23 @@ int call_field_status(const msc_ctx *ctx, int index, int i) {
   return R.hfctr[(size_t)i * kFieldCtrs + kFNaN] ? MSC_ENAN : MSC_OK;
 }
 
+int call_field_stats(const msc_ctx *ctx, int index, int i, msc_stats *st) {
+  const CallRec &R = ctx->calls[index];
+  if (i < 0 || i >= R.nfields) return MSC_EINVAL;
+  const unsigned long long *f = R.hfctr + (size_t)i * kFieldCtrs;
+  *st = msc_stats{};
+  st->n_vertices = R.n[i];
+  st->n_maxima = (int64_t)f[kFMaxima];
+  st->n_minima = (int64_t)f[kFMinima];
+  st->n_cells = R.has_ms[i] ? (int64_t)f[kFCells] : -1;
+  st->n_exits = (int64_t)f[kFExits];
+  st->tile_x = R.tile[0];
+  st->tile_y = R.tile[1];
+  st->tile_z = R.tile[2];
+  st->status = call_field_status(ctx, index, i);
+  return MSC_OK;
+}
+
 int finish_last(msc_ctx *ctx) {
   if (ctx->last_call < 0 || ctx->last_folded) return MSC_OK;
   CallRec &R = ctx->calls[ctx->last_call];

@@ -93,6 +93,11 @@ _SIGS = {
     "cc_label_grid_batched": ([_P, _I32, ctypes.POINTER(msc_mask), _P], _I32),
     "msc_set_workspace": ([_P, _P, ctypes.c_size_t], _I32),
     "msc_debug_inject": ([_I32, _I32], _I32),
+    "msc_graph_create": ([_P, _I32, ctypes.POINTER(msc_field), _P,
+                          ctypes.POINTER(_P)], _I32),
+    "msc_graph_launch": ([_P, _P], _I32),
+    "msc_graph_field_stats": ([_P, _I32, ctypes.POINTER(msc_stats)], _I32),
+    "msc_graph_destroy": ([_P], None),
     "msc_workspace_size": ([_P, _I32, _I32, _P, ctypes.POINTER(ctypes.c_size_t)],
                            _I32),
     "msc_pointer_jump": ([_P, _P, _I64, _I32, _I32, _P], _I32),
@@ -378,6 +383,47 @@ def segment_batched_into(fields, outs, dims=None, stream=None, check=True):
     _check(code, "msc_segment_batched")
     if check:
         _check_async(fields[0].device.index, "msc_segment_batched")
+
+
+class Graph:
+    """A batched segmentation captured into a HIP graph (msc_graph_*): the
+    same fields and outputs, replayed with one launch call each time.  The
+    constructor runs the call once (outputs valid on return)."""
+
+    def __init__(self, fields, outs, dims=None, stream=None):
+        if not fields:
+            raise ValueError("a graph needs at least one field")
+        dims = dims or [grid_dims(f.shape) for f in fields]
+        arr = _field_array(fields, outs, dims)
+        self._keep = (list(fields), [tuple(o) for o in outs])
+        self._g = _P()
+        _check(_lib.msc_graph_create(context(fields[0].device.index),
+                                     len(fields), arr,
+                                     _stream(fields[0], stream),
+                                     ctypes.byref(self._g)),
+               "msc_graph_create")
+        self._device = fields[0]
+
+    def launch(self, stream=None):
+        _check(_lib.msc_graph_launch(self._g, _stream(self._device, stream)),
+               "msc_graph_launch")
+
+    def field_stats(self, index: int) -> dict:
+        s = msc_stats()
+        _check(_lib.msc_graph_field_stats(self._g, int(index), ctypes.byref(s)),
+               "msc_graph_field_stats")
+        return {k: getattr(s, k) for k, _ in msc_stats._fields_}
+
+    def close(self):
+        if self._g:
+            _lib.msc_graph_destroy(self._g)
+            self._g = _P()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def segment_batched(fields, want=("asc", "desc", "ms"), stream=None,
