@@ -314,7 +314,12 @@ __global__ void __launch_bounds__(kCThreads) k_cc_cross(CBatch<B> b) {
   // just beyond them.  Entries hold tile-local roots (kOutside: unmasked or
   // outside the domain), decoded with their own tile's origin later.
   constexpr int BX = CTX + 1, BY = CTY + 1, BZ = CTZ + 1, BXY = BX * BY;
-  constexpr int BN = BXY * BZ, K = (BN + kCThreads - 1) / kCThreads;
+  constexpr int BN = BXY * BZ;
+  // The shell, in three disjoint slabs: bx >= CTX - 1 (all y, z); by >=
+  // CTY - 1 (bx below that); bz >= CTZ - 1 (bx and by below).
+  constexpr int S1 = 2 * BY * BZ, S2 = (CTX - 1) * 2 * BZ,
+                S3 = (CTX - 1) * (CTY - 1) * 2, SN = S1 + S2 + S3;
+  constexpr int K = (SN + kCThreads - 1) / kCThreads;
   __shared__ uint16_t box[BN];
   __shared__ uint32_t set[kCrossSlots];
   const int tid = threadIdx.x;
@@ -328,18 +333,37 @@ __global__ void __launch_bounds__(kCThreads) k_cc_cross(CBatch<B> b) {
   const CTile t = ctile_at(g, ti);
   {
     uint16_t val[K];
+    int at[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int i = tid + k * kCThreads;
-      const int bz = i / BXY, r = i - bz * BXY, by = r / BX, bx = r - by * BX;
-      const bool shell = bx >= CTX - 1 || by >= CTY - 1 || bz >= CTZ - 1;
+      int bx, by, bz;
+      if (i < S1) {
+        bz = i / (2 * BY);
+        const int r = i - bz * (2 * BY);
+        by = r >> 1;
+        bx = CTX - 1 + (r & 1);
+      } else if (i < S1 + S2) {
+        const int j = i - S1;
+        bz = j / (2 * (CTX - 1));
+        const int r = j - bz * (2 * (CTX - 1));
+        by = CTY - 1 + r / (CTX - 1);
+        bx = r % (CTX - 1);
+      } else {
+        const int j = i - S1 - S2;
+        bz = CTZ - 1 + j / ((CTX - 1) * (CTY - 1));
+        const int r = j % ((CTX - 1) * (CTY - 1));
+        by = r / (CTX - 1);
+        bx = r % (CTX - 1);
+      }
       const int64_t x = t.x0 + bx, y = t.y0 + by, z = t.z0 + bz;
-      const bool in = i < BN && shell && x < g.X && y < g.Y && z < g.Z;
+      const bool in = i < SN && x < g.X && y < g.Y && z < g.Z;
+      at[k] = i < SN ? bx + BX * (by + BY * bz) : -1;
       val[k] = in ? loc[x + g.X * y + g.XY * z] : kOutside;
     }
 #pragma unroll
     for (int k = 0; k < K; ++k)
-      if (tid + k * kCThreads < BN) box[tid + k * kCThreads] = val[k];
+      if (at[k] >= 0) box[at[k]] = val[k];
   }
   __syncthreads();
   // Every masked vertex on an upper face, with each of its higher-id
@@ -399,12 +423,19 @@ __global__ void __launch_bounds__(kCThreads) k_cc_final(CBatch<B> b) {
   const int cx = tid % CTX, cy = tid / CTX;
   const int64_t gx = t.x0 + cx, gy = t.y0 + cy;
   if (gx >= g.X || gy >= g.Y) return;
-  int nz = (int)((g.Z - t.z0) < CTZ ? (g.Z - t.z0) : CTZ);
+  const int nz = (int)((g.Z - t.z0) < CTZ ? (g.Z - t.z0) : CTZ);
+  const int64_t v0 = gx + g.X * gy + g.XY * t.z0;
+  // The column's tile-local roots, all loads in flight together.
+  uint16_t sl[CTZ];
+#pragma unroll
+  for (int lz = 0; lz < CTZ; ++lz)
+    sl[lz] = lz < nz ? loc[v0 + g.XY * lz] : kOutside;
   uint16_t last = kOutside;
   int64_t last_out = -1;
-  for (int lz = 0; lz < nz; ++lz) {
-    const int64_t v = gx + g.X * gy + g.XY * (t.z0 + lz);
-    const uint16_t s = loc[v];
+#pragma unroll
+  for (int lz = 0; lz < CTZ; ++lz) {
+    if (lz >= nz) break;
+    const uint16_t s = sl[lz];
     // Only tile-local roots are ever on a root path, and a root's entry is
     // overwritten (by its owner only) with its own final root, so concurrent
     // walks stay on ancestors and every entry ends as its final root.  A
@@ -414,7 +445,7 @@ __global__ void __launch_bounds__(kCThreads) k_cc_final(CBatch<B> b) {
       last_out = uf_root<int64_t>(L, ctile_global(g, t, s));
     }
     const bool root = s == cx + CTX * (cy + CTY * lz);
-    __atomic_store_n(&L[v],
+    __atomic_store_n(&L[v0 + g.XY * lz],
                      s == kOutside ? -1 : last_out + (root ? 0 : off),
                      __ATOMIC_RELAXED);
   }
