@@ -813,26 +813,57 @@ k_exit_link(const FieldDev *__restrict__ fds,
   const Geo &g = bt.fd.g;
   const Tile t = tile_at<C>(g, bt.tile);
   const int ttx = t.x0 / C::TX, tty = t.y0 / C::TY, ttz = t.z0 / C::TZ;
-  for (uint32_t k = threadIdx.x; k < n; k += kBlock) {
-    const int p = tl[k];
-    const int hz = p / C::HXY, r = p - hz * C::HXY, hy = r / C::HX,
-              hx = r - hy * C::HX;
-    const int dx = hx == 0 ? -1 : (hx == C::HX - 1 ? 1 : 0);
-    const int dy = hy == 0 ? -1 : (hy == C::HY - 1 ? 1 : 0);
-    const int dz = hz == 0 ? -1 : (hz == C::HZ - 1 ? 1 : 0);
-    const uint32_t u = (uint32_t)(ttx + dx) +
-                       g.ntx * ((uint32_t)(tty + dy) + g.nty * (uint32_t)(ttz + dz));
-    const Tile tu{t.x0 + dx * C::TX, t.y0 + dy * C::TY, t.z0 + dz * C::TZ};
-    const uint32_t v = (uint32_t)(t.x0 - 1 + hx) + g.X * (uint32_t)(t.y0 - 1 + hy) +
-                       g.XY * (uint32_t)(t.z0 - 1 + hz);
-    const bool desc = k >= sg.na;
-    const uint32_t lw = bt.fd.lp[v];
-    const uint32_t code = desc ? (lw >> 16) : (lw & 0xffffu);
-    if (code & kExitCode) {
-      const Seg su = seg[bt.fd.tile0 + u];
-      next[sg.base + k] = su.base + (desc ? su.na : 0u) + (code & (kExitCode - 1));
-    } else {
-      next[sg.base + k] = kRoot | owned_global<C>(g, tu, code);
+  // Each thread links E exits per round, with each kind of load issued for
+  // all of them before any is used (list entries, then the neighbours'
+  // codes, then the slot records the descent exits need).
+  constexpr int E = 4;
+  for (uint32_t k0 = threadIdx.x; k0 < n; k0 += E * kBlock) {
+    int p[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const uint32_t k = k0 + e * kBlock;
+      p[e] = k < n ? (int)tl[k] : -1;
+    }
+    uint32_t u[E], v[E], lw[E];
+    int dxs[E], dys[E], dzs[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int q = p[e] < 0 ? 0 : p[e];
+      const int hz = q / C::HXY, r = q - hz * C::HXY, hy = r / C::HX,
+                hx = r - hy * C::HX;
+      dxs[e] = hx == 0 ? -1 : (hx == C::HX - 1 ? 1 : 0);
+      dys[e] = hy == 0 ? -1 : (hy == C::HY - 1 ? 1 : 0);
+      dzs[e] = hz == 0 ? -1 : (hz == C::HZ - 1 ? 1 : 0);
+      u[e] = (uint32_t)(ttx + dxs[e]) +
+             g.ntx * ((uint32_t)(tty + dys[e]) + g.nty * (uint32_t)(ttz + dzs[e]));
+      v[e] = (uint32_t)(t.x0 - 1 + hx) + g.X * (uint32_t)(t.y0 - 1 + hy) +
+             g.XY * (uint32_t)(t.z0 - 1 + hz);
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) lw[e] = p[e] >= 0 ? bt.fd.lp[v[e]] : 0u;
+    uint32_t code[E], una[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const bool desc = k0 + e * kBlock >= sg.na;
+      code[e] = desc ? (lw[e] >> 16) : (lw[e] & 0xffffu);
+      // A tile's slots start at tile * 2 * kHalo; a descent exit's number
+      // counts from after that tile's ascent exits.
+      una[e] = p[e] >= 0 && desc && (code[e] & kExitCode)
+                   ? (uint32_t)seg[bt.fd.tile0 + u[e]].na
+                   : 0u;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      if (p[e] < 0) continue;
+      const uint32_t k = k0 + e * kBlock;
+      if (code[e] & kExitCode) {
+        next[sg.base + k] = (bt.fd.tile0 + u[e]) * (uint32_t)(2 * C::kHalo) +
+                            una[e] + (code[e] & (kExitCode - 1));
+      } else {
+        const Tile tu{t.x0 + dxs[e] * C::TX, t.y0 + dys[e] * C::TY,
+                      t.z0 + dzs[e] * C::TZ};
+        next[sg.base + k] = kRoot | owned_global<C>(g, tu, code[e]);
+      }
     }
   }
 }
@@ -914,22 +945,40 @@ k_exit_resolve(const uint32_t *__restrict__ order, uint32_t ntiles,
   const uint32_t cnt = desc ? sg.nd : sg.na;
   unsigned steps_max = 0, steps_sum = 0;
   bool bad = false;
-  for (uint32_t k = threadIdx.x; k < cnt; k += C::kThreads) {
-    uint32_t x = __atomic_load_n(&next[first + k], __ATOMIC_RELAXED);
-    unsigned steps = 0;
+  // Two exits per thread and round, chased side by side, so that their
+  // loads are in flight together.
+  for (uint32_t k0 = threadIdx.x; k0 < cnt; k0 += 2 * C::kThreads) {
+    const uint32_t k1 = k0 + C::kThreads;
+    const bool has1 = k1 < cnt;
+    uint32_t x0 = __atomic_load_n(&next[first + k0], __ATOMIC_RELAXED);
+    uint32_t x1 = has1 ? __atomic_load_n(&next[first + k1], __ATOMIC_RELAXED)
+                       : kRoot;
+    unsigned s0 = 0, s1 = 0;
     // Chains are acyclic and at most `count` long; the bound only turns a
     // broken invariant into an error instead of a hang.
-    while (!(x & kRoot)) {
-      if (x >= count || ++steps > count) {
-        bad = true;
-        x = kRoot;
-        break;
+    while (!(x0 & kRoot) || !(x1 & kRoot)) {
+      if (!(x0 & kRoot)) {
+        if (x0 >= count || ++s0 > count) {
+          bad = true;
+          x0 = kRoot;
+        } else {
+          x0 = __atomic_load_n(&next[x0], __ATOMIC_RELAXED);
+        }
       }
-      x = __atomic_load_n(&next[x], __ATOMIC_RELAXED);
+      if (!(x1 & kRoot)) {
+        if (x1 >= count || ++s1 > count) {
+          bad = true;
+          x1 = kRoot;
+        } else {
+          x1 = __atomic_load_n(&next[x1], __ATOMIC_RELAXED);
+        }
+      }
     }
-    __atomic_store_n(&next[first + k], x, __ATOMIC_RELAXED);
-    steps_max = steps > steps_max ? steps : steps_max;
-    steps_sum += steps;
+    __atomic_store_n(&next[first + k0], x0, __ATOMIC_RELAXED);
+    if (has1) __atomic_store_n(&next[first + k1], x1, __ATOMIC_RELAXED);
+    const unsigned sm = s0 > s1 ? s0 : s1;
+    steps_max = sm > steps_max ? sm : steps_max;
+    steps_sum += s0 + s1;
   }
   if (bad) atomicOr(ctr + kCtrOverflow, 2ull);
   for (int o = 32; o > 0; o >>= 1) {
@@ -975,8 +1024,22 @@ __device__ __forceinline__ void decode_setup(Decode<C> &s, uint32_t gt,
                                              const Geo &g, const Tile &t) {
   const Seg sg = seg[gt];
   const uint32_t n = (uint32_t)sg.na + sg.nd;
-  for (uint32_t k = threadIdx.x; k < n; k += C::kThreads)
-    s.tab[k] = (int32_t)(R[sg.base + k] & ~kRoot);
+  // Four resolved exits per thread and round, their loads in flight
+  // together.
+  constexpr uint32_t E = 4;
+  for (uint32_t k0 = threadIdx.x; k0 < n; k0 += E * C::kThreads) {
+    uint32_t r[E];
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e) {
+      const uint32_t k = k0 + e * C::kThreads;
+      r[e] = k < n ? R[sg.base + k] : 0u;
+    }
+#pragma unroll
+    for (uint32_t e = 0; e < E; ++e) {
+      const uint32_t k = k0 + e * C::kThreads;
+      if (k < n) s.tab[k] = (int32_t)(r[e] & ~kRoot);
+    }
+  }
   for (uint32_t r = threadIdx.x; r < (uint32_t)(C::TY * C::TZ);
        r += C::kThreads)
     s.tab[Decode<C>::kRows + r] =
