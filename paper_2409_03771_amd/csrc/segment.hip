@@ -282,14 +282,11 @@ struct ExitOut {
 // chip and cost far more than the kernels' own work at one per wave.
 // tstat[4 * tile + k] summed per field into fctr[field][which]; a wave whose
 // tiles all belong to one field adds once.
-__global__ void __launch_bounds__(kBlock)
-k_tile_stat_reduce(const uint32_t *__restrict__ tstat, int k, uint32_t nt,
-                   const uint32_t *__restrict__ tfield,
-                   unsigned long long *fctr, int which) {
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  const bool in = i < nt;
-  const uint32_t v = in ? tstat[4 * (size_t)i + k] : 0u;
-  const uint32_t fi = in ? tfield[i] : 0u;
+// One tile counter per lane into its field's counter: summed over the wave
+// when the wave's tiles share a field, else per lane.
+__device__ __forceinline__ void fold_stat(bool in, uint32_t v, uint32_t fi,
+                                          unsigned long long *fctr,
+                                          int which) {
   const uint32_t f0 = __builtin_amdgcn_readlane(fi, 0);
   if (__ballot(in && fi != f0) == 0) {
     uint32_t sum = v;
@@ -300,6 +297,32 @@ k_tile_stat_reduce(const uint32_t *__restrict__ tstat, int k, uint32_t nt,
   } else if (in && v) {
     atomicAdd(fctr + (size_t)fi * kFieldCtrs + which, (unsigned long long)v);
   }
+}
+
+__global__ void __launch_bounds__(kBlock)
+k_tile_stat_reduce(const uint32_t *__restrict__ tstat, int k, uint32_t nt,
+                   const uint32_t *__restrict__ tfield,
+                   unsigned long long *fctr, int which) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  const bool in = i < nt;
+  const uint32_t v = in ? tstat[4 * (size_t)i + k] : 0u;
+  const uint32_t fi = in ? tfield[i] : 0u;
+  fold_stat(in, v, fi, fctr, which);
+}
+
+// Maxima, minima and exits of every tile in one pass (tile counters 0, 1
+// and 3).
+__global__ void __launch_bounds__(kBlock)
+k_tile_stats3(const uint32_t *__restrict__ tstat, uint32_t nt,
+              const uint32_t *__restrict__ tfield, unsigned long long *fctr) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  const bool in = i < nt;
+  const uint4 c = in ? reinterpret_cast<const uint4 *>(tstat)[i]
+                     : make_uint4(0u, 0u, 0u, 0u);
+  const uint32_t fi = in ? tfield[i] : 0u;
+  fold_stat(in, c.x, fi, fctr, kFMaxima);
+  fold_stat(in, c.y, fi, fctr, kFMinima);
+  fold_stat(in, c.w, fi, fctr, kFExits);
 }
 
 // Per-block (longest chain, links followed) of the exit resolution into the
@@ -1392,6 +1415,31 @@ k_fill_tfield(const FieldDev *__restrict__ fds, int nfields, uint32_t *tfield,
   tfield[i] = (uint32_t)lo;
 }
 
+// Everything a call clears or fills before its first pass, in one launch:
+// the counter block, the tile -> field map, the per-field counters, the
+// tile-order histogram with its min/max pair (min starts at ~0), and the
+// per-tile counters.
+__global__ void __launch_bounds__(kBlock)
+k_call_setup(const FieldDev *__restrict__ fds, int nfields, uint32_t nt,
+             unsigned long long *ctr, uint32_t *tfield,
+             unsigned long long *fctr, uint32_t *hist, uint32_t *tstat) {
+  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  if (i < (uint32_t)kNumCounters) ctr[i] = 0ull;
+  if (i < (uint32_t)nfields * kFieldCtrs) fctr[i] = 0ull;
+  if (i < (uint32_t)kTileBuckets + 2)
+    hist[i] = i == (uint32_t)kTileBuckets ? ~0u : 0u;
+  if (i < nt) {
+    int lo = 0, hi = nfields - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (fds[mid].tile0 <= i) lo = mid;
+      else hi = mid - 1;
+    }
+    tfield[i] = (uint32_t)lo;
+    reinterpret_cast<uint4 *>(tstat)[i] = make_uint4(0u, 0u, 0u, 0u);
+  }
+}
+
 // Table capacity of every field that wants cells, chosen on the device from
 // its extremum counts: the first capacity (`regrow` == 0), or, when the pair
 // pass overflowed (`regrow` != 0), the capacity that always suffices, with
@@ -1709,23 +1757,19 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
     MSC_HIP_TRY(hipMemcpyAsync(fds, st, fbytes, hipMemcpyHostToDevice, s));
     MSC_TRY(slot_copied(ctx, slot, s));
   }
-  MSC_TRY(clear_counters(ctx, s));
-  k_fill_tfield<<<grid_for(nt), kBlock, 0, s>>>(fds, nfields, tfield, nt);
-  k_fill_u64<<<grid_for((uint64_t)nfields * kFieldCtrs), kBlock, 0, s>>>(
-      fctr, (uint32_t)(nfields * kFieldCtrs), 0ull);
-  k_fill_u32<<<grid_for(kTileBuckets + 2), kBlock, 0, s>>>(
-      hist, kTileBuckets + 2, 0u);
-  k_fill_u32<<<1, kBlock, 0, s>>>(mm, 1, ~0u);
-  k_fill_u32<<<grid_for(4ull * nt), kBlock, 0, s>>>(tstat, 4 * nt, 0u);
+  {
+    const uint64_t span = std::max<uint64_t>(
+        std::max<uint64_t>(nt, (uint64_t)nfields * kFieldCtrs),
+        std::max<uint64_t>(kTileBuckets + 2, kNumCounters));
+    k_call_setup<<<grid_for(span), kBlock, 0, s>>>(fds, nfields, nt, ctr,
+                                                   tfield, fctr, hist, tstat);
+  }
   MSC_HIP_TRY(hipGetLastError());
   ExitOut xo{seg, tkey, tstat, tlist};
   MSC_PHASE(ctx, s, "tile_local", 12.0 * total_n,
             (k_tile_local<C><<<nt, C::kThreads, 0, s>>>(fds, tfield, xo, ctr,
                                                         fctr)));
-  const int kStat[3] = {kFMaxima, kFMinima, kFExits};
-  for (int k = 0; k < 3; ++k)
-    k_tile_stat_reduce<<<grid_for(nt), kBlock, 0, s>>>(
-        tstat, k == 2 ? 3 : k, nt, tfield, fctr, kStat[k]);
+  k_tile_stats3<<<grid_for(nt), kBlock, 0, s>>>(tstat, nt, tfield, fctr);
   // Exit slots are fixed per tile (2 * kHalo from the tile's own base), so
   // no count has to come back to the host before the graph is built.
   MSC_PHASE(ctx, s, "exit_link", 18.0 * nt * (double)C::kHalo * 0.5,
