@@ -195,10 +195,19 @@ __global__ void __launch_bounds__(kCThreads) k_cc_tile(CBatch<B> b) {
   const int64_t v0 = gx + g.X * gy + g.XY * t.z0;
   auto local = [](int x, int y, int z) { return x + CTX * (y + CTY * z); };
 
-  uint32_t m = 0;  // this column's mask bits
+  // This column's mask bits.  The loads are unconditional, at addresses
+  // kept inside the mask (a plane past the column, or a column past the
+  // grid, reads a vertex that exists), so that all of them are in flight
+  // together; the planes past the column are then dropped.
+  uint32_t m = 0;
+  {
+    const int64_t vb = col_in ? v0 : 0;
+    uint8_t mv[CTZ];
 #pragma unroll
-  for (int lz = 0; lz < CTZ; ++lz)
-    m |= (uint32_t)(lz < nz && mask[v0 + g.XY * lz]) << lz;
+    for (int lz = 0; lz < CTZ; ++lz) mv[lz] = mask[vb + g.XY * (lz < nz ? lz : 0)];
+#pragma unroll
+    for (int lz = 0; lz < CTZ; ++lz) m |= (uint32_t)(lz < nz && mv[lz] != 0) << lz;
+  }
   // The column's runs of consecutive masked z: every vertex of a run points
   // at the run's first vertex, which settles every -z edge of the tile.
 #pragma unroll
