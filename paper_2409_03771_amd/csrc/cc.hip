@@ -505,15 +505,23 @@ k_csr_init(int64_t n, const int64_t *__restrict__ rp,
       for (int64_t e0 = rp[v]; e0 < end; e0 += kEdgeChunk) {
         int64_t u[kEdgeChunk];
         bool ok[kEdgeChunk];
+        // Loads are unconditional, at indices kept in range (the chunk's
+        // first entry; the vertex itself), so that a chunk's loads of each
+        // kind are all issued before any is used.
 #pragma unroll
         for (int j = 0; j < kEdgeChunk; ++j) {
-          u[j] = e0 + j < end ? (int64_t)ci[e0 + j] : v;
+          const int64_t c = (int64_t)ci[e0 + j < end ? e0 + j : e0];
+          u[j] = e0 + j < end ? c : v;
           ok[j] = u[j] >= 0 && u[j] < n;
           bad |= !ok[j];
         }
+        uint8_t mu[kEdgeChunk];
 #pragma unroll
         for (int j = 0; j < kEdgeChunk; ++j)
-          if (ok[j] && (!mask || mask[u[j]])) best = u[j] < best ? u[j] : best;
+          mu[j] = mask ? mask[ok[j] ? u[j] : v] : (uint8_t)1;
+#pragma unroll
+        for (int j = 0; j < kEdgeChunk; ++j)
+          if (ok[j] && mu[j]) best = u[j] < best ? u[j] : best;
       }
       L[v] = best;
     }
@@ -548,16 +556,25 @@ k_csr_union(int64_t n, const int64_t *__restrict__ rp,
   const int64_t end = rp[v + 1];
   for (int64_t e0 = rp[v]; e0 < end; e0 += kEdgeChunk) {
     int64_t u[kEdgeChunk], lu[kEdgeChunk];
+    // Unconditional loads at in-range indices, each kind issued for the
+    // whole chunk before any is used (the init pass has checked every index).
 #pragma unroll
     for (int j = 0; j < kEdgeChunk; ++j) {
-      u[j] = e0 + j < end ? (int64_t)ci[e0 + j] : v;
-      if (u[j] != v && mask && !mask[u[j]]) u[j] = v;
+      const int64_t c = (int64_t)ci[e0 + j < end ? e0 + j : e0];
+      u[j] = e0 + j < end ? c : v;
+    }
+    if (mask) {
+      uint8_t mu[kEdgeChunk];
+#pragma unroll
+      for (int j = 0; j < kEdgeChunk; ++j) mu[j] = mask[u[j]];
+#pragma unroll
+      for (int j = 0; j < kEdgeChunk; ++j)
+        if (!mu[j]) u[j] = v;
     }
 #pragma unroll
     for (int j = 0; j < kEdgeChunk; ++j)
-      lu[j] = u[j] == v ? lv
-                        : __hip_atomic_load(&L[u[j]], __ATOMIC_RELAXED,
-                                            __HIP_MEMORY_SCOPE_WORKGROUP);
+      lu[j] = __hip_atomic_load(&L[u[j]], __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
     for (int j = 0; j < kEdgeChunk; ++j)
       if (lu[j] != lv) uf_unite<int64_t>(L, v, u[j]);

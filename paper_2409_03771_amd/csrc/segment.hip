@@ -2130,6 +2130,21 @@ __device__ __forceinline__ RankCol rank_col(uint32_t X, uint32_t Y,
   return c;
 }
 
+// A rank tile column's final labels, every load issued before any is used
+// (unconditional: a plane past the column, or a column past the grid, reads
+// vertex 0's labels, which are then ignored).
+__device__ __forceinline__ void rank_col_labels(
+    const RankCol &c, uint32_t XY, const int32_t *__restrict__ asc,
+    const int32_t *__restrict__ desc, int32_t (&a)[kRankTZ],
+    int32_t (&d)[kRankTZ]) {
+#pragma unroll
+  for (uint32_t lz = 0; lz < kRankTZ; ++lz) {
+    const uint32_t v = lz < c.nz ? c.col + XY * (c.z0 + lz) : 0u;
+    a[lz] = asc[v];
+    d[lz] = desc[v];
+  }
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_rank_tile_pairs(uint32_t X, uint32_t Y, uint32_t Z,
                   const int32_t *__restrict__ asc,
@@ -2151,11 +2166,13 @@ k_rank_tile_pairs(uint32_t X, uint32_t Y, uint32_t Z,
   bool overflow = false;
   const bool first_lane = (tid & 63) == 0;
   unsigned long long last = kEmptyKey;
+  int32_t la[kRankTZ], ld[kRankTZ];
+  rank_col_labels(c, XY, asc, desc, la, ld);
 #pragma unroll
   for (uint32_t lz = 0; lz < kRankTZ; ++lz) {
     unsigned long long key = kEmptyKey;
     const uint32_t v = c.col + XY * (c.z0 + lz);
-    if (lz < c.nz) key = pair_key(asc[v], desc[v]);
+    if (lz < c.nz) key = pair_key(la[lz], ld[lz]);
     const unsigned long long left = __shfl_up(key, 1);
     const bool repeat = key == last || (!first_lane && key == left);
     last = key;
@@ -2202,12 +2219,14 @@ k_rank_tile_ms(uint32_t X, uint32_t Y, uint32_t Z,
   int last_slot = -1;
   int32_t last_cell = -1;
   uint32_t own = 0;
+  int32_t la[kRankTZ], ld[kRankTZ];
+  rank_col_labels(c, XY, asc, desc, la, ld);
 #pragma unroll
   for (uint32_t lz = 0; lz < kRankTZ; ++lz) {
     slot[lz] = -1;
     if (lz < c.nz) {
       const uint32_t v = c.col + XY * (c.z0 + lz);
-      const unsigned long long key = pair_key(asc[v], desc[v]);
+      const unsigned long long key = pair_key(la[lz], ld[lz]);
       if (key != last) {
         last = key;
         last_slot = pair_slot(skey, &sfill, key);
@@ -2399,16 +2418,18 @@ k_csr_steepest(int64_t n, int64_t nnz, const int64_t *__restrict__ rp,
     for (; e0 < e1; e0 += kRowChunk) {
       int32_t u[kRowChunk];
       float fu[kRowChunk];
+      // Unconditional loads at in-range indices (the chunk's first entry;
+      // the vertex itself), each kind issued for the whole chunk first.
 #pragma unroll
       for (int k = 0; k < kRowChunk; ++k) {
-        u[k] = e0 + k < e1 ? col[e0 + k] : -1;
+        const int32_t c = col[e0 + k < e1 ? e0 + k : e0];
+        u[k] = e0 + k < e1 ? c : -1;
         const bool ok = u[k] >= 0 && (int64_t)u[k] < n;
         bad |= e0 + k < e1 && !ok;
         if (!ok) u[k] = -1;
       }
 #pragma unroll
-      for (int k = 0; k < kRowChunk; ++k)
-        fu[k] = u[k] >= 0 ? f[u[k]] : 0.f;
+      for (int k = 0; k < kRowChunk; ++k) fu[k] = f[u[k] >= 0 ? u[k] : v];
 #pragma unroll
       for (int k = 0; k < kRowChunk; ++k) {
         if (u[k] < 0) continue;
