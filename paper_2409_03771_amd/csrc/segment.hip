@@ -53,13 +53,13 @@ struct Cfg {
   static constexpr int H = HXY * HZ;          // tile plus halo
   static constexpr int TXY = TX * TY;
   static constexpr int kThreads = TX * TY;    // one thread per z-column
-  static constexpr int kWords = (H + 31) / 32;
   static constexpr int kHalo = H - TX * TY * TZ;
   // The in-LDS pointers are 16-bit byte addresses: 4 * (target index) for
   // ascent, 4 * (target index) + 2 for descent.
   static_assert(4 * (H - 1) + 2 <= 0xffff, "tile-local pointers are 16-bit");
   static_assert(kThreads % 64 == 0 && kThreads <= 1024, "block shape");
-  static_assert(H % 4 == 0, "exit entries are taken four at a time");
+  static_assert((kHalo + kThreads - 1) / kThreads * (kThreads / 64) <= 64,
+                "one wave scans the exit counts");
   static_assert(TX * TY * TZ <= 0x8000 && kHalo < 0x8000,
                 "local pointer codes are 15-bit");
 };
@@ -137,6 +137,36 @@ __device__ __forceinline__ uint32_t halo_global(const Geo &g, const Tile &t,
   int hz = p / C::HXY, r = p - hz * C::HXY, hy = r / C::HX, hx = r - hy * C::HX;
   return (uint32_t)(t.x0 - 1 + hx) + g.X * (uint32_t)(t.y0 - 1 + hy) +
          g.XY * (uint32_t)(t.z0 - 1 + hz);
+}
+
+// Tile-plus-halo index of halo entry i, 0 <= i < kHalo, enumerating the
+// halo in increasing index: the bottom plane, then each middle plane's ring
+// (its first row, the two ends of every inner row, its last row), then the
+// top plane.
+template <class C>
+__device__ __forceinline__ int halo_index(int i) {
+  constexpr uint32_t R = 2 * C::HX + 2 * (C::HY - 2);  // ring of a plane
+  constexpr uint32_t B = C::HXY, M = B + (C::HZ - 2) * R;
+  const uint32_t u = (uint32_t)i;
+  if (u < B) return i;
+  if (u >= M) return (int)((C::HZ - 1) * C::HXY + (u - M));
+  const uint32_t r = u - B, pl = r / R, k = r - pl * R;
+  uint32_t q;
+  if (k < (uint32_t)C::HX) {
+    q = k;
+  } else if (k >= R - C::HX) {
+    q = (C::HY - 1) * C::HX + (k - (R - C::HX));
+  } else {
+    const uint32_t k2 = k - C::HX;
+    q = (1 + (k2 >> 1)) * C::HX + ((k2 & 1u) ? C::HX - 1 : 0);
+  }
+  return (int)((pl + 1) * C::HXY + q);
+}
+
+// Number of lanes below this one whose bit is set in a wave-wide mask.
+__device__ __forceinline__ uint32_t lanes_below(unsigned long long m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
 // Stored tile-local pointers are 16-bit codes: an owned target is
@@ -378,12 +408,10 @@ k_tile_local(const FieldDev *__restrict__ fds,
   // read is the next pointer of the same direction.
   __shared__ uint32_t lds[H];
   char *const lb = reinterpret_cast<char *>(lds);
-  // Exit bitsets over p (ascent, descent) and their word prefixes
-  // (ascent | descent << 16).
-  // The bitsets are stored 64 bits at a time (padded to an even count).
-  __shared__ __align__(8) uint32_t xa[C::kWords + 1], xd[C::kWords + 1];
-  __shared__ uint32_t pre[C::kWords];
-  __shared__ uint32_t scan_tmp[32];
+  // Marked halo entries per (round, wave) of the exit numbering, then
+  // their exclusive prefixes and the total (ascent | descent << 16).
+  __shared__ uint32_t s_cnt[(C::kHalo + C::kThreads - 1) / C::kThreads *
+                                (C::kThreads / 64) + 1];
   __shared__ float s_wsum[16];
   __shared__ uint32_t s_wext[16];  // per wave: maxima | minima << 16
 
@@ -694,89 +722,64 @@ k_tile_local(const FieldDev *__restrict__ fds,
   }
   __syncthreads();
 
-  // Marks to bitsets: the 64 lanes of a wave test 64 consecutive entries,
-  // so one ballot is two bitset words, stored by one lane as a 64-bit word.
-  {
-    constexpr int KB = (H + T - 1) / T;
-    const bool lane0 = (tid & 63) == 0;
-    const uint32_t w0 = (uint32_t)(tid >> 6) * 2u;  // wave-uniform
+  // Marked halves become exit codes.  Only halo entries can hold the mark,
+  // so only the halo is walked: halo entry i (halo_index, increasing in p)
+  // goes to thread i % T in round i / T.  Exits are numbered per direction
+  // in increasing p; that is the order of (round, wave, lane), so a marked
+  // entry's number is the count of marked entries of earlier (round, wave)
+  // pairs, scanned once, plus the marked lanes below it in its wave.
+  constexpr int KH = (C::kHalo + T - 1) / T, NW = T / 64;
+  const int lane = tid & 63, wv = tid >> 6;
+  int hp[KH];
+  bool am[KH], dm[KH];
+  unsigned long long bma[KH], bmd[KH];
 #pragma unroll
-    for (int k = 0; k < KB; ++k) {
-      const int p = tid + k * T;
-      const bool ok = (k + 1) * T <= H || p < H;
-      const uint32_t e = ok ? lds[p] : 0u;
-      const unsigned long long ma = __ballot(ok && (e & 0xffffu) == kMark);
-      const unsigned long long md = __ballot(ok && (e >> 16) == kMark);
-      const uint32_t w = w0 + (uint32_t)(k * (T / 32));
-      if (lane0 && w < (uint32_t)C::kWords) {
-        *reinterpret_cast<unsigned long long *>(xa + w) = ma;
-        *reinterpret_cast<unsigned long long *>(xd + w) = md;
-      }
-    }
+  for (int k = 0; k < KH; ++k) {
+    const int i = tid + k * T;
+    const bool ok = (k + 1) * T <= C::kHalo || i < C::kHalo;
+    hp[k] = halo_index<C>(ok ? i : 0);
+    const uint32_t e = lds[hp[k]];
+    am[k] = ok && (e & 0xffffu) == kMark;
+    dm[k] = ok && (e >> 16) == kMark;
+    bma[k] = __ballot(am[k]);
+    bmd[k] = __ballot(dm[k]);
+    if (lane == 0)
+      s_cnt[k * NW + wv] = (uint32_t)__popcll(bma[k]) |
+                           ((uint32_t)__popcll(bmd[k]) << 16);
   }
   __syncthreads();
-
-  // Exits are numbered per direction in increasing index.  Thread tid owns
-  // the consecutive words tid*W .. tid*W+W-1; one scan of packed counts
-  // (ascent | descent << 16, each below 2^16) serves both.
-  constexpr int W = (C::kWords + T - 1) / T;
-  uint32_t tot = 0;
-  {
-    uint32_t wa[W], wd[W];
-    uint32_t cnt = 0;
+  if (tid < 64) {  // exclusive scan of the (round, wave) counts
+    const uint32_t x = tid < KH * NW ? s_cnt[tid] : 0u;
+    uint32_t inc = x;
 #pragma unroll
-    for (int j = 0; j < W; ++j) {
-      const int w = tid * W + j;
-      wa[j] = w < C::kWords ? xa[w] : 0u;
-      wd[j] = w < C::kWords ? xd[w] : 0u;
-      cnt += __popc(wa[j]) | ((uint32_t)__popc(wd[j]) << 16);
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(inc, o);
+      if (lane >= o) inc += y;
     }
-    uint32_t run = block_exclusive_scan(cnt, scan_tmp, &tot);
-#pragma unroll
-    for (int j = 0; j < W; ++j) {
-      const int w = tid * W + j;
-      if (w < C::kWords) pre[w] = run;
-      run += __popc(wa[j]) | ((uint32_t)__popc(wd[j]) << 16);
-    }
+    if (tid < KH * NW) s_cnt[tid] = inc - x;
+    if (tid == 63) s_cnt[KH * NW] = inc;
   }
+  __syncthreads();
+  const uint32_t tot = s_cnt[KH * NW];
   const uint32_t na = tot & 0xffffu, nd = tot >> 16;
-  __syncthreads();
-
-  // Each marked entry becomes its exit code (bit 15 and the exit's number
-  // in its direction), and the tile's exit list gets its index (ascent
-  // exits first, then descent).  Thread q takes indices 4q .. 4q+3 (a nibble
-  // of bitset word q / 8) and reads its words and prefixes first.
   {
-    constexpr int Q = H / 4, KQ = (Q + T - 1) / T;
-    const uint32_t sh = 4u * (uint32_t)(tid & 7);
+    // Every halo entry's word gets both codes: a half that is nobody's
+    // target is never read again.  The list gets each exit's index; the
+    // stores of unmarked halves go to slot na + nd, which no exit uses (an
+    // unmarked half means fewer than 2 * kHalo exits) and nothing reads.
     uint16_t *tl = xo.tlist + (size_t)bt.gt * (2 * C::kHalo);
-    const uint32_t below_mask = (1u << sh) - 1u;
-    uint32_t ba[KQ], bd[KQ], bp[KQ];
+    const uint32_t trash = na + nd;
 #pragma unroll
-    for (int k = 0; k < KQ; ++k) {
-      const int q = tid + k * T;
-      ba[k] = q < Q ? xa[q >> 3] : 0u;
-      bd[k] = q < Q ? xd[q >> 3] : 0u;
-      bp[k] = q < Q ? pre[q >> 3] : 0u;
-    }
-#pragma unroll
-    for (int k = 0; k < KQ; ++k) {
-      const uint32_t p0 = 4u * (uint32_t)(tid + k * T);
-      uint32_t ra = (bp[k] & 0xffffu) + __popc(ba[k] & below_mask);
-      uint32_t rd = (bp[k] >> 16) + __popc(bd[k] & below_mask);
-      const uint32_t ma = (ba[k] >> sh) & 0xfu, md = (bd[k] >> sh) & 0xfu;
-      if (ma | md) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          if ((ma >> j) & 1u) {
-            st16(lb, 4u * (p0 + j), kExitCode | ra);
-            tl[ra++] = (uint16_t)(p0 + j);
-          }
-          if ((md >> j) & 1u) {
-            st16(lb, 4u * (p0 + j) + 2u, kExitCode | rd);
-            tl[na + rd++] = (uint16_t)(p0 + j);
-          }
-        }
+    for (int k = 0; k < KH; ++k) {
+      const int i = tid + k * T;
+      const bool ok = (k + 1) * T <= C::kHalo || i < C::kHalo;
+      const uint32_t base = s_cnt[k * NW + wv];
+      const uint32_t ra = (base & 0xffffu) + lanes_below(bma[k]);
+      const uint32_t rd = (base >> 16) + lanes_below(bmd[k]);
+      if (ok) {
+        lds[hp[k]] = (kExitCode | ra) | ((kExitCode | rd) << 16);
+        tl[am[k] ? ra : trash] = (uint16_t)hp[k];
+        tl[dm[k] ? na + rd : trash] = (uint16_t)hp[k];
       }
     }
   }
