@@ -578,12 +578,14 @@ k_tile_local(const FieldDev *__restrict__ fds,
     if (prev.lmin.v <= mn.v) mn = Best{prev.lmin.v, prev.lmin.o - 4 * HXY};
     if (next.umax.v >= mx.v) mx = Best{next.umax.v, next.umax.o + 4 * HXY};
     if (next.umin.v < mn.v) mn = Best{next.umin.v, next.umin.o + 4 * HXY};
-    const bool in = lz < nz;
     const uint32_t self = 4u * (uint32_t)(c0 + P * HXY);
     ka[lz % kFlush] = self + (uint32_t)mx.o;
     kd[lz % kFlush] = self + (uint32_t)mn.o + 2u;
-    nmax += __popcll(__builtin_amdgcn_ballot_w64(in && mx.o == 0));
-    nmin += __popcll(__builtin_amdgcn_ballot_w64(in && mn.o == 0));
+    // Each test is one compare into a lane mask, restricted to the
+    // columns that reach this plane.
+    const unsigned long long inm = __builtin_amdgcn_ballot_w64(lz < nz);
+    nmax += __popcll(__builtin_amdgcn_ballot_w64(mx.o == 0) & inm);
+    nmin += __popcll(__builtin_amdgcn_ballot_w64(mn.o == 0) & inm);
     prev = cur;
     cur = next;
     if (lz % kFlush == kFlush - 1) {
@@ -1108,10 +1110,12 @@ constexpr uint32_t kTableProbes = 512;
 
 // Insert (key, id) keeping the smallest id; reads before each atomic so that
 // the common case (key present with a smaller id) stays a plain load.
+// *at gets the key's slot when given.
 __device__ __forceinline__ bool table_insert(unsigned long long *keys,
                                              int32_t *vals, uint32_t mask,
                                              unsigned long long key,
-                                             int32_t id, unsigned *fresh) {
+                                             int32_t id, unsigned *fresh,
+                                             uint32_t *at = nullptr) {
   uint32_t h = (uint32_t)mix64(key) & mask;
 #pragma unroll 1
   for (uint32_t probe = 0; probe <= mask && probe < kTableProbes; ++probe) {
@@ -1126,6 +1130,7 @@ __device__ __forceinline__ bool table_insert(unsigned long long *keys,
     if (cur == key) {
       if (__atomic_load_n(&vals[h], __ATOMIC_RELAXED) > id)
         atomicMin(&vals[h], id);
+      if (at) *at = h;
       return true;
     }
     h = (h + 1) & mask;
@@ -1152,9 +1157,12 @@ constexpr int kPairSlots = 1024;
 constexpr unsigned kPairLimit = kPairSlots / 2;
 constexpr int kPairProbes = 16;
 
+// A pair's first claim takes the next dense number (the fill count before
+// it) into dense[slot], when given.
 __device__ __forceinline__ int pair_slot(unsigned long long *skey,
                                          unsigned *fill,
-                                         unsigned long long key) {
+                                         unsigned long long key,
+                                         uint16_t *dense = nullptr) {
   // The slot is local to the tile, so a multiply-free hash of the two
   // labels serves (the global table keeps its 64-bit mix).
   const uint32_t a = (uint32_t)(key >> 32), d = (uint32_t)key;
@@ -1166,7 +1174,8 @@ __device__ __forceinline__ int pair_slot(unsigned long long *skey,
       if (*fill >= kPairLimit) return -1;
       cur = atomicCAS(&skey[h], kEmptyKey, key);
       if (cur == kEmptyKey) {
-        atomicAdd(fill, 1u);
+        const unsigned k = atomicAdd(fill, 1u);
+        if (dense) dense[h] = (uint16_t)k;
         return (int)h;
       }
     }
@@ -1190,16 +1199,40 @@ __device__ __forceinline__ int32_t table_lookup(
   return -1;
 }
 
+// A tile whose vertices carry at most kCellIdx distinct pairs gets one byte
+// per vertex, the pair's dense number within the tile (tile-major, four
+// planes per word), and a record in its exit-list slots, which nothing reads
+// once the exits are linked: the number of pairs, then the slot of each in
+// the field's table.  The output pass then reads that byte instead of the
+// codes and needs no decoding; a tile with one pair needs no bytes at all.
+// Record 0 marks a tile that kept the per-vertex path.
+constexpr unsigned kCellIdx = 255;
+
+template <class C>
+__device__ __forceinline__ uint32_t *cell_record(uint16_t *tlist,
+                                                 uint32_t gt) {
+  static_assert(kCellIdx + 1 <= (unsigned)C::kHalo, "record fits the slots");
+  return reinterpret_cast<uint32_t *>(tlist + (size_t)gt * (2 * C::kHalo));
+}
+
+template <class C>
+__device__ __forceinline__ size_t cell_word(uint32_t gt, int j, int tid) {
+  return ((size_t)gt * (C::TZ / 4) + (size_t)j) * C::kThreads + (size_t)tid;
+}
+
 template <class C>
 __global__ void __launch_bounds__(C::kThreads)
 k_tile_pairs(const FieldDev *__restrict__ fds,
              const uint32_t *__restrict__ tfield, const Seg *__restrict__ seg,
              const uint32_t *__restrict__ R, unsigned long long *ctr,
-             uint32_t *tstat, uint32_t ntiles, const uint32_t *run) {
+             uint32_t *tstat, uint32_t ntiles, const uint32_t *run,
+             uint16_t *tlist, uint32_t *cidx) {
+  static_assert(C::TZ % 4 == 0, "four planes per index word");
   __shared__ Decode<C> s;
   __shared__ uint32_t s_fresh[C::kThreads / 64];
   __shared__ unsigned long long skey[kPairSlots];
   __shared__ int32_t sval[kPairSlots];
+  __shared__ uint16_t sdense[kPairSlots];
   __shared__ unsigned sfill;
   const int tid = threadIdx.x;
   // The second pass (after an overflow) runs only when *run is set, over a
@@ -1229,19 +1262,22 @@ k_tile_pairs(const FieldDev *__restrict__ fds,
     decode_setup<C>(s, bt.gt, seg, R, g, t);
 
     unsigned fresh = 0;
-    bool overflow = false;
-    // Only the smallest id of each pair matters.  A vertex whose pair equals
-    // that of the vertex below it (previous z of the column) or of the lane
-    // before it (a smaller id in the same plane) is not that smallest id and
-    // needs nothing; the smallest one matches neither, so it is never skipped.
-    // In smooth regions this leaves few lanes per plane, and most waves skip
-    // the insert altogether.
+    bool overflow = false, lost = false;
+    // Every run of equal pairs down a column finds its slot in the tile's
+    // table (two 16-bit slots per word).  Only the smallest id of each pair
+    // matters: a vertex whose pair equals that of the vertex below it
+    // (previous z of the column) or of the lane before it (a smaller id in
+    // the same plane) is not that smallest id and inserts nothing; the
+    // smallest one matches neither, so it is never skipped.
     const bool first_lane = (tid & 63) == 0;
     unsigned long long last = kEmptyKey;
+    int last_slot = -1;
+    uint32_t sp[C::TZ / 2];
   #pragma unroll
     for (int lz = 0; lz < C::TZ; ++lz) {
+      const bool in = lz < nz;
       unsigned long long key = kEmptyKey;
-      if (lz < nz) {
+      if (in) {
         // The final labels are written here, where the pass is bound by its
         // arithmetic and the stores overlap it; the output pass then writes
         // only the cell ids.
@@ -1251,25 +1287,53 @@ k_tile_pairs(const FieldDev *__restrict__ fds,
         plane_ptr(bt.fd.D, g, t.z0 + lz)[col] = d;
         key = pair_key(a, d);
       }
+      if (in && key != last) {
+        last_slot = pair_slot(skey, &sfill, key, sdense);
+        lost |= last_slot < 0;
+      }
       const unsigned long long left = __shfl_up(key, 1);
       const bool repeat = key == last || (!first_lane && key == left);
       last = key;
-      if (!repeat && key != kEmptyKey) {
+      const uint32_t s16 = (uint32_t)last_slot & 0xffffu;
+      sp[lz / 2] = (lz & 1) ? (sp[lz / 2] | (s16 << 16)) : s16;
+      if (!repeat && in) {
         const int32_t id = (int32_t)(col + g.XY * (uint32_t)(t.z0 + lz));
-        const int slot = pair_slot(skey, &sfill, key);
-        if (slot >= 0)
-          atomicMin(&sval[slot], id);
+        if (last_slot >= 0)
+          atomicMin(&sval[last_slot], id);
         else if (!table_insert(bt.fd.keys, bt.fd.vals, bt.fd.mask, key, id,
                                &fresh))
           overflow = true;
       }
     }
-    __syncthreads();
+    // Block-uniform from here: the tile keeps the byte path when every
+    // vertex found a slot and few enough pairs were claimed.
+    const bool any_lost = __syncthreads_or(lost);
+    const unsigned n = sfill;
+    const bool indexed = !any_lost && n <= kCellIdx;
+    uint32_t *rec = cell_record<C>(tlist, bt.gt);
     for (int i = tid; i < kPairSlots; i += C::kThreads) {
-      if (skey[i] != kEmptyKey &&
-          !table_insert(bt.fd.keys, bt.fd.vals, bt.fd.mask, skey[i], sval[i],
-                        &fresh))
-        overflow = true;
+      if (skey[i] != kEmptyKey) {
+        uint32_t at = 0;
+        if (!table_insert(bt.fd.keys, bt.fd.vals, bt.fd.mask, skey[i], sval[i],
+                          &fresh, &at))
+          overflow = true;
+        else if (indexed)
+          rec[1 + sdense[i]] = at;
+      }
+    }
+    if (tid == 0) rec[0] = indexed ? n : 0u;
+    if (indexed && n > 1) {
+  #pragma unroll
+      for (int j = 0; j < C::TZ / 4; ++j) {
+        uint32_t w = 0;
+  #pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int lz = 4 * j + b;
+          const uint32_t sl = (sp[lz / 2] >> (16 * (lz & 1))) & 0xffffu;
+          if (lz < nz) w |= (uint32_t)sdense[sl] << (8 * b);
+        }
+        cidx[cell_word<C>(bt.gt, j, tid)] = w;
+      }
     }
     // New pairs this tile inserted: summed per tile, folded per field later.
     for (int o = 32; o > 0; o >>= 1) fresh += __shfl_xor(fresh, o);
@@ -1289,7 +1353,8 @@ template <class C>
 __global__ void __launch_bounds__(C::kThreads)
 k_tile_write(const FieldDev *__restrict__ fds,
              const uint32_t *__restrict__ tfield, const Seg *__restrict__ seg,
-             const uint32_t *__restrict__ R) {
+             const uint32_t *__restrict__ R, uint16_t *tlist,
+             const uint32_t *__restrict__ cidx) {
   __shared__ Decode<C> s;
   __shared__ unsigned long long skey[kPairSlots];
   __shared__ int32_t scell[kPairSlots];
@@ -1301,15 +1366,33 @@ k_tile_write(const FieldDev *__restrict__ fds,
   int32_t *__restrict__ D = bt.fd.D;
   int32_t *__restrict__ ms = bt.fd.ms;
   const Tile t = tile_at<C>(g, bt.tile);
-  if (ms)
-    for (int i = tid; i < kPairSlots; i += C::kThreads) skey[i] = kEmptyKey;
-  if (tid == 0) sfill = 0;
   const int cx = tid % C::TX, cy = tid / C::TX;
   const int gx = t.x0 + cx, gy = t.y0 + cy;
   const bool col_in = gx < (int)g.X && gy < (int)g.Y;
   int nz = (int)g.Z - t.z0;
   nz = col_in ? (nz < C::TZ ? nz : C::TZ) : 0;
   const uint32_t col = (uint32_t)gx + g.X * (uint32_t)gy;
+  if (ms) {  // uniform over the block: ms belongs to the field
+    const uint32_t *rec = cell_record<C>(tlist, bt.gt);
+    const uint32_t n = __builtin_amdgcn_readfirstlane(rec[0]);
+    if (n > 0) {  // the byte path: each vertex's pair number in the tile
+      for (uint32_t k = tid; k < n; k += C::kThreads)
+        scell[k] = bt.fd.vals[rec[1 + k]];
+      uint32_t w[C::TZ / 4];
+#pragma unroll
+      for (int j = 0; j < C::TZ / 4; ++j)
+        w[j] = n > 1 ? cidx[cell_word<C>(bt.gt, j, tid)] : 0u;
+      __syncthreads();
+#pragma unroll
+      for (int lz = 0; lz < C::TZ; ++lz)
+        if (lz < nz)
+          plane_ptr(ms, g, t.z0 + lz)[col] =
+              scell[(w[lz / 4] >> (8 * (lz % 4))) & 0xffu];
+      return;
+    }
+    for (int i = tid; i < kPairSlots; i += C::kThreads) skey[i] = kEmptyKey;
+  }
+  if (tid == 0) sfill = 0;
   uint32_t code[C::TZ];
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz)
@@ -1691,7 +1774,9 @@ int plan_batch(int nfields, const msc_field *fields, BatchPlan &p) {
       align256(4ull * nt * sizeof(uint32_t)) +
       align256(4ull * nt * sizeof(unsigned long long)) +
       align256(2ull * C::kHalo * nt * sizeof(uint16_t)) + 8192 +
-      (p.any_ms ? align256(p.tab_slots * 8) + align256(p.tab_slots * 4) : 0);
+      (p.any_ms ? align256(p.tab_slots * 8) + align256(p.tab_slots * 4) +
+                      align256((size_t)nt * C::TX * C::TY * C::TZ)
+                : 0);
   return MSC_OK;
 }
 
@@ -1748,6 +1833,9 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
   unsigned long long *rstat = cv.take<unsigned long long>(4ull * nt);
   uint16_t *tlist = cv.take<uint16_t>(2ull * C::kHalo * nt);
   uint32_t *run = cv.take<uint32_t>(1);
+  uint32_t *cidx = any_ms ? cv.take<uint32_t>((size_t)nt * C::kThreads *
+                                               (C::TZ / 4))
+                          : nullptr;
 
   // The descriptors go up through a pinned slot; the tile -> field map is
   // built on the device.
@@ -1799,22 +1887,23 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
                                       ctx->table_first, 0, run);
     MSC_PHASE(ctx, s, "table_clear", 12.0 * total_n,
               (k_table_clear_all<<<cb, kBlock, 0, s>>>(fds, nfields, run)));
-    MSC_PHASE(ctx, s, "tile_pairs", 12.0 * total_n,
+    MSC_PHASE(ctx, s, "tile_pairs", 13.0 * total_n,
               (k_tile_pairs<C><<<nt, C::kThreads, 0, s>>>(
-                  fds, tfield, seg, next, ctr, tstat, nt, nullptr)));
+                  fds, tfield, seg, next, ctr, tstat, nt, nullptr, tlist,
+                  cidx)));
     k_table_plan<<<1, kBlock, 0, s>>>(fds, nfields, fctr, ctr,
                                       ctx->table_first, 1, run);
     k_table_clear_all<<<cb, kBlock, 0, s>>>(fds, nfields, run);
     const unsigned rb = nt < 4096u ? nt : 4096u;
     k_tile_pairs<C><<<rb, C::kThreads, 0, s>>>(fds, tfield, seg, next, ctr,
-                                               tstat, nt, run);
+                                               tstat, nt, run, tlist, cidx);
     MSC_HIP_TRY(hipGetLastError());
     k_tile_stat_reduce<<<grid_for(nt), kBlock, 0, s>>>(tstat, 2, nt, tfield,
                                                        fctr, kFCells);
   }
-  MSC_PHASE(ctx, s, "tile_write", (any_ms ? 8.0 : 12.0) * total_n,
+  MSC_PHASE(ctx, s, "tile_write", (any_ms ? 5.0 : 12.0) * total_n,
             (k_tile_write<C><<<nt, C::kThreads, 0, s>>>(fds, tfield, seg,
-                                                        next)));
+                                                        next, tlist, cidx)));
   // Counters back to the record's pinned memory, for the stats calls.
   CallRec &R = ctx->calls[rec];
   MSC_HIP_TRY(hipMemcpyAsync(R.hfctr, fctr, (size_t)nfields * kFieldCtrs * 8,
