@@ -123,6 +123,16 @@ __device__ __forceinline__ __attribute__((address_space(1))) T *plane_ptr(
   return (__attribute__((address_space(1))) T *)p + (size_t)g.XY * (uint32_t)z;
 }
 
+// A tile's codes of its first (side 0) and last (side 1) x column, side by
+// side in one array: the x-face exits of its x-neighbours read them from
+// there, consecutive exits from consecutive words, where a gather from the
+// field-ordered codes would fetch a whole row for each.
+template <class C>
+__device__ __forceinline__ size_t shell_word(uint32_t gt, uint32_t side,
+                                             uint32_t lz, uint32_t ly) {
+  return (((size_t)gt * 2 + side) * C::TZ + lz) * C::TY + ly;
+}
+
 template <class C>
 __device__ __forceinline__ Tile tile_at(const Geo &g, uint32_t t) {
   uint32_t tx = t % g.ntx, r = t / g.ntx;
@@ -305,6 +315,8 @@ struct ExitOut {
   uint32_t *tstat;     // per global tile: maxima, minima, cells, exits
   uint16_t *tlist;     // per global tile, 2*kHalo slots: halo index of each
                        // exit, ascent exits first (numbers are tile-local)
+  uint32_t *xs;        // per global tile: the codes of its first and last
+                       // x columns (shell_word)
 };
 
 // Counters are summed per block and written per tile, then folded by these
@@ -731,6 +743,10 @@ k_tile_local(const FieldDev *__restrict__ fds,
   // entry's number is the count of marked entries of earlier (round, wave)
   // pairs, scanned once, plus the marked lanes below it in its wave.
   constexpr int KH = (C::kHalo + T - 1) / T, NW = T / 64;
+  // Up to six rounds keep their halo indices and marks in registers for the
+  // second loop; more would spill, so those are taken again (each entry
+  // belongs to one thread, which reads it before rewriting it).
+  constexpr bool kKeep = KH <= 6;
   const int lane = tid & 63, wv = tid >> 6;
   int hp[KH];
   bool am[KH], dm[KH];
@@ -779,9 +795,17 @@ k_tile_local(const FieldDev *__restrict__ fds,
       const uint32_t ra = (base & 0xffffu) + lanes_below(bma[k]);
       const uint32_t rd = (base >> 16) + lanes_below(bmd[k]);
       if (ok) {
-        lds[hp[k]] = (kExitCode | ra) | ((kExitCode | rd) << 16);
-        tl[am[k] ? ra : trash] = (uint16_t)hp[k];
-        tl[dm[k] ? na + rd : trash] = (uint16_t)hp[k];
+        int p = hp[k];
+        bool ah = am[k], dh = dm[k];
+        if (!kKeep) {
+          p = halo_index<C>(i);
+          const uint32_t e = lds[p];
+          ah = (e & 0xffffu) == kMark;
+          dh = (e >> 16) == kMark;
+        }
+        lds[p] = (kExitCode | ra) | ((kExitCode | rd) << 16);
+        tl[ah ? ra : trash] = (uint16_t)p;
+        tl[dh ? na + rd : trash] = (uint16_t)p;
       }
     }
   }
@@ -791,11 +815,26 @@ k_tile_local(const FieldDev *__restrict__ fds,
   // owned target by its owned index, an exit by its number (bit 15 set), so
   // that later passes decode it with one lookup in the tile's resolved exits.
   const uint32_t col = (uint32_t)gx + g.X * (uint32_t)gy;
+  // The first and last columns also go to the tile's shell copy (a
+  // block-uniform base and a 32-bit offset per lane).
+  const bool xedge = cx == 0 || cx == C::TX - 1;
+  __attribute__((address_space(1))) uint32_t *const xsb =
+      (__attribute__((address_space(1))) uint32_t *)xo.xs +
+      shell_word<C>(bt.gt, 0u, 0u, 0u);
+  const uint32_t xso = (cx == 0 ? 0u : (uint32_t)(C::TZ * C::TY)) + (uint32_t)cy;
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz) {
     if (lz < nz)
       plane_ptr(bt.fd.lp, g, t.z0 + lz)[col] =
           ld16(lb, pa[lz]) | (ld16(lb, pd[lz]) << 16);
+  }
+  if (xedge) {
+#pragma unroll
+    for (int lz = 0; lz < C::TZ; ++lz) {
+      if (lz < nz)
+        xsb[xso + (uint32_t)(lz * C::TY)] =
+            ld16(lb, pa[lz]) | (ld16(lb, pd[lz]) << 16);
+    }
   }
   if (tid == 0) {
     xo.seg[bt.gt] =
@@ -833,7 +872,8 @@ template <class C>
 __global__ void __launch_bounds__(kBlock)
 k_exit_link(const FieldDev *__restrict__ fds,
             const uint32_t *__restrict__ tfield, const Seg *__restrict__ seg,
-            const uint16_t *__restrict__ tlist, uint32_t *__restrict__ next) {
+            const uint16_t *__restrict__ tlist,
+            const uint32_t *__restrict__ xs, uint32_t *__restrict__ next) {
   const BlockTile bt = block_tile(fds, tfield);
   const Seg sg = seg[bt.gt];
   const uint32_t n = (uint32_t)sg.na + sg.nd;
@@ -852,7 +892,8 @@ k_exit_link(const FieldDev *__restrict__ fds,
       const uint32_t k = k0 + e * kBlock;
       p[e] = k < n ? (int)tl[k] : -1;
     }
-    uint32_t u[E], v[E], lw[E];
+    uint32_t u[E], lw[E];
+    const uint32_t *src[E];
     int dxs[E], dys[E], dzs[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -864,11 +905,18 @@ k_exit_link(const FieldDev *__restrict__ fds,
       dzs[e] = hz == 0 ? -1 : (hz == C::HZ - 1 ? 1 : 0);
       u[e] = (uint32_t)(ttx + dxs[e]) +
              g.ntx * ((uint32_t)(tty + dys[e]) + g.nty * (uint32_t)(ttz + dzs[e]));
-      v[e] = (uint32_t)(t.x0 - 1 + hx) + g.X * (uint32_t)(t.y0 - 1 + hy) +
-             g.XY * (uint32_t)(t.z0 - 1 + hz);
+      // An exit on an x face lies in the neighbour's last (dx = -1) or
+      // first (dx = +1) column: read from that tile's shell copy.
+      const uint32_t v = (uint32_t)(t.x0 - 1 + hx) +
+                         g.X * (uint32_t)(t.y0 - 1 + hy) +
+                         g.XY * (uint32_t)(t.z0 - 1 + hz);
+      const uint32_t sw = (uint32_t)shell_word<C>(
+          bt.fd.tile0 + u[e], dxs[e] < 0 ? 1u : 0u,
+          (uint32_t)(hz - 1 - dzs[e] * C::TZ), (uint32_t)(hy - 1 - dys[e] * C::TY));
+      src[e] = dxs[e] != 0 ? xs + sw : bt.fd.lp + v;
     }
 #pragma unroll
-    for (int e = 0; e < E; ++e) lw[e] = p[e] >= 0 ? bt.fd.lp[v[e]] : 0u;
+    for (int e = 0; e < E; ++e) lw[e] = p[e] >= 0 ? *src[e] : 0u;
     uint32_t code[E], una[E];
 #pragma unroll
     for (int e = 0; e < E; ++e) {
@@ -1773,7 +1821,8 @@ int plan_batch(int nfields, const msc_field *fields, BatchPlan &p) {
       align256(nfields * kFieldCtrs * sizeof(unsigned long long)) +
       align256(4ull * nt * sizeof(uint32_t)) +
       align256(4ull * nt * sizeof(unsigned long long)) +
-      align256(2ull * C::kHalo * nt * sizeof(uint16_t)) + 8192 +
+      align256(2ull * C::kHalo * nt * sizeof(uint16_t)) +
+      align256(2ull * C::TY * C::TZ * nt * sizeof(uint32_t)) + 8192 +
       (p.any_ms ? align256(p.tab_slots * 8) + align256(p.tab_slots * 4) +
                       align256((size_t)nt * C::TX * C::TY * C::TZ)
                 : 0);
@@ -1832,6 +1881,7 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
   uint32_t *tstat = cv.take<uint32_t>(4ull * nt);
   unsigned long long *rstat = cv.take<unsigned long long>(4ull * nt);
   uint16_t *tlist = cv.take<uint16_t>(2ull * C::kHalo * nt);
+  uint32_t *xs = cv.take<uint32_t>(2ull * C::TY * C::TZ * nt);
   uint32_t *run = cv.take<uint32_t>(1);
   uint32_t *cidx = any_ms ? cv.take<uint32_t>((size_t)nt * C::kThreads *
                                                (C::TZ / 4))
@@ -1856,7 +1906,7 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
                                                    tfield, fctr, hist, tstat);
   }
   MSC_HIP_TRY(hipGetLastError());
-  ExitOut xo{seg, tkey, tstat, tlist};
+  ExitOut xo{seg, tkey, tstat, tlist, xs};
   MSC_PHASE(ctx, s, "tile_local", 12.0 * total_n,
             (k_tile_local<C><<<nt, C::kThreads, 0, s>>>(fds, tfield, xo, ctr,
                                                         fctr)));
@@ -1865,7 +1915,7 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
   // no count has to come back to the host before the graph is built.
   MSC_PHASE(ctx, s, "exit_link", 18.0 * nt * (double)C::kHalo * 0.5,
             (k_exit_link<C><<<nt, kBlock, 0, s>>>(fds, tfield, seg, tlist,
-                                                  next)));
+                                                  xs, next)));
   MSC_PHASE(ctx, s, "tile_order", 12.0 * nt,
             (k_key_minmax<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm),
              k_key_hist<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm, hist),
