@@ -996,65 +996,91 @@ __global__ void __launch_bounds__(1024) k_key_scan(uint32_t *hist) {
   hist[b0 + 3] = p + c0 + c1 + c2;
 }
 
+// The tiles' exit records in that order (the resolution reads its tile's
+// record with one load).
 __global__ void __launch_bounds__(kBlock)
 k_key_scatter(const uint32_t *__restrict__ key, uint32_t n,
               const uint32_t *__restrict__ mm, uint32_t *cursor,
-              uint32_t *__restrict__ order) {
+              const Seg *__restrict__ seg, Seg *__restrict__ oseg) {
   const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) order[atomicAdd(&cursor[key_bucket(key[i], mm)], 1u)] = i;
+  if (i < n) oseg[atomicAdd(&cursor[key_bucket(key[i], mm)], 1u)] = seg[i];
 }
 
 // Block b resolves one tile's exits of one direction: the first ntiles
 // blocks take ascent exits in decreasing mean, the rest descent exits in
 // increasing mean.  Each exit chases its successors until a final value.
-template <class C>
-__global__ void __launch_bounds__(C::kThreads)
-k_exit_resolve(const uint32_t *__restrict__ order, uint32_t ntiles,
-               const Seg *__restrict__ seg, uint32_t count, uint32_t *next,
-               unsigned long long *ctr, unsigned long long *rstat) {
-  __shared__ unsigned long long s_red[2][C::kThreads / 64];
+// Values other blocks write are read and written at device scope, so that
+// a chase can stop at an exit another tile has already resolved; whatever
+// it reads (a link or a final value) lies on its own path.
+constexpr int kResolveThreads = 256;
+constexpr int kResolveE = 4;  // exits chased side by side per thread
+
+__device__ __forceinline__ uint32_t load_dev(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__global__ void __launch_bounds__(kResolveThreads)
+k_exit_resolve(const Seg *__restrict__ oseg, uint32_t ntiles, uint32_t count,
+               uint32_t *next, unsigned long long *ctr,
+               unsigned long long *rstat) {
+  constexpr int T = kResolveThreads, E = kResolveE;
+  __shared__ unsigned long long s_red[2][T / 64];
   const bool desc = blockIdx.x >= ntiles;
-  const uint32_t tile =
-      desc ? order[blockIdx.x - ntiles] : order[ntiles - 1 - blockIdx.x];
-  const Seg sg = seg[tile];
+  const Seg sg =
+      desc ? oseg[blockIdx.x - ntiles] : oseg[ntiles - 1 - blockIdx.x];
   const uint32_t first = sg.base + (desc ? sg.na : 0u);
   const uint32_t cnt = desc ? sg.nd : sg.na;
   unsigned steps_max = 0, steps_sum = 0;
   bool bad = false;
-  // Two exits per thread and round, chased side by side, so that their
-  // loads are in flight together.
-  for (uint32_t k0 = threadIdx.x; k0 < cnt; k0 += 2 * C::kThreads) {
-    const uint32_t k1 = k0 + C::kThreads;
-    const bool has1 = k1 < cnt;
-    uint32_t x0 = __atomic_load_n(&next[first + k0], __ATOMIC_RELAXED);
-    uint32_t x1 = has1 ? __atomic_load_n(&next[first + k1], __ATOMIC_RELAXED)
-                       : kRoot;
-    unsigned s0 = 0, s1 = 0;
+  for (uint32_t k0 = threadIdx.x; k0 < cnt; k0 += E * T) {
+    // Every load of a round is issued before any is used: indices out of
+    // range, or of chases already final, read the thread's first slot.
+    uint32_t x[E];
+    unsigned st[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const uint32_t k = k0 + (uint32_t)(e * T);
+      x[e] = next[first + (k < cnt ? k : k0)];
+      st[e] = 0;
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (k0 + (uint32_t)(e * T) >= cnt) x[e] = kRoot;
     // Chains are acyclic and at most `count` long; the bound only turns a
     // broken invariant into an error instead of a hang.
-    while (!(x0 & kRoot) || !(x1 & kRoot)) {
-      if (!(x0 & kRoot)) {
-        if (x0 >= count || ++s0 > count) {
-          bad = true;
-          x0 = kRoot;
-        } else {
-          x0 = __atomic_load_n(&next[x0], __ATOMIC_RELAXED);
-        }
+    bool open = true;
+    while (open) {
+      uint32_t y[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const bool go = !(x[e] & kRoot) && x[e] < count;
+        y[e] = load_dev(next + (go ? x[e] : first + k0));
       }
-      if (!(x1 & kRoot)) {
-        if (x1 >= count || ++s1 > count) {
-          bad = true;
-          x1 = kRoot;
-        } else {
-          x1 = __atomic_load_n(&next[x1], __ATOMIC_RELAXED);
+      open = false;
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        if (!(x[e] & kRoot)) {
+          if (x[e] >= count || ++st[e] > count) {
+            bad = true;
+            x[e] = kRoot;
+          } else {
+            x[e] = y[e];
+          }
         }
+        open |= !(x[e] & kRoot);
       }
     }
-    __atomic_store_n(&next[first + k0], x0, __ATOMIC_RELAXED);
-    if (has1) __atomic_store_n(&next[first + k1], x1, __ATOMIC_RELAXED);
-    const unsigned sm = s0 > s1 ? s0 : s1;
+    unsigned sm = 0;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const uint32_t k = k0 + (uint32_t)(e * T);
+      if (k < cnt)
+        __hip_atomic_store(next + first + k, x[e], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      sm = st[e] > sm ? st[e] : sm;
+      steps_sum += st[e];
+    }
     steps_max = sm > steps_max ? sm : steps_max;
-    steps_sum += s0 + s1;
   }
   if (bad) atomicOr(ctr + kCtrOverflow, 2ull);
   for (int o = 32; o > 0; o >>= 1) {
@@ -1069,7 +1095,7 @@ k_exit_resolve(const uint32_t *__restrict__ order, uint32_t ntiles,
   __syncthreads();
   if (threadIdx.x == 0) {
     unsigned long long mx = 0, sum = 0;
-    for (int w = 0; w < C::kThreads / 64; ++w) {
+    for (int w = 0; w < T / 64; ++w) {
       mx = s_red[0][w] > mx ? s_red[0][w] : mx;
       sum += s_red[1][w];
     }
@@ -1815,7 +1841,7 @@ int plan_batch(int nfields, const msc_field *fields, BatchPlan &p) {
   p.nslots = nt * (uint32_t)(2 * C::kHalo);
   p.need =
       need_lp + need_scratch + align256((size_t)p.nslots * sizeof(uint32_t)) +
-      align256(nt * sizeof(Seg)) + 3 * align256(nt * sizeof(uint32_t)) +
+      2 * align256(nt * sizeof(Seg)) + 2 * align256(nt * sizeof(uint32_t)) +
       align256((kTileBuckets + 2) * sizeof(uint32_t)) +
       align256(nfields * sizeof(FieldDev)) +
       align256(nfields * kFieldCtrs * sizeof(unsigned long long)) +
@@ -1871,7 +1897,7 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
   uint32_t *next = cv.take<uint32_t>(nslots);
   Seg *seg = cv.take<Seg>(nt);
   uint32_t *tkey = cv.take<uint32_t>(nt);
-  uint32_t *torder = cv.take<uint32_t>(nt);
+  Seg *oseg = cv.take<Seg>(nt);
   uint32_t *tfield = cv.take<uint32_t>(nt);
   uint32_t *hist = cv.take<uint32_t>(kTileBuckets + 2);
   uint32_t *mm = hist + kTileBuckets;
@@ -1921,10 +1947,10 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
              k_key_hist<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm, hist),
              k_key_scan<<<1, 1024, 0, s>>>(hist),
              k_key_scatter<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm, hist,
-                                                           torder)));
+                                                           seg, oseg)));
   MSC_PHASE(ctx, s, "exit_resolve", 12.0 * nt * (double)C::kHalo * 0.5,
-            (k_exit_resolve<C><<<2 * nt, C::kThreads, 0, s>>>(
-                torder, nt, seg, nslots, next, ctr, rstat)));
+            (k_exit_resolve<<<2 * nt, kResolveThreads, 0, s>>>(
+                oseg, nt, nslots, next, ctr, rstat)));
   k_steps_reduce<<<kStepsBlocks, 1024, 0, s>>>(rstat, 2 * nt, ctr);
 
   if (any_ms) {
