@@ -168,7 +168,7 @@ def roofline_of(prof, workload=None, tile=None):
     avg_ms = dom["total_ms"] / dom["launches"]
     bpl = dom["bytes"] / dom["launches"]
     achieved = bpl / (avg_ms * 1e-3) / 1e9
-    templated = name.startswith(("tile_", "exit_"))
+    templated = name in ("tile_local", "tile_pairs", "tile_write", "exit_link")
     kname = "k_" + name + ("<%d,%d,%d>" % tile if tile and templated else "")
     out = {"bound": "hbm", "achieved": round(achieved, 1),
            "peak": HBM_PEAK_GBS, "unit": "GB/s",
