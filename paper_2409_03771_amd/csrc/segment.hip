@@ -1939,7 +1939,7 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
   k_tile_stats3<<<grid_for(nt), kBlock, 0, s>>>(tstat, nt, tfield, fctr);
   // Exit slots are fixed per tile (2 * kHalo from the tile's own base), so
   // no count has to come back to the host before the graph is built.
-  MSC_PHASE(ctx, s, "exit_link", 18.0 * nt * (double)C::kHalo * 0.5,
+  MSC_PHASE(ctx, s, "exit_link", 10.0 * nt * (double)C::kHalo * 0.5,
             (k_exit_link<C><<<nt, kBlock, 0, s>>>(fds, tfield, seg, tlist,
                                                   xs, next)));
   MSC_PHASE(ctx, s, "tile_order", 12.0 * nt,
