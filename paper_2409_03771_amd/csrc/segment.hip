@@ -1433,7 +1433,16 @@ k_tile_write(const FieldDev *__restrict__ fds,
   __shared__ unsigned long long skey[kPairSlots];
   __shared__ int32_t scell[kPairSlots];
   __shared__ unsigned sfill;
+  static_assert(kCellIdx <= (unsigned)C::kThreads, "a slot per thread");
   const int tid = threadIdx.x;
+  // The tile's cell record needs only the tile index, so its count and
+  // every slot it can hold (the record spans kHalo words) are loaded first,
+  // together with the tile's descriptors; the cell ids and the bytes follow
+  // in one more round trip.
+  const uint32_t *rec =
+      cell_record<C>(tlist, tile_of_block(blockIdx.x, gridDim.x));
+  const uint32_t r0 = rec[0];
+  const uint32_t rk = rec[1 + ((unsigned)tid < kCellIdx ? tid : 0)];
   const BlockTile bt = block_tile(fds, tfield);
   const Geo &g = bt.fd.g;
   int32_t *__restrict__ A = bt.fd.A;
@@ -1446,24 +1455,26 @@ k_tile_write(const FieldDev *__restrict__ fds,
   int nz = (int)g.Z - t.z0;
   nz = col_in ? (nz < C::TZ ? nz : C::TZ) : 0;
   const uint32_t col = (uint32_t)gx + g.X * (uint32_t)gy;
+  // Block-uniform: the byte path when the field wants cells and the tile
+  // kept one.
+  const uint32_t n = __builtin_amdgcn_readfirstlane(ms ? r0 : 0u);
+  const uint32_t cslot = (uint32_t)tid < n ? rk : 0u;
+  if (n > 0) {  // each vertex's pair number in the tile
+    uint32_t w[C::TZ / 4];
+#pragma unroll
+    for (int j = 0; j < C::TZ / 4; ++j)
+      w[j] = n > 1 ? cidx[cell_word<C>(bt.gt, j, tid)] : 0u;
+    const int32_t cell = bt.fd.vals[cslot];
+    if ((uint32_t)tid < n) scell[tid] = cell;
+    __syncthreads();
+#pragma unroll
+    for (int lz = 0; lz < C::TZ; ++lz)
+      if (lz < nz)
+        plane_ptr(ms, g, t.z0 + lz)[col] =
+            scell[(w[lz / 4] >> (8 * (lz % 4))) & 0xffu];
+    return;
+  }
   if (ms) {  // uniform over the block: ms belongs to the field
-    const uint32_t *rec = cell_record<C>(tlist, bt.gt);
-    const uint32_t n = __builtin_amdgcn_readfirstlane(rec[0]);
-    if (n > 0) {  // the byte path: each vertex's pair number in the tile
-      for (uint32_t k = tid; k < n; k += C::kThreads)
-        scell[k] = bt.fd.vals[rec[1 + k]];
-      uint32_t w[C::TZ / 4];
-#pragma unroll
-      for (int j = 0; j < C::TZ / 4; ++j)
-        w[j] = n > 1 ? cidx[cell_word<C>(bt.gt, j, tid)] : 0u;
-      __syncthreads();
-#pragma unroll
-      for (int lz = 0; lz < C::TZ; ++lz)
-        if (lz < nz)
-          plane_ptr(ms, g, t.z0 + lz)[col] =
-              scell[(w[lz / 4] >> (8 * (lz % 4))) & 0xffu];
-      return;
-    }
     for (int i = tid; i < kPairSlots; i += C::kThreads) skey[i] = kEmptyKey;
   }
   if (tid == 0) sfill = 0;
