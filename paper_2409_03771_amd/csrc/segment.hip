@@ -1127,21 +1127,28 @@ __device__ __forceinline__ void decode_setup(Decode<C> &s, uint32_t gt,
   const Seg sg = seg[gt];
   const uint32_t n = (uint32_t)sg.na + sg.nd;
   // Four resolved exits per thread and round, their loads in flight
-  // together.
+  // together (indices past the tile's exits read its first slot, so that no
+  // load sits in a branch of its own).  The first round, all that most
+  // tiles need, stands outside the loop, so that its loads do not wait for
+  // the caller's loads still in flight.
   constexpr uint32_t E = 4;
-  for (uint32_t k0 = threadIdx.x; k0 < n; k0 += E * C::kThreads) {
+  auto round = [&](uint32_t k0) {
     uint32_t r[E];
 #pragma unroll
     for (uint32_t e = 0; e < E; ++e) {
       const uint32_t k = k0 + e * C::kThreads;
-      r[e] = k < n ? R[sg.base + k] : 0u;
+      r[e] = R[sg.base + (k < n ? k : 0u)];
     }
 #pragma unroll
     for (uint32_t e = 0; e < E; ++e) {
       const uint32_t k = k0 + e * C::kThreads;
       if (k < n) s.tab[k] = (int32_t)(r[e] & ~kRoot);
     }
-  }
+  };
+  round(threadIdx.x);
+  for (uint32_t k0 = threadIdx.x + E * C::kThreads; k0 < n;
+       k0 += E * C::kThreads)
+    round(k0);
   for (uint32_t r = threadIdx.x; r < (uint32_t)(C::TY * C::TZ);
        r += C::kThreads)
     s.tab[Decode<C>::kRows + r] =
@@ -1296,6 +1303,7 @@ __device__ __forceinline__ size_t cell_word(uint32_t gt, int j, int tid) {
 
 template <class C>
 __global__ void __launch_bounds__(C::kThreads)
+__attribute__((amdgpu_waves_per_eu(8, 8)))
 k_tile_pairs(const FieldDev *__restrict__ fds,
              const uint32_t *__restrict__ tfield, const Seg *__restrict__ seg,
              const uint32_t *__restrict__ R, unsigned long long *ctr,
