@@ -78,7 +78,8 @@ struct Geo {
 // One field of a batch as the kernels see it.
 struct FieldDev {
   const float *f;
-  uint32_t *lp;                // packed codes, one per vertex
+  uint32_t *lp;                // packed codes, tile-major (code_word), one
+                               // array for the whole batch
   int32_t *A, *D, *ms;         // outputs (A/D may be library scratch)
   unsigned long long *keys;    // the field's pair table
   int32_t *vals;
@@ -121,6 +122,15 @@ template <class T>
 __device__ __forceinline__ __attribute__((address_space(1))) T *plane_ptr(
     T *p, const Geo &g, int z) {
   return (__attribute__((address_space(1))) T *)p + (size_t)g.XY * (uint32_t)z;
+}
+
+// The packed codes are stored tile-major: a tile's TZ planes of TX*TY
+// columns are one contiguous run, so every pass reads or writes whole runs
+// instead of a row of TX words per (y, z).  Positions outside the domain
+// have their word too (written and read, never used).
+template <class C>
+__device__ __forceinline__ size_t code_word(uint32_t gt, int lz, int tid) {
+  return ((size_t)gt * C::TZ + (size_t)lz) * C::kThreads + (size_t)tid;
 }
 
 // A tile's codes of its first (side 0) and last (side 1) x column, side by
@@ -814,7 +824,6 @@ k_tile_local(const FieldDev *__restrict__ fds,
   // The stored local pointer of every vertex is its target's code: an
   // owned target by its owned index, an exit by its number (bit 15 set), so
   // that later passes decode it with one lookup in the tile's resolved exits.
-  const uint32_t col = (uint32_t)gx + g.X * (uint32_t)gy;
   // The first and last columns also go to the tile's shell copy (a
   // block-uniform base and a 32-bit offset per lane).
   const bool xedge = cx == 0 || cx == C::TX - 1;
@@ -822,12 +831,13 @@ k_tile_local(const FieldDev *__restrict__ fds,
       (__attribute__((address_space(1))) uint32_t *)xo.xs +
       shell_word<C>(bt.gt, 0u, 0u, 0u);
   const uint32_t xso = (cx == 0 ? 0u : (uint32_t)(C::TZ * C::TY)) + (uint32_t)cy;
+  __attribute__((address_space(1))) uint32_t *const lpt =
+      (__attribute__((address_space(1))) uint32_t *)bt.fd.lp +
+      code_word<C>(bt.gt, 0, 0);
 #pragma unroll
-  for (int lz = 0; lz < C::TZ; ++lz) {
-    if (lz < nz)
-      plane_ptr(bt.fd.lp, g, t.z0 + lz)[col] =
-          ld16(lb, pa[lz]) | (ld16(lb, pd[lz]) << 16);
-  }
+  for (int lz = 0; lz < C::TZ; ++lz)
+    lpt[(uint32_t)(lz * C::kThreads + tid)] =
+        ld16(lb, pa[lz]) | (ld16(lb, pd[lz]) << 16);
   if (xedge) {
 #pragma unroll
     for (int lz = 0; lz < C::TZ; ++lz) {
@@ -905,15 +915,16 @@ k_exit_link(const FieldDev *__restrict__ fds,
       dzs[e] = hz == 0 ? -1 : (hz == C::HZ - 1 ? 1 : 0);
       u[e] = (uint32_t)(ttx + dxs[e]) +
              g.ntx * ((uint32_t)(tty + dys[e]) + g.nty * (uint32_t)(ttz + dzs[e]));
-      // An exit on an x face lies in the neighbour's last (dx = -1) or
-      // first (dx = +1) column: read from that tile's shell copy.
-      const uint32_t v = (uint32_t)(t.x0 - 1 + hx) +
-                         g.X * (uint32_t)(t.y0 - 1 + hy) +
-                         g.XY * (uint32_t)(t.z0 - 1 + hz);
-      const uint32_t sw = (uint32_t)shell_word<C>(
-          bt.fd.tile0 + u[e], dxs[e] < 0 ? 1u : 0u,
-          (uint32_t)(hz - 1 - dzs[e] * C::TZ), (uint32_t)(hy - 1 - dys[e] * C::TY));
-      src[e] = dxs[e] != 0 ? xs + sw : bt.fd.lp + v;
+      // The exit's position in the owner tile; an exit on an x face lies in
+      // the owner's last (dx = -1) or first (dx = +1) column and is read
+      // from that tile's shell copy.
+      const uint32_t ou = bt.fd.tile0 + u[e];
+      const int lx = hx - 1 - dxs[e] * C::TX, ly = hy - 1 - dys[e] * C::TY,
+                lzo = hz - 1 - dzs[e] * C::TZ;
+      src[e] = dxs[e] != 0
+                   ? xs + shell_word<C>(ou, dxs[e] < 0 ? 1u : 0u,
+                                        (uint32_t)lzo, (uint32_t)ly)
+                   : bt.fd.lp + code_word<C>(ou, lzo, lx + C::TX * ly);
     }
 #pragma unroll
     for (int e = 0; e < E; ++e) lw[e] = p[e] >= 0 ? *src[e] : 0u;
@@ -1301,9 +1312,19 @@ __device__ __forceinline__ size_t cell_word(uint32_t gt, int j, int tid) {
   return ((size_t)gt * (C::TZ / 4) + (size_t)j) * C::kThreads + (size_t)tid;
 }
 
+// Waves per SIMD that the pair pass's LDS (its decode and pair tables,
+// about 14 KB besides the decode table) leaves room for, at most 8; the
+// register budget is held to match (8 waves: 64 VGPRs).
+template <class C>
+constexpr int pair_waves() {
+  constexpr int lds = 4 * (2 * C::kHalo + C::TY * C::TZ) + 14 * 1024 + 256;
+  constexpr int w = (160 * 1024 / lds) * (C::kThreads / 64) / 4;
+  return w < 8 ? w : 8;
+}
+
 template <class C>
 __global__ void __launch_bounds__(C::kThreads)
-__attribute__((amdgpu_waves_per_eu(8, 8)))
+__attribute__((amdgpu_waves_per_eu(pair_waves<C>(), pair_waves<C>())))
 k_tile_pairs(const FieldDev *__restrict__ fds,
              const uint32_t *__restrict__ tfield, const Seg *__restrict__ seg,
              const uint32_t *__restrict__ R, unsigned long long *ctr,
@@ -1340,7 +1361,7 @@ k_tile_pairs(const FieldDev *__restrict__ fds,
     uint32_t code[C::TZ];
   #pragma unroll
     for (int lz = 0; lz < C::TZ; ++lz)
-      code[lz] = lz < nz ? plane_ptr(bt.fd.lp, g, t.z0 + lz)[col] : 0u;
+      code[lz] = bt.fd.lp[code_word<C>(bt.gt, lz, tid)];
     decode_setup<C>(s, bt.gt, seg, R, g, t);
 
     unsigned fresh = 0;
@@ -1489,7 +1510,7 @@ k_tile_write(const FieldDev *__restrict__ fds,
   uint32_t code[C::TZ];
 #pragma unroll
   for (int lz = 0; lz < C::TZ; ++lz)
-    code[lz] = lz < nz ? plane_ptr(bt.fd.lp, g, t.z0 + lz)[col] : 0u;
+    code[lz] = bt.fd.lp[code_word<C>(bt.gt, lz, tid)];
   decode_setup<C>(s, bt.gt, seg, R, g, t);
 
   int16_t slot[C::TZ];
@@ -1840,7 +1861,6 @@ int plan_batch(int nfields, const msc_field *fields, BatchPlan &p) {
     p.fd[i].tile0 = (uint32_t)total_tiles;
     total_tiles += nt;
     p.total_n += g.N;
-    need_lp += align256((size_t)g.N * sizeof(uint32_t));
     if (!fields[i].asc) need_scratch += align256((size_t)g.N * sizeof(int32_t));
     if (!fields[i].desc) need_scratch += align256((size_t)g.N * sizeof(int32_t));
     if (total_tiles > INT32_MAX / 2) return MSC_ERANGE;
@@ -1858,6 +1878,7 @@ int plan_batch(int nfields, const msc_field *fields, BatchPlan &p) {
   const uint32_t nt = (uint32_t)total_tiles;
   p.nt = nt;
   p.nslots = nt * (uint32_t)(2 * C::kHalo);
+  need_lp = align256((size_t)nt * C::TX * C::TY * C::TZ * sizeof(uint32_t));
   p.need =
       need_lp + need_scratch + align256((size_t)p.nslots * sizeof(uint32_t)) +
       2 * align256(nt * sizeof(Seg)) + 2 * align256(nt * sizeof(uint32_t)) +
@@ -1902,9 +1923,10 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
     keys = cv.take<unsigned long long>(tab_slots);
     vals = cv.take<int32_t>(tab_slots);
   }
+  uint32_t *lp = cv.take<uint32_t>((size_t)nt * C::TX * C::TY * C::TZ);
   for (int i = 0; i < nfields; ++i) {
     fd[i].f = fields[i].field;
-    fd[i].lp = cv.take<uint32_t>(fd[i].g.N);
+    fd[i].lp = lp;
     fd[i].A = fields[i].asc ? fields[i].asc : cv.take<int32_t>(fd[i].g.N);
     fd[i].D = fields[i].desc ? fields[i].desc : cv.take<int32_t>(fd[i].g.N);
     fd[i].ms = fields[i].ms;
