@@ -397,15 +397,18 @@ MSC_API int cc_label_grid_ranks(msc_ctx *ctx, const uint8_t *mask,
  * labels, with no context and no allocation of any kind.  The tile-local
  * roots live in a static device array of 2^27 16-bit entries (256 MiB on
  * each GPU the library runs on, held until the process ends), taken on the
- * call's first use on a device.
+ * call's first use on a device.  The roots are stored by whole 32x16x16
+ * tiles, so a call may cover at most 2^14 tiles: ceil(X/32) * ceil(Y/16) *
+ * ceil(Z/16) <= 16384 (512^3 vertices, or fewer when the sides are not
+ * multiples of the tile).
  *
  *  Runs on the current HIP device; mask, dims, labels and stream as
- *  cc_label_grid.  At most 2^27 vertices (512^3).
+ *  cc_label_grid.
  *  Every call on one GPU shares that GPU's array: calls whose work overlaps
  *  on the device (two streams, or two host threads) race; calls on one
  *  stream are ordered and safe.
- *  Errors: MSC_EINVAL (NULL pointers, dims < 1), MSC_ERANGE (more than 2^27
- *  vertices), MSC_EHIP.
+ *  Errors: MSC_EINVAL (NULL pointers, dims < 1), MSC_ERANGE (more than 2^14
+ *  tiles), MSC_EHIP.
  */
 MSC_API int cc_label_grid_noalloc(const uint8_t *mask, const int64_t dims[3],
                                   int64_t *labels, void *stream);

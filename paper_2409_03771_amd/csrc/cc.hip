@@ -121,6 +121,13 @@ __device__ __forceinline__ CTile ctile_at(const CGeo &g, int64_t t) {
   return CTile{tx * CTX, ty * CTY, tz * CTZ};
 }
 
+// The tile-local roots are stored tile-major: tile t's kCOwned entries,
+// indexed by the tile-local index, are one contiguous run, so the passes
+// read and write whole runs instead of a row of CTX entries per (y, z).
+__device__ __forceinline__ int64_t loc_index(int64_t t, int l) {
+  return t * kCOwned + l;
+}
+
 // Global id of the tile-local index l (lx + CTX*(ly + CTY*lz)).
 __device__ __forceinline__ int64_t ctile_global(const CGeo &g, const CTile &t,
                                                 int l) {
@@ -134,7 +141,7 @@ __device__ __forceinline__ int64_t ctile_global(const CGeo &g, const CTile &t,
 struct CGrid {
   const uint8_t *mask;
   int64_t *L;      // labels, also the union-find parent array
-  uint16_t *loc;   // tile-local roots (workspace)
+  uint16_t *loc;   // tile-local roots (workspace), tile-major (loc_index)
   int64_t off;     // added to every label (a slab inside a larger grid)
   int64_t X, Y, Z;
   uint32_t tile0;  // first tile of this mask in the launch
@@ -260,17 +267,17 @@ __global__ void __launch_bounds__(kCThreads) k_cc_tile(CBatch<B> b) {
   int run_head = -1, run_root = -1;
   for (int lz = 0; lz < nz; ++lz) {
     const int64_t v = v0 + g.XY * lz;
+    const int l = local(cx, cy, lz);
     if (!((m >> lz) & 1u)) {
-      loc[v] = kOutside;
+      loc[loc_index(ti, l)] = kOutside;
       continue;
     }
-    const int l = local(cx, cy, lz);
     const int h = local(cx, cy, run_start(m, lz));
     if (h != run_head) {
       run_head = h;
       run_root = uf_find<int32_t>(par, h);
     }
-    loc[v] = (uint16_t)run_root;
+    loc[loc_index(ti, l)] = (uint16_t)run_root;
     if (run_root == l) L[v] = v;  // tile-local roots start as global roots
   }
 }
@@ -368,7 +375,9 @@ __global__ void __launch_bounds__(kCThreads) k_cc_cross(CBatch<B> b) {
       const int64_t x = t.x0 + bx, y = t.y0 + by, z = t.z0 + bz;
       const bool in = i < SN && x < g.X && y < g.Y && z < g.Z;
       at[k] = i < SN ? bx + BX * (by + BY * bz) : -1;
-      val[k] = in ? loc[x + g.X * y + g.XY * z] : kOutside;
+      const int64_t tn = x / CTX + g.ntx * (y / CTY + g.nty * (z / CTZ));
+      const int ln = (int)(x % CTX) + CTX * ((int)(y % CTY) + CTY * (int)(z % CTZ));
+      val[k] = in ? loc[loc_index(tn, ln)] : kOutside;
     }
 #pragma unroll
     for (int k = 0; k < K; ++k)
@@ -434,16 +443,15 @@ __global__ void __launch_bounds__(kCThreads) k_cc_final(CBatch<B> b) {
   if (gx >= g.X || gy >= g.Y) return;
   const int nz = (int)((g.Z - t.z0) < CTZ ? (g.Z - t.z0) : CTZ);
   const int64_t v0 = gx + g.X * gy + g.XY * t.z0;
-  // The column's tile-local roots, all loads in flight together.
+  // The column's tile-local roots, all loads in flight together (entries
+  // past the domain's last plane exist in the tile's run and are not used).
   uint16_t sl[CTZ];
 #pragma unroll
   for (int lz = 0; lz < CTZ; ++lz)
-    sl[lz] = lz < nz ? loc[v0 + g.XY * lz] : kOutside;
+    sl[lz] = loc[loc_index(ti, tid + kCThreads * lz)];
   uint16_t last = kOutside;
   int64_t last_out = -1;
-#pragma unroll
-  for (int lz = 0; lz < CTZ; ++lz) {
-    if (lz >= nz) break;
+  for (int lz = 0; lz < nz; ++lz) {
     const uint16_t s = sl[lz];
     // Only tile-local roots are ever on a root path, and a root's entry is
     // overwritten (by its owner only) with its own final root, so concurrent
@@ -478,7 +486,8 @@ __global__ void __launch_bounds__(kCThreads) k_cc_root_shift(CBatch<B> b) {
   int nz = (int)((g.Z - t.z0) < CTZ ? (g.Z - t.z0) : CTZ);
   for (int lz = 0; lz < nz; ++lz) {
     const int64_t v = gx + g.X * gy + g.XY * (t.z0 + lz);
-    if (loc[v] == cx + CTX * (cy + CTY * lz)) L[v] += off;
+    const int l = cx + CTX * (cy + CTY * lz);
+    if (loc[loc_index(ti, l)] == l) L[v] += off;
   }
 }
 
@@ -677,8 +686,9 @@ int64_t cc_tiles(int64_t X, int64_t Y, int64_t Z) {
 size_t cc_grid_workspace(int n, const msc_mask *masks) {
   size_t need = 4096;
   for (int i = 0; i < n; ++i)
-    need += align256((size_t)(masks[i].dims[0] * masks[i].dims[1] *
-                              masks[i].dims[2]) * sizeof(uint16_t));
+    need += align256((size_t)cc_tiles(masks[i].dims[0], masks[i].dims[1],
+                                      masks[i].dims[2]) *
+                     kCOwned * sizeof(uint16_t));
   return need;
 }
 
@@ -688,9 +698,10 @@ int cc_grid_run(msc_ctx *ctx, const uint8_t *mask, int64_t X, int64_t Y,
   const int64_t N = X * Y * Z;
   const int64_t ntiles = cc_tiles(X, Y, Z);
   if (ntiles > INT32_MAX) return MSC_ERANGE;
-  MSC_TRY(reserve(ctx, ctx->ws, align256(N * sizeof(uint16_t)) + 4096));
+  MSC_TRY(reserve(ctx, ctx->ws,
+                  align256(ntiles * kCOwned * sizeof(uint16_t)) + 4096));
   Carver cv(ctx->ws);
-  uint16_t *loc = cv.take<uint16_t>(N);
+  uint16_t *loc = cv.take<uint16_t>(ntiles * kCOwned);
   CBatch<1> b{1, {CGrid{mask, labels, loc, label_off, X, Y, Z, 0u}}};
   MSC_TRY(cc_launch(ctx, b, (uint32_t)ntiles, N, label_off != 0, s));
   if (!sync) return MSC_OK;
@@ -729,8 +740,9 @@ int cc_grid_batch_run(msc_ctx *ctx, int n, const msc_mask *masks,
     }
     if (i == n) break;
     const int64_t N = d[0] * d[1] * d[2];
-    b.g[b.n++] = CGrid{masks[i].mask, masks[i].labels, cv.take<uint16_t>(N), 0,
-                       d[0], d[1], d[2], (uint32_t)tiles};
+    b.g[b.n++] = CGrid{masks[i].mask, masks[i].labels,
+                       cv.take<uint16_t>(nt * kCOwned), 0, d[0], d[1], d[2],
+                       (uint32_t)tiles};
     tiles += (uint64_t)nt;
     verts += N;
   }
@@ -817,11 +829,11 @@ int jump_run(msc_ctx *ctx, int64_t *d, int64_t n, int rounds, int sync,
 
 namespace {
 
-// 16-bit tile-local root per vertex: 2^27 entries (256 MiB per GPU the
-// library runs on, held until the process ends) bound a call at 2^27
-// vertices (512^3).
-constexpr int64_t kNoAllocMaxVertices = INT64_C(1) << 27;
-static __device__ __align__(256) uint16_t scratch[kNoAllocMaxVertices];
+// 16-bit tile-local root per vertex, stored by whole tiles: 2^27 entries
+// (256 MiB per GPU the library runs on, held until the process ends) bound a
+// call at 2^14 tiles of 32x16x16 (512^3 vertices).
+constexpr int64_t kNoAllocEntries = INT64_C(1) << 27;
+static __device__ __align__(256) uint16_t scratch[kNoAllocEntries];
 
 constexpr int kMaxDevices = 64;
 std::mutex g_scratch_mu;
@@ -854,18 +866,17 @@ extern "C" int cc_label_grid_noalloc(const uint8_t *mask,
   if (!mask || !labels || !dims) return MSC_EINVAL;
   for (int k = 0; k < 3; ++k)
     if (dims[k] < 1) return MSC_EINVAL;
-  if (dims[0] > kNoAllocMaxVertices || dims[1] > kNoAllocMaxVertices ||
-      dims[2] > kNoAllocMaxVertices ||
-      dims[0] * dims[1] > kNoAllocMaxVertices ||
-      dims[0] * dims[1] * dims[2] > kNoAllocMaxVertices)
+  // Each factor is bounded first, so that the tile count cannot overflow.
+  if (dims[0] > kNoAllocEntries || dims[1] > kNoAllocEntries ||
+      dims[2] > kNoAllocEntries ||
+      cc_tiles(dims[0], dims[1], dims[2]) * kCOwned > kNoAllocEntries)
     return MSC_ERANGE;
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess) return MSC_EHIP;
   uint16_t *loc = nullptr;
   MSC_TRY(scratch_of(dev, &loc));
   const int64_t X = dims[0], Y = dims[1], Z = dims[2];
-  const unsigned nb = (unsigned)(((X + CTX - 1) / CTX) * ((Y + CTY - 1) / CTY) *
-                                 ((Z + CTZ - 1) / CTZ));
+  const unsigned nb = (unsigned)cc_tiles(X, Y, Z);
   const CBatch<1> b{1, {CGrid{mask, labels, loc, 0, X, Y, Z, 0u}}};
   hipStream_t s = static_cast<hipStream_t>(stream);
   // Every entry of `loc` the kernels read is written first (k_cc_tile
