@@ -962,9 +962,19 @@ k_exit_link(const FieldDev *__restrict__ fds,
 // its own path to a final value, whatever has been resolved already.
 constexpr int kTileBuckets = 4096;
 
-__global__ void __launch_bounds__(kBlock)
+// The ordering kernels run 1024-thread blocks and fold per block in LDS
+// first: tile means crowd into a few buckets, and global atomics on one
+// address serialise across the chip.
+constexpr int kOrderBlock = 1024;
+
+inline unsigned order_grid(uint32_t n) {
+  return (n + kOrderBlock - 1) / kOrderBlock;
+}
+
+__global__ void __launch_bounds__(kOrderBlock)
 k_key_minmax(const uint32_t *__restrict__ key, uint32_t n, uint32_t *mm) {
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
+  __shared__ uint32_t s_lo[kOrderBlock / 64], s_hi[kOrderBlock / 64];
+  const uint32_t i = blockIdx.x * kOrderBlock + threadIdx.x;
   uint32_t lo = ~0u, hi = 0;
   if (i < n) lo = hi = key[i];
   for (int o = 32; o > 0; o >>= 1) {
@@ -972,9 +982,20 @@ k_key_minmax(const uint32_t *__restrict__ key, uint32_t n, uint32_t *mm) {
     lo = a < lo ? a : lo;
     hi = b > hi ? b : hi;
   }
-  if ((threadIdx.x & 63) == 0 && lo <= hi) {
-    atomicMin(&mm[0], lo);
-    atomicMax(&mm[1], hi);
+  if ((threadIdx.x & 63) == 0) {
+    s_lo[threadIdx.x >> 6] = lo;
+    s_hi[threadIdx.x >> 6] = hi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < kOrderBlock / 64; ++w) {
+      lo = s_lo[w] < lo ? s_lo[w] : lo;
+      hi = s_hi[w] > hi ? s_hi[w] : hi;
+    }
+    if (lo <= hi) {
+      atomicMin(&mm[0], lo);
+      atomicMax(&mm[1], hi);
+    }
   }
 }
 
@@ -985,11 +1006,17 @@ __device__ __forceinline__ uint32_t key_bucket(uint32_t key,
   return b < kTileBuckets ? (uint32_t)b : kTileBuckets - 1;
 }
 
-__global__ void __launch_bounds__(kBlock)
+__global__ void __launch_bounds__(kOrderBlock)
 k_key_hist(const uint32_t *__restrict__ key, uint32_t n,
            const uint32_t *__restrict__ mm, uint32_t *hist) {
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) atomicAdd(&hist[key_bucket(key[i], mm)], 1u);
+  __shared__ uint32_t cnt[kTileBuckets];
+  for (int b = threadIdx.x; b < kTileBuckets; b += kOrderBlock) cnt[b] = 0;
+  __syncthreads();
+  const uint32_t i = blockIdx.x * kOrderBlock + threadIdx.x;
+  if (i < n) atomicAdd(&cnt[key_bucket(key[i], mm)], 1u);
+  __syncthreads();
+  for (int b = threadIdx.x; b < kTileBuckets; b += kOrderBlock)
+    if (cnt[b]) atomicAdd(&hist[b], cnt[b]);
 }
 
 // Exclusive scan of kTileBuckets counts in place (one block of 1024
@@ -1008,13 +1035,24 @@ __global__ void __launch_bounds__(1024) k_key_scan(uint32_t *hist) {
 }
 
 // The tiles' exit records in that order (the resolution reads its tile's
-// record with one load).
-__global__ void __launch_bounds__(kBlock)
+// record with one load).  A tile's place: its block's share of its bucket
+// (one global atomic per bucket and block), then its rank in that share.
+__global__ void __launch_bounds__(kOrderBlock)
 k_key_scatter(const uint32_t *__restrict__ key, uint32_t n,
               const uint32_t *__restrict__ mm, uint32_t *cursor,
               const Seg *__restrict__ seg, Seg *__restrict__ oseg) {
-  const uint32_t i = blockIdx.x * kBlock + threadIdx.x;
-  if (i < n) oseg[atomicAdd(&cursor[key_bucket(key[i], mm)], 1u)] = seg[i];
+  __shared__ uint32_t cnt[kTileBuckets];
+  for (int b = threadIdx.x; b < kTileBuckets; b += kOrderBlock) cnt[b] = 0;
+  __syncthreads();
+  const uint32_t i = blockIdx.x * kOrderBlock + threadIdx.x;
+  const bool in = i < n;
+  const uint32_t b = in ? key_bucket(key[i], mm) : 0u;
+  const uint32_t r = in ? atomicAdd(&cnt[b], 1u) : 0u;
+  __syncthreads();
+  for (int k = threadIdx.x; k < kTileBuckets; k += kOrderBlock)
+    if (cnt[k]) cnt[k] = atomicAdd(&cursor[k], cnt[k]);
+  __syncthreads();
+  if (in) oseg[cnt[b] + r] = seg[i];
 }
 
 // Block b resolves one tile's exits of one direction: the first ntiles
@@ -1984,11 +2022,13 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
             (k_exit_link<C><<<nt, kBlock, 0, s>>>(fds, tfield, seg, tlist,
                                                   xs, next)));
   MSC_PHASE(ctx, s, "tile_order", 12.0 * nt,
-            (k_key_minmax<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm),
-             k_key_hist<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm, hist),
+            (k_key_minmax<<<order_grid(nt), kOrderBlock, 0, s>>>(tkey, nt,
+                                                                 mm),
+             k_key_hist<<<order_grid(nt), kOrderBlock, 0, s>>>(tkey, nt, mm,
+                                                              hist),
              k_key_scan<<<1, 1024, 0, s>>>(hist),
-             k_key_scatter<<<grid_for(nt), kBlock, 0, s>>>(tkey, nt, mm, hist,
-                                                           seg, oseg)));
+             k_key_scatter<<<order_grid(nt), kOrderBlock, 0, s>>>(
+                 tkey, nt, mm, hist, seg, oseg)));
   MSC_PHASE(ctx, s, "exit_resolve", 12.0 * nt * (double)C::kHalo * 0.5,
             (k_exit_resolve<<<2 * nt, kResolveThreads, 0, s>>>(
                 oseg, nt, nslots, next, ctr, rstat)));
