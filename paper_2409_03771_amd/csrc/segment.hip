@@ -679,8 +679,9 @@ k_tile_local(const FieldDev *__restrict__ fds,
   // read from another entry is an ancestor of it (a concurrent reader sees
   // the old or the new value, both on the vertex's own path).  Each round
   // gathers the successors of all the column's entries first (one wait for
-  // the lot), then stores the ones that changed.  Two rounds per iteration,
-  // alternating between two register sets, so that no copies are needed.
+  // the lot), then stores them.  Two rounds per iteration, alternating
+  // between two register sets, so that no copies are needed.  A round
+  // reports whether any of the wave's own entries changed.
   auto round = [&](const uint32_t (&sa)[C::TZ], const uint32_t (&sd)[C::TZ],
                    uint32_t (&da)[C::TZ], uint32_t (&dd)[C::TZ]) -> bool {
 #pragma unroll
@@ -698,30 +699,35 @@ k_tile_local(const FieldDev *__restrict__ fds,
       changed |= (da[lz] != sa[lz]) | (dd[lz] != sd[lz]);
       own[HXY * lz] = da[lz] | (dd[lz] << 16);
     }
-    return __syncthreads_or(changed);
+    return __ballot(changed) != 0ull;
   };
   {
-    // Pointer doubling over a forest of H nodes settles within about
-    // log2(H) + 1 rounds; the bound only turns a broken invariant into an
-    // error (counter bit 2) instead of a hang.
-    constexpr int kMaxPairs = 16;
+    // Each wave jumps until its own entries are final, with no barrier
+    // between rounds: a round that changes none of them leaves every one
+    // naming a fixed point, which no later write changes, whatever the other
+    // waves have stored so far.  A wave that is done leaves its SIMD to the
+    // others until the block meets at the barrier.  Doubling settles within
+    // about log2(H) + 1 rounds; the bound only turns a broken invariant into
+    // an error (counter bit 2) instead of a hang.
+    constexpr int kMaxPairs = 64;
     uint32_t qa[C::TZ], qd[C::TZ];
-    int it = 0;
-    for (;; ++it) {
-      if (it == kMaxPairs) {
-        if (tid == 0) atomicOr(ctr + kCtrOverflow, 4ull);
-        break;
-      }
+    bool open = true;
+    for (int it = 0; it < kMaxPairs; ++it) {
       if (!round(pa, pd, qa, qd)) {
 #pragma unroll
         for (int lz = 0; lz < C::TZ; ++lz) {
           pa[lz] = qa[lz];
           pd[lz] = qd[lz];
         }
+        open = false;
         break;
       }
-      if (!round(qa, qd, pa, pd)) break;
+      if (!round(qa, qd, pa, pd)) {
+        open = false;
+        break;
+      }
     }
+    if (__syncthreads_or(open) && tid == 0) atomicOr(ctr + kCtrOverflow, 4ull);
   }
 
   // Every pointer is final: it names an extremum of the tile or a halo
