@@ -528,7 +528,8 @@ def batch_leg(args, msc, synth, torch, dev):
             "batched_gvps": round(n / (b_ms * 1e-3) / 1e9, 3),
             "plain_gvps": round(n / (p_ms * 1e-3) / 1e9, 3),
             "speedup_vs_plain": round(p_ms / b_ms, 2),
-            "steps": steps, "roofline": roofline_of(prof)}
+            "steps": steps,
+            "roofline": roofline_of(prof, tile=tuple(tune["tile"]))}
 
 
 def bench_batch(args, msc, synth, torch, dev):
