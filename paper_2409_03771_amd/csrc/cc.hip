@@ -90,6 +90,69 @@ __device__ __forceinline__ bool uf_unite(T *par, T a, T b) {
   }
 }
 
+// The same on a forest in device memory, where every step of a walk is a
+// round trip: the two walks of a union advance side by side (each step's
+// loads for both are issued before either is used; a walk that has reached
+// its root reloads it harmlessly), and the accesses are at device scope,
+// which is all that one device's workgroups need.
+__device__ __forceinline__ int64_t ld_dev(const int64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void uf_find2_dev(int64_t *par, int64_t &a,
+                                             int64_t &b) {
+  bool ra = false, rb = false;
+  while (!(ra && rb)) {
+    const int64_t pa = ld_dev(&par[a]), pb = ld_dev(&par[b]);
+    const int64_t ga = ld_dev(&par[pa]), gb = ld_dev(&par[pb]);
+    if (!ra) {
+      if (pa == a) {
+        ra = true;
+      } else if (ga == pa) {
+        a = pa;
+        ra = true;
+      } else {
+        // Path halving: ga is an ancestor of a, so this only shortens it.
+        __hip_atomic_store(&par[a], ga, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        a = ga;
+      }
+    }
+    if (!rb) {
+      if (pb == b) {
+        rb = true;
+      } else if (gb == pb) {
+        b = pb;
+        rb = true;
+      } else {
+        __hip_atomic_store(&par[b], gb, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        b = gb;
+      }
+    }
+  }
+}
+
+__device__ __forceinline__ bool uf_unite_dev(int64_t *par, int64_t a,
+                                             int64_t b) {
+  bool changed = false;
+  for (;;) {
+    uf_find2_dev(par, a, b);
+    if (a == b) return changed;
+    if (a > b) {
+      const int64_t t = a;
+      a = b;
+      b = t;
+    }
+    int64_t expect = b;
+    if (__hip_atomic_compare_exchange_strong(
+            &par[b], &expect, a, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+            __HIP_MEMORY_SCOPE_AGENT))
+      return true;
+    changed = true;  // b moved meanwhile; retry from the new trees
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Grid masks
 // ---------------------------------------------------------------------------
@@ -318,7 +381,7 @@ __device__ __forceinline__ void cross_unite(const CGeo &g, const CTile &t,
   const uint32_t lv = key & 0x1fffu, nbr = (key >> 13) & 7u, lu = key >> 16;
   const CTile tu{t.x0 + (nbr & 1u ? CTX : 0), t.y0 + (nbr & 2u ? CTY : 0),
                  t.z0 + (nbr & 4u ? CTZ : 0)};
-  uf_unite<int64_t>(L, ctile_global(g, t, (int)lv),
+  uf_unite_dev(L, ctile_global(g, t, (int)lv),
                     ctile_global(g, tu, (int)lu));
 }
 
@@ -586,7 +649,7 @@ k_csr_union(int64_t n, const int64_t *__restrict__ rp,
                                 __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
     for (int j = 0; j < kEdgeChunk; ++j)
-      if (lu[j] != lv) uf_unite<int64_t>(L, v, u[j]);
+      if (lu[j] != lv) uf_unite_dev(L, v, u[j]);
   }
 }
 
@@ -935,7 +998,7 @@ k_rank_cc_stitch(const uint8_t *__restrict__ mask, int64_t X, int64_t Y,
       }
       const int64_t pa = __shfl_up(a, 1), pb = __shfl_up(b, 1);
       const bool first = (threadIdx.x & 63) == 0 || pa != a || pb != b;
-      if (a >= 0 && a != b && first) uf_unite<int64_t>(L, a, b);
+      if (a >= 0 && a != b && first) uf_unite_dev(L, a, b);
     }
   }
 }
