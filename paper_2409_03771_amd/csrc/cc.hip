@@ -561,6 +561,77 @@ __global__ void __launch_bounds__(kCThreads) k_cc_root_shift(CBatch<B> b) {
 // Edges of a CSR row handled together, so that their gathers overlap.
 constexpr int kEdgeChunk = 8;
 
+// Unions of v with u[j] for every j with need[j]: the roots of v and of
+// those u[j] are found first with all the walks side by side (each step's
+// loads for every walk issued before any is used; walks that are done, or
+// not needed, reload a root harmlessly), then each u[j]'s root is hooked to
+// v's in turn, the smaller root winning.  A hook whose root has moved
+// meanwhile walks that pair again and retries; the merged root is then v's.
+__device__ __forceinline__ void uf_unite_row_dev(
+    int64_t *par, int64_t v, const int64_t (&u)[kEdgeChunk],
+    const bool (&need)[kEdgeChunk]) {
+  constexpr int W = kEdgeChunk + 1;
+  int64_t r[W];
+  bool open[W];
+  r[0] = v;
+  open[0] = true;
+#pragma unroll
+  for (int j = 0; j < kEdgeChunk; ++j) {
+    r[j + 1] = need[j] ? u[j] : v;
+    open[j + 1] = need[j];
+  }
+  for (;;) {
+    bool any = false;
+#pragma unroll
+    for (int i = 0; i < W; ++i) any |= open[i];
+    if (!any) break;
+    int64_t pr[W], gr[W];
+#pragma unroll
+    for (int i = 0; i < W; ++i) pr[i] = ld_dev(&par[r[i]]);
+#pragma unroll
+    for (int i = 0; i < W; ++i) gr[i] = ld_dev(&par[pr[i]]);
+#pragma unroll
+    for (int i = 0; i < W; ++i) {
+      if (!open[i]) continue;
+      if (pr[i] == r[i]) {
+        open[i] = false;
+      } else if (gr[i] == pr[i]) {
+        r[i] = pr[i];
+        open[i] = false;
+      } else {
+        __hip_atomic_store(&par[r[i]], gr[i], __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+        r[i] = gr[i];
+      }
+    }
+  }
+  int64_t rv = r[0];
+#pragma unroll
+  for (int j = 0; j < kEdgeChunk; ++j) {
+    if (!need[j]) continue;
+    int64_t a = rv, b = r[j + 1];
+    for (;;) {
+      if (a == b) {
+        rv = a;
+        break;
+      }
+      if (a > b) {
+        const int64_t t = a;
+        a = b;
+        b = t;
+      }
+      int64_t expect = b;
+      if (__hip_atomic_compare_exchange_strong(
+              &par[b], &expect, a, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+              __HIP_MEMORY_SCOPE_AGENT)) {
+        rv = a;
+        break;
+      }
+      uf_find2_dev(par, a, b);  // b moved meanwhile; retry from the new trees
+    }
+  }
+}
+
 __global__ void __launch_bounds__(kBlock)
 k_csr_init(int64_t n, const int64_t *__restrict__ rp,
            const int32_t *__restrict__ ci, const uint8_t *__restrict__ mask,
@@ -647,9 +718,10 @@ k_csr_union(int64_t n, const int64_t *__restrict__ rp,
     for (int j = 0; j < kEdgeChunk; ++j)
       lu[j] = __hip_atomic_load(&L[u[j]], __ATOMIC_RELAXED,
                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+    bool need[kEdgeChunk];
 #pragma unroll
-    for (int j = 0; j < kEdgeChunk; ++j)
-      if (lu[j] != lv) uf_unite_dev(L, v, u[j]);
+    for (int j = 0; j < kEdgeChunk; ++j) need[j] = lu[j] != lv;
+    uf_unite_row_dev(L, v, u, need);
   }
 }
 
