@@ -177,8 +177,8 @@ def roofline_of(prof, workload=None, tile=None):
            "kernel": kname, "avg_ms": round(avg_ms, 4),
            "bytes_per_launch": bpl}
     if name == "tile_local":
-        # The steepest pass's algorithmic bytes as the survey counts them
-        # (f 4 + two int32 pointers 8 = 12 B/vertex); the kernel itself
+        # The steepest pass's algorithmic bytes counted as the field and
+        # two int32 pointers (f 4 + 8 = 12 B/vertex); the kernel itself
         # writes one packed 32-bit code per vertex (f 4 + code 4 = 8 B).
         n = bpl / 12.0
         out["bytes_per_vertex"] = 12
