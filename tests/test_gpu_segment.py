@@ -234,3 +234,57 @@ def test_calls_on_two_streams_are_ordered(msc):
     for f, o in ((f1, o1), (f2, o2)):
         for name, g, w in zip(("asc", "desc", "ms"), o, O.segment(f)):
             np.testing.assert_array_equal(g.cpu().numpy(), w, err_msg=name)
+
+
+def _mixed_pair_field():
+    """96 x 48 x 48 (3 x 3 x 3 tiles of 32 x 16 x 16): one smooth bump, with
+    U[-0.05, 0.05] noise added in the far corner tile.  Its tiles hold one
+    (asc, desc) pair, a few, and hundreds to thousands, so the output pass
+    takes all three of its paths in one call (no bytes for a one-pair tile,
+    the byte per vertex for up to 255 pairs, the per-vertex path beyond)."""
+    X, Y, Z = 96, 48, 48
+    z, y, x = np.meshgrid(np.arange(Z), np.arange(Y), np.arange(X),
+                          indexing="ij")
+    f = np.exp(-(((x - 40.5) / 25.0) ** 2 + ((y - 20.5) / 12.0) ** 2 +
+                 ((z - 20.5) / 12.0) ** 2)).astype(np.float32)
+    rng = np.random.default_rng(7)
+    f[32:48, 32:48, 64:96] += rng.uniform(-0.05, 0.05,
+                                          size=(16, 16, 32)).astype(np.float32)
+    return f
+
+
+def _pairs_per_tile(a, d, shape, tile=(16, 16, 32)):
+    a = a.reshape(shape)
+    d = d.reshape(shape)
+    out = []
+    for z0 in range(0, shape[0], tile[0]):
+        for y0 in range(0, shape[1], tile[1]):
+            for x0 in range(0, shape[2], tile[2]):
+                sl = (slice(z0, z0 + tile[0]), slice(y0, y0 + tile[1]),
+                      slice(x0, x0 + tile[2]))
+                out.append(len(set(zip(a[sl].ravel().tolist(),
+                                       d[sl].ravel().tolist()))))
+    return out
+
+
+def test_output_pass_paths_in_one_call(msc):
+    f = _mixed_pair_field()
+    want = O.segment(f)
+    # The input covers every path: decided on the oracle's labels alone.
+    counts = _pairs_per_tile(want[0], want[1], f.shape)
+    assert min(counts) == 1 and max(counts) > 255
+    assert any(1 < c <= 255 for c in counts)
+    msc.set_tile(32, 16, 16)
+    got = gpu_segment(msc, f)
+    for name, g, w in zip(("asc", "desc", "ms"), got, want):
+        np.testing.assert_array_equal(g, w, err_msg=name)
+    # The same field inside a batch, beside a pure-noise field whose every
+    # tile takes the per-vertex path.
+    noise = np.random.default_rng(8).random((20, 40, 70)).astype(np.float32)
+    dev = [torch.from_numpy(f).cuda(), torch.from_numpy(noise).cuda()]
+    outs = msc.segment_batched(dev)
+    torch.cuda.synchronize()
+    for fld, out in zip((f, noise), outs):
+        ref = O.segment(fld)
+        for name, g, w in zip(("asc", "desc", "ms"), out, ref):
+            np.testing.assert_array_equal(g.cpu().numpy(), w, err_msg=name)
