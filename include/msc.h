@@ -140,10 +140,10 @@ MSC_API int msc_workspace_size(const msc_ctx *ctx, int kind, int n,
  *  ms     device, int32[N] or NULL: Morse-Smale cell id = smallest vertex id
  *         u with asc[u] == asc[v] and desc[u] == desc[v].
  *  Asynchronous on `stream`.  Workspace (device, held by the context):
- *  about 9.5 bytes per vertex with 32x16x16 tiles (4 more for each of asc
- *  and desc passed as NULL), plus a cell table of which at most 2 * N
- *  slots of 12 bytes are reserved and only the part the extremum counts
- *  call for is used; msc_workspace_size gives the exact figure.
+ *  about 9.5 bytes per vertex with 32x16x16 tiles, plus a cell table of
+ *  which at most 2 * N slots of 12 bytes are reserved and only the part the
+ *  extremum counts call for is used; msc_workspace_size gives the exact
+ *  figure.  Labels passed as NULL are neither written nor kept.
  *  Errors returned: MSC_EINVAL (dims < 1, field NULL, all outputs NULL),
  *          MSC_ERANGE (N > INT32_MAX), MSC_ENOMEM, MSC_EHIP.
  *  Reported by msc_last_status after the work has run: MSC_ENAN (outputs

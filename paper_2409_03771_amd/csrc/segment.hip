@@ -80,7 +80,7 @@ struct FieldDev {
   const float *f;
   uint32_t *lp;                // packed codes, tile-major (code_word), one
                                // array for the whole batch
-  int32_t *A, *D, *ms;         // outputs (A/D may be library scratch)
+  int32_t *A, *D, *ms;         // outputs; NULL when not wanted
   unsigned long long *keys;    // the field's pair table
   int32_t *vals;
   uint32_t mask;               // table capacity - 1
@@ -1430,8 +1430,9 @@ k_tile_pairs(const FieldDev *__restrict__ fds,
         // only the cell ids.
         const int32_t a = decode_final<C>(s, code[lz] & 0xffffu, false);
         const int32_t d = decode_final<C>(s, code[lz] >> 16, true);
-        plane_ptr(bt.fd.A, g, t.z0 + lz)[col] = a;
-        plane_ptr(bt.fd.D, g, t.z0 + lz)[col] = d;
+        // Only the labels the caller wants (block-uniform tests).
+        if (bt.fd.A) plane_ptr(bt.fd.A, g, t.z0 + lz)[col] = a;
+        if (bt.fd.D) plane_ptr(bt.fd.D, g, t.z0 + lz)[col] = d;
         key = pair_key(a, d);
       }
       if (in && key != last) {
@@ -1570,8 +1571,8 @@ k_tile_write(const FieldDev *__restrict__ fds,
       a = decode_final<C>(s, code[lz] & 0xffffu, false);
       d = decode_final<C>(s, code[lz] >> 16, true);
       if (!ms) {  // with cells, the pair pass has written the labels
-        plane_ptr(A, g, t.z0 + lz)[col] = a;
-        plane_ptr(D, g, t.z0 + lz)[col] = d;
+        if (A) plane_ptr(A, g, t.z0 + lz)[col] = a;
+        if (D) plane_ptr(D, g, t.z0 + lz)[col] = d;
       }
     }
     slot[lz] = -1;
@@ -1887,7 +1888,7 @@ int plan_batch(int nfields, const msc_field *fields, BatchPlan &p) {
   p.fd.assign(nfields, FieldDev{});
   p.tab_off.assign(nfields, 0);
   uint64_t total_tiles = 0;
-  size_t need_lp = 0, need_scratch = 0;
+  size_t need_lp = 0;
   for (int i = 0; i < nfields; ++i) {
     const int64_t X = fields[i].dims[0], Y = fields[i].dims[1],
                   Z = fields[i].dims[2];
@@ -1905,8 +1906,6 @@ int plan_batch(int nfields, const msc_field *fields, BatchPlan &p) {
     p.fd[i].tile0 = (uint32_t)total_tiles;
     total_tiles += nt;
     p.total_n += g.N;
-    if (!fields[i].asc) need_scratch += align256((size_t)g.N * sizeof(int32_t));
-    if (!fields[i].desc) need_scratch += align256((size_t)g.N * sizeof(int32_t));
     if (total_tiles > INT32_MAX / 2) return MSC_ERANGE;
     if (fields[i].ms) {
       // Room for the largest table the field can need; the device uses
@@ -1924,7 +1923,7 @@ int plan_batch(int nfields, const msc_field *fields, BatchPlan &p) {
   p.nslots = nt * (uint32_t)(2 * C::kHalo);
   need_lp = align256((size_t)nt * C::TX * C::TY * C::TZ * sizeof(uint32_t));
   p.need =
-      need_lp + need_scratch + align256((size_t)p.nslots * sizeof(uint32_t)) +
+      need_lp + align256((size_t)p.nslots * sizeof(uint32_t)) +
       2 * align256(nt * sizeof(Seg)) + 2 * align256(nt * sizeof(uint32_t)) +
       align256((kTileBuckets + 2) * sizeof(uint32_t)) +
       align256(nfields * sizeof(FieldDev)) +
@@ -1971,8 +1970,8 @@ int segment_batch(msc_ctx *ctx, int nfields, const msc_field *fields,
   for (int i = 0; i < nfields; ++i) {
     fd[i].f = fields[i].field;
     fd[i].lp = lp;
-    fd[i].A = fields[i].asc ? fields[i].asc : cv.take<int32_t>(fd[i].g.N);
-    fd[i].D = fields[i].desc ? fields[i].desc : cv.take<int32_t>(fd[i].g.N);
+    fd[i].A = fields[i].asc;  // labels nobody wants are not written
+    fd[i].D = fields[i].desc;
     fd[i].ms = fields[i].ms;
     fd[i].keys = fields[i].ms ? keys + tab_off[i] : nullptr;
     fd[i].vals = fields[i].ms ? vals + tab_off[i] : nullptr;
